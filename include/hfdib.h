@@ -1,0 +1,216 @@
+/*
+ * hfdib.h -- C ABI of the MI355X library for the IB-aware steady SIMPLE
+ * iteration of the hybrid fictitious domain-immersed boundary (HFDIB) RANS
+ * method (Kubickova & Isoz, "Extending the hybrid fictitious domain-immersed
+ * boundary method for Reynolds-averaged turbulence modeling").
+ *
+ * Problem statement followed by the entry points:
+ *   - a fluid/solid domain on a uniform Cartesian grid, the solid given by the
+ *     cell indicator lambda in [0,1] (Sec. "Mask fields construction", eq. for
+ *     lambda);
+ *   - the steady RANS equations with IB source f_ib and the lambda-masked
+ *     continuity equation (eq. of the governing equations), closed by a
+ *     two-equation model with S_ib in the k equation (Sec. "Governing
+ *     equations", "Immersed boundary-induced source terms");
+ *   - inlet/outlet/wall conditions and inlet turbulence (boundary-condition
+ *     paragraph of the pipe-flow section), upwind convection and implicit
+ *     under-relaxation (paragraph "Numerical schemes");
+ *   - the SIMPLE loop extended by the IB steps (figure of the SIMPLE algorithm
+ *     and the paragraph "SIMPLE-based solution strategy").
+ *
+ * Memory: every heavy buffer is caller-owned device memory.  The caller
+ * allocates one workspace of hfdib_workspace_bytes() bytes on the device and
+ * keeps it alive for the lifetime of the context; the library never calls
+ * hipMalloc.  Arrays are FP64, structure-of-arrays, cell index
+ * c = i + nx*(j + ny*k) (x fastest).  Face-flux arrays phi_x, phi_y, phi_z hold
+ * (nx+1)*ny*nz, nx*(ny+1)*nz and nx*ny*(nz+1) values (flux in the +axis
+ * direction), face index f = i + (nx+1)*(j + ny*k) etc.
+ *
+ * Streams: all device work of a context is enqueued on the hipStream_t given to
+ * hfdib_init_grid (NULL = default stream).  Pointers passed in are consumed in
+ * stream order.  Host synchronisation happens only where documented.
+ *
+ * Errors: every int-returning call returns an hfdib_status; no exception
+ * crosses the ABI.  On HFDIB_EDEVICE the HIP error string is kept and returned
+ * by hfdib_last_error().  A context is not thread safe; separate contexts are
+ * independent.
+ */
+#ifndef HFDIB_H
+#define HFDIB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HFDIB_ABI_VERSION 1
+
+typedef enum {
+  HFDIB_OK = 0,
+  HFDIB_EINVAL = -1,    /* invalid argument, lambda NaN or outside [0,1], capacity exceeded */
+  HFDIB_ENOMEM = -2,    /* workspace smaller than hfdib_workspace_bytes() */
+  HFDIB_EDEVICE = -3,   /* a HIP runtime error; message in hfdib_last_error() */
+  HFDIB_EDIVERGED = -4, /* NaN/Inf in the state or residual blow-up */
+  HFDIB_ESTATE = -5     /* call out of order (e.g. iterate before set_indicator) */
+} hfdib_status;
+
+typedef enum {
+  HFDIB_BC_INLET = 0,  /* Dirichlet u = u_in, k, eps/omega; zero-gradient p */
+  HFDIB_BC_OUTLET = 1, /* p = 0; zero-gradient u, k, eps/omega */
+  HFDIB_BC_NOSLIP = 2, /* u = 0 with log-law wall viscosity; wall functions for eps/omega */
+  HFDIB_BC_SLIP = 3,   /* no flux; zero-gradient u (normal part 0 in gradients) and scalars */
+  HFDIB_BC_EMPTY = 4   /* z faces of a 2D grid */
+} hfdib_bc_kind;
+
+typedef enum { HFDIB_LAMINAR = 0, HFDIB_KEPS = 1, HFDIB_KOMEGA_SST = 2 } hfdib_model;
+typedef enum { HFDIB_FP64 = 0, HFDIB_MIXED = 1 } hfdib_precision;
+
+/* Grid and boundary data.  dim = 2 requires nz = 1 and EMPTY z faces.
+ * bc[] order: xmin, xmax, ymin, ymax, zmin, zmax. */
+typedef struct {
+  int dim;
+  int nx, ny, nz;
+  double x0, y0, z0;
+  double dx, dy, dz;
+  int bc[6];
+  double u_in[3];
+  double k_in, eps_in, omega_in;
+} hfdib_grid_desc;
+
+/* Solver configuration.  hfdib_default_config() fills every field. */
+typedef struct {
+  int abi_version;      /* must equal HFDIB_ABI_VERSION */
+  int model;            /* hfdib_model */
+  int precision;        /* hfdib_precision; MIXED is reserved (returns EINVAL) */
+  int n_sweeps;         /* red-black Gauss-Seidel sweeps per transport solve (>= 1) */
+  double nu;            /* kinematic viscosity (> 0) */
+  double urf_u, urf_p, urf_t; /* under-relaxation of momentum, pressure, turbulence, in (0,1] */
+  double p_rtol;        /* relative residual target of the pressure PCG solve */
+  int p_maxit;          /* PCG iteration cap per pressure solve */
+  int recorrect;        /* 1: re-impose u_ib on forced cells after the velocity update */
+  int bc_capacity;      /* max boundary (and in-solid, wall) cells; 0 = automatic */
+  int reserved0;
+  /* wall treatment */
+  double Cmu, kappa, E, beta1_wf, Ceps2_wf, C_wf, ylam;
+  /* standard k-epsilon */
+  double C1, C2, sigma_k, sigma_eps;
+  /* Menter SST */
+  double sigma_k1, sigma_w1, beta_1, gamma_1, sigma_k2, sigma_w2, beta_2, gamma_2, a1, c_lim;
+  /* safeguards */
+  double bound_frac, yperp_min_frac, cd_floor;
+} hfdib_config;
+
+typedef struct hfdib_ctx hfdib_ctx;
+
+/* Field identifiers for hfdib_get_field / hfdib_set_field (FP64 device arrays). */
+enum {
+  HFDIB_FIELD_UX = 0, HFDIB_FIELD_UY, HFDIB_FIELD_UZ, HFDIB_FIELD_P,
+  HFDIB_FIELD_K, HFDIB_FIELD_EPS_OR_OMEGA, HFDIB_FIELD_NUT,
+  HFDIB_FIELD_PHI_X, HFDIB_FIELD_PHI_Y, HFDIB_FIELD_PHI_Z,
+  HFDIB_FIELD_LAMBDA,   /* get only */
+  HFDIB_FIELD_CLASS,    /* get only: 0 free-stream, 1 boundary, 2 in-solid */
+  HFDIB_FIELD_ALPHA_U,  /* get only: alpha_u of the last iteration */
+  HFDIB_FIELD_WALLDIST, /* get only: SST wall distance */
+  HFDIB_FIELD_COUNT
+};
+
+/* Per-boundary-cell records for hfdib_get_ib_array (device destination). */
+enum {
+  HFDIB_IB_BC_CELLS = 0, /* int32[n_bc], increasing cell index */
+  HFDIB_IB_IC_CELLS,     /* int32[n_ic] */
+  HFDIB_IB_WALL_CELLS,   /* int32[n_wall]: free-stream cells next to no-slip domain faces */
+  HFDIB_IB_NORMAL,       /* double[3*n_bc], (nx,ny,nz) per cell */
+  HFDIB_IB_YPERP,        /* double[n_bc] */
+  HFDIB_IB_YEFF,         /* double[n_bc] */
+  HFDIB_IB_MODE,         /* int32[n_bc]: 3 quadratic, 2 linear, 1 constant */
+  HFDIB_IB_LAGRANGE,     /* double[3*n_bc] weights of (S, P1, P2) */
+  HFDIB_IB_ST1_IDX,      /* int32[8*n_bc] */
+  HFDIB_IB_ST1_W,        /* double[8*n_bc] */
+  HFDIB_IB_ST2_IDX,      /* int32[8*n_bc] */
+  HFDIB_IB_ST2_W,        /* double[8*n_bc] */
+  HFDIB_IB_YPLUS,        /* double[n_bc]: y+ of the last iteration */
+  HFDIB_IB_UTAU_LOGLAW,  /* double[n_bc]: log-law u_tau of the last iteration (0 off branch) */
+  HFDIB_IB_WALL_Y,       /* double[n_wall] */
+  HFDIB_IB_COUNT
+};
+
+/* Returns HFDIB_ABI_VERSION. */
+int hfdib_abi_version(void);
+
+/* Fills *cfg with the defaults (standard model constants, URF 0.7/0.3/0.85,
+ * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1). */
+void hfdib_default_config(hfdib_config* cfg);
+
+/* Bytes of device workspace a context needs for this grid and configuration. */
+int hfdib_workspace_bytes(const hfdib_grid_desc* d, const hfdib_config* c, size_t* bytes);
+
+/* Creates a context.  Copies d and c, lays out the caller's workspace (device
+ * pointer, >= hfdib_workspace_bytes, 256-byte aligned) and records the stream
+ * (a hipStream_t, NULL for the default stream).  No device work is enqueued. */
+int hfdib_init_grid(const hfdib_grid_desc* d, const hfdib_config* c, void* workspace,
+                    size_t bytes, void* hip_stream, hfdib_ctx** out);
+
+/* Sets the indicator field (Sec. "Mask fields construction") and runs the
+ * per-lambda precompute: cell groups, normals, sigma, y_perp, y_eff,
+ * interpolation stencils, wall-function cells and (SST) the wall distance; then
+ * resets the state to the initial conditions.  lambda_dev: N doubles in [0,1]
+ * (device).  solid_vel_dev: 3*N doubles (ux block, uy block, uz block) with the
+ * solid velocity, or NULL for a resting solid.  Both are copied.  Synchronises
+ * the stream once (to validate lambda and read list sizes).
+ * Errors: EINVAL for NaN/out-of-range lambda or list capacity exceeded. */
+int hfdib_set_indicator(hfdib_ctx* ctx, const double* lambda_dev, const double* solid_vel_dev);
+
+/* Runs up to max_iters SIMPLE iterations (the paper's extended loop).  Stops
+ * early when tol > 0 and the largest normalised residual <= tol (checked every
+ * check_every iterations, which is where the host synchronises).  tol <= 0 runs
+ * exactly max_iters.  *iters_done (nullable) receives the count; res_out
+ * (nullable, host, 6 doubles) the residuals of Ux, Uy, Uz, p, k, eps/omega of the
+ * last iteration.  Returns EDIVERGED on NaN/Inf. */
+int hfdib_simple_iterate(hfdib_ctx* ctx, int max_iters, double tol, int check_every,
+                         int* iters_done, double* res_out);
+
+/* Copies a field to / from caller device memory (stream ordered). */
+int hfdib_get_field(hfdib_ctx* ctx, int field_id, double* dst_dev);
+int hfdib_set_field(hfdib_ctx* ctx, int field_id, const double* src_dev);
+
+/* Sizes of the precomputed lists: counts[0] = n_bc, [1] = n_ic, [2] = n_wall. */
+int hfdib_get_counts(hfdib_ctx* ctx, int* counts);
+
+/* Copies one per-boundary-cell record array (HFDIB_IB_*) to dst_dev. */
+int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);
+
+/* Solves the pressure-correction system alone: sum_f c_f (p_P - p_nb) +
+ * sum_outlet c_b p_P = rhs with c_f = mean(rAU)|S_f|/d_f and
+ * c_b = rAU_P|S|/(d/2) on outlet faces of cells with lambda = 0 (requires
+ * set_indicator).  rAU_dev, rhs_dev: N doubles; p_dev: initial guess in,
+ * solution out.  Conjugate gradients preconditioned by one geometric-multigrid
+ * V-cycle; stops at relative residual <= rtol or maxit iterations.
+ * *iters and *relres (host, nullable) report the outcome.  Synchronises. */
+int hfdib_pressure_solve(hfdib_ctx* ctx, const double* rAU_dev, const double* rhs_dev,
+                         double* p_dev, double rtol, int maxit, int* iters, double* relres);
+
+/* Statistics of the last hfdib_simple_iterate call (host, 8 doubles):
+ * [0] total PCG iterations, [1] iterations done, [2] max PCG iterations in one
+ * solve, [3] last pressure relative residual. */
+int hfdib_last_stats(hfdib_ctx* ctx, double* out8);
+
+/* Per-kernel timing with HIP events on the context stream.  enable != 0 starts
+ * recording (events around every launch of the named kernel class, see
+ * hfdib_timing_query); 0 stops.  Adds host overhead; off by default. */
+int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
+/* kernel_class: 0 pressure operator apply (fine level), 1 momentum sweep,
+ * 2 momentum assembly, 3 whole pressure solve, 4 whole SIMPLE iteration.
+ * Returns accumulated milliseconds and the launch count (host pointers).
+ * Synchronises the stream. */
+int hfdib_timing_query(hfdib_ctx* ctx, int kernel_class, double* total_ms, long long* count);
+
+void hfdib_destroy(hfdib_ctx* ctx);
+const char* hfdib_status_string(int status);
+const char* hfdib_last_error(const hfdib_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFDIB_H */

@@ -1,0 +1,629 @@
+// C ABI of the HFDIB SIMPLE library: workspace layout, context lifecycle,
+// iteration driver, field access and kernel timing.
+#include "device_common.h"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <utility>
+#include <vector>
+
+namespace hfdib {
+
+int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where) {
+  if (c) {
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return HFDIB_EDEVICE;
+}
+
+struct Timers {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pend[T_NCLASS];
+  hipEvent_t open[T_NCLASS] = {};
+  double ms[T_NCLASS] = {};
+  long long cnt[T_NCLASS] = {};
+};
+
+static void timers_flush(hfdib_ctx* c) {
+  Timers* T = c->timers;
+  (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < T_NCLASS; ++k) {
+    for (auto& pr : T->pend[k]) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        T->ms[k] += ms;
+        T->cnt[k] += 1;
+      }
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    T->pend[k].clear();
+  }
+}
+
+void timer_begin(hfdib_ctx* c, int cls) {
+  Timers* T = c->timers;
+  if (!T || !T->on) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, c->stream);
+  T->open[cls] = e;
+}
+
+void timer_end(hfdib_ctx* c, int cls) {
+  Timers* T = c->timers;
+  if (!T || !T->on || !T->open[cls]) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  (void)hipEventRecord(e, c->stream);
+  T->pend[cls].push_back({T->open[cls], e});
+  T->open[cls] = nullptr;
+  if (T->pend[cls].size() > 4096) timers_flush(c);
+}
+
+// ---------------------------------------------------------------- layout
+struct Bump {
+  char* base;
+  size_t off;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+static void level_dims(hfdib_ctx* c) {
+  const Params& P = c->P;
+  c->nlev = 1;
+  Level& L0 = c->lev[0];
+  L0.nx = P.nx;
+  L0.ny = P.ny;
+  L0.nz = P.nz;
+  L0.N = P.N;
+  while (c->nlev < MAX_LEVELS) {
+    Level& F = c->lev[c->nlev - 1];
+    bool ok = F.nx % 2 == 0 && F.ny % 2 == 0 && F.nx / 2 >= 2 && F.ny / 2 >= 2 && F.N > 64;
+    if (P.dim == 3) ok = ok && F.nz % 2 == 0 && F.nz / 2 >= 2;
+    if (!ok) break;
+    Level& L = c->lev[c->nlev];
+    L.nx = F.nx / 2;
+    L.ny = F.ny / 2;
+    L.nz = P.dim == 3 ? F.nz / 2 : 1;
+    L.N = (long long)L.nx * L.ny * L.nz;
+    c->nlev++;
+  }
+}
+
+static size_t layout(hfdib_ctx* c, char* base) {
+  const Params& P = c->P;
+  long long N = P.N;
+  Bump B{base, 0};
+  for (int q = 0; q < 3; ++q) c->u[q] = B.take<double>(N);
+  c->p = B.take<double>(N);
+  c->pnew = B.take<double>(N);
+  c->k = B.take<double>(N);
+  c->w = B.take<double>(N);
+  c->nut = B.take<double>(N);
+  c->lam = B.take<double>(N);
+  c->dw = B.take<double>(N);
+  for (int q = 0; q < 3; ++q) c->rhs[q] = B.take<double>(N);
+  c->aPr = B.take<double>(N);
+  for (int q = 0; q < 3; ++q) c->hbya[q] = B.take<double>(N);
+  c->rAU = B.take<double>(N);
+  for (int q = 0; q < 9; ++q) c->grad[q] = B.take<double>(N);
+  c->S2 = B.take<double>(N);
+  c->F1 = B.take<double>(N);
+  for (int q = 0; q < 3; ++q) c->uib[q] = B.take<double>(N);
+  c->kib = B.take<double>(N);
+  c->wib = B.take<double>(N);
+  c->Pk = B.take<double>(N);
+  for (int q = 0; q < 3; ++q) c->us[q] = B.take<double>(N);
+  c->t0 = B.take<double>(N);
+  c->t1 = B.take<double>(N);
+  c->t2 = B.take<double>(N);
+  c->rhs_p = B.take<double>(N);
+  c->px = B.take<double>(N);
+  c->pr = B.take<double>(N);
+  c->pz = B.take<double>(N);
+  c->pd = B.take<double>(N);
+  c->pq = B.take<double>(N);
+  c->flags = B.take<uint8_t>(N);
+  c->phi[0] = B.take<double>((long long)(P.nx + 1) * P.ny * P.nz);
+  c->phi[1] = B.take<double>((long long)P.nx * (P.ny + 1) * P.nz);
+  c->phi[2] = B.take<double>((long long)P.nx * P.ny * (P.nz + 1));
+  int cap = c->cap;
+  c->bc_cells = B.take<int>(cap);
+  c->ic_cells = B.take<int>(cap);
+  c->wall_cells = B.take<int>(cap);
+  c->bc_n = B.take<double>(3LL * cap);
+  c->bc_yperp = B.take<double>(cap);
+  c->bc_yeff = B.take<double>(cap);
+  c->bc_L = B.take<double>(3LL * cap);
+  c->bc_w1 = B.take<double>(8LL * cap);
+  c->bc_w2 = B.take<double>(8LL * cap);
+  c->bc_s1 = B.take<int>(8LL * cap);
+  c->bc_s2 = B.take<int>(8LL * cap);
+  c->bc_mode = B.take<int>(cap);
+  c->bc_yplus = B.take<double>(cap);
+  c->bc_utau = B.take<double>(cap);
+  c->bc_utauU = B.take<double>(cap);
+  c->wall_y = B.take<double>(cap);
+  c->wall_n = B.take<double>(3LL * cap);
+  c->wall_yplus = B.take<double>(cap);
+  c->wall_utau = B.take<double>(cap);
+  c->ipts = B.take<double>(3LL * cap);
+  dim3 g = grid3(P);
+  long long nblk3 = (long long)g.x * g.y * g.z;
+  long long nb1 = nblocks1(N);
+  long long ps = nblk3 > nb1 ? nblk3 : nb1;
+  c->pstride = (ps + 63) / 64 * 64;
+  c->partials = B.take<double>(16 * c->pstride);
+  c->scal = B.take<double>(512);
+  c->iscal = B.take<int>(64);
+  for (int l = 1; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    L.r = B.take<double>(L.N);
+    L.z = B.take<double>(L.N);
+    L.diag = B.take<double>(L.N);
+    L.cx = B.take<double>((long long)(L.nx + 1) * L.ny * L.nz);
+    L.cy = B.take<double>((long long)L.nx * (L.ny + 1) * L.nz);
+    L.cz = B.take<double>((long long)L.nx * L.ny * (L.nz + 1));
+  }
+  return B.off + 256;
+}
+
+static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::string* why) {
+  if (!d || !c) {
+    *why = "null descriptor";
+    return HFDIB_EINVAL;
+  }
+  if (c->abi_version != HFDIB_ABI_VERSION) {
+    *why = "config abi_version mismatch";
+    return HFDIB_EINVAL;
+  }
+  if (d->dim != 2 && d->dim != 3) {
+    *why = "dim must be 2 or 3";
+    return HFDIB_EINVAL;
+  }
+  if (d->nx < 4 || d->ny < 4 || d->nz < 1 || (d->dim == 2 && d->nz != 1) || (d->dim == 3 && d->nz < 4)) {
+    *why = "grid too small (>= 4 cells per active axis; nz = 1 in 2D)";
+    return HFDIB_EINVAL;
+  }
+  if (!(d->dx > 0.0 && d->dy > 0.0 && d->dz > 0.0)) {
+    *why = "cell sizes must be positive";
+    return HFDIB_EINVAL;
+  }
+  for (int f = 0; f < 6; ++f) {
+    int b = d->bc[f];
+    if (b < HFDIB_BC_INLET || b > HFDIB_BC_EMPTY) {
+      *why = "invalid boundary kind";
+      return HFDIB_EINVAL;
+    }
+    bool zf = f >= 4;
+    if (d->dim == 2 && zf && b != HFDIB_BC_EMPTY) {
+      *why = "2D grids need EMPTY z faces";
+      return HFDIB_EINVAL;
+    }
+    if ((d->dim == 3 || !zf) && b == HFDIB_BC_EMPTY) {
+      *why = "EMPTY is only valid for the z faces of 2D grids";
+      return HFDIB_EINVAL;
+    }
+  }
+  if (!(c->nu > 0.0)) {
+    *why = "nu must be positive";
+    return HFDIB_EINVAL;
+  }
+  if (!(c->urf_u > 0.0 && c->urf_u <= 1.0 && c->urf_p > 0.0 && c->urf_p <= 1.0 && c->urf_t > 0.0 && c->urf_t <= 1.0)) {
+    *why = "under-relaxation factors must lie in (0, 1]";
+    return HFDIB_EINVAL;
+  }
+  if (c->n_sweeps < 1 || c->p_maxit < 1 || !(c->p_rtol > 0.0)) {
+    *why = "n_sweeps >= 1, p_maxit >= 1 and p_rtol > 0 are required";
+    return HFDIB_EINVAL;
+  }
+  if (c->model < HFDIB_LAMINAR || c->model > HFDIB_KOMEGA_SST) {
+    *why = "invalid model";
+    return HFDIB_EINVAL;
+  }
+  if (c->precision != HFDIB_FP64) {
+    *why = "only FP64 precision is available in this library version";
+    return HFDIB_EINVAL;
+  }
+  if (c->model != HFDIB_LAMINAR) {
+    double win = c->model == HFDIB_KEPS ? d->eps_in : d->omega_in;
+    if (!(d->k_in > 0.0 && win > 0.0)) {
+      *why = "turbulent models need positive inlet k and eps/omega";
+      return HFDIB_EINVAL;
+    }
+  }
+  return HFDIB_OK;
+}
+
+static void fill_params(hfdib_ctx* c) {
+  const hfdib_grid_desc& d = c->desc;
+  const hfdib_config& g = c->cfg;
+  Params& P = c->P;
+  memset(&P, 0, sizeof(P));
+  P.dim = d.dim;
+  P.nx = d.nx;
+  P.ny = d.ny;
+  P.nz = d.nz;
+  P.N = (long long)d.nx * d.ny * d.nz;
+  P.x0 = d.x0;
+  P.y0 = d.y0;
+  P.z0 = d.z0;
+  P.dx = d.dx;
+  P.dy = d.dy;
+  P.dz = d.dz;
+  P.area[0] = d.dy * d.dz;
+  P.area[1] = d.dx * d.dz;
+  P.area[2] = d.dx * d.dy;
+  P.delta[0] = d.dx;
+  P.delta[1] = d.dy;
+  P.delta[2] = d.dz;
+  P.V = d.dx * d.dy * d.dz;
+  P.h = d.dim == 2 ? std::sqrt(d.dx * d.dy) : std::pow(P.V, 1.0 / 3.0);
+  for (int f = 0; f < 6; ++f) P.bc[f] = d.bc[f];
+  for (int q = 0; q < 3; ++q) P.u_in[q] = d.u_in[q];
+  P.k_in = d.k_in;
+  P.w_in = g.model == HFDIB_KEPS ? d.eps_in : (g.model == HFDIB_KOMEGA_SST ? d.omega_in : 0.0);
+  P.model = g.model;
+  P.n_sweeps = g.n_sweeps;
+  P.nu = g.nu;
+  P.urf_u = g.urf_u;
+  P.urf_p = g.urf_p;
+  P.urf_t = g.urf_t;
+  P.Cmu = g.Cmu;
+  P.kappa = g.kappa;
+  P.E = g.E;
+  P.beta1_wf = g.beta1_wf;
+  P.Ceps2_wf = g.Ceps2_wf;
+  P.C_wf = g.C_wf;
+  P.ylam = g.ylam;
+  P.C1 = g.C1;
+  P.C2 = g.C2;
+  P.sigma_k = g.sigma_k;
+  P.sigma_eps = g.sigma_eps;
+  P.sigma_k1 = g.sigma_k1;
+  P.sigma_w1 = g.sigma_w1;
+  P.beta_1 = g.beta_1;
+  P.gamma_1 = g.gamma_1;
+  P.sigma_k2 = g.sigma_k2;
+  P.sigma_w2 = g.sigma_w2;
+  P.beta_2 = g.beta_2;
+  P.gamma_2 = g.gamma_2;
+  P.a1 = g.a1;
+  P.c_lim = g.c_lim;
+  P.bound_frac = g.bound_frac;
+  P.yperp_min_frac = g.yperp_min_frac;
+  P.cd_floor = g.cd_floor;
+  P.Cmu25 = std::pow(g.Cmu, 0.25);
+  P.sqrtCmu = std::sqrt(g.Cmu);
+  P.recorrect = g.recorrect;
+}
+
+static int capacity_for(long long N, int requested) {
+  if (requested > 0) return requested;
+  long long cap = N <= (1LL << 20) ? N : N / 8 + 4096;
+  return (int)cap;
+}
+
+// small field conversion kernels
+__global__ void k_flag_field(long long n, const uint8_t* flags, int which, double* out) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c >= n) return;
+  uint8_t f = flags[c];
+  if (which == 0) out[c] = (f & F_IC) ? 2.0 : ((f & F_BC) ? 1.0 : 0.0);
+  else out[c] = (f & F_ALPHA_U) ? 1.0 : 0.0;
+}
+__global__ void k_fill0(long long n, double* a) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) a[c] = 0.0;
+}
+
+}  // namespace hfdib
+
+using namespace hfdib;
+
+extern "C" {
+
+int hfdib_abi_version(void) { return HFDIB_ABI_VERSION; }
+
+void hfdib_default_config(hfdib_config* c) {
+  if (!c) return;
+  memset(c, 0, sizeof(*c));
+  c->abi_version = HFDIB_ABI_VERSION;
+  c->model = HFDIB_KEPS;
+  c->precision = HFDIB_FP64;
+  c->n_sweeps = 2;
+  c->nu = 1e-5;
+  c->urf_u = 0.7;
+  c->urf_p = 0.3;
+  c->urf_t = 0.85;
+  c->p_rtol = 1e-2;
+  c->p_maxit = 200;
+  c->recorrect = 1;
+  c->bc_capacity = 0;
+  c->Cmu = 0.09;
+  c->kappa = 0.41;
+  c->E = 9.8;
+  c->beta1_wf = 0.075;
+  c->Ceps2_wf = 1.9;
+  c->C_wf = 11.0;
+  c->ylam = 11.0;
+  c->C1 = 1.44;
+  c->C2 = 1.92;
+  c->sigma_k = 1.0;
+  c->sigma_eps = 1.3;
+  c->sigma_k1 = 0.85;
+  c->sigma_w1 = 0.5;
+  c->beta_1 = 0.075;
+  c->gamma_1 = 0.5532;
+  c->sigma_k2 = 1.0;
+  c->sigma_w2 = 0.856;
+  c->beta_2 = 0.0828;
+  c->gamma_2 = 0.4404;
+  c->a1 = 0.31;
+  c->c_lim = 10.0;
+  c->bound_frac = 1e-10;
+  c->yperp_min_frac = 1e-6;
+  c->cd_floor = 1e-10;
+}
+
+int hfdib_workspace_bytes(const hfdib_grid_desc* d, const hfdib_config* c, size_t* bytes) {
+  std::string why;
+  int st = check_inputs(d, c, &why);
+  if (st != HFDIB_OK) return st;
+  if (!bytes) return HFDIB_EINVAL;
+  hfdib_ctx tmp;
+  tmp.desc = *d;
+  tmp.cfg = *c;
+  fill_params(&tmp);
+  tmp.cap = capacity_for(tmp.P.N, c->bc_capacity);
+  level_dims(&tmp);
+  *bytes = layout(&tmp, nullptr);
+  return HFDIB_OK;
+}
+
+int hfdib_init_grid(const hfdib_grid_desc* d, const hfdib_config* c, void* workspace, size_t bytes, void* hip_stream,
+                    hfdib_ctx** out) {
+  if (!out) return HFDIB_EINVAL;
+  *out = nullptr;
+  std::string why;
+  int st = check_inputs(d, c, &why);
+  if (st != HFDIB_OK) return st;
+  if (!workspace || ((uintptr_t)workspace & 255)) return HFDIB_EINVAL;
+  hfdib_ctx* ctx = new (std::nothrow) hfdib_ctx();
+  if (!ctx) return HFDIB_ENOMEM;
+  ctx->desc = *d;
+  ctx->cfg = *c;
+  fill_params(ctx);
+  ctx->cap = capacity_for(ctx->P.N, c->bc_capacity);
+  level_dims(ctx);
+  size_t need = layout(ctx, nullptr);
+  if (bytes < need) {
+    delete ctx;
+    return HFDIB_ENOMEM;
+  }
+  ctx->ws = (char*)workspace;
+  ctx->ws_bytes = bytes;
+  layout(ctx, ctx->ws);
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->ready = 0;
+  ctx->timers = new (std::nothrow) Timers();
+  memset(ctx->stats, 0, sizeof(ctx->stats));
+  *out = ctx;
+  return HFDIB_OK;
+}
+
+int hfdib_set_indicator(hfdib_ctx* c, const double* lambda_dev, const double* solid_vel_dev) {
+  if (!c || !lambda_dev) return HFDIB_EINVAL;
+  const Params& P = c->P;
+  size_t nb = (size_t)P.N * sizeof(double);
+  HFDIB_CHECK(c, hipMemcpyAsync(c->lam, lambda_dev, nb, hipMemcpyDeviceToDevice, c->stream), "copy lambda");
+  int n1 = nblocks1(P.N);
+  for (int q = 0; q < 3; ++q) {
+    if (solid_vel_dev)
+      HFDIB_CHECK(c, hipMemcpyAsync(c->us[q], solid_vel_dev + (size_t)q * P.N, nb, hipMemcpyDeviceToDevice, c->stream),
+                  "copy solid velocity");
+    else
+      hipLaunchKernelGGL(k_fill0, dim3(n1), dim3(NTHREADS), 0, c->stream, P.N, c->us[q]);
+  }
+  hipLaunchKernelGGL(k_fill0, dim3(n1), dim3(NTHREADS), 0, c->stream, P.N, c->dw);
+  HFDIB_CHECK_LAUNCH(c, "set_indicator");
+  c->ready = 0;
+  int st = geometry_precompute(c);
+  if (st != HFDIB_OK) return st;
+  st = init_state(c);
+  if (st != HFDIB_OK) return st;
+  c->ready = 1;
+  return HFDIB_OK;
+}
+
+int hfdib_simple_iterate(hfdib_ctx* c, int max_iters, double tol, int check_every, int* iters_done,
+                         double* res_out) {
+  if (!c) return HFDIB_EINVAL;
+  if (!c->ready) {
+    c->err = "hfdib_set_indicator has not been called";
+    return HFDIB_ESTATE;
+  }
+  if (max_iters < 0) return HFDIB_EINVAL;
+  memset(c->stats, 0, sizeof(c->stats));
+  double res[6] = {0, 0, 0, 0, 0, 0};
+  int done = 0;
+  int status = HFDIB_OK;
+  for (int it = 0; it < max_iters; ++it) {
+    bool check = (tol > 0.0 && check_every > 0 && (it + 1) % check_every == 0) || it == max_iters - 1;
+    int st = simple_step(c, it, check ? res : nullptr);
+    ++done;
+    if (st != HFDIB_OK) {
+      status = st;
+      break;
+    }
+    if (check) {
+      bool finite = true;
+      double mx = 0.0;
+      for (int q = 0; q < 6; ++q) {
+        if (!std::isfinite(res[q])) finite = false;
+        mx = res[q] > mx ? res[q] : mx;
+      }
+      if (!finite) {
+        c->err = "non-finite residual";
+        status = HFDIB_EDIVERGED;
+        break;
+      }
+      if (tol > 0.0 && mx <= tol) break;
+    }
+  }
+  c->stats[1] = done;
+  if (iters_done) *iters_done = done;
+  if (res_out) memcpy(res_out, res, sizeof(res));
+  return status;
+}
+
+static double* field_ptr(hfdib_ctx* c, int id, size_t* n) {
+  const Params& P = c->P;
+  *n = (size_t)P.N;
+  switch (id) {
+    case HFDIB_FIELD_UX: return c->u[0];
+    case HFDIB_FIELD_UY: return c->u[1];
+    case HFDIB_FIELD_UZ: return c->u[2];
+    case HFDIB_FIELD_P: return c->p;
+    case HFDIB_FIELD_K: return c->k;
+    case HFDIB_FIELD_EPS_OR_OMEGA: return c->w;
+    case HFDIB_FIELD_NUT: return c->nut;
+    case HFDIB_FIELD_PHI_X: *n = (size_t)(P.nx + 1) * P.ny * P.nz; return c->phi[0];
+    case HFDIB_FIELD_PHI_Y: *n = (size_t)P.nx * (P.ny + 1) * P.nz; return c->phi[1];
+    case HFDIB_FIELD_PHI_Z: *n = (size_t)P.nx * P.ny * (P.nz + 1); return c->phi[2];
+    case HFDIB_FIELD_LAMBDA: return c->lam;
+    case HFDIB_FIELD_WALLDIST: return c->dw;
+    default: return nullptr;
+  }
+}
+
+int hfdib_get_field(hfdib_ctx* c, int id, double* dst) {
+  if (!c || !dst) return HFDIB_EINVAL;
+  if (id == HFDIB_FIELD_CLASS || id == HFDIB_FIELD_ALPHA_U) {
+    hipLaunchKernelGGL(k_flag_field, dim3(nblocks1(c->P.N)), dim3(NTHREADS), 0, c->stream, c->P.N, c->flags,
+                       id == HFDIB_FIELD_CLASS ? 0 : 1, dst);
+    HFDIB_CHECK_LAUNCH(c, "get_field");
+    return HFDIB_OK;
+  }
+  size_t n;
+  double* src = field_ptr(c, id, &n);
+  if (!src) return HFDIB_EINVAL;
+  HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "get_field");
+  return HFDIB_OK;
+}
+
+int hfdib_set_field(hfdib_ctx* c, int id, const double* src) {
+  if (!c || !src) return HFDIB_EINVAL;
+  if (id > HFDIB_FIELD_PHI_Z) return HFDIB_EINVAL;
+  size_t n;
+  double* dst = field_ptr(c, id, &n);
+  if (!dst) return HFDIB_EINVAL;
+  HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "set_field");
+  if (id <= HFDIB_FIELD_UZ) c->grad_stale = 1;
+  return HFDIB_OK;
+}
+
+int hfdib_get_counts(hfdib_ctx* c, int* counts) {
+  if (!c || !counts) return HFDIB_EINVAL;
+  if (!c->ready) return HFDIB_ESTATE;
+  counts[0] = c->n_bc;
+  counts[1] = c->n_ic;
+  counts[2] = c->n_wall;
+  return HFDIB_OK;
+}
+
+int hfdib_get_ib_array(hfdib_ctx* c, int id, void* dst) {
+  if (!c || !dst) return HFDIB_EINVAL;
+  if (!c->ready) return HFDIB_ESTATE;
+  const void* src = nullptr;
+  size_t bytes = 0;
+  size_t nb = (size_t)c->n_bc, nw = (size_t)c->n_wall;
+  switch (id) {
+    case HFDIB_IB_BC_CELLS: src = c->bc_cells; bytes = nb * 4; break;
+    case HFDIB_IB_IC_CELLS: src = c->ic_cells; bytes = (size_t)c->n_ic * 4; break;
+    case HFDIB_IB_WALL_CELLS: src = c->wall_cells; bytes = nw * 4; break;
+    case HFDIB_IB_NORMAL: src = c->bc_n; bytes = nb * 24; break;
+    case HFDIB_IB_YPERP: src = c->bc_yperp; bytes = nb * 8; break;
+    case HFDIB_IB_YEFF: src = c->bc_yeff; bytes = nb * 8; break;
+    case HFDIB_IB_MODE: src = c->bc_mode; bytes = nb * 4; break;
+    case HFDIB_IB_LAGRANGE: src = c->bc_L; bytes = nb * 24; break;
+    case HFDIB_IB_ST1_IDX: src = c->bc_s1; bytes = nb * 32; break;
+    case HFDIB_IB_ST1_W: src = c->bc_w1; bytes = nb * 64; break;
+    case HFDIB_IB_ST2_IDX: src = c->bc_s2; bytes = nb * 32; break;
+    case HFDIB_IB_ST2_W: src = c->bc_w2; bytes = nb * 64; break;
+    case HFDIB_IB_YPLUS: src = c->bc_yplus; bytes = nb * 8; break;
+    case HFDIB_IB_UTAU_LOGLAW: src = c->bc_utauU; bytes = nb * 8; break;
+    case HFDIB_IB_WALL_Y: src = c->wall_y; bytes = nw * 8; break;
+    default: return HFDIB_EINVAL;
+  }
+  if (bytes == 0) return HFDIB_OK;
+  HFDIB_CHECK(c, hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->stream), "get_ib_array");
+  return HFDIB_OK;
+}
+
+int hfdib_pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* p, double rtol, int maxit,
+                         int* iters, double* relres) {
+  if (!c || !rAU || !rhs || !p || !(rtol > 0.0) || maxit < 1) return HFDIB_EINVAL;
+  if (!c->ready) return HFDIB_ESTATE;
+  int it = 0;
+  double rr = 0.0;
+  int st = pressure_solve(c, rAU, rhs, p, rtol, maxit, &it, &rr, nullptr);
+  if (iters) *iters = it;
+  if (relres) *relres = rr;
+  if (st == HFDIB_OK) HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "pressure solve sync");
+  return st;
+}
+
+int hfdib_last_stats(hfdib_ctx* c, double* out8) {
+  if (!c || !out8) return HFDIB_EINVAL;
+  memcpy(out8, c->stats, sizeof(c->stats));
+  return HFDIB_OK;
+}
+
+int hfdib_timing_enable(hfdib_ctx* c, int enable) {
+  if (!c || !c->timers) return HFDIB_EINVAL;
+  if (!enable) timers_flush(c);
+  c->timers->on = enable != 0;
+  return HFDIB_OK;
+}
+
+int hfdib_timing_query(hfdib_ctx* c, int cls, double* total_ms, long long* count) {
+  if (!c || !c->timers || cls < 0 || cls >= T_NCLASS) return HFDIB_EINVAL;
+  timers_flush(c);
+  if (total_ms) *total_ms = c->timers->ms[cls];
+  if (count) *count = c->timers->cnt[cls];
+  return HFDIB_OK;
+}
+
+void hfdib_destroy(hfdib_ctx* c) {
+  if (!c) return;
+  if (c->timers) {
+    timers_flush(c);
+    delete c->timers;
+  }
+  delete c;
+}
+
+const char* hfdib_status_string(int s) {
+  switch (s) {
+    case HFDIB_OK: return "ok";
+    case HFDIB_EINVAL: return "invalid argument";
+    case HFDIB_ENOMEM: return "workspace too small";
+    case HFDIB_EDEVICE: return "HIP runtime error";
+    case HFDIB_EDIVERGED: return "diverged";
+    case HFDIB_ESTATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+const char* hfdib_last_error(const hfdib_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

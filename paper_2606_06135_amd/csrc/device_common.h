@@ -1,0 +1,159 @@
+// Device helpers shared by the HFDIB kernels: indexing, boundary faces,
+// deterministic block reductions (wave64 shuffles + LDS), geometric helpers.
+#pragma once
+
+#include "hfdib_internal.h"
+
+namespace hfdib {
+
+// ---------------------------------------------------------------- indexing
+__device__ __forceinline__ long long cidx(const Params& P, int i, int j, int k) {
+  return (long long)i + (long long)P.nx * ((long long)j + (long long)P.ny * k);
+}
+// face index of the face on the low side of cell (i,j,k), normal d
+__device__ __forceinline__ long long fidx(const Params& P, int d, int i, int j, int k) {
+  if (d == 0) return (long long)i + (long long)(P.nx + 1) * ((long long)j + (long long)P.ny * k);
+  if (d == 1) return (long long)i + (long long)P.nx * ((long long)j + (long long)(P.ny + 1) * k);
+  return (long long)i + (long long)P.nx * ((long long)j + (long long)P.ny * k);
+}
+__device__ __forceinline__ int ncell(const Params& P, int d) { return d == 0 ? P.nx : (d == 1 ? P.ny : P.nz); }
+__device__ __forceinline__ long long stride(const Params& P, int d) {
+  return d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+}
+__device__ __forceinline__ int comp(int d, int i, int j, int k) { return d == 0 ? i : (d == 1 ? j : k); }
+
+// true when the cell touches the domain face (d, s)
+__device__ __forceinline__ bool on_bnd(const Params& P, int d, int s, int i, int j, int k) {
+  int a = comp(d, i, j, k);
+  return s < 0 ? (a == 0) : (a == ncell(P, d) - 1);
+}
+__device__ __forceinline__ int face_kind(const Params& P, int d, int s) { return P.bc[2 * d + (s > 0 ? 1 : 0)]; }
+
+// outward flux of cell (i,j,k) through its face (d, s)
+__device__ __forceinline__ double outward_flux(const Params& P, const double* const* phi, int d, int s, int i,
+                                               int j, int k) {
+  long long f = fidx(P, d, i, j, k);
+  if (s > 0) {
+    long long off = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+    return phi[d][f + off];
+  }
+  return -phi[d][f];
+}
+
+struct Phi3 {
+  const double* a[3];
+  __device__ __forceinline__ const double* const* ptr() const { return a; }
+};
+
+// ---------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Block-wide sums of NV values (256 threads = 4 waves), result written by
+// thread 0 to part[v*pstride + blk].  Fixed reduction order: deterministic.
+template <int NV>
+__device__ __forceinline__ void block_sums_store(const double (&v)[NV], double* part, long long pstride,
+                                                 long long blk) {
+  __shared__ double lds[4][NV];
+  int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  int lane = tid & 63, wid = tid >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double s = wave_sum(v[q]);
+    if (lane == 0) lds[wid][q] = s;
+  }
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double s = lds[0][q];
+      for (int w = 1; w < 4; ++w) s += lds[w][q];
+      part[(long long)q * pstride + blk] = s;
+    }
+  }
+}
+
+__device__ __forceinline__ long long block_linear() {
+  return (long long)blockIdx.x + (long long)gridDim.x * ((long long)blockIdx.y + (long long)gridDim.y * blockIdx.z);
+}
+
+// ---------------------------------------------------------------- geometry
+struct V3 {
+  double x, y, z;
+};
+__device__ __forceinline__ V3 center(const Params& P, int i, int j, int k) {
+  V3 c;
+  c.x = P.x0 + ((double)i + 0.5) * P.dx;
+  c.y = P.y0 + ((double)j + 0.5) * P.dy;
+  c.z = P.dim == 3 ? P.z0 + ((double)k + 0.5) * P.dz : 0.0;
+  return c;
+}
+
+// central-difference gradient of lambda, one-sided at the domain edges
+__device__ __forceinline__ V3 grad_lambda(const Params& P, const double* lam, int i, int j, int k) {
+  V3 g = {0.0, 0.0, 0.0};
+  long long c = cidx(P, i, j, k);
+  for (int d = 0; d < P.dim; ++d) {
+    int n = ncell(P, d);
+    if (n <= 1) continue;
+    int a = comp(d, i, j, k);
+    long long st = stride(P, d);
+    double D = P.delta[d];
+    double val;
+    if (a == 0)
+      val = (lam[c + st] - lam[c]) / D;
+    else if (a == n - 1)
+      val = (lam[c] - lam[c - st]) / D;
+    else
+      val = (lam[c + st] - lam[c - st]) / (2.0 * D);
+    if (d == 0) g.x = val;
+    else if (d == 1) g.y = val;
+    else g.z = val;
+  }
+  return g;
+}
+
+// outward normal n = -grad(lambda)/|grad(lambda)|, with the fallback to the
+// normalised sum of (P - N) over in-solid Moore neighbours
+__device__ V3 cell_normal(const Params& P, const double* lam, const uint8_t* flags, int i, int j, int k) {
+  V3 g = grad_lambda(P, lam, i, j, k);
+  double nrm = sqrt(g.x * g.x + g.y * g.y + g.z * g.z);
+  V3 n;
+  if (nrm * P.h >= 1e-12) {
+    n.x = -g.x / nrm;
+    n.y = -g.y / nrm;
+    n.z = -g.z / nrm;
+    return n;
+  }
+  V3 acc = {0.0, 0.0, 0.0};
+  int zr = P.dim == 3 ? 1 : 0;
+  for (int ox = -1; ox <= 1; ++ox)
+    for (int oy = -1; oy <= 1; ++oy)
+      for (int oz = -zr; oz <= zr; ++oz) {
+        if (ox == 0 && oy == 0 && oz == 0) continue;
+        int ii = i + ox, jj = j + oy, kk = k + oz;
+        if (ii < 0 || ii >= P.nx || jj < 0 || jj >= P.ny || kk < 0 || kk >= P.nz) continue;
+        if (flags[cidx(P, ii, jj, kk)] & F_IC) {
+          acc.x -= ox * P.dx;
+          acc.y -= oy * P.dy;
+          acc.z -= oz * P.dz;
+        }
+      }
+  double a = sqrt(acc.x * acc.x + acc.y * acc.y + acc.z * acc.z);
+  if (a > 0.0) {
+    acc.x /= a;
+    acc.y /= a;
+    acc.z /= a;
+  }
+  return acc;
+}
+
+}  // namespace hfdib

@@ -1,0 +1,161 @@
+// Internal declarations of the HFDIB SIMPLE library (gfx950, HIP).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+
+#include "../../include/hfdib.h"
+
+namespace hfdib {
+
+// cell flag bits (uint8 per cell)
+enum : uint8_t {
+  F_IC = 1u,       // in-solid cell (lambda >= 0.5)
+  F_BC = 2u,       // boundary cell
+  F_SOLID = 4u,    // lambda > 0 (domain faces of such cells are walls inside the solid)
+  F_ALPHA_U = 8u,  // alpha_u = alpha_k of the current iteration
+  F_ALPHA_W = 16u, // alpha_omega (in-solid, boundary and domain-wall cells)
+  F_WALL = 32u,    // free-stream cell next to a no-slip domain face
+  F_RED = 64u      // (i+j+k) even
+};
+
+constexpr int NTHREADS = 256;
+constexpr int MAX_PARTIAL_BLOCKS = 2048;  // per reduction slot
+constexpr int NRED = 24;                  // reduction slots per pass
+constexpr int MAX_LEVELS = 12;
+
+// Plain-old-data parameters passed by value to every kernel.
+struct Params {
+  int dim, nx, ny, nz;
+  long long N;
+  double x0, y0, z0, dx, dy, dz;
+  double area[3], delta[3], V, h;
+  int bc[6];
+  double u_in[3], k_in, w_in;  // w_in: eps_in (k-eps) or omega_in (SST)
+  int model;
+  int n_sweeps;
+  double nu, urf_u, urf_p, urf_t;
+  double Cmu, kappa, E, beta1_wf, Ceps2_wf, C_wf, ylam;
+  double C1, C2, sigma_k, sigma_eps;
+  double sigma_k1, sigma_w1, beta_1, gamma_1, sigma_k2, sigma_w2, beta_2, gamma_2, a1, c_lim;
+  double bound_frac, yperp_min_frac, cd_floor;
+  double Cmu25, sqrtCmu;  // Cmu^(1/4), sqrt(Cmu) (host-computed)
+  int recorrect;
+};
+
+// Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).
+struct Level {
+  int nx, ny, nz;
+  long long N;
+  double* r;
+  double* z;
+  double* cx;    // (nx+1)*ny*nz face coefficients
+  double* cy;    // nx*(ny+1)*nz
+  double* cz;    // nx*ny*(nz+1)
+  double* diag;  // N
+};
+
+struct Timers;
+
+}  // namespace hfdib
+
+struct hfdib_ctx {
+  hfdib_grid_desc desc;
+  hfdib_config cfg;
+  hfdib::Params P;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  int ready;  // set_indicator done
+  std::string err;
+
+  // --- cell arrays (N)
+  double *u[3], *p, *k, *w, *nut, *lam, *dw;
+  double *rhs[3], *aPr, *hbya[3], *rAU, *grad[9], *S2, *F1;
+  double *uib[3], *kib, *wib, *Pk, *us[3];
+  double *t0, *t1, *t2;  // scratch (turbulence rhs / diagonal)
+  double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
+  uint8_t* flags;
+  // --- face arrays
+  double* phi[3];
+  // --- lists
+  int cap;  // capacity of each list
+  int *bc_cells, *ic_cells, *wall_cells;
+  double *bc_n, *bc_yperp, *bc_yeff, *bc_L, *bc_w1, *bc_w2, *bc_yplus, *bc_utau, *bc_utauU;
+  int *bc_mode, *bc_s1, *bc_s2;
+  double *wall_y, *wall_n, *wall_yplus, *wall_utau;
+  int n_bc, n_ic, n_wall;
+  // --- interface points for the SST wall distance
+  double* ipts;  // 3*cap
+  int n_ipts;
+  // --- reductions
+  double* partials;  // 16 rows of pstride partial sums
+  long long pstride;
+  double* scal;      // 512 scalars
+  int* iscal;        // 64 ints
+  double* host_scal; // pinned? plain host mirror (filled by sync copies)
+  // --- multigrid
+  int nlev;
+  hfdib::Level lev[hfdib::MAX_LEVELS];
+  // --- stats
+  double stats[8];
+  double last_pres[3];
+  int grad_stale;
+  // --- timing
+  hfdib::Timers* timers;
+};
+
+namespace hfdib {
+
+// launch helpers
+inline dim3 grid3(const Params& P) {
+  return dim3((P.nx + 63) / 64, (P.ny + 3) / 4, P.nz);
+}
+inline dim3 block3() { return dim3(64, 4, 1); }
+inline int nblocks1(long long n) {
+  long long b = (n + NTHREADS - 1) / NTHREADS;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// error plumbing
+int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);
+#define HFDIB_CHECK_LAUNCH(ctx, where)                                  \
+  do {                                                                  \
+    hipError_t _e = hipGetLastError();                                  \
+    if (_e != hipSuccess) return hfdib::set_hip_error(ctx, _e, where);  \
+  } while (0)
+#define HFDIB_CHECK(ctx, call, where)                                  \
+  do {                                                                 \
+    hipError_t _e = (call);                                            \
+    if (_e != hipSuccess) return hfdib::set_hip_error(ctx, _e, where); \
+  } while (0)
+
+// timing classes
+enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_NCLASS = 5 };
+void timer_begin(hfdib_ctx* c, int cls);
+void timer_end(hfdib_ctx* c, int cls);
+
+// stages (each returns an hfdib_status)
+int geometry_precompute(hfdib_ctx* c);
+int init_state(hfdib_ctx* c);
+int simple_step(hfdib_ctx* c, int it, double* res6_dev_slot);
+int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol,
+                   int maxit, int* iters, double* relres, const double* xmean_dev);
+int mg_setup_levels(hfdib_ctx* c);
+
+// deterministic reduction of `nval` rows of per-block partial sums into
+// ctx->scal[SCAL_PCG + out + v]; op selects a PCG scalar update (pressure.hip)
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0);
+int turbulence_stage(hfdib_ctx* c);
+int gradient_only(hfdib_ctx* c);
+// offsets (relative to SCAL_PCG) of device scalars
+enum {
+  SC_MEANS = 100,    // means of u, v, w, p, k (5) and of omega/eps after fixing (1)
+  SC_RESSUM = 120,   // residual sums: U 9, omega/eps 3, k 3
+  SC_RES = 150,      // normalised residuals Ux, Uy, Uz, p, k, eps/omega
+  SC_WMAX = 160      // max of omega/eps over boundary and free-stream cells
+};
+constexpr int SCAL_PCG = 64;
+
+}  // namespace hfdib

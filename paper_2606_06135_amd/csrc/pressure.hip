@@ -1,0 +1,562 @@
+// Pressure-correction system of the lambda-masked continuity equation:
+//   sum_f c_f (p_P - p_nb) + sum_outlet c_b p_P = rhs,
+//   c_f = mean(rAU) |S_f| / d_f,  c_b = rAU_P |S| / (d/2)  (SPD, 5/7-point).
+// Conjugate gradients preconditioned by one symmetric geometric-multigrid
+// V-cycle (red-black Gauss-Seidel, 1 pre- and 1 post-sweep per level,
+// piecewise-constant transfer, rediscretised coarse operators).  The fine
+// level is matrix free (coefficients from rAU); coarse levels store face
+// coefficients.  All dot products are deterministic two-pass reductions.
+#include "device_common.h"
+
+#include <cmath>
+#include <vector>
+
+namespace hfdib {
+
+enum {
+  S_RHO = 0, S_ALPHA, S_BETA, S_RR, S_BB, S_DQ, S_RZ, S_RES0, S_RES1, S_RES2,  // pcg scalars
+};
+
+// ---------------------------------------------------------------- fine level
+struct FineOp {
+  const double* rAU;
+  const uint8_t* flags;
+};
+
+__device__ __forceinline__ double fine_coef(const Params& P, const FineOp& O, long long c, int d, int s, int i,
+                                            int j, int k, long long* nb) {
+  if (on_bnd(P, d, s, i, j, k)) {
+    *nb = -1;
+    if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID))
+      return O.rAU[c] * P.area[d] / (0.5 * P.delta[d]);
+    return 0.0;
+  }
+  long long n = c + s * stride(P, d);
+  *nb = n;
+  return s > 0 ? 0.5 * (O.rAU[c] + O.rAU[n]) * P.area[d] / P.delta[d]
+               : 0.5 * (O.rAU[n] + O.rAU[c]) * P.area[d] / P.delta[d];
+}
+
+// y = A x (and partial sums of x.y)
+__global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, double* part, long long pstride) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  double v[1] = {0.0};
+  if (i < P.nx && j < P.ny) {
+    long long c = cidx(P, i, j, k);
+    double xc = x[c];
+    double acc = 0.0;
+    for (int d = 0; d < P.dim; ++d)
+      for (int s = -1; s <= 1; s += 2) {
+        long long n;
+        double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
+        acc += n < 0 ? cf * xc : cf * (xc - x[n]);
+      }
+    y[c] = acc;
+    v[0] = xc * acc;
+  }
+  block_sums_store<1>(v, part, pstride, block_linear());
+}
+
+// r = b - A x; partial sums of r.r, b.b and (for the SIMPLE residual) |r|,
+// |Ax - A xbar|, |b - A xbar| with xbar = *xmean (nullable)
+__global__ void k_fine_residual(Params P, FineOp O, const double* b, const double* x, double* r, const double* xmean,
+                                double* part, long long pstride) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  double v[5] = {0, 0, 0, 0, 0};
+  if (i < P.nx && j < P.ny) {
+    long long c = cidx(P, i, j, k);
+    double xc = x[c];
+    double acc = 0.0, bnd = 0.0;
+    for (int d = 0; d < P.dim; ++d)
+      for (int s = -1; s <= 1; s += 2) {
+        long long n;
+        double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
+        if (n < 0) {
+          acc += cf * xc;
+          bnd += cf;
+        } else {
+          acc += cf * (xc - x[n]);
+        }
+      }
+    double bc = b[c];
+    double rc = bc - acc;
+    r[c] = rc;
+    v[0] = rc * rc;
+    v[1] = bc * bc;
+    if (xmean) {
+      double Axb = bnd * (*xmean);
+      v[2] = fabs(rc);
+      v[3] = fabs(acc - Axb);
+      v[4] = fabs(bc - Axb);
+    }
+  }
+  block_sums_store<5>(v, part, pstride, block_linear());
+}
+
+// red-black Gauss-Seidel half sweep on the fine level; init != 0 means z was
+// zero before this (first red) sweep: red cells z = r/diag, black cells z = 0
+__global__ void k_fine_smooth(Params P, FineOp O, const double* r, double* z, int color, int init) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  bool mine = ((i + j + k) & 1) == color;
+  if (init && !mine) {
+    z[c] = 0.0;
+    return;
+  }
+  if (!mine) return;
+  double diag = 0.0, nb = 0.0;
+  for (int d = 0; d < P.dim; ++d)
+    for (int s = -1; s <= 1; s += 2) {
+      long long n;
+      double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
+      diag += cf;
+      if (n >= 0 && !init) nb += cf * z[n];
+    }
+  z[c] = (r[c] + nb) / diag;
+}
+
+// ---------------------------------------------------------------- coarse levels
+struct LevelDev {
+  int nx, ny, nz, dim;
+  long long N;
+  double* r;
+  double* z;
+  const double* cx;
+  const double* cy;
+  const double* cz;
+  const double* diag;
+};
+
+__device__ __forceinline__ long long lidx(const LevelDev& L, int i, int j, int k) {
+  return (long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k);
+}
+
+// coefficients of level 1 from the fine operator: sum of the fine face
+// coefficients on each coarse face, halved (rediscretisation on the 2h grid)
+__global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDev L, double* cx, double* cy, double* cz) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int J = blockIdx.y * blockDim.y + threadIdx.y;
+  int K = blockIdx.z;
+  int nzs = L.dim == 3 ? 2 : 1;
+  // x faces: I in [0, nx]
+  if (I <= L.nx && J < L.ny && K < L.nz) {
+    double s = 0.0;
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < nzs; ++e) {
+        int j = 2 * J + b, k = L.dim == 3 ? 2 * K + e : 0;
+        if (I < L.nx) {
+          int i = 2 * I;
+          long long n;
+          s += fine_coef(P, O, cidx(P, i, j, k), 0, -1, i, j, k, &n);
+        } else {
+          int i = 2 * I - 1;
+          long long n;
+          s += fine_coef(P, O, cidx(P, i, j, k), 0, +1, i, j, k, &n);
+        }
+      }
+    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+  }
+  if (I < L.nx && J <= L.ny && K < L.nz) {
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int e = 0; e < nzs; ++e) {
+        int i = 2 * I + a, k = L.dim == 3 ? 2 * K + e : 0;
+        long long n;
+        if (J < L.ny) {
+          int j = 2 * J;
+          s += fine_coef(P, O, cidx(P, i, j, k), 1, -1, i, j, k, &n);
+        } else {
+          int j = 2 * J - 1;
+          s += fine_coef(P, O, cidx(P, i, j, k), 1, +1, i, j, k, &n);
+        }
+      }
+    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = 0.5 * s;
+  }
+  if (L.dim == 3 && I < L.nx && J < L.ny && K <= L.nz) {
+    // z faces K in [0, nz]: the launch has nz+1 planes
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        int i = 2 * I + a, j = 2 * J + b;
+        long long n;
+        if (K < L.nz) {
+          int k = 2 * K;
+          s += fine_coef(P, O, cidx(P, i, j, k), 2, -1, i, j, k, &n);
+        } else {
+          int k = 2 * K - 1;
+          s += fine_coef(P, O, cidx(P, i, j, k), 2, +1, i, j, k, &n);
+        }
+      }
+    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+  }
+}
+
+// coefficients of level l+1 from the stored coefficients of level l (F)
+__global__ void k_coarsen_level(LevelDev F, LevelDev L, double* cx, double* cy, double* cz) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int J = blockIdx.y * blockDim.y + threadIdx.y;
+  int K = blockIdx.z;
+  int nzs = L.dim == 3 ? 2 : 1;
+  if (I <= L.nx && J < L.ny && K < L.nz) {
+    double s = 0.0;
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < nzs; ++e) {
+        int j = 2 * J + b, k = L.dim == 3 ? 2 * K + e : 0;
+        s += F.cx[(long long)(2 * I) + (long long)(F.nx + 1) * ((long long)j + (long long)F.ny * k)];
+      }
+    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+  }
+  if (I < L.nx && J <= L.ny && K < L.nz) {
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int e = 0; e < nzs; ++e) {
+        int i = 2 * I + a, k = L.dim == 3 ? 2 * K + e : 0;
+        s += F.cy[(long long)i + (long long)F.nx * ((long long)(2 * J) + (long long)(F.ny + 1) * k)];
+      }
+    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = 0.5 * s;
+  }
+  if (L.dim == 3 && I < L.nx && J < L.ny && K <= L.nz) {
+    double s = 0.0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        int i = 2 * I + a, j = 2 * J + b;
+        s += F.cz[(long long)i + (long long)F.nx * ((long long)j + (long long)F.ny * (2 * K))];
+      }
+    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+  }
+}
+
+__global__ void k_level_diag(LevelDev L, double* diag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= L.nx || j >= L.ny) return;
+  double s = L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
+             L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
+             L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] +
+             L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)];
+  if (L.dim == 3)
+    s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] +
+         L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))];
+  diag[lidx(L, i, j, k)] = s;
+}
+
+// off-diagonal sum sum_nb c z_nb at (i,j,k) of a stored level
+__device__ __forceinline__ double level_nbsum(const LevelDev& L, const double* z, int i, int j, int k) {
+  long long c = lidx(L, i, j, k);
+  double s = 0.0;
+  if (i > 0) s += L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * z[c - 1];
+  if (i < L.nx - 1)
+    s += L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * z[c + 1];
+  if (j > 0) s += L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] * z[c - L.nx];
+  if (j < L.ny - 1)
+    s += L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)] * z[c + L.nx];
+  if (L.dim == 3) {
+    long long sz = (long long)L.nx * L.ny;
+    if (k > 0) s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] * z[c - sz];
+    if (k < L.nz - 1) s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))] * z[c + sz];
+  }
+  return s;
+}
+
+__global__ void k_level_smooth(LevelDev L, int color, int init) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= L.nx || j >= L.ny) return;
+  long long c = lidx(L, i, j, k);
+  bool mine = ((i + j + k) & 1) == color;
+  if (init && !mine) {
+    L.z[c] = 0.0;
+    return;
+  }
+  if (!mine) return;
+  double nb = init ? 0.0 : level_nbsum(L, L.z, i, j, k);
+  L.z[c] = (L.r[c] + nb) / L.diag[c];
+}
+
+// restriction of the fine residual r - A z onto level 1 (sum over children)
+__global__ void k_restrict_fine(Params P, FineOp O, const double* r, const double* z, LevelDev C) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int J = blockIdx.y * blockDim.y + threadIdx.y;
+  int K = blockIdx.z;
+  if (I >= C.nx || J >= C.ny) return;
+  int nzs = C.dim == 3 ? 2 : 1;
+  double s = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < nzs; ++e) {
+        int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
+        long long c = cidx(P, i, j, k);
+        double zc = z[c], acc = 0.0;
+        for (int d = 0; d < P.dim; ++d)
+          for (int sg = -1; sg <= 1; sg += 2) {
+            long long n;
+            double cf = fine_coef(P, O, c, d, sg, i, j, k, &n);
+            acc += n < 0 ? cf * zc : cf * (zc - z[n]);
+          }
+        s += r[c] - acc;
+      }
+  C.r[lidx(C, I, J, K)] = s;
+}
+
+__global__ void k_restrict_level(LevelDev F, LevelDev C) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int J = blockIdx.y * blockDim.y + threadIdx.y;
+  int K = blockIdx.z;
+  if (I >= C.nx || J >= C.ny) return;
+  int nzs = C.dim == 3 ? 2 : 1;
+  double s = 0.0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < nzs; ++e) {
+        int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
+        long long c = lidx(F, i, j, k);
+        double Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
+        s += F.r[c] - Az;
+      }
+  C.r[lidx(C, I, J, K)] = s;
+}
+
+// z_fine += z_coarse(parent)
+__global__ void k_prolong(int fnx, int fny, int fnz, int dim, double* zf, LevelDev C) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= fnx || j >= fny) return;
+  long long c = (long long)i + (long long)fnx * ((long long)j + (long long)fny * k);
+  zf[c] += C.z[lidx(C, i / 2, j / 2, dim == 3 ? k / 2 : 0)];
+}
+
+// coarsest level: symmetric red-black Gauss-Seidel (m forward then m backward
+// colour pairs) from zero, by a single workgroup
+__global__ void k_coarse_solve(LevelDev L, int m) {
+  long long N = L.N;
+  for (long long c = threadIdx.x; c < N; c += blockDim.x) L.z[c] = 0.0;
+  __syncthreads();
+  for (int it = 0; it < 2 * m; ++it) {
+    for (int h = 0; h < 2; ++h) {
+      int color = it < m ? h : 1 - h;
+      for (long long c = threadIdx.x; c < N; c += blockDim.x) {
+        int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long long)L.nx * L.ny));
+        if (((i + j + k) & 1) != color) continue;
+        L.z[c] = (L.r[c] + level_nbsum(L, L.z, i, j, k)) / L.diag[c];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------- vector ops
+__global__ void k_copy_vec(long long n, const double* a, double* b) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) b[c] = a[c];
+}
+
+__global__ void k_dot(long long n, const double* a, const double* b, double* part, long long pstride) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  double v[1] = {c < n ? a[c] * b[c] : 0.0};
+  block_sums_store<1>(v, part, pstride, blockIdx.x);
+}
+
+__global__ void k_axpy2(long long n, const double* scal, double* x, const double* d, double* r, const double* q,
+                        double* part, long long pstride) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  double a = scal[S_ALPHA];
+  double v[1] = {0.0};
+  if (c < n) {
+    x[c] += a * d[c];
+    double rc = r[c] - a * q[c];
+    r[c] = rc;
+    v[0] = rc * rc;
+  }
+  block_sums_store<1>(v, part, pstride, blockIdx.x);
+}
+
+__global__ void k_xpby(long long n, const double* scal, const double* z, double* d) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) d[c] = z[c] + scal[S_BETA] * d[c];
+}
+
+// finalize: sums of `nval` partial rows -> scal[out+v]; then PCG scalar update
+// op: 0 none, 1 alpha = rho / dq, 2 beta = rz / rho, rho = rz
+__global__ void k_finalize(const double* part, long long pstride, int nblk, int nval, double* scal, int out, int op,
+                           double divisor) {
+  __shared__ double lds[NTHREADS];
+  for (int v = 0; v < nval; ++v) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += NTHREADS) s += part[(long long)v * pstride + b];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = NTHREADS / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) scal[out + v] = divisor == 1.0 ? lds[0] : lds[0] / divisor;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (op == 1) {
+      double dq = scal[out];
+      scal[S_ALPHA] = dq != 0.0 ? scal[S_RHO] / dq : 0.0;
+    } else if (op == 2) {
+      double rz = scal[out];
+      scal[S_BETA] = scal[S_RHO] != 0.0 ? rz / scal[S_RHO] : 0.0;
+      scal[S_RHO] = rz;
+    } else if (op == 3) {
+      scal[S_RHO] = scal[out];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host side
+static LevelDev levdev(hfdib_ctx* c, int l) {
+  Level& L = c->lev[l];
+  LevelDev d;
+  d.nx = L.nx;
+  d.ny = L.ny;
+  d.nz = L.nz;
+  d.dim = c->P.dim;
+  d.N = L.N;
+  d.r = L.r;
+  d.z = L.z;
+  d.cx = L.cx;
+  d.cy = L.cy;
+  d.cz = L.cz;
+  d.diag = L.diag;
+  return d;
+}
+static dim3 lgrid(int nx, int ny, int nz) { return dim3((nx + 63) / 64, (ny + 3) / 4, nz); }
+
+// finalize helper; partial slots live in ctx->partials with row stride c->pstride
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NTHREADS), 0, c->stream, c->partials, c->pstride, nblk, nval,
+                     c->scal + SCAL_PCG, out, op, divisor);
+}
+
+static void vcycle(hfdib_ctx* c, const FineOp& O, const double* r, double* z) {
+  const Params& P = c->P;
+  dim3 g = grid3(P), b = block3();
+  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 0, 1);
+  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 1, 0);
+  if (c->nlev > 1) {
+    LevelDev L1 = levdev(c, 1);
+    hipLaunchKernelGGL(k_restrict_fine, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, z, L1);
+    for (int l = 1; l < c->nlev; ++l) {
+      LevelDev L = levdev(c, l);
+      dim3 gl = lgrid(L.nx, L.ny, L.nz);
+      if (l == c->nlev - 1) {
+        hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(NTHREADS), 0, c->stream, L, 16);
+        break;
+      }
+      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 0, 1);
+      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 1, 0);
+      LevelDev C = levdev(c, l + 1);
+      hipLaunchKernelGGL(k_restrict_level, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
+    }
+    for (int l = c->nlev - 2; l >= 1; --l) {
+      LevelDev L = levdev(c, l);
+      LevelDev C = levdev(c, l + 1);
+      dim3 gl = lgrid(L.nx, L.ny, L.nz);
+      hipLaunchKernelGGL(k_prolong, gl, b, 0, c->stream, L.nx, L.ny, L.nz, L.dim, L.z, C);
+      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 1, 0);
+      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 0, 0);
+    }
+    hipLaunchKernelGGL(k_prolong, g, b, 0, c->stream, P.nx, P.ny, P.nz, P.dim, z, L1);
+  }
+  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 1, 0);
+  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 0, 0);
+}
+
+static void build_levels(hfdib_ctx* c, const FineOp& O) {
+  const Params& P = c->P;
+  dim3 b = block3();
+  for (int l = 1; l < c->nlev; ++l) {
+    Level& L = c->lev[l];
+    LevelDev Ld = levdev(c, l);
+    dim3 gf((L.nx + 1 + 63) / 64, (L.ny + 1 + 3) / 4, P.dim == 3 ? L.nz + 1 : 1);
+    if (l == 1)
+      hipLaunchKernelGGL(k_coarsen_from_fine, gf, b, 0, c->stream, P, O, Ld, L.cx, L.cy, L.cz);
+    else
+      hipLaunchKernelGGL(k_coarsen_level, gf, b, 0, c->stream, levdev(c, l - 1), Ld, L.cx, L.cy, L.cz);
+    hipLaunchKernelGGL(k_level_diag, lgrid(L.nx, L.ny, L.nz), b, 0, c->stream, Ld, L.diag);
+  }
+}
+
+int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol, int maxit, int* iters,
+                   double* relres, const double* xmean_dev) {
+  const Params& P = c->P;
+  FineOp O{rAU, c->flags};
+  dim3 g = grid3(P), b = block3();
+  long long nblk3 = (long long)g.x * g.y * g.z;
+  int nb1 = nblocks1(P.N);
+  double* r = c->pr;
+  double* z = c->pz;
+  double* d = c->pd;
+  double* q = c->pq;
+  double* S = c->scal + SCAL_PCG;
+  timer_begin(c, T_PSOLVE);
+  build_levels(c, O);
+  hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, O, rhs, x, r, xmean_dev, c->partials, c->pstride);
+  launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [16]=rr0 [17]=bb [18..20]=residual sums
+  HFDIB_CHECK_LAUNCH(c, "pcg init");
+  double hs[8];
+  HFDIB_CHECK(c, hipMemcpyAsync(hs, S + S_BB + 16, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+  HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+  double rr = hs[0], bb = hs[1];
+  c->last_pres[0] = hs[2];
+  c->last_pres[1] = hs[3];
+  c->last_pres[2] = hs[4];
+  double bnorm = sqrt(bb);
+  double target = rtol * (bnorm > 0.0 ? bnorm : 1.0);
+  int it = 0;
+  if (!(sqrt(rr) <= target)) {
+    vcycle(c, O, r, z);
+    hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
+    launch_finalize(c, nb1, 1, S_RZ, 3);
+    hipLaunchKernelGGL(k_copy_vec, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, z, d);
+    for (it = 1; it <= maxit; ++it) {
+      timer_begin(c, T_PAPPLY);
+      hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
+      timer_end(c, T_PAPPLY);
+      launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
+      hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, q, c->partials,
+                         c->pstride);
+      launch_finalize(c, nb1, 1, S_RR, 0);
+      HFDIB_CHECK_LAUNCH(c, "pcg iteration");
+      HFDIB_CHECK(c, hipMemcpyAsync(hs, S + S_RR, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+      HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+      rr = hs[0];
+      if (!std::isfinite(rr)) {
+        c->err = "non-finite residual in the pressure solve";
+        timer_end(c, T_PSOLVE);
+        return HFDIB_EDIVERGED;
+      }
+      if (sqrt(rr) <= target) break;
+      vcycle(c, O, r, z);
+      hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
+      launch_finalize(c, nb1, 1, S_RZ, 2);
+      hipLaunchKernelGGL(k_xpby, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, z, d);
+    }
+    if (it > maxit) it = maxit;
+  }
+  timer_end(c, T_PSOLVE);
+  HFDIB_CHECK_LAUNCH(c, "pcg");
+  if (iters) *iters = it;
+  if (relres) *relres = sqrt(rr) / (bnorm > 0.0 ? bnorm : 1.0);
+  return HFDIB_OK;
+}
+
+int mg_setup_levels(hfdib_ctx* c) {
+  (void)c;
+  return HFDIB_OK;
+}
+
+}  // namespace hfdib

@@ -1,0 +1,646 @@
+// Momentum predictor, IB forcing/correction, pressure-corrector right-hand side
+// and velocity/flux update of the extended SIMPLE loop (figure of the SIMPLE
+// algorithm; eqs. of the governing equations, of f_ib and of the correction).
+#include "device_common.h"
+
+namespace hfdib {
+
+struct Mom {
+  const double* u[3];
+  const double* p;
+  const double* phi[3];
+  const double* nut;
+  const double* k;
+  const uint8_t* flags;
+  const double* uib[3];
+  const double* grad[9];  // grad[i*3+j] = d u_j / d x_i
+};
+
+__device__ __forceinline__ double nut_wall(const Params& P, double yp) {
+  if (!(yp > P.ylam)) return 0.0;
+  double v = P.kappa * yp / log(P.E * yp) - 1.0;
+  return P.nu * (v > 0.0 ? v : 0.0);
+}
+
+// interior neighbour coefficient a_nb = D_f + max(-F_f, 0) (upwind, bounded form)
+__device__ __forceinline__ double anb_coef(const Params& P, double gP, double gN, int d, double F) {
+  double mf = -F;
+  return 0.5 * (gP + gN) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
+}
+
+// Gauss face value of velocity component cc on a domain face
+__device__ __forceinline__ double u_bface(const Params& P, int cc, int d, int s, bool solid, double uP) {
+  if (solid) return uP;
+  int kind = face_kind(P, d, s);
+  if (kind == HFDIB_BC_INLET) return P.u_in[cc];
+  if (kind == HFDIB_BC_NOSLIP) return 0.0;
+  if (kind == HFDIB_BC_SLIP) return cc == d ? 0.0 : uP;
+  return uP;
+}
+__device__ __forceinline__ double p_bface(const Params& P, int d, int s, bool solid, double pP) {
+  if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !solid) return 0.0;
+  return pP;
+}
+
+// V (grad p)_c at cell (i,j,k), Gauss with linear interpolation
+__device__ __forceinline__ double gradp_V(const Params& P, const double* p, uint8_t fl, int cc, int i, int j,
+                                          int k, long long c) {
+  long long st = stride(P, cc);
+  double pP = p[c];
+  bool solid = fl & F_SOLID;
+  double fp = on_bnd(P, cc, +1, i, j, k) ? p_bface(P, cc, +1, solid, pP) : 0.5 * (pP + p[c + st]);
+  double fm = on_bnd(P, cc, -1, i, j, k) ? p_bface(P, cc, -1, solid, pP) : 0.5 * (p[c - st] + pP);
+  return P.V * ((fp - fm) / P.delta[cc]);
+}
+
+// ---------------------------------------------------------------- state init
+__global__ void k_init_cells(Params P, const double* lam, const double* us0, const double* us1, const double* us2,
+                             double* u0, double* u1, double* u2, double* p, double* k, double* w, double* nut) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c >= P.N) return;
+  bool fl = lam[c] < 0.5;
+  u0[c] = fl ? P.u_in[0] : us0[c];
+  u1[c] = fl ? P.u_in[1] : us1[c];
+  u2[c] = P.dim == 2 ? 0.0 : (fl ? P.u_in[2] : us2[c]);
+  p[c] = 0.0;
+  if (P.model == HFDIB_KEPS) {
+    k[c] = P.k_in;
+    w[c] = P.w_in;
+    nut[c] = P.Cmu * P.k_in * P.k_in / P.w_in;
+  } else if (P.model == HFDIB_KOMEGA_SST) {
+    k[c] = P.k_in;
+    w[c] = P.w_in;
+    nut[c] = P.k_in / P.w_in;
+  } else {
+    k[c] = 0.0;
+    w[c] = 0.0;
+    nut[c] = 0.0;
+  }
+}
+
+// face fluxes of a cell vector field: linear interpolation inside; inlet u_in.S,
+// outlet owner value, walls / slip / solid-owner faces 0.  Each thread writes the
+// high face of its cell and, on the low domain boundary, the low face.
+__global__ void k_interp_flux(Params P, const double* v0, const double* v1, const double* v2, const uint8_t* flags,
+                              double* phx, double* phy, double* phz) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  const double* v[3] = {v0, v1, v2};
+  double* ph[3] = {phx, phy, phz};
+  bool solid = flags[c] & F_SOLID;
+  for (int d = 0; d < P.dim; ++d) {
+    double A = P.area[d];
+    long long f = fidx(P, d, i, j, k);
+    long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+    for (int s = -1; s <= 1; s += 2) {
+      if (!on_bnd(P, d, s, i, j, k)) {
+        if (s > 0) ph[d][f + fo] = 0.5 * (v[d][c] + v[d][c + stride(P, d)]) * A;
+        continue;
+      }
+      int kind = face_kind(P, d, s);
+      double val;
+      if (kind == HFDIB_BC_INLET) val = P.u_in[d] * A;
+      else if (kind == HFDIB_BC_OUTLET) val = v[d][c] * A;
+      else val = 0.0;
+      if (solid) val = 0.0;
+      ph[d][s > 0 ? f + fo : f] = val;
+    }
+  }
+}
+
+// sums of u, v, w, p, k over all cells (means for the residual normalisation)
+__global__ void k_sums5(Params P, const double* a0, const double* a1, const double* a2, const double* a3,
+                        const double* a4, double* part, long long pstride) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  double v[5] = {0, 0, 0, 0, 0};
+  if (c < P.N) {
+    v[0] = a0[c];
+    v[1] = a1[c];
+    v[2] = a2[c];
+    v[3] = a3[c];
+    v[4] = a4[c];
+  }
+  block_sums_store<5>(v, part, pstride, blockIdx.x);
+}
+
+// ---------------------------------------------------------------- IB-pre
+// boundary cells: u_tau = Cmu^(1/4) sqrt(k_P), y+ = y_eff u_tau / nu (eq. for
+// y+ and u_tau), alpha_u = alpha_k = [y+ <= y+_lam] (eq. for alpha_u), and the
+// imposed velocity from the quadratic along n_P through (0,u_s), P1, P2.
+__global__ void k_ib_pre(Params P, int nbc, const int* bc_cells, const double* bc_yeff, const double* bc_L,
+                         const int* st1, const double* w1, const int* st2, const double* w2, const double* kold,
+                         const double* u0, const double* u1, const double* u2, const double* us0, const double* us1,
+                         const double* us2, uint8_t* flags, double* ub0, double* ub1, double* ub2, double* bc_utau,
+                         double* bc_yplus) {
+  int b = blockIdx.x * NTHREADS + threadIdx.x;
+  if (b >= nbc) return;
+  int c = bc_cells[b];
+  double ut = 0.0, yp = 0.0;
+  if (P.model != HFDIB_LAMINAR) {
+    double kk = kold[c];
+    ut = P.Cmu25 * sqrt(kk > 0.0 ? kk : 0.0);
+    yp = bc_yeff[b] * ut / P.nu;
+  }
+  bc_utau[b] = ut;
+  bc_yplus[b] = yp;
+  bool a = yp <= P.ylam;
+  uint8_t f = flags[c];
+  flags[c] = a ? (uint8_t)(f | F_ALPHA_U) : (uint8_t)(f & ~F_ALPHA_U);
+  if (!a) return;
+  const double* uu[3] = {u0, u1, u2};
+  const double* us[3] = {us0, us1, us2};
+  double* ub[3] = {ub0, ub1, ub2};
+  double L0 = bc_L[3 * b], L1 = bc_L[3 * b + 1], L2 = bc_L[3 * b + 2];
+  for (int cc = 0; cc < P.dim; ++cc) {
+    double v1 = 0.0, v2 = 0.0;
+    for (int q = 0; q < 8; ++q) v1 += w1[8 * b + q] * uu[cc][st1[8 * b + q]];
+    for (int q = 0; q < 8; ++q) v2 += w2[8 * b + q] * uu[cc][st2[8 * b + q]];
+    ub[cc][c] = L0 * us[cc][c] + L1 * v1 + L2 * v2;
+  }
+}
+
+__global__ void k_wall_pre(Params P, int nw, const int* wall_cells, const double* wall_y, const double* kold,
+                           double* wall_utau, double* wall_yplus) {
+  int b = blockIdx.x * NTHREADS + threadIdx.x;
+  if (b >= nw) return;
+  double ut = 0.0, yp = 0.0;
+  if (P.model != HFDIB_LAMINAR) {
+    double kk = kold[wall_cells[b]];
+    ut = P.Cmu25 * sqrt(kk > 0.0 ? kk : 0.0);
+    yp = wall_y[b] * ut / P.nu;
+  }
+  wall_utau[b] = ut;
+  wall_yplus[b] = yp;
+}
+
+// ---------------------------------------------------------------- momentum
+// Assembly of the relaxed momentum rows with the explicit IB source
+// (discrete f_ib = alpha [M(u~) + grad p]), plus the normalised-residual sums
+// of the rows that are solved (alpha_u = 0).
+__global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
+                               const double* means, double* part, long long pstride) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  bool act = i < P.nx && j < P.ny;
+  double red[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (act) {
+    long long c = cidx(P, i, j, k);
+    uint8_t fl = M.flags[c];
+    bool solid = fl & F_SOLID;
+    double nuP = P.nu + M.nut[c];
+    double anb[6];
+    long long nbi[6];
+    double aP = 0.0;
+    // interior neighbour coefficients, faces in the order W, E, S, N, B, T
+    for (int d = 0; d < P.dim; ++d)
+      for (int s = -1; s <= 1; s += 2) {
+        int q = 2 * d + (s > 0);
+        if (on_bnd(P, d, s, i, j, k)) {
+          anb[q] = 0.0;
+          nbi[q] = c;
+          continue;
+        }
+        long long n = c + s * stride(P, d);
+        double F = outward_flux(P, M.phi, d, s, i, j, k);
+        anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, F);
+        nbi[q] = n;
+        aP += anb[q];
+      }
+    // Dirichlet domain faces (inlet, no-slip) of cells with lambda = 0
+    double bsrc[3] = {0.0, 0.0, 0.0};
+    for (int d = 0; d < P.dim; ++d)
+      for (int s = -1; s <= 1; s += 2) {
+        if (!on_bnd(P, d, s, i, j, k) || solid) continue;
+        int kind = face_kind(P, d, s);
+        if (kind != HFDIB_BC_INLET && kind != HFDIB_BC_NOSLIP) continue;
+        double Gb = nuP;
+        if (kind == HFDIB_BC_NOSLIP) {
+          if (P.model == HFDIB_LAMINAR) {
+            Gb = P.nu;
+          } else {
+            double kk = M.k[c];
+            double ut = P.Cmu25 * sqrt(kk > 0.0 ? kk : 0.0);
+            double ypf = 0.5 * P.delta[d] * ut / P.nu;
+            Gb = P.nu + nut_wall(P, ypf);
+          }
+        }
+        double F = outward_flux(P, M.phi, d, s, i, j, k);
+        double mf = -F;
+        double a = Gb * P.area[d] / (0.5 * P.delta[d]) + (mf > 0.0 ? mf : 0.0);
+        aP += a;
+        for (int cc = 0; cc < P.dim; ++cc) {
+          double ubv = kind == HFDIB_BC_INLET ? P.u_in[cc] : 0.0;
+          bsrc[cc] += a * ubv;
+        }
+      }
+    double urf = P.urf_u;
+    double aPr = aP / urf;
+    aPr_out[c] = aPr;
+    bool alpha = fl & F_ALPHA_U;
+    double* rhs[3] = {rhs0, rhs1, rhs2};
+    for (int cc = 0; cc < P.dim; ++cc) {
+      // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f
+      double T = 0.0;
+      for (int d = 0; d < P.dim; ++d)
+        for (int s = -1; s <= 1; s += 2) {
+          const double* G = M.grad[cc * 3 + d];
+          double nuf, gf;
+          if (on_bnd(P, d, s, i, j, k)) {
+            nuf = nuP;
+            gf = G[c];
+          } else {
+            long long n = c + s * stride(P, d);
+            nuf = 0.5 * (nuP + (P.nu + M.nut[n]));
+            gf = 0.5 * (G[c] + G[n]);
+          }
+          T += (double)s * P.area[d] * nuf * gf;
+        }
+      double b0 = T + bsrc[cc];
+      double g = gradp_V(P, M.p, fl, cc, i, j, k, c);
+      const double* u = M.u[cc];
+      double uo = u[c];
+      double r = (1.0 - urf) / urf * aP * uo;
+      double rh;
+      if (alpha) {
+        const double* ub = M.uib[cc];
+        double nbt = 0.0;
+        for (int q = 0; q < 2 * P.dim; ++q) {
+          if (nbi[q] == c) continue;
+          long long n = nbi[q];
+          double ut = (M.flags[n] & F_ALPHA_U) ? ub[n] : u[n];
+          nbt += anb[q] * ut;
+        }
+        double ut = ub[c];
+        rh = (aP * ut - nbt) + r;
+      } else {
+        rh = (b0 - g) + r;
+      }
+      rhs[cc][c] = rh;
+      if (!alpha) {
+        double nb = 0.0, one = 0.0;
+        for (int q = 0; q < 2 * P.dim; ++q) {
+          if (nbi[q] == c) continue;
+          nb += anb[q] * u[nbi[q]];
+          one += anb[q];
+        }
+        double Ax = aPr * uo - nb;
+        double Axb = (aPr - one) * means[cc];
+        red[3 * cc + 0] = fabs(rh - Ax);
+        red[3 * cc + 1] = fabs(Ax - Axb);
+        red[3 * cc + 2] = fabs(rh - Axb);
+      }
+    }
+  }
+  block_sums_store<9>(red, part, pstride, block_linear());
+}
+
+// one colour of a red-black Gauss-Seidel sweep over the three components
+__global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
+                            const double* aPr, double* u0, double* u1, double* u2, int color) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  if (((i + j + k) & 1) != color) return;
+  long long c = cidx(P, i, j, k);
+  double nuP = P.nu + M.nut[c];
+  double anb[6];
+  long long nbi[6];
+  for (int d = 0; d < P.dim; ++d)
+    for (int s = -1; s <= 1; s += 2) {
+      int q = 2 * d + (s > 0);
+      if (on_bnd(P, d, s, i, j, k)) {
+        anb[q] = 0.0;
+        nbi[q] = c;
+        continue;
+      }
+      long long n = c + s * stride(P, d);
+      anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, outward_flux(P, M.phi, d, s, i, j, k));
+      nbi[q] = n;
+    }
+  double a = aPr[c];
+  double* uu[3] = {u0, u1, u2};
+  const double* rr[3] = {rhs0, rhs1, rhs2};
+  for (int cc = 0; cc < P.dim; ++cc) {
+    double nb = 0.0;
+    for (int q = 0; q < 2 * P.dim; ++q) {
+      if (nbi[q] == c) continue;
+      nb += anb[q] * uu[cc][nbi[q]];
+    }
+    uu[cc][c] = (rr[cc][c] + nb) / a;
+  }
+}
+
+// u <- u + alpha_u (u_ib - u) on forced cells (list kernels: boundary cells with
+// alpha_u, and every in-solid cell)
+__global__ void k_correct_list(Params P, int n, const int* cells, const uint8_t* flags, const double* ub0,
+                               const double* ub1, const double* ub2, double* u0, double* u1, double* u2) {
+  int b = blockIdx.x * NTHREADS + threadIdx.x;
+  if (b >= n) return;
+  int c = cells[b];
+  if (!(flags[c] & F_ALPHA_U)) return;
+  u0[c] = u0[c] + 1.0 * (ub0[c] - u0[c]);
+  u1[c] = u1[c] + 1.0 * (ub1[c] - u1[c]);
+  if (P.dim == 3) u2[c] = u2[c] + 1.0 * (ub2[c] - u2[c]);
+}
+
+// HbyA = (sum a_nb u_nb + rhs + V grad p_old) / a'_P and rAU = V / a'_P
+__global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
+                       const double* aPr, double* h0, double* h1, double* h2, double* rAU) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  double nuP = P.nu + M.nut[c];
+  uint8_t fl = M.flags[c];
+  double anb[6];
+  long long nbi[6];
+  for (int d = 0; d < P.dim; ++d)
+    for (int s = -1; s <= 1; s += 2) {
+      int q = 2 * d + (s > 0);
+      if (on_bnd(P, d, s, i, j, k)) {
+        anb[q] = 0.0;
+        nbi[q] = c;
+        continue;
+      }
+      long long n = c + s * stride(P, d);
+      anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, outward_flux(P, M.phi, d, s, i, j, k));
+      nbi[q] = n;
+    }
+  double a = aPr[c];
+  const double* rr[3] = {rhs0, rhs1, rhs2};
+  double* hh[3] = {h0, h1, h2};
+  for (int cc = 0; cc < P.dim; ++cc) {
+    double nb = 0.0;
+    for (int q = 0; q < 2 * P.dim; ++q) {
+      if (nbi[q] == c) continue;
+      nb += anb[q] * M.u[cc][nbi[q]];
+    }
+    double H = nb + rr[cc][c] + gradp_V(P, M.p, fl, cc, i, j, k, c);
+    hh[cc][c] = H / a;
+  }
+  if (P.dim == 2) h2[c] = 0.0;
+  rAU[c] = P.V / a;
+}
+
+// face flux predictor phi* from HbyA (overwrites phi) and the pressure
+// right-hand side -(1 - lambda_P) sum_f phi*_out (lambda-masked continuity)
+__global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const double* h2, const double* lam,
+                           const uint8_t* flags, double* phx, double* phy, double* phz, double* rhs_p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  const double* hv[3] = {h0, h1, h2};
+  double* ph[3] = {phx, phy, phz};
+  bool solid = flags[c] & F_SOLID;
+  double div = 0.0;
+  for (int d = 0; d < P.dim; ++d) {
+    double A = P.area[d];
+    long long f = fidx(P, d, i, j, k);
+    long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+    for (int s = -1; s <= 1; s += 2) {
+      double val;
+      if (!on_bnd(P, d, s, i, j, k)) {
+        long long n = c + s * stride(P, d);
+        val = s > 0 ? 0.5 * (hv[d][c] + hv[d][n]) * A : 0.5 * (hv[d][n] + hv[d][c]) * A;
+        if (s > 0) ph[d][f + fo] = val;
+      } else {
+        int kind = face_kind(P, d, s);
+        if (kind == HFDIB_BC_INLET) val = P.u_in[d] * A;
+        else if (kind == HFDIB_BC_OUTLET) val = hv[d][c] * A;
+        else val = 0.0;
+        if (solid) val = 0.0;
+        ph[d][s > 0 ? f + fo : f] = val;
+      }
+      div += s > 0 ? val : -val;
+    }
+  }
+  rhs_p[c] = -(1.0 - lam[c]) * div;
+}
+
+// flux correction with the solved pressure and relaxation of p (into pnew)
+__global__ void k_flux_correct(Params P, const double* rAU, const double* psol, const double* pold,
+                               const uint8_t* flags, double* phx, double* phy, double* phz, double* pnew) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  double* ph[3] = {phx, phy, phz};
+  bool solid = flags[c] & F_SOLID;
+  for (int d = 0; d < P.dim; ++d) {
+    long long f = fidx(P, d, i, j, k);
+    long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+    if (!on_bnd(P, d, +1, i, j, k)) {
+      long long n = c + stride(P, d);
+      double cf = 0.5 * (rAU[c] + rAU[n]) * P.area[d] / P.delta[d];
+      ph[d][f + fo] = ph[d][f + fo] - cf * (psol[n] - psol[c]);
+    }
+    for (int s = -1; s <= 1; s += 2) {
+      if (!on_bnd(P, d, s, i, j, k) || face_kind(P, d, s) != HFDIB_BC_OUTLET) continue;
+      double cb = solid ? 0.0 : rAU[c] * P.area[d] / (0.5 * P.delta[d]);
+      long long ff = s > 0 ? f + fo : f;
+      ph[d][ff] = ph[d][ff] + (double)s * cb * psol[c];
+    }
+  }
+  pnew[c] = pold[c] + P.urf_p * (psol[c] - pold[c]);
+}
+
+// u = HbyA - rAU grad p (relaxed p), optional re-imposition of u_ib, copy p
+__global__ void k_vel_update(Params P, const double* h0, const double* h1, const double* h2, const double* aPr,
+                             const double* pnew, const uint8_t* flags, const double* ub0, const double* ub1,
+                             const double* ub2, double* u0, double* u1, double* u2, double* p) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int j = blockIdx.y * blockDim.y + threadIdx.y;
+  int k = blockIdx.z;
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  uint8_t fl = flags[c];
+  const double* hv[3] = {h0, h1, h2};
+  const double* ub[3] = {ub0, ub1, ub2};
+  double* uu[3] = {u0, u1, u2};
+  double a = aPr[c];
+  bool alpha = (fl & F_ALPHA_U) && P.recorrect;
+  for (int cc = 0; cc < P.dim; ++cc) {
+    double v = hv[cc][c] - gradp_V(P, pnew, fl, cc, i, j, k, c) / a;
+    if (alpha) v = v + 1.0 * (ub[cc][c] - v);
+    uu[cc][c] = v;
+  }
+}
+
+__global__ void k_copy(long long n, const double* src, double* dst) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) dst[c] = src[c];
+}
+
+}  // namespace hfdib
+
+// ====================================================================== host
+namespace hfdib {
+
+static Mom make_mom(hfdib_ctx* c) {
+  Mom M;
+  for (int q = 0; q < 3; ++q) {
+    M.u[q] = c->u[q];
+    M.phi[q] = c->phi[q];
+    M.uib[q] = c->uib[q];
+  }
+  M.p = c->p;
+  M.nut = c->nut;
+  M.k = c->k;
+  M.flags = c->flags;
+  for (int q = 0; q < 9; ++q) M.grad[q] = c->grad[q];
+  return M;
+}
+
+__global__ void k_init_ib(Params P, int nic, const int* ic_cells, const double* us0, const double* us1,
+                          const double* us2, double* ub0, double* ub1, double* ub2, double* kib) {
+  int b = blockIdx.x * NTHREADS + threadIdx.x;
+  if (b >= nic) return;
+  int c = ic_cells[b];
+  ub0[c] = us0[c];
+  ub1[c] = us1[c];
+  ub2[c] = us2[c];
+  kib[c] = 0.0;
+}
+
+__global__ void k_fill(long long n, double* a, double v) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) a[c] = v;
+}
+
+// initial conditions (u_in in cells with lambda < 0.5, the solid velocity in
+// in-solid cells, p = 0, inlet turbulence) and the derived fluxes / gradients
+int init_state(hfdib_ctx* c) {
+  const Params& P = c->P;
+  int nb = nblocks1(P.N);
+  hipLaunchKernelGGL(k_init_cells, dim3(nb), dim3(NTHREADS), 0, c->stream, P, c->lam, c->us[0], c->us[1], c->us[2],
+                     c->u[0], c->u[1], c->u[2], c->p, c->k, c->w, c->nut);
+  hipLaunchKernelGGL(k_interp_flux, grid3(P), block3(), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags,
+                     c->phi[0], c->phi[1], c->phi[2]);
+  for (int q = 0; q < 9; ++q) hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->grad[q], 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->kib, 0.0);
+  hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->wib, 0.0);
+  for (int q = 0; q < 3; ++q)
+    hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->uib[q], 0.0);
+  if (c->n_ic > 0)
+    hipLaunchKernelGGL(k_init_ib, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_ic, c->ic_cells,
+                       c->us[0], c->us[1], c->us[2], c->uib[0], c->uib[1], c->uib[2], c->kib);
+  HFDIB_CHECK_LAUNCH(c, "init state");
+  c->grad_stale = 1;
+  return HFDIB_OK;
+}
+
+__global__ void k_residuals(const double* S, int dim, int turb, double* out) {
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 3; ++q) {
+    const double* r = S + SC_RESSUM + 3 * q;
+    out[q] = q < dim ? r[0] / (r[1] + r[2] + 1e-300) : 0.0;
+  }
+  const double* rp = S + 22;  // pressure residual sums written by the PCG set-up
+  out[3] = rp[0] / (rp[1] + rp[2] + 1e-300);
+  if (turb) {
+    const double* rk = S + SC_RESSUM + 12;
+    const double* rw = S + SC_RESSUM + 9;
+    out[4] = rk[0] / (rk[1] + rk[2] + 1e-300);
+    out[5] = rw[0] / (rw[1] + rw[2] + 1e-300);
+  } else {
+    out[4] = 0.0;
+    out[5] = 0.0;
+  }
+}
+
+int simple_step(hfdib_ctx* c, int it, double* res_host) {
+  (void)it;
+  const Params& P = c->P;
+  dim3 g = grid3(P), b = block3();
+  long long nblk3 = (long long)g.x * g.y * g.z;
+  int nb1 = nblocks1(P.N);
+  double* S = c->scal + SCAL_PCG;
+  int st;
+  if (c->grad_stale) {
+    if ((st = gradient_only(c)) != HFDIB_OK) return st;
+    c->grad_stale = 0;
+  }
+  timer_begin(c, T_ITER);
+  // means of the previous iterate (residual normalisation)
+  hipLaunchKernelGGL(k_sums5, dim3(nb1), dim3(NTHREADS), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->p, c->k,
+                     c->partials, c->pstride);
+  launch_finalize(c, nb1, 5, SC_MEANS, 0, (double)P.N);
+  // 1. IB-pre
+  if (c->n_bc > 0)
+    hipLaunchKernelGGL(k_ib_pre, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
+                       c->bc_yeff, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->k, c->u[0], c->u[1], c->u[2],
+                       c->us[0], c->us[1], c->us[2], c->flags, c->uib[0], c->uib[1], c->uib[2], c->bc_utau,
+                       c->bc_yplus);
+  if (c->n_wall > 0)
+    hipLaunchKernelGGL(k_wall_pre, dim3(nblocks1(c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_wall,
+                       c->wall_cells, c->wall_y, c->k, c->wall_utau, c->wall_yplus);
+  // 2. momentum predictor
+  Mom M = make_mom(c);
+  timer_begin(c, T_MOMASM);
+  hipLaunchKernelGGL(k_mom_assemble, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
+                     S + SC_MEANS, c->partials, c->pstride);
+  timer_end(c, T_MOMASM);
+  launch_finalize(c, (int)nblk3, 9, SC_RESSUM, 0);
+  for (int s = 0; s < P.n_sweeps; ++s)
+    for (int color = 0; color < 2; ++color) {
+      timer_begin(c, T_MOMSWEEP);
+      hipLaunchKernelGGL(k_mom_sweep, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
+                         c->u[1], c->u[2], color);
+      timer_end(c, T_MOMSWEEP);
+    }
+  // 3. u <- u + alpha_u (u_ib - u)
+  if (c->n_bc > 0)
+    hipLaunchKernelGGL(k_correct_list, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc,
+                       c->bc_cells, c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1], c->u[2]);
+  if (c->n_ic > 0)
+    hipLaunchKernelGGL(k_correct_list, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_ic,
+                       c->ic_cells, c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1], c->u[2]);
+  // 4. pressure corrector
+  hipLaunchKernelGGL(k_hbya, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->hbya[0],
+                     c->hbya[1], c->hbya[2], c->rAU);
+  hipLaunchKernelGGL(k_flux_rhs, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->lam, c->flags,
+                     c->phi[0], c->phi[1], c->phi[2], c->rhs_p);
+  hipLaunchKernelGGL(k_copy, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, c->p, c->px);
+  HFDIB_CHECK_LAUNCH(c, "momentum stage");
+  int iters = 0;
+  double relres = 0.0;
+  st = pressure_solve(c, c->rAU, c->rhs_p, c->px, c->cfg.p_rtol, c->cfg.p_maxit, &iters, &relres, S + SC_MEANS + 3);
+  if (st != HFDIB_OK) return st;
+  c->stats[0] += iters;
+  c->stats[2] = iters > c->stats[2] ? iters : c->stats[2];
+  c->stats[3] = relres;
+  // 5. flux and velocity update
+  hipLaunchKernelGGL(k_flux_correct, g, b, 0, c->stream, P, c->rAU, c->px, c->p, c->flags, c->phi[0], c->phi[1],
+                     c->phi[2], c->pnew);
+  hipLaunchKernelGGL(k_vel_update, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->aPr, c->pnew,
+                     c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1], c->u[2], c->p);
+  double* tmp = c->p;
+  c->p = c->pnew;
+  c->pnew = tmp;
+  HFDIB_CHECK_LAUNCH(c, "velocity update");
+  // 6. turbulence (or, laminar, the gradient the next momentum predictor uses)
+  if (P.model != HFDIB_LAMINAR) st = turbulence_stage(c);
+  else st = gradient_only(c);
+  if (st != HFDIB_OK) return st;
+  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, c->stream, S, P.dim, P.model != HFDIB_LAMINAR ? 1 : 0,
+                     S + SC_RES);
+  timer_end(c, T_ITER);
+  HFDIB_CHECK_LAUNCH(c, "residuals");
+  if (res_host) {
+    HFDIB_CHECK(c, hipMemcpyAsync(res_host, S + SC_RES, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+                "residual copy");
+    HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "residual sync");
+  }
+  return HFDIB_OK;
+}
+
+}  // namespace hfdib

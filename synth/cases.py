@@ -1,0 +1,229 @@
+"""Workload descriptions: grid, boundary kinds, fluid/model parameters and lambda.
+
+Every number here is an *input* of the solver.  The shapes follow the paper's
+test cases (backward-facing step, Ahmed body, channel flows) as synthetic
+stand-ins: none of the paper's meshes or data is used.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+from typing import Dict, Tuple
+
+import numpy as np
+
+from . import geometry as G
+
+FACES = ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax")
+BC_KINDS = ("inlet", "outlet", "noslip", "slip", "empty")
+MODELS = ("laminar", "keps", "sst")
+
+# Model constants.  The paper defers their values to the turbulence-model
+# literature; these are the standard published values and both implementations
+# receive them from here as inputs.
+DEFAULT_CONSTANTS: Dict[str, float] = {
+    # wall treatment (eqs. for k_vis, u_tau, omega_ib, P_ib, alpha masks)
+    "Cmu": 0.09, "kappa": 0.41, "E": 9.8, "beta1_wf": 0.075, "Ceps2_wf": 1.9,
+    "C_wf": 11.0, "ylam": 11.0,
+    # standard k-epsilon
+    "C1": 1.44, "C2": 1.92, "sigma_k": 1.0, "sigma_eps": 1.3,
+    # Menter SST (multiplicative diffusion coefficients)
+    "sigma_k1": 0.85, "sigma_w1": 0.5, "beta_1": 0.075, "gamma_1": 0.5532,
+    "sigma_k2": 1.0, "sigma_w2": 0.856, "beta_2": 0.0828, "gamma_2": 0.4404,
+    "a1": 0.31, "c_lim": 10.0,
+    # numerical safeguards
+    "bound_frac": 1e-10,      # k >= bound_frac*k_in, eps/omega >= bound_frac*inlet value
+    "yperp_min_frac": 1e-6,   # y_perp >= yperp_min_frac*h
+    "cd_floor": 1e-10,        # SST cross-diffusion floor
+}
+
+
+@dataclasses.dataclass
+class CaseSpec:
+    name: str
+    dim: int
+    nx: int
+    ny: int
+    nz: int
+    x0: float
+    y0: float
+    z0: float
+    dx: float
+    dy: float
+    dz: float
+    bc: Tuple[str, str, str, str, str, str]  # kinds of xmin,xmax,ymin,ymax,zmin,zmax
+    u_in: Tuple[float, float, float]
+    k_in: float
+    eps_in: float
+    omega_in: float
+    nu: float
+    model: str
+    urf_u: float = 0.7
+    urf_p: float = 0.3
+    urf_t: float = 0.85
+    n_sweeps: int = 2
+    constants: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(DEFAULT_CONSTANTS))
+    lam: np.ndarray = None
+    seed: int = 0
+
+    @property
+    def shape(self):
+        return (self.nz, self.ny, self.nx)
+
+    @property
+    def ncells(self):
+        return self.nx * self.ny * self.nz
+
+    def lambda_sha256(self):
+        return hashlib.sha256(np.ascontiguousarray(self.lam, dtype=np.float64).tobytes()).hexdigest()
+
+    def validate(self):
+        assert self.dim in (2, 3)
+        if self.dim == 2:
+            assert self.nz == 1 and self.bc[4] == "empty" and self.bc[5] == "empty"
+        for b in self.bc:
+            assert b in BC_KINDS
+        assert self.model in MODELS
+        assert self.lam is not None and self.lam.shape == self.shape
+        return self
+
+
+def inlet_turbulence(U, intensity, length_scale, Cmu=0.09):
+    """Inlet turbulence from intensity and length scale, as prescribed in the
+    paper's boundary-condition paragraph (k = 3/2 U^2 I^2, eps = Cmu k^1.5 / l,
+    omega = eps / (Cmu k))."""
+    k = 1.5 * (U * intensity) ** 2
+    eps = Cmu * k ** 1.5 / length_scale
+    omega = eps / (Cmu * k)
+    return k, eps, omega
+
+
+def _spec(**kw):
+    return CaseSpec(**kw)
+
+
+# ---------------------------------------------------------------------------
+# configurations
+# ---------------------------------------------------------------------------
+
+def case_bfs(nx=160, ny=40, h=1.0, model="keps"):
+    """2D backward-facing step as an immersed 1h x 3h block at the inlet bottom of
+    a 20h x 5h domain; Re_h = 5000 (nu = 2e-4), inlet U = 1, I = 5 %,
+    mixing length 0.07 h.  The block lies on cell faces, so lambda is 0/1."""
+    dx = 20.0 * h / nx
+    dy = 5.0 * h / ny
+    k, eps, om = inlet_turbulence(1.0, 0.05, 0.07 * h)
+    s = _spec(name=f"bfs_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+              x0=0.0, y0=0.0, z0=0.0, dx=dx, dy=dy, dz=1.0,
+              bc=("inlet", "outlet", "noslip", "slip", "empty", "empty"),
+              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
+              nu=2e-4, model=model)
+    s.lam = G.lambda_from_sdf(G.sdf_box((-np.inf, -np.inf, -np.inf), (3.0 * h, 1.0 * h, np.inf)), s)
+    return s.validate()
+
+
+def case_ahmed(scale=1, model="sst"):
+    """Ahmed-like body (1.044 x 0.389 x 0.288, front radius 0.1, 25 deg slant,
+    ground clearance 0.05) in a channel x in [-2, 5.68], y in [-1.44, 1.44],
+    z in [0, 2.88].  scale=1 gives 256 x 96 x 96 cells (dx = 0.03), scale=2 gives
+    512 x 192 x 192 (dx = 0.015).  Re = 7.7e5 on the body length, U = 1,
+    inlet I = 2 %, length scale a tenth of the body height."""
+    d = 0.03 / scale
+    nx, ny, nz = 256 * scale, 96 * scale, 96 * scale
+    k, eps, om = inlet_turbulence(1.0, 0.02, 0.1 * 0.288)
+    s = _spec(name=f"ahmed_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+              x0=-2.0, y0=-1.44, z0=0.0, dx=d, dy=d, dz=d,
+              bc=("inlet", "outlet", "slip", "slip", "noslip", "slip"),
+              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
+              nu=1.044 / 7.7e5, model=model)
+    s.lam = G.lambda_from_sdf(G.sdf_ahmed_like(), s)
+    return s.validate()
+
+
+def case_ahmed_small(model="sst", nx=48, ny=16, nz=16, d=0.06):
+    """Reduced Ahmed-like case for oracle-speed parity tests: the same body in a
+    tighter box x in [-0.5, -0.5 + nx d], y centred, z from the ground."""
+    k, eps, om = inlet_turbulence(1.0, 0.02, 0.1 * 0.288)
+    s = _spec(name=f"ahmed_small_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+              x0=-0.5, y0=-0.5 * ny * d, z0=0.0, dx=d, dy=d, dz=d,
+              bc=("inlet", "outlet", "slip", "slip", "noslip", "slip"),
+              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
+              nu=1.044 / 7.7e5, model=model)
+    s.lam = G.lambda_from_sdf(G.sdf_ahmed_like(), s)
+    return s.validate()
+
+
+def case_channel_ib(nx=48, n_fluid=8, n_solid=2, H=1.0, nu=0.1, U=1.0,
+                    model="laminar", urf_u=0.7, urf_p=0.3):
+    """2D channel whose walls are immersed solid bands on cell faces:
+    n_solid solid rows below and above n_fluid fluid rows of height H.
+    Uniform inlet U; outlet at x max.  Domain faces adjacent to the solid bands
+    are handled as walls inside the solid."""
+    d = H / n_fluid
+    ny = n_fluid + 2 * n_solid
+    y0 = -n_solid * d
+    s = _spec(name=f"channel_ib_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+              x0=0.0, y0=y0, z0=0.0, dx=d, dy=d, dz=1.0,
+              bc=("inlet", "outlet", "slip", "slip", "empty", "empty"),
+              u_in=(U, 0.0, 0.0), k_in=1e-4, eps_in=1e-5, omega_in=1.0,
+              nu=nu, model=model, urf_u=urf_u, urf_p=urf_p)
+    lo_band = G.sdf_box((-np.inf, -np.inf, -np.inf), (np.inf, 0.0, np.inf))
+    hi_band = G.sdf_box((-np.inf, H, -np.inf), (np.inf, np.inf, np.inf))
+    s.lam = G.lambda_from_sdf(lambda x, y, z: np.minimum(lo_band(x, y, z), hi_band(x, y, z)), s)
+    return s.validate()
+
+
+def case_channel_bodyfitted(nx=48, n_fluid=8, H=1.0, nu=0.1, U=1.0,
+                            model="laminar", urf_u=0.7, urf_p=0.3):
+    """2D channel with no-slip domain walls at y = 0 and y = H (no solid)."""
+    d = H / n_fluid
+    s = _spec(name=f"channel_bf_{nx}x{n_fluid}", dim=2, nx=nx, ny=n_fluid, nz=1,
+              x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=1.0,
+              bc=("inlet", "outlet", "noslip", "noslip", "empty", "empty"),
+              u_in=(U, 0.0, 0.0), k_in=1e-4, eps_in=1e-5, omega_in=1.0,
+              nu=nu, model=model, urf_u=urf_u, urf_p=urf_p)
+    s.lam = np.zeros(s.shape)
+    return s.validate()
+
+
+def case_cavity_block(nx=24, ny=12, model="laminar"):
+    """Small 2D inflow/outflow box with a grid-aligned block in the middle."""
+    d = 1.0 / ny
+    s = _spec(name=f"block2d_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+              x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=1.0,
+              bc=("inlet", "outlet", "noslip", "slip", "empty", "empty"),
+              u_in=(1.0, 0.0, 0.0), k_in=1e-3, eps_in=1e-4, omega_in=1.0,
+              nu=1e-2, model=model)
+    s.lam = G.lambda_from_sdf(G.sdf_box((0.5, 0.25, -np.inf), (0.75, 0.5, np.inf)), s)
+    return s.validate()
+
+
+def case_small_body3d(nx=24, ny=12, nz=12, model="laminar", shape="sphere", nu=1e-2):
+    """Small 3D duct with a sphere (cut cells) or a grid-aligned box."""
+    d = 1.0 / ny
+    k, eps, om = inlet_turbulence(1.0, 0.05, 0.07)
+    s = _spec(name=f"{shape}3d_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
+              x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=d,
+              bc=("inlet", "outlet", "slip", "slip", "noslip", "slip"),
+              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
+              nu=nu, model=model)
+    if shape == "sphere":
+        f = G.sdf_sphere((0.6, 0.5, 0.5), 0.2)
+    else:
+        f = G.sdf_box((0.5, 0.375, 0.375), (0.75, 0.625, 0.625))
+    s.lam = G.lambda_from_sdf(f, s)
+    return s.validate()
+
+
+def case_uniform_duct(nx=64, ny=4, model="keps", U=1.0, L=1.0):
+    """2D slip-walled duct without solid: uniform inflow carrying decaying
+    turbulence (no shear, so production vanishes)."""
+    d = L / nx
+    s = _spec(name=f"duct_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+              x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=1.0,
+              bc=("inlet", "outlet", "slip", "slip", "empty", "empty"),
+              u_in=(U, 0.0, 0.0), k_in=1e-2, eps_in=1e-2, omega_in=1e-2 / (0.09 * 1e-2),
+              nu=1e-5, model=model)
+    s.lam = np.zeros(s.shape)
+    return s.validate()
