@@ -90,7 +90,9 @@ typedef struct {
   int p_maxit;          /* PCG iteration cap per pressure solve */
   int recorrect;        /* 1: re-impose u_ib on forced cells after the velocity update */
   int bc_capacity;      /* max boundary (and in-solid, wall) cells; 0 = automatic */
-  int reserved0;
+  int continuity;       /* lambda-masked continuity: 0 = div u = 0 wherever lambda < 1 (pressure
+                           rhs sum_f phi*_f there, 0 in lambda = 1 cells); 1 = rhs scaled by
+                           (1 - lambda) in every cell */
   /* wall treatment */
   double Cmu, kappa, E, beta1_wf, Ceps2_wf, C_wf, ylam;
   /* standard k-epsilon */
@@ -139,7 +141,7 @@ enum {
 int hfdib_abi_version(void);
 
 /* Fills *cfg with the defaults (standard model constants, URF 0.7/0.3/0.85,
- * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1). */
+ * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1, continuity 0). */
 void hfdib_default_config(hfdib_config* cfg);
 
 /* Bytes of device workspace a context needs for this grid and configuration. */

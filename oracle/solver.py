@@ -39,7 +39,8 @@ DIRS = None  # filled per grid: list of (d, s)
 
 
 class Simple:
-    def __init__(self, spec, geo=None, solid_vel=None, p_solver="direct", p_rtol=1e-12, recorrect=True):
+    def __init__(self, spec, geo=None, solid_vel=None, p_solver="direct", p_rtol=1e-12, recorrect=True,
+                 continuity="literal"):
         self.spec = spec
         self.g = Grid(spec)
         self.C = dict(spec.constants)
@@ -51,6 +52,7 @@ class Simple:
         self.p_solver = p_solver
         self.p_rtol = p_rtol
         self.recorrect = recorrect
+        self.continuity = continuity
         self.ic = self.geo.tag == IC
         self.bcm = self.geo.tag == BC
         self.bc_cells = self.geo.bc_cells
@@ -264,6 +266,9 @@ class Simple:
             diag[g.interior_hi(d)] += cint[d]
         for (d, s, c) in cout:
             diag[g.bnd(d, s)] += c
+        # rows without any coupling (forced cells surrounded by forced cells) are
+        # identity rows; their right-hand side keeps p unchanged
+        diag = np.where(diag == 0.0, 1.0, diag)
         rows.append(lin.ravel())
         cols.append(lin.ravel())
         vals.append(diag.ravel())
@@ -365,15 +370,28 @@ class Simple:
             u[c] = np.where(alpha, uc + 1.0 * (uib[c] - uc), uc)
 
         # ---- 3.4 pressure corrector ----------------------------------------
-        rAU = V / aPr
+        # Forced cells carry no pressure gradient in their momentum row (f_ib
+        # contains +grad p), so their velocity does not respond to pressure:
+        # rAU = 0 there and H has no pressure term.
+        rAU = np.where(alpha, 0.0, V / aPr)
         HbyA = [np.zeros(g.shape) for _ in range(3)]
         for c in g.axes:
-            H = self.nbsum(anb, u[c]) + RHS[c] + gP[c]
+            H = np.where(alpha, self.nbsum(anb, u[c]) + RHS[c], self.nbsum(anb, u[c]) + RHS[c] + gP[c])
             HbyA[c] = H / aPr
         phis = self.interpolated_flux(HbyA)
         div_star = sum(g.outward_flux(phis, d, s) for (d, s) in self.dirs)
-        bp = -(1.0 - self.lam) * div_star
+        # (1 - lambda) div u = 0.  "literal": div u = 0 wherever 1 - lambda != 0 and
+        # no condition where lambda = 1 (the Laplacian row keeps p harmonic there);
+        # "weighted": the predictor divergence scaled by (1 - lambda) in every cell
+        if self.continuity == "literal":
+            bp = np.where(self.lam < 1.0, -div_star, 0.0)
+        else:
+            bp = -(1.0 - self.lam) * div_star
         A = self.pressure_matrix(rAU)
+        iso = np.ones(g.shape, dtype=bool) & alpha
+        for (d, s) in self.dirs:
+            iso &= ~g.has_neighbor(d, s) | g.neighbor(alpha, d, s, fill=False)
+        bp = np.where(iso, p_old, bp)  # identity rows: p unchanged
         bflat = bp.ravel()
         pflat_old = p_old.ravel()
         Ax = A @ pflat_old
@@ -394,7 +412,7 @@ class Simple:
         p = p_old + sp_.urf_p * (p_sol - p_old)
         gPn = self.pressure_gradient_V(p)
         for c in g.axes:
-            u[c] = HbyA[c] - gPn[c] / aPr
+            u[c] = np.where(alpha, HbyA[c], HbyA[c] - gPn[c] / aPr)
             if self.recorrect:
                 u[c] = np.where(alpha, u[c] + 1.0 * (uib[c] - u[c]), u[c])
         self.u, self.p, self.phi = u, p, phi

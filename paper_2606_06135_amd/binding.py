@@ -46,7 +46,7 @@ class Config(C.Structure):
     _fields_ = [("abi_version", C.c_int), ("model", C.c_int), ("precision", C.c_int), ("n_sweeps", C.c_int),
                 ("nu", C.c_double), ("urf_u", C.c_double), ("urf_p", C.c_double), ("urf_t", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("recorrect", C.c_int),
-                ("bc_capacity", C.c_int), ("reserved0", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
+                ("bc_capacity", C.c_int), ("continuity", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
 
 
 class HfdibError(RuntimeError):
@@ -111,7 +111,7 @@ def default_config():
     return cfg
 
 
-def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0):
+def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0, continuity="literal"):
     """Grid descriptor and configuration from a case description (any object with
     the attributes of synth.CaseSpec)."""
     d = GridDesc()
@@ -132,6 +132,7 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
     c.p_maxit = p_maxit
     c.recorrect = 1 if recorrect else 0
     c.bc_capacity = bc_capacity
+    c.continuity = {"literal": 0, "weighted": 1}[continuity]
     for n in _CONST_NAMES:
         if n in spec.constants:
             setattr(c, n, float(spec.constants[n]))

@@ -229,6 +229,10 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "invalid model";
     return HFDIB_EINVAL;
   }
+  if (c->continuity != 0 && c->continuity != 1) {
+    *why = "continuity must be 0 or 1";
+    return HFDIB_EINVAL;
+  }
   if (c->precision != HFDIB_FP64) {
     *why = "only FP64 precision is available in this library version";
     return HFDIB_EINVAL;
@@ -304,6 +308,7 @@ static void fill_params(hfdib_ctx* c) {
   P.Cmu25 = std::pow(g.Cmu, 0.25);
   P.sqrtCmu = std::sqrt(g.Cmu);
   P.recorrect = g.recorrect;
+  P.continuity = g.continuity;
 }
 
 static int capacity_for(long long N, int requested) {

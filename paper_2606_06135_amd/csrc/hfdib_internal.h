@@ -42,6 +42,7 @@ struct Params {
   double bound_frac, yperp_min_frac, cd_floor;
   double Cmu25, sqrtCmu;  // Cmu^(1/4), sqrt(Cmu) (host-computed)
   int recorrect;
+  int continuity;
 };
 
 // Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).

@@ -46,13 +46,15 @@ __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, dou
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
     double xc = x[c];
-    double acc = 0.0;
+    double acc = 0.0, dg = 0.0;
     for (int d = 0; d < P.dim; ++d)
       for (int s = -1; s <= 1; s += 2) {
         long long n;
         double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
         acc += n < 0 ? cf * xc : cf * (xc - x[n]);
+        dg += cf;
       }
+    if (dg == 0.0) acc = xc;  // uncoupled row: identity
     y[c] = acc;
     v[0] = xc * acc;
   }
@@ -70,11 +72,12 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
     double xc = x[c];
-    double acc = 0.0, bnd = 0.0;
+    double acc = 0.0, bnd = 0.0, dg = 0.0;
     for (int d = 0; d < P.dim; ++d)
       for (int s = -1; s <= 1; s += 2) {
         long long n;
         double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
+        dg += cf;
         if (n < 0) {
           acc += cf * xc;
           bnd += cf;
@@ -82,6 +85,11 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
           acc += cf * (xc - x[n]);
         }
       }
+    bool ident = dg == 0.0;  // uncoupled row: identity
+    if (ident) {
+      acc = xc;
+      bnd = 1.0;
+    }
     double bc = b[c];
     double rc = bc - acc;
     r[c] = rc;
@@ -119,7 +127,7 @@ __global__ void k_fine_smooth(Params P, FineOp O, const double* r, double* z, in
       diag += cf;
       if (n >= 0 && !init) nb += cf * z[n];
     }
-  z[c] = (r[c] + nb) / diag;
+  z[c] = diag == 0.0 ? r[c] : (r[c] + nb) / diag;
 }
 
 // ---------------------------------------------------------------- coarse levels
@@ -245,7 +253,7 @@ __global__ void k_level_diag(LevelDev L, double* diag) {
   if (L.dim == 3)
     s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] +
          L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))];
-  diag[lidx(L, i, j, k)] = s;
+  diag[lidx(L, i, j, k)] = s == 0.0 ? 1.0 : s;  // uncoupled coarse cells: identity
 }
 
 // off-diagonal sum sum_nb c z_nb at (i,j,k) of a stored level
@@ -295,13 +303,15 @@ __global__ void k_restrict_fine(Params P, FineOp O, const double* r, const doubl
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = cidx(P, i, j, k);
-        double zc = z[c], acc = 0.0;
+        double zc = z[c], acc = 0.0, dg = 0.0;
         for (int d = 0; d < P.dim; ++d)
           for (int sg = -1; sg <= 1; sg += 2) {
             long long n;
             double cf = fine_coef(P, O, c, d, sg, i, j, k, &n);
             acc += n < 0 ? cf * zc : cf * (zc - z[n]);
+            dg += cf;
           }
+        if (dg == 0.0) acc = zc;
         s += r[c] - acc;
       }
   C.r[lidx(C, I, J, K)] = s;

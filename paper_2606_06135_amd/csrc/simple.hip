@@ -375,23 +375,27 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
   double a = aPr[c];
   const double* rr[3] = {rhs0, rhs1, rhs2};
   double* hh[3] = {h0, h1, h2};
+  // forced cells: no pressure term in the momentum row (f_ib contains +grad p),
+  // hence no pressure-velocity coupling (rAU = 0)
+  bool forced = fl & F_ALPHA_U;
   for (int cc = 0; cc < P.dim; ++cc) {
     double nb = 0.0;
     for (int q = 0; q < 2 * P.dim; ++q) {
       if (nbi[q] == c) continue;
       nb += anb[q] * M.u[cc][nbi[q]];
     }
-    double H = nb + rr[cc][c] + gradp_V(P, M.p, fl, cc, i, j, k, c);
+    double H = forced ? nb + rr[cc][c] : nb + rr[cc][c] + gradp_V(P, M.p, fl, cc, i, j, k, c);
     hh[cc][c] = H / a;
   }
   if (P.dim == 2) h2[c] = 0.0;
-  rAU[c] = P.V / a;
+  rAU[c] = forced ? 0.0 : P.V / a;
 }
 
 // face flux predictor phi* from HbyA (overwrites phi) and the pressure
 // right-hand side -(1 - lambda_P) sum_f phi*_out (lambda-masked continuity)
 __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const double* h2, const double* lam,
-                           const uint8_t* flags, double* phx, double* phy, double* phz, double* rhs_p) {
+                           const uint8_t* flags, const double* pold, double* phx, double* phy, double* phz,
+                           double* rhs_p) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   int k = blockIdx.z;
@@ -422,7 +426,20 @@ __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const d
       div += s > 0 ? val : -val;
     }
   }
-  rhs_p[c] = -(1.0 - lam[c]) * div;
+  // lambda-masked continuity (1 - lambda) div u = 0: either div u = 0 wherever
+  // lambda < 1, or the predictor divergence weighted by (1 - lambda)
+  double l = lam[c];
+  double rp = P.continuity == 0 ? (l < 1.0 ? -div : 0.0) : -(1.0 - l) * div;
+  // a forced cell whose face neighbours are all forced has no pressure coupling:
+  // identity row, p unchanged
+  if (flags[c] & F_ALPHA_U) {
+    bool iso = true;
+    for (int d = 0; d < P.dim; ++d)
+      for (int s = -1; s <= 1; s += 2)
+        if (!on_bnd(P, d, s, i, j, k) && !(flags[c + s * stride(P, d)] & F_ALPHA_U)) iso = false;
+    if (iso) rp = pold[c];
+  }
+  rhs_p[c] = rp;
 }
 
 // flux correction with the solved pressure and relaxation of p (into pnew)
@@ -468,8 +485,9 @@ __global__ void k_vel_update(Params P, const double* h0, const double* h1, const
   double* uu[3] = {u0, u1, u2};
   double a = aPr[c];
   bool alpha = (fl & F_ALPHA_U) && P.recorrect;
+  bool forced = fl & F_ALPHA_U;
   for (int cc = 0; cc < P.dim; ++cc) {
-    double v = hv[cc][c] - gradp_V(P, pnew, fl, cc, i, j, k, c) / a;
+    double v = forced ? hv[cc][c] : hv[cc][c] - gradp_V(P, pnew, fl, cc, i, j, k, c) / a;
     if (alpha) v = v + 1.0 * (ub[cc][c] - v);
     uu[cc][c] = v;
   }
@@ -608,7 +626,7 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   hipLaunchKernelGGL(k_hbya, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->hbya[0],
                      c->hbya[1], c->hbya[2], c->rAU);
   hipLaunchKernelGGL(k_flux_rhs, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->lam, c->flags,
-                     c->phi[0], c->phi[1], c->phi[2], c->rhs_p);
+                     c->p, c->phi[0], c->phi[1], c->phi[2], c->rhs_p);
   hipLaunchKernelGGL(k_copy, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, c->p, c->px);
   HFDIB_CHECK_LAUNCH(c, "momentum stage");
   int iters = 0;
