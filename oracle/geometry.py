@@ -11,7 +11,8 @@ Readings where the paper is silent (each listed in the design notes):
   |grad lambda| h < 1e-12 the normal falls back to the normalised sum of
   (P - N) over in-solid Moore neighbours N;
 * the in-solid neighbour N minimises -n_P.(P - N); values within 1e-12 h are
-  ties, broken by the smaller |P - N| and then the lower linear index;
+  ties, broken by the smaller |P - N|; y_perp is the mean over neighbours that
+  are still tied (a choice that keeps mirror-symmetric geometry symmetric);
 * y_perp is clamped to >= yperp_min_frac * h;
 * interpolation points P1 = P + m h n_P and P2 = P + (m+1) h n_P with m = 1,
   moved outward (m = 2, 3) while P1 or P2 is unusable (outside the domain, or
@@ -213,6 +214,23 @@ def _pad8(cells, ws, own):
     return cells, ws
 
 
+def _yperp_via(g, lam_flat, sig_flat, lam, tag, gl, P, i, j, k, ii, jj, kk):
+    """y_perp of boundary cell P (lambda_P = 0) through its in-solid neighbour N"""
+    cn = _lin(g, ii, jj, kk)
+    N = _center(g, ii, jj, kk)
+    if lam_flat[cn] < 1.0:
+        # second case: distance from P to the plane through N + |sigma_N| n_N
+        nN = cell_normal(g, lam, tag, gl, ii, jj, kk)
+        return float(nN @ (P - (N + abs(sig_flat[cn]) * nN)))
+    # third case: distance to the mean of the vertices shared by P and N
+    vp = {(i + a, j + bb, k + cc) for a in (0, 1) for bb in (0, 1) for cc in ((0, 1) if g.dim == 3 else (0,))}
+    vn = {(ii + a, jj + bb, kk + cc) for a in (0, 1) for bb in (0, 1) for cc in ((0, 1) if g.dim == 3 else (0,))}
+    shared = np.array(sorted(vp & vn), dtype=np.float64)
+    m = shared.mean(axis=0)
+    vmean = np.array([g.o[0] + m[0] * g.dx, g.o[1] + m[1] * g.dy, g.o[2] + m[2] * g.dz if g.dim == 3 else 0.0])
+    return float(np.sqrt((P - vmean) @ (P - vmean)))
+
+
 def precompute(spec, with_wall_distance=None):
     g = Grid(spec)
     lam = np.asarray(spec.lam, dtype=np.float64)
@@ -247,8 +265,10 @@ def precompute(spec, with_wall_distance=None):
         if 0.0 < lp < 0.5:
             yp = abs(sig_flat[c])  # eq. for y_perp, first case
         else:
-            # in-solid neighbour minimising -n_P.(P - N)
+            # in-solid neighbour minimising -n_P.(P - N); among equal values the
+            # nearer one; y_perp is averaged over neighbours that remain tied
             best = None
+            ysum, ycnt = 0.0, 0
             for (ox, oy, oz) in moore_offsets(g.dim):
                 ii, jj, kk = i + ox, j + oy, k + oz
                 if not (0 <= ii < g.nx and 0 <= jj < g.ny and 0 <= kk < g.nz):
@@ -259,34 +279,15 @@ def precompute(spec, with_wall_distance=None):
                 PN = P - _center(g, ii, jj, kk)
                 v = -float(nP @ PN)
                 dist = float(np.sqrt(PN @ PN))
-                key = (v, dist, cn)
-                if best is None:
-                    best = key
-                    continue
-                if v < best[0] - TIE_TOL * h:
-                    best = key
-                elif abs(v - best[0]) <= TIE_TOL * h:
-                    if dist < best[1] - TIE_TOL * h or (abs(dist - best[1]) <= TIE_TOL * h and cn < best[2]):
-                        best = key
-            cn = best[2]
-            nstar[b] = cn
-            ii, jj, kk = _unlin(g, cn)
-            N = _center(g, ii, jj, kk)
-            ln = lam_flat[cn]
-            if ln < 1.0:
-                nN = cell_normal(g, lam, tag, gl, ii, jj, kk)
-                yp = float(nN @ (P - (N + abs(sig_flat[cn]) * nN)))  # second case
-            else:
-                # third case: distance to the mean of the vertices shared by P and N
-                vp = {(i + a, j + bb, k + cc) for a in (0, 1) for bb in (0, 1)
-                      for cc in ((0, 1) if g.dim == 3 else (0,))}
-                vn = {(ii + a, jj + bb, kk + cc) for a in (0, 1) for bb in (0, 1)
-                      for cc in ((0, 1) if g.dim == 3 else (0,))}
-                shared = np.array(sorted(vp & vn), dtype=np.float64)
-                m = shared.mean(axis=0)
-                vmean = np.array([g.o[0] + m[0] * g.dx, g.o[1] + m[1] * g.dy,
-                                  g.o[2] + m[2] * g.dz if g.dim == 3 else 0.0])
-                yp = float(np.sqrt((P - vmean) @ (P - vmean)))
+                if best is None or v < best[0] - TIE_TOL * h or (
+                        abs(v - best[0]) <= TIE_TOL * h and dist < best[1] - TIE_TOL * h):
+                    best = (v, dist, cn)
+                    ysum, ycnt = _yperp_via(g, lam_flat, sig_flat, lam, tag, gl, P, i, j, k, ii, jj, kk), 1
+                elif abs(v - best[0]) <= TIE_TOL * h and abs(dist - best[1]) <= TIE_TOL * h:
+                    ysum += _yperp_via(g, lam_flat, sig_flat, lam, tag, gl, P, i, j, k, ii, jj, kk)
+                    ycnt += 1
+            nstar[b] = best[2]
+            yp = ysum / ycnt
         yp = max(yp, C["yperp_min_frac"] * h)
         yperp[b] = yp
         # interpolation points along n_P

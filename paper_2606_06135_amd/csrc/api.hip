@@ -28,6 +28,9 @@ struct Timers {
 
 static void timers_flush(hfdib_ctx* c) {
   Timers* T = c->timers;
+  bool any = false;
+  for (int k = 0; k < T_NCLASS; ++k) any = any || !T->pend[k].empty();
+  if (!any) return;
   (void)hipStreamSynchronize(c->stream);
   for (int k = 0; k < T_NCLASS; ++k) {
     for (auto& pr : T->pend[k]) {

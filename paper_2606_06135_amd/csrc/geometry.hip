@@ -193,10 +193,11 @@ __global__ void k_bc_geometry(Params P, int nbc, const int* bc_cells, const doub
   if (lp > 0.0 && lp < 0.5) {
     yp = fabs(h * atanh(1.0 - 2.0 * lp));  // first case: |sigma_P|
   } else {
-    // in-solid neighbour minimising -n_P.(P - N); ties (1e-12 h) by distance, then index
+    // in-solid neighbour minimising -n_P.(P - N); among equal values (1e-12 h) the
+    // nearer one; y_perp is the mean over neighbours that remain tied
     bool have = false;
-    double bv = 0.0, bd = 0.0;
-    int bn = -1, bi = 0, bj = 0, bk = 0;
+    double bv = 0.0, bd = 0.0, ysum = 0.0;
+    int ycnt = 0;
     int zr = P.dim == 3 ? 1 : 0;
     for (int ox = -1; ox <= 1; ++ox)
       for (int oy = -1; oy <= 1; ++oy)
@@ -210,48 +211,42 @@ __global__ void k_bc_geometry(Params P, int nbc, const int* bc_cells, const doub
           double px = Pc.x - N.x, py = Pc.y - N.y, pz = Pc.z - N.z;
           double v = -(nP.x * px + nP.y * py + nP.z * pz);
           double dist = sqrt(px * px + py * py + pz * pz);
-          bool take = false;
-          if (!have) take = true;
-          else if (v < bv - 1e-12 * h) take = true;
-          else if (fabs(v - bv) <= 1e-12 * h) {
-            if (dist < bd - 1e-12 * h || (fabs(dist - bd) <= 1e-12 * h && cn < bn)) take = true;
+          bool better = !have || v < bv - 1e-12 * h || (fabs(v - bv) <= 1e-12 * h && dist < bd - 1e-12 * h);
+          bool tie = have && !better && fabs(v - bv) <= 1e-12 * h && fabs(dist - bd) <= 1e-12 * h;
+          if (!better && !tie) continue;
+          double yv;
+          double ln = lam[cn];
+          if (ln < 1.0) {
+            // second case: distance to the plane through N + |sigma_N| n_N
+            V3 nN = cell_normal(P, lam, flags, ii, jj, kk);
+            double sN = fabs(h * atanh(1.0 - 2.0 * ln));
+            double qx = Pc.x - (N.x + sN * nN.x), qy = Pc.y - (N.y + sN * nN.y), qz = Pc.z - (N.z + sN * nN.z);
+            yv = nN.x * qx + nN.y * qy + nN.z * qz;
+          } else {
+            // third case: distance to the mean of the vertices shared by P and N
+            double mx = (double)i + 0.5 + 0.5 * (double)ox;
+            double my = (double)j + 0.5 + 0.5 * (double)oy;
+            double vx = P.x0 + mx * P.dx, vy = P.y0 + my * P.dy, vz = 0.0;
+            if (P.dim == 3) {
+              double mz = (double)k + 0.5 + 0.5 * (double)oz;
+              vz = P.z0 + mz * P.dz;
+            }
+            double qx = Pc.x - vx, qy = Pc.y - vy, qz = Pc.z - vz;
+            yv = sqrt(qx * qx + qy * qy + qz * qz);
           }
-          if (take) {
+          if (better) {
             have = true;
             bv = v;
             bd = dist;
-            bn = cn;
-            bi = ii;
-            bj = jj;
-            bk = kk;
+            ysum = yv;
+            ycnt = 1;
+          } else {
+            ysum += yv;
+            ycnt += 1;
           }
         }
-    if (bn < 0) {  // cannot happen for a boundary cell with lambda = 0 (it has an in-solid neighbour)
-      bn = c;
-      bi = i;
-      bj = j;
-      bk = k;
-    }
-    V3 N = center(P, bi, bj, bk);
-    double ln = lam[bn];
-    if (ln < 1.0) {
-      // second case: distance to the plane through N + |sigma_N| n_N
-      V3 nN = cell_normal(P, lam, flags, bi, bj, bk);
-      double sN = fabs(h * atanh(1.0 - 2.0 * ln));
-      double qx = Pc.x - (N.x + sN * nN.x), qy = Pc.y - (N.y + sN * nN.y), qz = Pc.z - (N.z + sN * nN.z);
-      yp = nN.x * qx + nN.y * qy + nN.z * qz;
-    } else {
-      // third case: distance to the mean of the vertices shared by P and N
-      double mx = (double)i + 0.5 + 0.5 * (double)(bi - i);
-      double my = (double)j + 0.5 + 0.5 * (double)(bj - j);
-      double vx = P.x0 + mx * P.dx, vy = P.y0 + my * P.dy, vz = 0.0;
-      if (P.dim == 3) {
-        double mz = (double)k + 0.5 + 0.5 * (double)(bk - k);
-        vz = P.z0 + mz * P.dz;
-      }
-      double qx = Pc.x - vx, qy = Pc.y - vy, qz = Pc.z - vz;
-      yp = sqrt(qx * qx + qy * qy + qz * qz);
-    }
+    // a boundary cell with lambda = 0 always has an in-solid neighbour
+    yp = ycnt > 0 ? ysum / ycnt : 0.0;
   }
   double ymin = P.yperp_min_frac * h;
   yp = yp > ymin ? yp : ymin;
