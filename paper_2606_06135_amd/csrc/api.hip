@@ -117,8 +117,6 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->aPr = B.take<double>(N);
   for (int q = 0; q < 3; ++q) c->hbya[q] = B.take<double>(N);
   c->rAU = B.take<double>(N);
-  for (int q = 0; q < 9; ++q) c->grad[q] = B.take<double>(N);
-  c->S2 = B.take<double>(N);
   c->F1 = B.take<double>(N);
   for (int q = 0; q < 3; ++q) c->uib[q] = B.take<double>(N);
   c->kib = B.take<double>(N);
@@ -535,7 +533,6 @@ int hfdib_set_field(hfdib_ctx* c, int id, const double* src) {
   double* dst = field_ptr(c, id, &n);
   if (!dst) return HFDIB_EINVAL;
   HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "set_field");
-  if (id <= HFDIB_FIELD_UZ) c->grad_stale = 1;
   return HFDIB_OK;
 }
 

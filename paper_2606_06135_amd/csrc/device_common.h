@@ -81,8 +81,77 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[NV], double* 
   }
 }
 
+// Full-grid kernels run on a 1D grid of 64 x 4 tiles (grid3()).  Consecutive
+// workgroups are dispatched round-robin over the 8 XCDs; the logical tile order
+// is remapped so that each XCD works on a contiguous run of tiles (x fastest,
+// then y, then z) and the y/z halo rows a tile needs stay in that XCD's L2.
+__device__ __forceinline__ void tile_ijk(const Params& P, int& i, int& j, int& k) {
+  unsigned nb = gridDim.x, b = blockIdx.x;
+  unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, id = b >> 3;
+  unsigned L = x < r ? x * (q + 1) + id : r * (q + 1) + (x - r) * q + id;
+  int tx = (P.nx + 63) >> 6, ty = (P.ny + 3) >> 2;
+  int bx = (int)(L % (unsigned)tx);
+  unsigned rest = L / (unsigned)tx;
+  int by = (int)(rest % (unsigned)ty);
+  k = (int)(rest / (unsigned)ty);
+  i = bx * 64 + (int)threadIdx.x;
+  j = by * 4 + (int)threadIdx.y;
+}
+
 __device__ __forceinline__ long long block_linear() {
   return (long long)blockIdx.x + (long long)gridDim.x * ((long long)blockIdx.y + (long long)gridDim.y * blockIdx.z);
+}
+
+// ---------------------------------------------------------------- gradients
+// Gauss face value of velocity component cc on the domain face (d, s)
+__device__ __forceinline__ double u_bface(const Params& P, int cc, int d, int s, bool solid, double uP) {
+  if (solid) return uP;
+  int kind = face_kind(P, d, s);
+  if (kind == HFDIB_BC_INLET) return P.u_in[cc];
+  if (kind == HFDIB_BC_NOSLIP) return 0.0;
+  if (kind == HFDIB_BC_SLIP) return cc == d ? 0.0 : uP;
+  return uP;
+}
+// Gauss face value of a transported scalar (inlet value at inlets, else zero gradient)
+__device__ __forceinline__ double sc_bface(const Params& P, int d, int s, bool solid, double vP, double vin) {
+  if (face_kind(P, d, s) == HFDIB_BC_INLET && !solid) return vin;
+  return vP;
+}
+// (psi_+ - psi_-)/delta_d with linear face interpolation (Gauss gradient)
+__device__ __forceinline__ double ggrad(const Params& P, const double* a, long long c, int d, int i, int j, int k,
+                                       double fb_p, double fb_m) {
+  long long st = stride(P, d);
+  double fp = on_bnd(P, d, +1, i, j, k) ? fb_p : 0.5 * (a[c] + a[c + st]);
+  double fm = on_bnd(P, d, -1, i, j, k) ? fb_m : 0.5 * (a[c - st] + a[c]);
+  return (fp - fm) / P.delta[d];
+}
+// d u_jj / d x_ii at cell (i,j,k) (index c, lambda > 0 flag `solid`)
+__device__ __forceinline__ double gradu(const Params& P, const double* const* u, bool solid, int ii, int jj, int i,
+                                        int j, int k, long long c) {
+  const double* a = u[jj];
+  double uP = a[c];
+  return ggrad(P, a, c, ii, i, j, k, u_bface(P, jj, ii, +1, solid, uP), u_bface(P, jj, ii, -1, solid, uP));
+}
+// full velocity gradient G[ii][jj] = d u_jj / d x_ii at a cell (zero outside dim)
+__device__ __forceinline__ void gradu_all(const Params& P, const double* const* u, bool solid, int i, int j, int k,
+                                          long long c, double (&G)[3][3]) {
+#pragma unroll
+  for (int jj = 0; jj < 3; ++jj)
+#pragma unroll
+    for (int ii = 0; ii < 3; ++ii)
+      G[ii][jj] = (ii < P.dim && jj < P.dim) ? gradu(P, u, solid, ii, jj, i, j, k, c) : 0.0;
+}
+// 2 S:S with S the symmetric part of G (summed over all nine entries)
+__device__ __forceinline__ double strain2(const double (&G)[3][3]) {
+  double S2 = 0.0;
+#pragma unroll
+  for (int ii = 0; ii < 3; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 3; ++jj) {
+      double sij = 0.5 * (G[ii][jj] + G[jj][ii]);
+      S2 = S2 + 2.0 * sij * sij;
+    }
+  return S2;
 }
 
 // ---------------------------------------------------------------- geometry

@@ -21,9 +21,8 @@ __global__ void k_validate(Params P, const double* lam, int* bad) {
 // (walls inside the solid on domain faces), the red colour and the free-stream
 // cells touching a no-slip domain face.
 __global__ void k_classify(Params P, const double* lam, uint8_t* flags) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   double l = lam[c];
@@ -337,9 +336,8 @@ __global__ void k_wall_geometry(Params P, int nw, const int* wall_cells, double*
 // midpoints of faces between lambda = 0 and lambda = 1 face neighbours.  Each
 // cell contributes at most 1 + dim points; slots are compacted afterwards.
 __global__ void k_iface_points(Params P, const double* lam, const uint8_t* flags, double* pts, int* cnt, int cap) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   double l = lam[c];

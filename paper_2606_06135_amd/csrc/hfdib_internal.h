@@ -73,7 +73,7 @@ struct hfdib_ctx {
 
   // --- cell arrays (N)
   double *u[3], *p, *k, *w, *nut, *lam, *dw;
-  double *rhs[3], *aPr, *hbya[3], *rAU, *grad[9], *S2, *F1;
+  double *rhs[3], *aPr, *hbya[3], *rAU, *F1;
   double *uib[3], *kib, *wib, *Pk, *us[3];
   double *t0, *t1, *t2;  // scratch (turbulence rhs / diagonal)
   double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
@@ -102,7 +102,6 @@ struct hfdib_ctx {
   // --- stats
   double stats[8];
   double last_pres[3];
-  int grad_stale;
   // --- timing
   hfdib::Timers* timers;
 };
@@ -111,7 +110,7 @@ namespace hfdib {
 
 // launch helpers
 inline dim3 grid3(const Params& P) {
-  return dim3((P.nx + 63) / 64, (P.ny + 3) / 4, P.nz);
+  return dim3((unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4) * P.nz), 1, 1);
 }
 inline dim3 block3() { return dim3(64, 4, 1); }
 inline int nblocks1(long long n) {
@@ -147,9 +146,8 @@ int mg_setup_levels(hfdib_ctx* c);
 
 // deterministic reduction of `nval` rows of per-block partial sums into
 // ctx->scal[SCAL_PCG + out + v]; op selects a PCG scalar update (pressure.hip)
-void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0);
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0);
 int turbulence_stage(hfdib_ctx* c);
-int gradient_only(hfdib_ctx* c);
 // offsets (relative to SCAL_PCG) of device scalars
 enum {
   SC_MEANS = 100,    // means of u, v, w, p, k (5) and of omega/eps after fixing (1)

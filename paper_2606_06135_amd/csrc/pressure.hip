@@ -39,9 +39,8 @@ __device__ __forceinline__ double fine_coef(const Params& P, const FineOp& O, lo
 
 // y = A x (and partial sums of x.y)
 __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, double* part, long long pstride) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   double v[1] = {0.0};
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
@@ -65,9 +64,8 @@ __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, dou
 // |Ax - A xbar|, |b - A xbar| with xbar = *xmean (nullable)
 __global__ void k_fine_residual(Params P, FineOp O, const double* b, const double* x, double* r, const double* xmean,
                                 double* part, long long pstride) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   double v[5] = {0, 0, 0, 0, 0};
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
@@ -108,9 +106,8 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
 // red-black Gauss-Seidel half sweep on the fine level; init != 0 means z was
 // zero before this (first red) sweep: red cells z = r/diag, black cells z = 0
 __global__ void k_fine_smooth(Params P, FineOp O, const double* r, double* z, int color, int init) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   bool mine = ((i + j + k) & 1) == color;
@@ -364,6 +361,98 @@ __global__ void k_coarse_solve(LevelDev L, int m) {
   }
 }
 
+// ---------------------------------------------------------------- tail V-cycle
+// The small coarse levels (each <= TAIL_MAX cells) are processed by one
+// workgroup: pre-smoothing, restriction, the coarsest solve, prolongation and
+// post-smoothing with barriers between the passes (one launch instead of ~5 per
+// level).  Same arithmetic as the per-level kernels.
+constexpr long long TAIL_MAX = 1024;
+constexpr int TAIL_LDS = 1024;
+constexpr int TAIL_THREADS = 1024;
+struct TailLevels {
+  LevelDev L[MAX_LEVELS];
+  int n;
+};
+
+__device__ __forceinline__ void tail_smooth(const LevelDev& L, int color, int init) {
+  for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
+    int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long long)L.nx * L.ny));
+    bool mine = ((i + j + k) & 1) == color;
+    if (init && !mine) {
+      L.z[c] = 0.0;
+      continue;
+    }
+    if (!mine) continue;
+    double nb = init ? 0.0 : level_nbsum(L, L.z, i, j, k);
+    L.z[c] = (L.r[c] + nb) / L.diag[c];
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevels T, int m) {
+  int n = T.n;
+  for (int t = 0; t < n - 1; ++t) {
+    const LevelDev& F = T.L[t];
+    const LevelDev& C = T.L[t + 1];
+    tail_smooth(F, 0, 1);
+    tail_smooth(F, 1, 0);
+    int nzs = C.dim == 3 ? 2 : 1;
+    for (long long q = threadIdx.x; q < C.N; q += TAIL_THREADS) {
+      int I = (int)(q % C.nx), J = (int)((q / C.nx) % C.ny), K = (int)(q / ((long long)C.nx * C.ny));
+      double sacc = 0.0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          for (int e = 0; e < nzs; ++e) {
+            int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
+            long long c = lidx(F, i, j, k);
+            double Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
+            sacc += F.r[c] - Az;
+          }
+      C.r[q] = sacc;
+    }
+    __syncthreads();
+  }
+  // coarsest level: symmetric red-black Gauss-Seidel from zero, in LDS
+  const LevelDev& L = T.L[n - 1];
+  if (L.N <= TAIL_LDS) {
+    __shared__ double zs[TAIL_LDS], rs[TAIL_LDS], ds[TAIL_LDS];
+    for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
+      zs[c] = 0.0;
+      rs[c] = L.r[c];
+      ds[c] = L.diag[c];
+    }
+    __syncthreads();
+    for (int it = 0; it < 2 * m; ++it)
+      for (int h = 0; h < 2; ++h) {
+        int color = it < m ? h : 1 - h;
+        for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
+          int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long long)L.nx * L.ny));
+          if (((i + j + k) & 1) != color) continue;
+          zs[c] = (rs[c] + level_nbsum(L, zs, i, j, k)) / ds[c];
+        }
+        __syncthreads();
+      }
+    for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) L.z[c] = zs[c];
+    __syncthreads();
+  } else {
+    for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) L.z[c] = 0.0;
+    __syncthreads();
+    for (int it = 0; it < 2 * m; ++it)
+      for (int h = 0; h < 2; ++h) tail_smooth(L, it < m ? h : 1 - h, 0);
+  }
+  for (int t = n - 2; t >= 0; --t) {
+    const LevelDev& F = T.L[t];
+    const LevelDev& C = T.L[t + 1];
+    for (long long c = threadIdx.x; c < F.N; c += TAIL_THREADS) {
+      int i = (int)(c % F.nx), j = (int)((c / F.nx) % F.ny), k = (int)(c / ((long long)F.nx * F.ny));
+      F.z[c] += C.z[lidx(C, i / 2, j / 2, F.dim == 3 ? k / 2 : 0)];
+    }
+    __syncthreads();
+    tail_smooth(F, 1, 0);
+    tail_smooth(F, 0, 0);
+  }
+}
+
 // ---------------------------------------------------------------- vector ops
 __global__ void k_copy_vec(long long n, const double* a, double* b) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
@@ -395,24 +484,36 @@ __global__ void k_xpby(long long n, const double* scal, const double* z, double*
   if (c < n) d[c] = z[c] + scal[S_BETA] * d[c];
 }
 
-// finalize: sums of `nval` partial rows -> scal[out+v]; then PCG scalar update
-// op: 0 none, 1 alpha = rho / dq, 2 beta = rz / rho, rho = rz
-__global__ void k_finalize(const double* part, long long pstride, int nblk, int nval, double* scal, int out, int op,
-                           double divisor) {
-  __shared__ double lds[NTHREADS];
+// finalize: reduces `nval` rows of per-block partials -> scal[out+v] (sums, or
+// maxima for op 4), then an optional PCG scalar update.  One workgroup of 1024
+// threads; fixed reduction order (deterministic).
+// op: 0 none, 1 alpha = rho / dq, 2 beta = rz / rho, rho = rz, 3 rho = value, 4 max
+constexpr int FIN_THREADS = 1024;
+__global__ void __launch_bounds__(FIN_THREADS)
+k_finalize(const double* part, long long pstride, int nblk, int nval, double* scal, int out, int op,
+           double divisor) {
+  __shared__ double lds[FIN_THREADS / 64];
+  int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int v = 0; v < nval; ++v) {
+    const double* row = part + (long long)v * pstride;
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += NTHREADS) s += part[(long long)v * pstride + b];
-    lds[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = NTHREADS / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) lds[threadIdx.x] += lds[threadIdx.x + off];
-      __syncthreads();
+    if (op == 4) {
+      for (int b = tid; b < nblk; b += FIN_THREADS) s = fmax(s, row[b]);
+      s = wave_max(s);
+    } else {
+      for (int b = tid; b < nblk; b += FIN_THREADS) s += row[b];
+      s = wave_sum(s);
     }
-    if (threadIdx.x == 0) scal[out + v] = divisor == 1.0 ? lds[0] : lds[0] / divisor;
+    if (lane == 0) lds[wid] = s;
+    __syncthreads();
+    if (tid == 0) {
+      double t = lds[0];
+      for (int w = 1; w < FIN_THREADS / 64; ++w) t = op == 4 ? fmax(t, lds[w]) : t + lds[w];
+      scal[out + v] = divisor == 1.0 ? t : t / divisor;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
     if (op == 1) {
       double dq = scal[out];
       scal[S_ALPHA] = dq != 0.0 ? scal[S_RHO] / dq : 0.0;
@@ -446,9 +547,9 @@ static LevelDev levdev(hfdib_ctx* c, int l) {
 static dim3 lgrid(int nx, int ny, int nz) { return dim3((nx + 63) / 64, (ny + 3) / 4, nz); }
 
 // finalize helper; partial slots live in ctx->partials with row stride c->pstride
-void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NTHREADS), 0, c->stream, c->partials, c->pstride, nblk, nval,
-                     c->scal + SCAL_PCG, out, op, divisor);
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, c->stream, c->partials + (long long)row0 * c->pstride,
+                     c->pstride, nblk, nval, c->scal + SCAL_PCG, out, op, divisor);
 }
 
 static void vcycle(hfdib_ctx* c, const FineOp& O, const double* r, double* z) {
@@ -459,27 +560,31 @@ static void vcycle(hfdib_ctx* c, const FineOp& O, const double* r, double* z) {
   if (c->nlev > 1) {
     LevelDev L1 = levdev(c, 1);
     hipLaunchKernelGGL(k_restrict_fine, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, z, L1);
-    for (int l = 1; l < c->nlev; ++l) {
+    // large coarse levels: one kernel per pass
+    int l = 1;
+    while (l < c->nlev - 1 && c->lev[l].N > TAIL_MAX) {
       LevelDev L = levdev(c, l);
       dim3 gl = lgrid(L.nx, L.ny, L.nz);
-      if (l == c->nlev - 1) {
-        hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(NTHREADS), 0, c->stream, L, 16);
-        break;
-      }
       hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 0, 1);
       hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 1, 0);
       LevelDev C = levdev(c, l + 1);
       hipLaunchKernelGGL(k_restrict_level, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
+      ++l;
     }
-    for (int l = c->nlev - 2; l >= 1; --l) {
-      LevelDev L = levdev(c, l);
-      LevelDev C = levdev(c, l + 1);
+    // small levels l..nlev-1 (and the coarsest solve) in one workgroup
+    TailLevels T;
+    T.n = c->nlev - l;
+    for (int t = 0; t < T.n; ++t) T.L[t] = levdev(c, l + t);
+    hipLaunchKernelGGL(k_tail_vcycle, dim3(1), dim3(TAIL_THREADS), 0, c->stream, T, 6);
+    for (int q = l - 1; q >= 1; --q) {
+      LevelDev L = levdev(c, q);
+      LevelDev C = levdev(c, q + 1);
       dim3 gl = lgrid(L.nx, L.ny, L.nz);
       hipLaunchKernelGGL(k_prolong, gl, b, 0, c->stream, L.nx, L.ny, L.nz, L.dim, L.z, C);
       hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 1, 0);
       hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 0, 0);
     }
-    hipLaunchKernelGGL(k_prolong, g, b, 0, c->stream, P.nx, P.ny, P.nz, P.dim, z, L1);
+    hipLaunchKernelGGL(k_prolong, lgrid(P.nx, P.ny, P.nz), b, 0, c->stream, P.nx, P.ny, P.nz, P.dim, z, L1);
   }
   hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 1, 0);
   hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 0, 0);
@@ -515,52 +620,53 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
   timer_begin(c, T_PSOLVE);
   build_levels(c, O);
   hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, O, rhs, x, r, xmean_dev, c->partials, c->pstride);
-  launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [16]=rr0 [17]=bb [18..20]=residual sums
-  HFDIB_CHECK_LAUNCH(c, "pcg init");
-  double hs[8];
-  HFDIB_CHECK(c, hipMemcpyAsync(hs, S + S_BB + 16, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
-  HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
-  double rr = hs[0], bb = hs[1];
-  c->last_pres[0] = hs[2];
-  c->last_pres[1] = hs[3];
-  c->last_pres[2] = hs[4];
-  double bnorm = sqrt(bb);
-  double target = rtol * (bnorm > 0.0 ? bnorm : 1.0);
-  int it = 0;
-  if (!(sqrt(rr) <= target)) {
+  launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [20]=rr0 [21]=bb [22..24]=residual sums
+  // at least one PCG iteration is done; the host reads the residual after each
+  // iteration (one synchronisation per iteration, none before the first)
+  vcycle(c, O, r, z);
+  hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
+  launch_finalize(c, nb1, 1, S_RZ, 3);
+  hipLaunchKernelGGL(k_copy_vec, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, z, d);
+  double hs[32];
+  double rr = 0.0, bnorm = 1.0, target = 0.0;
+  int it;
+  for (it = 1; it <= maxit; ++it) {
+    timer_begin(c, T_PAPPLY);
+    hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
+    timer_end(c, T_PAPPLY);
+    launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
+    hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, q, c->partials,
+                       c->pstride);
+    launch_finalize(c, nb1, 1, S_RR, 0);
+    HFDIB_CHECK_LAUNCH(c, "pcg iteration");
+    HFDIB_CHECK(c, hipMemcpyAsync(hs, S, 25 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+    HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+    if (it == 1) {
+      double bb = hs[S_BB + 17];
+      bnorm = sqrt(bb) > 0.0 ? sqrt(bb) : 1.0;
+      target = rtol * bnorm;
+      c->last_pres[0] = hs[22];
+      c->last_pres[1] = hs[23];
+      c->last_pres[2] = hs[24];
+    }
+    rr = hs[S_RR];
+    if (!std::isfinite(rr)) {
+      c->err = "non-finite residual in the pressure solve";
+      timer_end(c, T_PSOLVE);
+      return HFDIB_EDIVERGED;
+    }
+    if (sqrt(rr) <= target) break;
+    if (it == maxit) break;
     vcycle(c, O, r, z);
     hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
-    launch_finalize(c, nb1, 1, S_RZ, 3);
-    hipLaunchKernelGGL(k_copy_vec, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, z, d);
-    for (it = 1; it <= maxit; ++it) {
-      timer_begin(c, T_PAPPLY);
-      hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
-      timer_end(c, T_PAPPLY);
-      launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
-      hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, q, c->partials,
-                         c->pstride);
-      launch_finalize(c, nb1, 1, S_RR, 0);
-      HFDIB_CHECK_LAUNCH(c, "pcg iteration");
-      HFDIB_CHECK(c, hipMemcpyAsync(hs, S + S_RR, sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
-      HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
-      rr = hs[0];
-      if (!std::isfinite(rr)) {
-        c->err = "non-finite residual in the pressure solve";
-        timer_end(c, T_PSOLVE);
-        return HFDIB_EDIVERGED;
-      }
-      if (sqrt(rr) <= target) break;
-      vcycle(c, O, r, z);
-      hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
-      launch_finalize(c, nb1, 1, S_RZ, 2);
-      hipLaunchKernelGGL(k_xpby, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, z, d);
-    }
-    if (it > maxit) it = maxit;
+    launch_finalize(c, nb1, 1, S_RZ, 2);
+    hipLaunchKernelGGL(k_xpby, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, z, d);
   }
+  if (it > maxit) it = maxit;
   timer_end(c, T_PSOLVE);
   HFDIB_CHECK_LAUNCH(c, "pcg");
   if (iters) *iters = it;
-  if (relres) *relres = sqrt(rr) / (bnorm > 0.0 ? bnorm : 1.0);
+  if (relres) *relres = sqrt(rr) / bnorm;
   return HFDIB_OK;
 }
 

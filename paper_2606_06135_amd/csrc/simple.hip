@@ -11,9 +11,12 @@ struct Mom {
   const double* phi[3];
   const double* nut;
   const double* k;
+  const double* w;
+  const double* dw;
   const uint8_t* flags;
   const double* uib[3];
-  const double* grad[9];  // grad[i*3+j] = d u_j / d x_i
+  double* F1;  // SST blending of the previous iterate (written by the assembly)
+  double* kw;  // grad k . grad omega of the previous iterate (SST)
 };
 
 __device__ __forceinline__ double nut_wall(const Params& P, double yp) {
@@ -28,15 +31,6 @@ __device__ __forceinline__ double anb_coef(const Params& P, double gP, double gN
   return 0.5 * (gP + gN) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
 }
 
-// Gauss face value of velocity component cc on a domain face
-__device__ __forceinline__ double u_bface(const Params& P, int cc, int d, int s, bool solid, double uP) {
-  if (solid) return uP;
-  int kind = face_kind(P, d, s);
-  if (kind == HFDIB_BC_INLET) return P.u_in[cc];
-  if (kind == HFDIB_BC_NOSLIP) return 0.0;
-  if (kind == HFDIB_BC_SLIP) return cc == d ? 0.0 : uP;
-  return uP;
-}
 __device__ __forceinline__ double p_bface(const Params& P, int d, int s, bool solid, double pP) {
   if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !solid) return 0.0;
   return pP;
@@ -83,9 +77,8 @@ __global__ void k_init_cells(Params P, const double* lam, const double* us0, con
 // high face of its cell and, on the low domain boundary, the low face.
 __global__ void k_interp_flux(Params P, const double* v0, const double* v1, const double* v2, const uint8_t* flags,
                               double* phx, double* phy, double* phz) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   const double* v[3] = {v0, v1, v2};
@@ -177,14 +170,45 @@ __global__ void k_wall_pre(Params P, int nw, const int* wall_cells, const double
 }
 
 // ---------------------------------------------------------------- momentum
+// Neighbour coefficients of a momentum row at an active cell: anb[q] for the
+// faces q = 2d + (s > 0) in the order W, E, S, N, B, T, bit q of the returned
+// mask set for interior faces (0 and clear on domain faces and beyond dim).
+// Loops are unrolled over three directions so that every index is static.
+__device__ __forceinline__ unsigned mom_anb(const Params& P, const Mom& M, double nuP, int i, int j, int k,
+                                            long long c, double (&anb)[6]) {
+  unsigned vm = 0u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sh = 0; sh < 2; ++sh) {
+      const int s = sh ? 1 : -1, q = 2 * d + sh;
+      anb[q] = 0.0;
+      if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
+        long long n = c + s * stride(P, d);
+        anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, outward_flux(P, M.phi, d, s, i, j, k));
+        vm |= 1u << q;
+      }
+    }
+  return vm;
+}
+// sum over interior faces of anb * x_nb, faces in the order W, E, S, N, B, T
+__device__ __forceinline__ double nb_sum(const Params& P, const double (&anb)[6], unsigned vm, const double* x,
+                                         long long c) {
+  double nb = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if (vm & (1u << q)) nb += anb[q] * x[c + ((q & 1) ? 1 : -1) * stride(P, q >> 1)];
+  return nb;
+}
+
 // Assembly of the relaxed momentum rows with the explicit IB source
 // (discrete f_ib = alpha [M(u~) + grad p]), plus the normalised-residual sums
 // of the rows that are solved (alpha_u = 0).
 __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
                                const double* means, double* part, long long pstride) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  double wmx = 0.0;  // max of omega/eps of the previous iterate over boundary and free-stream cells
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   bool act = i < P.nx && j < P.ny;
   double red[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (act) {
@@ -193,28 +217,19 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
     bool solid = fl & F_SOLID;
     double nuP = P.nu + M.nut[c];
     double anb[6];
-    long long nbi[6];
+    unsigned vm = mom_anb(P, M, nuP, i, j, k, c, anb);
     double aP = 0.0;
-    // interior neighbour coefficients, faces in the order W, E, S, N, B, T
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        int q = 2 * d + (s > 0);
-        if (on_bnd(P, d, s, i, j, k)) {
-          anb[q] = 0.0;
-          nbi[q] = c;
-          continue;
-        }
-        long long n = c + s * stride(P, d);
-        double F = outward_flux(P, M.phi, d, s, i, j, k);
-        anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, F);
-        nbi[q] = n;
-        aP += anb[q];
-      }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (vm & (1u << q)) aP += anb[q];
     // Dirichlet domain faces (inlet, no-slip) of cells with lambda = 0
     double bsrc[3] = {0.0, 0.0, 0.0};
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        if (!on_bnd(P, d, s, i, j, k) || solid) continue;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int sh = 0; sh < 2; ++sh) {
+        const int s = sh ? 1 : -1;
+        if (d >= P.dim || !on_bnd(P, d, s, i, j, k) || solid) continue;
         int kind = face_kind(P, d, s);
         if (kind != HFDIB_BC_INLET && kind != HFDIB_BC_NOSLIP) continue;
         double Gb = nuP;
@@ -232,7 +247,9 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
         double mf = -F;
         double a = Gb * P.area[d] / (0.5 * P.delta[d]) + (mf > 0.0 ? mf : 0.0);
         aP += a;
-        for (int cc = 0; cc < P.dim; ++cc) {
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          if (cc >= P.dim) continue;
           double ubv = kind == HFDIB_BC_INLET ? P.u_in[cc] : 0.0;
           bsrc[cc] += a * ubv;
         }
@@ -242,23 +259,33 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
     aPr_out[c] = aPr;
     bool alpha = fl & F_ALPHA_U;
     double* rhs[3] = {rhs0, rhs1, rhs2};
-    for (int cc = 0; cc < P.dim; ++cc) {
-      // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      if (cc >= P.dim) continue;
+      // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f, the
+      // face gradient being the mean of the two cell (Gauss) gradients
       double T = 0.0;
-      for (int d = 0; d < P.dim; ++d)
-        for (int s = -1; s <= 1; s += 2) {
-          const double* G = M.grad[cc * 3 + d];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d >= P.dim) continue;
+        double GP = gradu(P, M.u, solid, cc, d, i, j, k, c);
+#pragma unroll
+        for (int sh = 0; sh < 2; ++sh) {
+          const int s = sh ? 1 : -1;
           double nuf, gf;
           if (on_bnd(P, d, s, i, j, k)) {
             nuf = nuP;
-            gf = G[c];
+            gf = GP;
           } else {
             long long n = c + s * stride(P, d);
+            int in = i + (d == 0 ? s : 0), jn = j + (d == 1 ? s : 0), kn = k + (d == 2 ? s : 0);
+            double GN = gradu(P, M.u, (M.flags[n] & F_SOLID) != 0, cc, d, in, jn, kn, n);
             nuf = 0.5 * (nuP + (P.nu + M.nut[n]));
-            gf = 0.5 * (G[c] + G[n]);
+            gf = 0.5 * (GP + GN);
           }
           T += (double)s * P.area[d] * nuf * gf;
         }
+      }
       double b0 = T + bsrc[cc];
       double g = gradp_V(P, M.p, fl, cc, i, j, k, c);
       const double* u = M.u[cc];
@@ -268,9 +295,10 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
       if (alpha) {
         const double* ub = M.uib[cc];
         double nbt = 0.0;
-        for (int q = 0; q < 2 * P.dim; ++q) {
-          if (nbi[q] == c) continue;
-          long long n = nbi[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          if (!(vm & (1u << q))) continue;
+          long long n = c + ((q & 1) ? 1 : -1) * stride(P, q >> 1);
           double ut = (M.flags[n] & F_ALPHA_U) ? ub[n] : u[n];
           nbt += anb[q] * ut;
         }
@@ -282,9 +310,10 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
       rhs[cc][c] = rh;
       if (!alpha) {
         double nb = 0.0, one = 0.0;
-        for (int q = 0; q < 2 * P.dim; ++q) {
-          if (nbi[q] == c) continue;
-          nb += anb[q] * u[nbi[q]];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          if (!(vm & (1u << q))) continue;
+          nb += anb[q] * u[c + ((q & 1) ? 1 : -1) * stride(P, q >> 1)];
           one += anb[q];
         }
         double Ax = aPr * uo - nb;
@@ -294,45 +323,59 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
         red[3 * cc + 2] = fabs(rh - Axb);
       }
     }
+    // turbulence inputs of the previous iterate (k, omega unchanged until the
+    // turbulence stage): SST blending F1 and grad k . grad omega; omega maximum
+    if (P.model == HFDIB_KOMEGA_SST) {
+      double kk = M.k[c], ww = M.w[c];
+      double gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d >= P.dim) continue;
+        gk[d] = ggrad(P, M.k, c, d, i, j, k, sc_bface(P, d, +1, solid, kk, P.k_in), sc_bface(P, d, -1, solid, kk, P.k_in));
+        gw[d] = ggrad(P, M.w, c, d, i, j, k, sc_bface(P, d, +1, solid, ww, P.w_in), sc_bface(P, d, -1, solid, ww, P.w_in));
+      }
+      double kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
+      double dwc = M.dw[c];
+      double bs = P.Cmu;
+      double cd = 2.0 * P.sigma_w2 / ww * kw;
+      cd = cd > P.cd_floor ? cd : P.cd_floor;
+      double a = sqrt(kk) / (bs * ww * dwc);
+      double bb = 500.0 * P.nu / (dwc * dwc * ww);
+      double m1 = a > bb ? a : bb;
+      double m2 = 4.0 * P.sigma_w2 * kk / (cd * dwc * dwc);
+      double arg1 = m1 < m2 ? m1 : m2;
+      double a2 = arg1 * arg1;
+      M.F1[c] = tanh(a2 * a2);
+      M.kw[c] = kw;
+    }
+    if (P.model != HFDIB_LAMINAR && !(fl & F_IC)) wmx = M.w[c];
   }
   block_sums_store<9>(red, part, pstride, block_linear());
+  if (P.model != HFDIB_LAMINAR) {
+    __shared__ double lmax[4];
+    double m = wave_max(wmx);
+    int tid = threadIdx.x + blockDim.x * threadIdx.y;
+    if ((tid & 63) == 0) lmax[tid >> 6] = m;
+    __syncthreads();
+    if (tid == 0) part[9 * pstride + block_linear()] = fmax(fmax(lmax[0], lmax[1]), fmax(lmax[2], lmax[3]));
+  }
 }
 
 // one colour of a red-black Gauss-Seidel sweep over the three components
 __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
                             const double* aPr, double* u0, double* u1, double* u2, int color) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   if (((i + j + k) & 1) != color) return;
   long long c = cidx(P, i, j, k);
   double nuP = P.nu + M.nut[c];
   double anb[6];
-  long long nbi[6];
-  for (int d = 0; d < P.dim; ++d)
-    for (int s = -1; s <= 1; s += 2) {
-      int q = 2 * d + (s > 0);
-      if (on_bnd(P, d, s, i, j, k)) {
-        anb[q] = 0.0;
-        nbi[q] = c;
-        continue;
-      }
-      long long n = c + s * stride(P, d);
-      anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, outward_flux(P, M.phi, d, s, i, j, k));
-      nbi[q] = n;
-    }
+  unsigned vm = mom_anb(P, M, nuP, i, j, k, c, anb);
   double a = aPr[c];
-  double* uu[3] = {u0, u1, u2};
-  const double* rr[3] = {rhs0, rhs1, rhs2};
-  for (int cc = 0; cc < P.dim; ++cc) {
-    double nb = 0.0;
-    for (int q = 0; q < 2 * P.dim; ++q) {
-      if (nbi[q] == c) continue;
-      nb += anb[q] * uu[cc][nbi[q]];
-    }
-    uu[cc][c] = (rr[cc][c] + nb) / a;
-  }
+  u0[c] = (rhs0[c] + nb_sum(P, anb, vm, u0, c)) / a;
+  u1[c] = (rhs1[c] + nb_sum(P, anb, vm, u1, c)) / a;
+  if (P.dim == 3) u2[c] = (rhs2[c] + nb_sum(P, anb, vm, u2, c)) / a;
 }
 
 // u <- u + alpha_u (u_ib - u) on forced cells (list kernels: boundary cells with
@@ -351,39 +394,24 @@ __global__ void k_correct_list(Params P, int n, const int* cells, const uint8_t*
 // HbyA = (sum a_nb u_nb + rhs + V grad p_old) / a'_P and rAU = V / a'_P
 __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
                        const double* aPr, double* h0, double* h1, double* h2, double* rAU) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   double nuP = P.nu + M.nut[c];
   uint8_t fl = M.flags[c];
   double anb[6];
-  long long nbi[6];
-  for (int d = 0; d < P.dim; ++d)
-    for (int s = -1; s <= 1; s += 2) {
-      int q = 2 * d + (s > 0);
-      if (on_bnd(P, d, s, i, j, k)) {
-        anb[q] = 0.0;
-        nbi[q] = c;
-        continue;
-      }
-      long long n = c + s * stride(P, d);
-      anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, outward_flux(P, M.phi, d, s, i, j, k));
-      nbi[q] = n;
-    }
+  unsigned vm = mom_anb(P, M, nuP, i, j, k, c, anb);
   double a = aPr[c];
   const double* rr[3] = {rhs0, rhs1, rhs2};
   double* hh[3] = {h0, h1, h2};
   // forced cells: no pressure term in the momentum row (f_ib contains +grad p),
   // hence no pressure-velocity coupling (rAU = 0)
   bool forced = fl & F_ALPHA_U;
-  for (int cc = 0; cc < P.dim; ++cc) {
-    double nb = 0.0;
-    for (int q = 0; q < 2 * P.dim; ++q) {
-      if (nbi[q] == c) continue;
-      nb += anb[q] * M.u[cc][nbi[q]];
-    }
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    if (cc >= P.dim) continue;
+    double nb = nb_sum(P, anb, vm, M.u[cc], c);
     double H = forced ? nb + rr[cc][c] : nb + rr[cc][c] + gradp_V(P, M.p, fl, cc, i, j, k, c);
     hh[cc][c] = H / a;
   }
@@ -396,9 +424,8 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
 __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const double* h2, const double* lam,
                            const uint8_t* flags, const double* pold, double* phx, double* phy, double* phz,
                            double* rhs_p) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   const double* hv[3] = {h0, h1, h2};
@@ -445,9 +472,8 @@ __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const d
 // flux correction with the solved pressure and relaxation of p (into pnew)
 __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, const double* pold,
                                const uint8_t* flags, double* phx, double* phy, double* phz, double* pnew) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   double* ph[3] = {phx, phy, phz};
@@ -474,9 +500,8 @@ __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, 
 __global__ void k_vel_update(Params P, const double* h0, const double* h1, const double* h2, const double* aPr,
                              const double* pnew, const uint8_t* flags, const double* ub0, const double* ub1,
                              const double* ub2, double* u0, double* u1, double* u2, double* p) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   uint8_t fl = flags[c];
@@ -513,8 +538,11 @@ static Mom make_mom(hfdib_ctx* c) {
   M.p = c->p;
   M.nut = c->nut;
   M.k = c->k;
+  M.w = c->w;
+  M.dw = c->dw;
   M.flags = c->flags;
-  for (int q = 0; q < 9; ++q) M.grad[q] = c->grad[q];
+  M.F1 = c->F1;
+  M.kw = c->t2;
   return M;
 }
 
@@ -543,7 +571,6 @@ int init_state(hfdib_ctx* c) {
                      c->u[0], c->u[1], c->u[2], c->p, c->k, c->w, c->nut);
   hipLaunchKernelGGL(k_interp_flux, grid3(P), block3(), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags,
                      c->phi[0], c->phi[1], c->phi[2]);
-  for (int q = 0; q < 9; ++q) hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->grad[q], 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->kib, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->wib, 0.0);
   for (int q = 0; q < 3; ++q)
@@ -552,7 +579,6 @@ int init_state(hfdib_ctx* c) {
     hipLaunchKernelGGL(k_init_ib, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_ic, c->ic_cells,
                        c->us[0], c->us[1], c->us[2], c->uib[0], c->uib[1], c->uib[2], c->kib);
   HFDIB_CHECK_LAUNCH(c, "init state");
-  c->grad_stale = 1;
   return HFDIB_OK;
 }
 
@@ -583,10 +609,6 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   int st;
-  if (c->grad_stale) {
-    if ((st = gradient_only(c)) != HFDIB_OK) return st;
-    c->grad_stale = 0;
-  }
   timer_begin(c, T_ITER);
   // means of the previous iterate (residual normalisation)
   hipLaunchKernelGGL(k_sums5, dim3(nb1), dim3(NTHREADS), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->p, c->k,
@@ -608,6 +630,9 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                      S + SC_MEANS, c->partials, c->pstride);
   timer_end(c, T_MOMASM);
   launch_finalize(c, (int)nblk3, 9, SC_RESSUM, 0);
+  if (P.model != HFDIB_LAMINAR) {
+    launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4, 1.0, 9);  // partial row 9: omega maxima
+  }
   for (int s = 0; s < P.n_sweeps; ++s)
     for (int color = 0; color < 2; ++color) {
       timer_begin(c, T_MOMSWEEP);
@@ -645,10 +670,11 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   c->p = c->pnew;
   c->pnew = tmp;
   HFDIB_CHECK_LAUNCH(c, "velocity update");
-  // 6. turbulence (or, laminar, the gradient the next momentum predictor uses)
-  if (P.model != HFDIB_LAMINAR) st = turbulence_stage(c);
-  else st = gradient_only(c);
-  if (st != HFDIB_OK) return st;
+  // 6. turbulence
+  if (P.model != HFDIB_LAMINAR) {
+    st = turbulence_stage(c);
+    if (st != HFDIB_OK) return st;
+  }
   hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, c->stream, S, P.dim, P.model != HFDIB_LAMINAR ? 1 : 0,
                      S + SC_RES);
   timer_end(c, T_ITER);

@@ -7,114 +7,25 @@
 
 namespace hfdib {
 
-struct Turb {
+struct U3 {
   const double* u[3];
-  const double* phi[3];
-  const uint8_t* flags;
-  double* grad[9];
-  double* S2;
-  double* Pk;
-  double* F1;
-  double* kw;  // grad k . grad omega (SST)
-  const double* k;
-  const double* w;
-  const double* nut;
-  const double* dw;
 };
 
-__device__ __forceinline__ double sc_bface(const Params& P, int d, int s, bool solid, double vP, double vin) {
-  if (face_kind(P, d, s) == HFDIB_BC_INLET && !solid) return vin;
-  return vP;
-}
-__device__ __forceinline__ double u_bface_t(const Params& P, int cc, int d, int s, bool solid, double uP) {
-  if (solid) return uP;
-  int kind = face_kind(P, d, s);
-  if (kind == HFDIB_BC_INLET) return P.u_in[cc];
-  if (kind == HFDIB_BC_NOSLIP) return 0.0;
-  if (kind == HFDIB_BC_SLIP) return cc == d ? 0.0 : uP;
-  return uP;
+__device__ __forceinline__ void cell_ijk(const Params& P, long long c, int& i, int& j, int& k) {
+  i = (int)(c % P.nx);
+  long long r = c / P.nx;
+  j = (int)(r % P.ny);
+  k = (int)(r / P.ny);
 }
 
-// (psi_+ - psi_-)/delta_d with linear face interpolation
-__device__ __forceinline__ double ggrad(const Params& P, const double* a, long long c, int d, int i, int j, int k,
-                                       double fb_p, double fb_m) {
-  long long st = stride(P, d);
-  double fp = on_bnd(P, d, +1, i, j, k) ? fb_p : 0.5 * (a[c] + a[c + st]);
-  double fm = on_bnd(P, d, -1, i, j, k) ? fb_m : 0.5 * (a[c - st] + a[c]);
-  return (fp - fm) / P.delta[d];
-}
-
-__device__ __forceinline__ void atomic_max_pos(double* addr, double v) {
-  // positive doubles order like their bit patterns
-  atomicMax((unsigned long long*)addr, (unsigned long long)__double_as_longlong(v));
-}
-
-// gradient tensor of u, 2 S:S, production, SST blending F1 and the maximum of
-// omega (eps) over boundary and free-stream cells
-__global__ void k_turb_grad(Params P, Turb T, double* wmax) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
-  double mx = 0.0;
-  bool act = i < P.nx && j < P.ny;
-  if (act) {
-    long long c = cidx(P, i, j, k);
-    uint8_t fl = T.flags[c];
-    bool solid = fl & F_SOLID;
-    double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    for (int jj = 0; jj < P.dim; ++jj) {
-      const double* u = T.u[jj];
-      double uP = u[c];
-      for (int ii = 0; ii < P.dim; ++ii)
-        G[ii][jj] = ggrad(P, u, c, ii, i, j, k, u_bface_t(P, jj, ii, +1, solid, uP),
-                          u_bface_t(P, jj, ii, -1, solid, uP));
-    }
-    for (int ii = 0; ii < P.dim; ++ii)
-      for (int jj = 0; jj < P.dim; ++jj) T.grad[ii * 3 + jj][c] = G[ii][jj];
-    double S2 = 0.0;
-    for (int ii = 0; ii < 3; ++ii)
-      for (int jj = 0; jj < 3; ++jj) {
-        double sij = 0.5 * (G[ii][jj] + G[jj][ii]);
-        S2 = S2 + 2.0 * sij * sij;
-      }
-    T.S2[c] = S2;
-    if (P.model != HFDIB_LAMINAR) {
-      double kk = T.k[c], ww = T.w[c];
-      double Gp = T.nut[c] * S2;
-      if (P.model == HFDIB_KOMEGA_SST) {
-        double gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
-        for (int d = 0; d < P.dim; ++d) {
-          gk[d] = ggrad(P, T.k, c, d, i, j, k, sc_bface(P, d, +1, solid, kk, P.k_in),
-                        sc_bface(P, d, -1, solid, kk, P.k_in));
-          gw[d] = ggrad(P, T.w, c, d, i, j, k, sc_bface(P, d, +1, solid, ww, P.w_in),
-                        sc_bface(P, d, -1, solid, ww, P.w_in));
-        }
-        double kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
-        double dw = T.dw[c];
-        double bs = P.Cmu;
-        double cd = 2.0 * P.sigma_w2 / ww * kw;
-        cd = cd > P.cd_floor ? cd : P.cd_floor;
-        double a = sqrt(kk) / (bs * ww * dw);
-        double bb = 500.0 * P.nu / (dw * dw * ww);
-        double m1 = a > bb ? a : bb;
-        double m2 = 4.0 * P.sigma_w2 * kk / (cd * dw * dw);
-        double arg1 = m1 < m2 ? m1 : m2;
-        double a2 = arg1 * arg1;
-        T.F1[c] = tanh(a2 * a2);
-        T.kw[c] = kw;
-        double lim = P.c_lim * bs * kk * ww;
-        T.Pk[c] = Gp < lim ? Gp : lim;
-      } else {
-        T.Pk[c] = Gp;
-      }
-      if (!(fl & F_IC)) mx = ww;
-    }
-  }
-  if (P.model != HFDIB_LAMINAR) {
-    double m = wave_max(mx);
-    int tid = threadIdx.x + blockDim.x * threadIdx.y;
-    if ((tid & 63) == 0 && m > 0.0) atomic_max_pos(wmax, m);
-  }
+// production of k by the closure (k-eps: nu_t 2S:S; SST: limited by
+// c_lim beta* k omega), from the current velocity and the k, omega, nu_t
+// entering the turbulence stage
+__device__ __forceinline__ double model_production(const Params& P, double S2, double nut, double kk, double ww) {
+  double Gp = nut * S2;
+  if (P.model != HFDIB_KOMEGA_SST) return Gp;
+  double lim = P.c_lim * P.Cmu * kk * ww;
+  return Gp < lim ? Gp : lim;
 }
 
 __device__ __forceinline__ double omega_ib(const Params& P, double yp, double y, double ut) {
@@ -129,26 +40,26 @@ __device__ __forceinline__ double prod_ib(const Params& P, double yp, double Gk,
 
 // boundary cells (mode 0) and domain-wall cells (mode 1): imposed omega/eps and
 // production; the omega field takes its fixed value on these rows
-struct Grad9 {
-  const double* g[9];
-};
-
 __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, const double* nv, const double* ypl,
-                          const double* utl, const double* kold, Grad9 grad, double* Pk, double* wib, double* w) {
+                          const double* utl, const uint8_t* flags, U3 U, const double* kold, const double* nut,
+                          double* Pk, double* wib, double* w) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= n) return;
   int c = cells[b];
+  int i, j, k;
+  cell_ijk(P, c, i, j, k);
+  double G[3][3];
+  gradu_all(P, U.u, flags[c] & F_SOLID, i, j, k, c, G);
   double yp = ypl[b], ut = utl[b], y = yv[b];
   double om = omega_ib(P, yp, y, ut);
-  double val = P.model == HFDIB_KEPS ? P.Cmu * kold[c] * om : om;
+  double kk = kold[c];
+  double val = P.model == HFDIB_KEPS ? P.Cmu * kk * om : om;
   double ng[3] = {0.0, 0.0, 0.0};
   for (int jj = 0; jj < 3; ++jj)
-    for (int ii = 0; ii < 3; ++ii) {
-      double g = (ii < P.dim && jj < P.dim) ? grad.g[ii * 3 + jj][c] : 0.0;
-      ng[jj] += nv[3 * b + ii] * g;
-    }
+    for (int ii = 0; ii < 3; ++ii) ng[jj] += nv[3 * b + ii] * G[ii][jj];
   double ng2 = ng[0] * ng[0] + ng[1] * ng[1] + ng[2] * ng[2];
-  Pk[c] = prod_ib(P, yp, Pk[c], ng2);
+  double Pm = model_production(P, strain2(G), nut[c], kk, w[c]);
+  Pk[c] = prod_ib(P, yp, Pm, ng2);
   wib[c] = val;
   w[c] = val;
 }
@@ -179,24 +90,48 @@ __device__ __forceinline__ double gam(const Params& P, int eq, long long c, cons
 
 struct Scal {
   const double* phi[3];
+  const double* u[3];
   const uint8_t* flags;
   const double* nut;
   const double* F1;
   const double* kw;
-  const double* Pk;
+  double* Pk;  // closure production on free rows (written by the omega assembly)
   const double* k;  // k_old
   double* w;        // omega/eps (fixed values already in place)
   const double* wib;
   const double* kib;
 };
 
+// neighbour coefficients of a scalar row (faces W, E, S, N, B, T; bit q of the
+// returned mask set for interior faces), loops unrolled for static indexing
+__device__ __forceinline__ unsigned scal_anb(const Params& P, const Scal& S, int eq, double gP, int i, int j, int k,
+                                             long long c, double (&anb)[6]) {
+  unsigned vm = 0u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sh = 0; sh < 2; ++sh) {
+      const int s = sh ? 1 : -1, q = 2 * d + sh;
+      anb[q] = 0.0;
+      if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
+        long long n = c + s * stride(P, d);
+        double mf = -outward_flux(P, S.phi, d, s, i, j, k);
+        anb[q] = 0.5 * (gP + gam(P, eq, n, S.nut, S.F1)) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
+        vm |= 1u << q;
+      }
+    }
+  return vm;
+}
+__device__ __forceinline__ long long nb_index(const Params& P, int q, long long c) {
+  return c + ((q & 1) ? 1 : -1) * stride(P, q >> 1);
+}
+
 // assembly of the omega (eps, eq = 0) or k (eq = 1) rows; rhs -> rhs_out,
 // relaxed diagonal -> aPr_out; residual sums of the solved rows
 __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, const double* xmean,
                                   double* part, long long pstride) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   double red[3] = {0, 0, 0};
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
@@ -204,28 +139,19 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     bool solid = fl & F_SOLID;
     double gP = gam(P, eq, c, S.nut, S.F1);
     double anb[6];
-    long long nbi[6];
+    unsigned vm = scal_anb(P, S, eq, gP, i, j, k, c, anb);
     double aP = 0.0;
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        int q = 2 * d + (s > 0);
-        if (on_bnd(P, d, s, i, j, k)) {
-          anb[q] = 0.0;
-          nbi[q] = c;
-          continue;
-        }
-        long long n = c + s * stride(P, d);
-        double F = outward_flux(P, S.phi, d, s, i, j, k);
-        double mf = -F;
-        anb[q] = 0.5 * (gP + gam(P, eq, n, S.nut, S.F1)) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
-        nbi[q] = n;
-        aP += anb[q];
-      }
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      if (vm & (1u << q)) aP += anb[q];
     double vin = eq == 0 ? P.w_in : P.k_in;
     double b0 = 0.0;
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        if (!on_bnd(P, d, s, i, j, k) || solid || face_kind(P, d, s) != HFDIB_BC_INLET) continue;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int sh = 0; sh < 2; ++sh) {
+        const int s = sh ? 1 : -1;
+        if (d >= P.dim || !on_bnd(P, d, s, i, j, k) || solid || face_kind(P, d, s) != HFDIB_BC_INLET) continue;
         double F = outward_flux(P, S.phi, d, s, i, j, k);
         double mf = -F;
         double a = gP * P.area[d] / (0.5 * P.delta[d]) + (mf > 0.0 ? mf : 0.0);
@@ -239,15 +165,24 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     bool skip;
     if (eq == 0) {
       double wo = S.w[c];
+      double Pc;
+      if (fl & F_ALPHA_W) {
+        Pc = S.Pk[c];
+      } else {
+        double G[3][3];
+        gradu_all(P, S.u, solid, i, j, k, c, G);
+        Pc = model_production(P, strain2(G), S.nut[c], kold, wo);
+        S.Pk[c] = Pc;
+      }
       if (P.model == HFDIB_KEPS) {
         aP = aP + P.C2 * wo / kold * V;
-        b0 = b0 + P.C1 * S.Pk[c] * wo / kold * V;
+        b0 = b0 + P.C1 * Pc * wo / kold * V;
       } else {
         double f = S.F1[c];
         double beta = f * P.beta_1 + (1.0 - f) * P.beta_2;
         double gamma = f * P.gamma_1 + (1.0 - f) * P.gamma_2;
         aP = aP + beta * wo * V;
-        b0 = b0 + gamma * (wo / kold) * S.Pk[c] * V;
+        b0 = b0 + gamma * (wo / kold) * Pc * V;
         double CD = (1.0 - f) * 2.0 * P.sigma_w2 * S.kw[c] / wo;
         b0 = b0 + (CD > 0.0 ? CD * V : 0.0);
         aP = aP + (CD < 0.0 ? -CD / wo * V : 0.0);
@@ -269,9 +204,10 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       skip = fl & F_ALPHA_U;
       if (skip) {
         double nbt = 0.0;
-        for (int q = 0; q < 2 * P.dim; ++q) {
-          if (nbi[q] == c) continue;
-          long long n = nbi[q];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          if (!(vm & (1u << q))) continue;
+          long long n = nb_index(P, q, c);
           double kt = (S.flags[n] & F_ALPHA_U) ? S.kib[n] : S.k[n];
           nbt += anb[q] * kt;
         }
@@ -286,9 +222,10 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     if (!skip) {
       const double* xv = eq == 0 ? S.w : S.k;
       double nb = 0.0, one = 0.0;
-      for (int q = 0; q < 2 * P.dim; ++q) {
-        if (nbi[q] == c) continue;
-        nb += anb[q] * xv[nbi[q]];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        if (!(vm & (1u << q))) continue;
+        nb += anb[q] * xv[nb_index(P, q, c)];
         one += anb[q];
       }
       double Ax = aPr * x - nb;
@@ -305,24 +242,19 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 // are not updated
 __global__ void k_scalar_sweep(Params P, Scal S, int eq, const double* rhs, const double* aPr, double* x, int color,
                                uint8_t fixmask) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   if (((i + j + k) & 1) != color) return;
   long long c = cidx(P, i, j, k);
   if (S.flags[c] & fixmask) return;
   double gP = gam(P, eq, c, S.nut, S.F1);
+  double anb[6];
+  unsigned vm = scal_anb(P, S, eq, gP, i, j, k, c, anb);
   double nb = 0.0;
-  for (int d = 0; d < P.dim; ++d)
-    for (int s = -1; s <= 1; s += 2) {
-      if (on_bnd(P, d, s, i, j, k)) continue;
-      long long n = c + s * stride(P, d);
-      double F = outward_flux(P, S.phi, d, s, i, j, k);
-      double mf = -F;
-      double a = 0.5 * (gP + gam(P, eq, n, S.nut, S.F1)) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
-      nb += a * x[n];
-    }
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if (vm & (1u << q)) nb += anb[q] * x[nb_index(P, q, c)];
   x[c] = (rhs[c] + nb) / aPr[c];
 }
 
@@ -352,10 +284,12 @@ __global__ void k_kib(Params P, int nbc, const int* bc_cells, const uint8_t* fla
 
 // k <- k + alpha_k (k_ib - k), bounding, turbulent viscosity of the model
 // (in-solid cells 0); eps/omega is already bounded
-__global__ void k_turb_final(Params P, const uint8_t* flags, const double* kib, double* k, const double* w,
-                             const double* S2, const double* dw, double* nut) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  if (c >= P.N) return;
+__global__ void k_turb_final(Params P, const uint8_t* flags, U3 U, const double* kib, double* k, const double* w,
+                             const double* dw, double* nut) {
+  int i, j, kz;
+  tile_ijk(P, i, j, kz);
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, kz);
   uint8_t fl = flags[c];
   double kk = k[c];
   if (fl & F_ALPHA_U) kk = kk + 1.0 * (kib[c] - kk);
@@ -373,7 +307,9 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* kib, 
     double bb = 500.0 * P.nu / (d * d * ww);
     double arg2 = a > bb ? a : bb;
     double F2 = tanh(arg2 * arg2);
-    double den1 = P.a1 * ww, den2 = sqrt(S2[c]) * F2;
+    double G[3][3];
+    gradu_all(P, U.u, fl & F_SOLID, i, j, kz, c, G);
+    double den1 = P.a1 * ww, den2 = sqrt(strain2(G)) * F2;
     nt = P.a1 * kk / (den1 > den2 ? den1 : den2);
   }
   if (fl & F_IC) nt = 0.0;
@@ -432,34 +368,6 @@ __global__ void k_set1(double* a, double v) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *a = v;
 }
 
-static Turb make_turb(hfdib_ctx* c) {
-  Turb T;
-  for (int q = 0; q < 3; ++q) {
-    T.u[q] = c->u[q];
-    T.phi[q] = c->phi[q];
-  }
-  T.flags = c->flags;
-  for (int q = 0; q < 9; ++q) T.grad[q] = c->grad[q];
-  T.S2 = c->S2;
-  T.Pk = c->Pk;
-  T.F1 = c->F1;
-  T.kw = c->t2;
-  T.k = c->k;
-  T.w = c->w;
-  T.nut = c->nut;
-  T.dw = c->dw;
-  return T;
-}
-
-int gradient_only(hfdib_ctx* c) {
-  Params P = c->P;
-  P.model = HFDIB_LAMINAR;
-  Turb T = make_turb(c);
-  hipLaunchKernelGGL(k_turb_grad, grid3(P), block3(), 0, c->stream, P, T, c->scal + SCAL_PCG + SC_WMAX);
-  HFDIB_CHECK_LAUNCH(c, "gradient");
-  return HFDIB_OK;
-}
-
 int turbulence_stage(hfdib_ctx* c) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3();
@@ -467,26 +375,28 @@ int turbulence_stage(hfdib_ctx* c) {
   int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   double* wmax = S + SC_WMAX;
-  hipLaunchKernelGGL(k_set1, dim3(1), dim3(64), 0, c->stream, wmax, 0.0);
-  Turb T = make_turb(c);
-  hipLaunchKernelGGL(k_turb_grad, g, b, 0, c->stream, P, T, wmax);
-  Grad9 G9;
-  for (int q = 0; q < 9; ++q) G9.g[q] = c->grad[q];
-  // imposed omega/eps and production on boundary, wall and in-solid cells
+  U3 U;
+  for (int q = 0; q < 3; ++q) U.u[q] = c->u[q];
+  // imposed omega/eps and production on boundary, wall and in-solid cells (the
+  // maximum of omega/eps over cells outside the in-solid group was reduced in the momentum
+  // assembly, before any omega/eps value changed)
   if (c->n_bc > 0)
     hipLaunchKernelGGL(k_turb_ib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
-                       c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau, c->k, G9, c->Pk, c->wib, c->w);
+                       c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau, c->flags, U, c->k, c->nut, c->Pk, c->wib, c->w);
   if (c->n_wall > 0)
     hipLaunchKernelGGL(k_turb_ib, dim3(nblocks1(c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_wall,
-                       c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau, c->k, G9, c->Pk,
-                       c->wib, c->w);
+                       c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau, c->flags, U, c->k, c->nut,
+                       c->Pk, c->wib, c->w);
   if (c->n_ic > 0)
     hipLaunchKernelGGL(k_turb_ic, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, c->n_ic, c->ic_cells,
                        wmax, c->Pk, c->wib, c->w);
   hipLaunchKernelGGL(k_sum1, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, c->w, c->partials, c->pstride);
   launch_finalize(c, nb1, 1, SC_MEANS + 5, 0, (double)P.N);
   Scal Sc;
-  for (int q = 0; q < 3; ++q) Sc.phi[q] = c->phi[q];
+  for (int q = 0; q < 3; ++q) {
+    Sc.phi[q] = c->phi[q];
+    Sc.u[q] = c->u[q];
+  }
   Sc.flags = c->flags;
   Sc.nut = c->nut;
   Sc.F1 = c->F1;
@@ -515,7 +425,7 @@ int turbulence_stage(hfdib_ctx* c) {
   for (int s = 0; s < P.n_sweeps; ++s)
     for (int color = 0; color < 2; ++color)
       hipLaunchKernelGGL(k_scalar_sweep, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, c->k, color, (uint8_t)0);
-  hipLaunchKernelGGL(k_turb_final, dim3(nb1), dim3(NTHREADS), 0, c->stream, P, c->flags, c->kib, c->k, c->w, c->S2,
+  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, U, c->kib, c->k, c->w,
                      c->dw, c->nut);
   if (c->n_bc > 0) {
     hipLaunchKernelGGL(k_nut_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
