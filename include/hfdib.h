@@ -82,7 +82,13 @@ typedef struct {
 typedef struct {
   int abi_version;      /* must equal HFDIB_ABI_VERSION */
   int model;            /* hfdib_model */
-  int precision;        /* hfdib_precision; MIXED is reserved (returns EINVAL) */
+  int precision;        /* hfdib_precision.  FP64: every step in FP64.  MIXED: the state, every
+                           assembly, defect, residual norm, reduction, the PCG vectors and dots and
+                           the log-law Newton stay FP64; the momentum and k, eps/omega red-black
+                           sweeps solve for an FP32 correction of the FP64 defect (coefficients
+                           from FP32 mirrors, x <- x + d in FP64) and the multigrid preconditioner
+                           (smoothing, transfers, coarse operators) runs in FP32.  The workspace
+                           size depends on this field. */
   int n_sweeps;         /* red-black Gauss-Seidel sweeps per transport solve (>= 1) */
   double nu;            /* kinematic viscosity (> 0) */
   double urf_u, urf_p, urf_t; /* under-relaxation of momentum, pressure, turbulence, in (0,1] */

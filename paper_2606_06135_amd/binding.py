@@ -111,7 +111,8 @@ def default_config():
     return cfg
 
 
-def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0, continuity="literal"):
+def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0, continuity="literal",
+                     precision="fp64"):
     """Grid descriptor and configuration from a case description (any object with
     the attributes of synth.CaseSpec)."""
     d = GridDesc()
@@ -133,6 +134,7 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
     c.recorrect = 1 if recorrect else 0
     c.bc_capacity = bc_capacity
     c.continuity = {"literal": 0, "weighted": 1}[continuity]
+    c.precision = {"fp64": 0, "mixed": 1}[precision]
     for n in _CONST_NAMES:
         if n in spec.constants:
             setattr(c, n, float(spec.constants[n]))

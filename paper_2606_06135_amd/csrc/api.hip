@@ -165,14 +165,44 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->partials = B.take<double>(16 * c->pstride);
   c->scal = B.take<double>(512);
   c->iscal = B.take<int>(64);
+  bool mixed = P.precision == HFDIB_MIXED;
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
-    L.r = B.take<double>(L.N);
-    L.z = B.take<double>(L.N);
-    L.diag = B.take<double>(L.N);
-    L.cx = B.take<double>((long long)(L.nx + 1) * L.ny * L.nz);
-    L.cy = B.take<double>((long long)L.nx * (L.ny + 1) * L.nz);
-    L.cz = B.take<double>((long long)L.nx * L.ny * (L.nz + 1));
+    long long fx = (long long)(L.nx + 1) * L.ny * L.nz, fy = (long long)L.nx * (L.ny + 1) * L.nz,
+              fz = (long long)L.nx * L.ny * (L.nz + 1);
+    L.r = L.z = L.diag = L.cx = L.cy = L.cz = nullptr;
+    L.r32 = L.z32 = L.diag32 = L.cx32 = L.cy32 = L.cz32 = nullptr;
+    if (mixed) {
+      L.r32 = B.take<float>(L.N);
+      L.z32 = B.take<float>(L.N);
+      L.diag32 = B.take<float>(L.N);
+      L.cx32 = B.take<float>(fx);
+      L.cy32 = B.take<float>(fy);
+      L.cz32 = B.take<float>(fz);
+    } else {
+      L.r = B.take<double>(L.N);
+      L.z = B.take<double>(L.N);
+      L.diag = B.take<double>(L.N);
+      L.cx = B.take<double>(fx);
+      L.cy = B.take<double>(fy);
+      L.cz = B.take<double>(fz);
+    }
+  }
+  // FP32 arrays of the mixed policy
+  for (int q = 0; q < 3; ++q) c->r32[q] = c->d32[q] = c->phi32[q] = nullptr;
+  c->a32 = c->nut32 = c->F1_32 = c->rAU32 = c->pr32 = c->pz32 = nullptr;
+  if (mixed) {
+    for (int q = 0; q < 3; ++q) c->r32[q] = B.take<float>(N);
+    for (int q = 0; q < 3; ++q) c->d32[q] = B.take<float>(N);
+    c->a32 = B.take<float>(N);
+    c->phi32[0] = B.take<float>((long long)(P.nx + 1) * P.ny * P.nz);
+    c->phi32[1] = B.take<float>((long long)P.nx * (P.ny + 1) * P.nz);
+    c->phi32[2] = B.take<float>((long long)P.nx * P.ny * (P.nz + 1));
+    c->nut32 = B.take<float>(N);
+    c->F1_32 = B.take<float>(N);
+    c->rAU32 = B.take<float>(N);
+    c->pr32 = B.take<float>(N);
+    c->pz32 = B.take<float>(N);
   }
   return B.off + 256;
 }
@@ -234,8 +264,8 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "continuity must be 0 or 1";
     return HFDIB_EINVAL;
   }
-  if (c->precision != HFDIB_FP64) {
-    *why = "only FP64 precision is available in this library version";
+  if (c->precision != HFDIB_FP64 && c->precision != HFDIB_MIXED) {
+    *why = "precision must be HFDIB_FP64 or HFDIB_MIXED";
     return HFDIB_EINVAL;
   }
   if (c->model != HFDIB_LAMINAR) {
@@ -310,6 +340,7 @@ static void fill_params(hfdib_ctx* c) {
   P.sqrtCmu = std::sqrt(g.Cmu);
   P.recorrect = g.recorrect;
   P.continuity = g.continuity;
+  P.precision = g.precision;
 }
 
 static int capacity_for(long long N, int requested) {
@@ -533,7 +564,7 @@ int hfdib_set_field(hfdib_ctx* c, int id, const double* src) {
   double* dst = field_ptr(c, id, &n);
   if (!dst) return HFDIB_EINVAL;
   HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "set_field");
-  return HFDIB_OK;
+  return hfdib::refresh_mirrors(c);
 }
 
 int hfdib_get_counts(hfdib_ctx* c, int* counts) {

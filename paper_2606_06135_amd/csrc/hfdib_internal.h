@@ -43,9 +43,12 @@ struct Params {
   double Cmu25, sqrtCmu;  // Cmu^(1/4), sqrt(Cmu) (host-computed)
   int recorrect;
   int continuity;
+  int precision;  // HFDIB_FP64 or HFDIB_MIXED
 };
 
 // Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).
+// FP64 storage under the FP64 policy, FP32 storage under the mixed policy (the
+// other set of pointers is null).
 struct Level {
   int nx, ny, nz;
   long long N;
@@ -55,6 +58,7 @@ struct Level {
   double* cy;    // nx*(ny+1)*nz
   double* cz;    // nx*ny*(nz+1)
   double* diag;  // N
+  float *r32, *z32, *cx32, *cy32, *cz32, *diag32;
 };
 
 struct Timers;
@@ -80,6 +84,12 @@ struct hfdib_ctx {
   uint8_t* flags;
   // --- face arrays
   double* phi[3];
+  // --- FP32 arrays of the mixed policy (null under FP64): defects and
+  // corrections of the stencil solves, mirrors of the sweep coefficients
+  // (relaxed diagonal, face fluxes, nu_t, SST blending), pressure smoother
+  // inputs (rAU) and the preconditioner residual / output
+  float *r32[3], *d32[3], *a32, *phi32[3], *nut32, *F1_32;
+  float *rAU32, *pr32, *pz32;
   // --- lists
   int cap;  // capacity of each list
   int *bc_cells, *ic_cells, *wall_cells;
@@ -142,7 +152,7 @@ int init_state(hfdib_ctx* c);
 int simple_step(hfdib_ctx* c, int it, double* res6_dev_slot);
 int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol,
                    int maxit, int* iters, double* relres, const double* xmean_dev);
-int mg_setup_levels(hfdib_ctx* c);
+int refresh_mirrors(hfdib_ctx* c);
 
 // deterministic reduction of `nval` rows of per-block partial sums into
 // ctx->scal[SCAL_PCG + out + v]; op selects a PCG scalar update (pressure.hip)

@@ -6,6 +6,10 @@
 // piecewise-constant transfer, rediscretised coarse operators).  The fine
 // level is matrix free (coefficients from rAU); coarse levels store face
 // coefficients.  All dot products are deterministic two-pass reductions.
+// Precision: the CG vectors, the operator apply, the residual and every dot
+// product are FP64.  The V-cycle is templated on its storage type: FP64, or
+// FP32 in the mixed policy (FP32 mirrors of rAU, of the residual and of every
+// coarse operator; the preconditioner output is read back by the FP64 CG).
 #include "device_common.h"
 
 #include <cmath>
@@ -18,23 +22,25 @@ enum {
 };
 
 // ---------------------------------------------------------------- fine level
-struct FineOp {
-  const double* rAU;
+template <typename T>
+struct FineOpT {
+  const T* rAU;
   const uint8_t* flags;
 };
+using FineOp = FineOpT<double>;
 
-__device__ __forceinline__ double fine_coef(const Params& P, const FineOp& O, long long c, int d, int s, int i,
-                                            int j, int k, long long* nb) {
+template <typename T>
+__device__ __forceinline__ T fine_coef(const Params& P, const FineOpT<T>& O, long long c, int d, int s, int i, int j,
+                                       int k, long long* nb) {
+  const T A = (T)P.area[d], D = (T)P.delta[d];
   if (on_bnd(P, d, s, i, j, k)) {
     *nb = -1;
-    if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID))
-      return O.rAU[c] * P.area[d] / (0.5 * P.delta[d]);
-    return 0.0;
+    if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID)) return O.rAU[c] * A / ((T)0.5 * D);
+    return (T)0;
   }
   long long n = c + s * stride(P, d);
   *nb = n;
-  return s > 0 ? 0.5 * (O.rAU[c] + O.rAU[n]) * P.area[d] / P.delta[d]
-               : 0.5 * (O.rAU[n] + O.rAU[c]) * P.area[d] / P.delta[d];
+  return s > 0 ? (T)0.5 * (O.rAU[c] + O.rAU[n]) * A / D : (T)0.5 * (O.rAU[n] + O.rAU[c]) * A / D;
 }
 
 // y = A x (and partial sums of x.y)
@@ -62,8 +68,8 @@ __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, dou
 
 // r = b - A x; partial sums of r.r, b.b and (for the SIMPLE residual) |r|,
 // |Ax - A xbar|, |b - A xbar| with xbar = *xmean (nullable)
-__global__ void k_fine_residual(Params P, FineOp O, const double* b, const double* x, double* r, const double* xmean,
-                                double* part, long long pstride) {
+__global__ void k_fine_residual(Params P, FineOp O, const double* b, const double* x, double* r, float* r32,
+                                const double* xmean, double* part, long long pstride) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   double v[5] = {0, 0, 0, 0, 0};
@@ -91,6 +97,7 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
     double bc = b[c];
     double rc = bc - acc;
     r[c] = rc;
+    if (r32) r32[c] = (float)rc;
     v[0] = rc * rc;
     v[1] = bc * bc;
     if (xmean) {
@@ -105,47 +112,55 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
 
 // red-black Gauss-Seidel half sweep on the fine level; init != 0 means z was
 // zero before this (first red) sweep: red cells z = r/diag, black cells z = 0
-__global__ void k_fine_smooth(Params P, FineOp O, const double* r, double* z, int color, int init) {
+template <typename T>
+__global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* r, T* z, int color, int init) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   bool mine = ((i + j + k) & 1) == color;
   if (init && !mine) {
-    z[c] = 0.0;
+    z[c] = (T)0;
     return;
   }
   if (!mine) return;
-  double diag = 0.0, nb = 0.0;
-  for (int d = 0; d < P.dim; ++d)
-    for (int s = -1; s <= 1; s += 2) {
+  T diag = (T)0, nb = (T)0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sh = 0; sh < 2; ++sh) {
+      if (d >= P.dim) continue;
       long long n;
-      double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
+      T cf = fine_coef(P, O, c, d, sh ? 1 : -1, i, j, k, &n);
       diag += cf;
       if (n >= 0 && !init) nb += cf * z[n];
     }
-  z[c] = diag == 0.0 ? r[c] : (r[c] + nb) / diag;
+  z[c] = diag == (T)0 ? r[c] : (r[c] + nb) / diag;
 }
 
 // ---------------------------------------------------------------- coarse levels
-struct LevelDev {
+template <typename T>
+struct LevelDevT {
   int nx, ny, nz, dim;
   long long N;
-  double* r;
-  double* z;
-  const double* cx;
-  const double* cy;
-  const double* cz;
-  const double* diag;
+  T* r;
+  T* z;
+  const T* cx;
+  const T* cy;
+  const T* cz;
+  const T* diag;
 };
 
-__device__ __forceinline__ long long lidx(const LevelDev& L, int i, int j, int k) {
+template <typename T>
+__device__ __forceinline__ long long lidx(const LevelDevT<T>& L, int i, int j, int k) {
   return (long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k);
 }
 
-// coefficients of level 1 from the fine operator: sum of the fine face
-// coefficients on each coarse face, halved (rediscretisation on the 2h grid)
-__global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDev L, double* cx, double* cy, double* cz) {
+// coefficients of level 1 from the fine operator (always evaluated in FP64 from
+// rAU, then stored as T): sum of the fine face coefficients on each coarse
+// face, halved (rediscretisation on the 2h grid)
+template <typename T>
+__global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDevT<T> L, T* cx, T* cy, T* cz) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   int J = blockIdx.y * blockDim.y + threadIdx.y;
   int K = blockIdx.z;
@@ -166,7 +181,7 @@ __global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDev L, double* cx, 
           s += fine_coef(P, O, cidx(P, i, j, k), 0, +1, i, j, k, &n);
         }
       }
-    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = (T)(0.5 * s);
   }
   if (I < L.nx && J <= L.ny && K < L.nz) {
     double s = 0.0;
@@ -182,7 +197,7 @@ __global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDev L, double* cx, 
           s += fine_coef(P, O, cidx(P, i, j, k), 1, +1, i, j, k, &n);
         }
       }
-    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = 0.5 * s;
+    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = (T)(0.5 * s);
   }
   if (L.dim == 3 && I < L.nx && J < L.ny && K <= L.nz) {
     // z faces K in [0, nz]: the launch has nz+1 planes
@@ -199,64 +214,67 @@ __global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDev L, double* cx, 
           s += fine_coef(P, O, cidx(P, i, j, k), 2, +1, i, j, k, &n);
         }
       }
-    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = (T)(0.5 * s);
   }
 }
 
 // coefficients of level l+1 from the stored coefficients of level l (F)
-__global__ void k_coarsen_level(LevelDev F, LevelDev L, double* cx, double* cy, double* cz) {
+template <typename T>
+__global__ void k_coarsen_level(LevelDevT<T> F, LevelDevT<T> L, T* cx, T* cy, T* cz) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   int J = blockIdx.y * blockDim.y + threadIdx.y;
   int K = blockIdx.z;
   int nzs = L.dim == 3 ? 2 : 1;
   if (I <= L.nx && J < L.ny && K < L.nz) {
-    double s = 0.0;
+    T s = (T)0;
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
         int j = 2 * J + b, k = L.dim == 3 ? 2 * K + e : 0;
         s += F.cx[(long long)(2 * I) + (long long)(F.nx + 1) * ((long long)j + (long long)F.ny * k)];
       }
-    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = (T)0.5 * s;
   }
   if (I < L.nx && J <= L.ny && K < L.nz) {
-    double s = 0.0;
+    T s = (T)0;
     for (int a = 0; a < 2; ++a)
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, k = L.dim == 3 ? 2 * K + e : 0;
         s += F.cy[(long long)i + (long long)F.nx * ((long long)(2 * J) + (long long)(F.ny + 1) * k)];
       }
-    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = 0.5 * s;
+    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = (T)0.5 * s;
   }
   if (L.dim == 3 && I < L.nx && J < L.ny && K <= L.nz) {
-    double s = 0.0;
+    T s = (T)0;
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
         int i = 2 * I + a, j = 2 * J + b;
         s += F.cz[(long long)i + (long long)F.nx * ((long long)j + (long long)F.ny * (2 * K))];
       }
-    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = 0.5 * s;
+    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = (T)0.5 * s;
   }
 }
 
-__global__ void k_level_diag(LevelDev L, double* diag) {
+template <typename T>
+__global__ void k_level_diag(LevelDevT<T> L, T* diag) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   int k = blockIdx.z;
   if (i >= L.nx || j >= L.ny) return;
-  double s = L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
-             L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
-             L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] +
-             L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)];
+  T s = L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
+        L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
+        L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] +
+        L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)];
   if (L.dim == 3)
     s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] +
          L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))];
-  diag[lidx(L, i, j, k)] = s == 0.0 ? 1.0 : s;  // uncoupled coarse cells: identity
+  diag[lidx(L, i, j, k)] = s == (T)0 ? (T)1 : s;  // uncoupled coarse cells: identity
 }
 
 // off-diagonal sum sum_nb c z_nb at (i,j,k) of a stored level
-__device__ __forceinline__ double level_nbsum(const LevelDev& L, const double* z, int i, int j, int k) {
+template <typename T>
+__device__ __forceinline__ T level_nbsum(const LevelDevT<T>& L, const T* z, int i, int j, int k) {
   long long c = lidx(L, i, j, k);
-  double s = 0.0;
+  T s = (T)0;
   if (i > 0) s += L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * z[c - 1];
   if (i < L.nx - 1)
     s += L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * z[c + 1];
@@ -271,7 +289,8 @@ __device__ __forceinline__ double level_nbsum(const LevelDev& L, const double* z
   return s;
 }
 
-__global__ void k_level_smooth(LevelDev L, int color, int init) {
+template <typename T>
+__global__ void k_level_smooth(LevelDevT<T> L, int color, int init) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   int k = blockIdx.z;
@@ -279,61 +298,67 @@ __global__ void k_level_smooth(LevelDev L, int color, int init) {
   long long c = lidx(L, i, j, k);
   bool mine = ((i + j + k) & 1) == color;
   if (init && !mine) {
-    L.z[c] = 0.0;
+    L.z[c] = (T)0;
     return;
   }
   if (!mine) return;
-  double nb = init ? 0.0 : level_nbsum(L, L.z, i, j, k);
+  T nb = init ? (T)0 : level_nbsum(L, L.z, i, j, k);
   L.z[c] = (L.r[c] + nb) / L.diag[c];
 }
 
 // restriction of the fine residual r - A z onto level 1 (sum over children)
-__global__ void k_restrict_fine(Params P, FineOp O, const double* r, const double* z, LevelDev C) {
+template <typename T>
+__global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* r, const T* z, LevelDevT<T> C) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   int J = blockIdx.y * blockDim.y + threadIdx.y;
   int K = blockIdx.z;
   if (I >= C.nx || J >= C.ny) return;
   int nzs = C.dim == 3 ? 2 : 1;
-  double s = 0.0;
+  T s = (T)0;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = cidx(P, i, j, k);
-        double zc = z[c], acc = 0.0, dg = 0.0;
-        for (int d = 0; d < P.dim; ++d)
-          for (int sg = -1; sg <= 1; sg += 2) {
+        T zc = z[c], acc = (T)0, dg = (T)0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int sh = 0; sh < 2; ++sh) {
+            if (d >= P.dim) continue;
             long long n;
-            double cf = fine_coef(P, O, c, d, sg, i, j, k, &n);
+            T cf = fine_coef(P, O, c, d, sh ? 1 : -1, i, j, k, &n);
             acc += n < 0 ? cf * zc : cf * (zc - z[n]);
             dg += cf;
           }
-        if (dg == 0.0) acc = zc;
+        if (dg == (T)0) acc = zc;
         s += r[c] - acc;
       }
   C.r[lidx(C, I, J, K)] = s;
 }
 
-__global__ void k_restrict_level(LevelDev F, LevelDev C) {
+template <typename T>
+__global__ void k_restrict_level(LevelDevT<T> F, LevelDevT<T> C) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   int J = blockIdx.y * blockDim.y + threadIdx.y;
   int K = blockIdx.z;
   if (I >= C.nx || J >= C.ny) return;
   int nzs = C.dim == 3 ? 2 : 1;
-  double s = 0.0;
+  T s = (T)0;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = lidx(F, i, j, k);
-        double Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
+        T Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
         s += F.r[c] - Az;
       }
   C.r[lidx(C, I, J, K)] = s;
 }
 
 // z_fine += z_coarse(parent)
-__global__ void k_prolong(int fnx, int fny, int fnz, int dim, double* zf, LevelDev C) {
+template <typename T>
+__global__ void k_prolong(int fnx, int fny, int fnz, int dim, T* zf, LevelDevT<T> C) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   int j = blockIdx.y * blockDim.y + threadIdx.y;
   int k = blockIdx.z;
@@ -342,82 +367,67 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int dim, double* zf, LevelD
   zf[c] += C.z[lidx(C, i / 2, j / 2, dim == 3 ? k / 2 : 0)];
 }
 
-// coarsest level: symmetric red-black Gauss-Seidel (m forward then m backward
-// colour pairs) from zero, by a single workgroup
-__global__ void k_coarse_solve(LevelDev L, int m) {
-  long long N = L.N;
-  for (long long c = threadIdx.x; c < N; c += blockDim.x) L.z[c] = 0.0;
-  __syncthreads();
-  for (int it = 0; it < 2 * m; ++it) {
-    for (int h = 0; h < 2; ++h) {
-      int color = it < m ? h : 1 - h;
-      for (long long c = threadIdx.x; c < N; c += blockDim.x) {
-        int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long long)L.nx * L.ny));
-        if (((i + j + k) & 1) != color) continue;
-        L.z[c] = (L.r[c] + level_nbsum(L, L.z, i, j, k)) / L.diag[c];
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // ---------------------------------------------------------------- tail V-cycle
 // The small coarse levels (each <= TAIL_MAX cells) are processed by one
 // workgroup: pre-smoothing, restriction, the coarsest solve, prolongation and
 // post-smoothing with barriers between the passes (one launch instead of ~5 per
-// level).  Same arithmetic as the per-level kernels.
+// level).  Same arithmetic as the per-level kernels.  The coarsest solve is a
+// symmetric red-black Gauss-Seidel from zero (m forward then m backward colour
+// pairs) held in LDS.
 constexpr long long TAIL_MAX = 1024;
 constexpr int TAIL_LDS = 1024;
 constexpr int TAIL_THREADS = 1024;
-struct TailLevels {
-  LevelDev L[MAX_LEVELS];
+template <typename T>
+struct TailLevelsT {
+  LevelDevT<T> L[MAX_LEVELS];
   int n;
 };
 
-__device__ __forceinline__ void tail_smooth(const LevelDev& L, int color, int init) {
+template <typename T>
+__device__ __forceinline__ void tail_smooth(const LevelDevT<T>& L, int color, int init) {
   for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
     int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long long)L.nx * L.ny));
     bool mine = ((i + j + k) & 1) == color;
     if (init && !mine) {
-      L.z[c] = 0.0;
+      L.z[c] = (T)0;
       continue;
     }
     if (!mine) continue;
-    double nb = init ? 0.0 : level_nbsum(L, L.z, i, j, k);
+    T nb = init ? (T)0 : level_nbsum(L, L.z, i, j, k);
     L.z[c] = (L.r[c] + nb) / L.diag[c];
   }
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevels T, int m) {
-  int n = T.n;
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL, int m) {
+  int n = TL.n;
   for (int t = 0; t < n - 1; ++t) {
-    const LevelDev& F = T.L[t];
-    const LevelDev& C = T.L[t + 1];
+    const LevelDevT<T>& F = TL.L[t];
+    const LevelDevT<T>& C = TL.L[t + 1];
     tail_smooth(F, 0, 1);
     tail_smooth(F, 1, 0);
     int nzs = C.dim == 3 ? 2 : 1;
     for (long long q = threadIdx.x; q < C.N; q += TAIL_THREADS) {
       int I = (int)(q % C.nx), J = (int)((q / C.nx) % C.ny), K = (int)(q / ((long long)C.nx * C.ny));
-      double sacc = 0.0;
+      T sacc = (T)0;
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
           for (int e = 0; e < nzs; ++e) {
             int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
             long long c = lidx(F, i, j, k);
-            double Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
+            T Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
             sacc += F.r[c] - Az;
           }
       C.r[q] = sacc;
     }
     __syncthreads();
   }
-  // coarsest level: symmetric red-black Gauss-Seidel from zero, in LDS
-  const LevelDev& L = T.L[n - 1];
+  const LevelDevT<T>& L = TL.L[n - 1];
   if (L.N <= TAIL_LDS) {
-    __shared__ double zs[TAIL_LDS], rs[TAIL_LDS], ds[TAIL_LDS];
+    __shared__ T zs[TAIL_LDS], rs[TAIL_LDS], ds[TAIL_LDS];
     for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
-      zs[c] = 0.0;
+      zs[c] = (T)0;
       rs[c] = L.r[c];
       ds[c] = L.diag[c];
     }
@@ -428,21 +438,21 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevels T, int 
         for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
           int i = (int)(c % L.nx), j = (int)((c / L.nx) % L.ny), k = (int)(c / ((long long)L.nx * L.ny));
           if (((i + j + k) & 1) != color) continue;
-          zs[c] = (rs[c] + level_nbsum(L, zs, i, j, k)) / ds[c];
+          zs[c] = (rs[c] + level_nbsum(L, (const T*)zs, i, j, k)) / ds[c];
         }
         __syncthreads();
       }
     for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) L.z[c] = zs[c];
     __syncthreads();
   } else {
-    for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) L.z[c] = 0.0;
+    for (long long c = threadIdx.x; c < L.N; c += TAIL_THREADS) L.z[c] = (T)0;
     __syncthreads();
     for (int it = 0; it < 2 * m; ++it)
       for (int h = 0; h < 2; ++h) tail_smooth(L, it < m ? h : 1 - h, 0);
   }
   for (int t = n - 2; t >= 0; --t) {
-    const LevelDev& F = T.L[t];
-    const LevelDev& C = T.L[t + 1];
+    const LevelDevT<T>& F = TL.L[t];
+    const LevelDevT<T>& C = TL.L[t + 1];
     for (long long c = threadIdx.x; c < F.N; c += TAIL_THREADS) {
       int i = (int)(c % F.nx), j = (int)((c / F.nx) % F.ny), k = (int)(c / ((long long)F.nx * F.ny));
       F.z[c] += C.z[lidx(C, i / 2, j / 2, F.dim == 3 ? k / 2 : 0)];
@@ -454,19 +464,22 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevels T, int 
 }
 
 // ---------------------------------------------------------------- vector ops
-__global__ void k_copy_vec(long long n, const double* a, double* b) {
+template <typename TA>
+__global__ void k_copy_vec(long long n, const TA* a, double* b) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  if (c < n) b[c] = a[c];
+  if (c < n) b[c] = (double)a[c];
 }
 
-__global__ void k_dot(long long n, const double* a, const double* b, double* part, long long pstride) {
+template <typename TB>
+__global__ void k_dot(long long n, const double* a, const TB* b, double* part, long long pstride) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  double v[1] = {c < n ? a[c] * b[c] : 0.0};
+  double v[1] = {c < n ? a[c] * (double)b[c] : 0.0};
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
-__global__ void k_axpy2(long long n, const double* scal, double* x, const double* d, double* r, const double* q,
-                        double* part, long long pstride) {
+// x += alpha d, r -= alpha q (and its FP32 copy when r32 is given); partial r.r
+__global__ void k_axpy2(long long n, const double* scal, double* x, const double* d, double* r, float* r32,
+                        const double* q, double* part, long long pstride) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
   double a = scal[S_ALPHA];
   double v[1] = {0.0};
@@ -474,14 +487,21 @@ __global__ void k_axpy2(long long n, const double* scal, double* x, const double
     x[c] += a * d[c];
     double rc = r[c] - a * q[c];
     r[c] = rc;
+    if (r32) r32[c] = (float)rc;
     v[0] = rc * rc;
   }
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
-__global__ void k_xpby(long long n, const double* scal, const double* z, double* d) {
+template <typename TZ>
+__global__ void k_xpby(long long n, const double* scal, const TZ* z, double* d) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  if (c < n) d[c] = z[c] + scal[S_BETA] * d[c];
+  if (c < n) d[c] = (double)z[c] + scal[S_BETA] * d[c];
+}
+
+__global__ void k_to_f32(long long n, const double* a, float* b) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) b[c] = (float)a[c];
 }
 
 // finalize: reduces `nval` rows of per-block partials -> scal[out+v] (sums, or
@@ -528,21 +548,25 @@ k_finalize(const double* part, long long pstride, int nblk, int nval, double* sc
 }
 
 // ---------------------------------------------------------------- host side
-static LevelDev levdev(hfdib_ctx* c, int l) {
-  Level& L = c->lev[l];
-  LevelDev d;
-  d.nx = L.nx;
-  d.ny = L.ny;
-  d.nz = L.nz;
-  d.dim = c->P.dim;
-  d.N = L.N;
-  d.r = L.r;
-  d.z = L.z;
-  d.cx = L.cx;
-  d.cy = L.cy;
-  d.cz = L.cz;
-  d.diag = L.diag;
-  return d;
+template <typename T>
+struct LevelPick;
+template <>
+struct LevelPick<double> {
+  static LevelDevT<double> get(hfdib_ctx* c, int l) {
+    Level& L = c->lev[l];
+    return LevelDevT<double>{L.nx, L.ny, L.nz, c->P.dim, L.N, L.r, L.z, L.cx, L.cy, L.cz, L.diag};
+  }
+};
+template <>
+struct LevelPick<float> {
+  static LevelDevT<float> get(hfdib_ctx* c, int l) {
+    Level& L = c->lev[l];
+    return LevelDevT<float>{L.nx, L.ny, L.nz, c->P.dim, L.N, L.r32, L.z32, L.cx32, L.cy32, L.cz32, L.diag32};
+  }
+};
+template <typename T>
+static LevelDevT<T> levdev(hfdib_ctx* c, int l) {
+  return LevelPick<T>::get(c, l);
 }
 static dim3 lgrid(int nx, int ny, int nz) { return dim3((nx + 63) / 64, (ny + 3) / 4, nz); }
 
@@ -552,81 +576,89 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
                      c->pstride, nblk, nval, c->scal + SCAL_PCG, out, op, divisor);
 }
 
-static void vcycle(hfdib_ctx* c, const FineOp& O, const double* r, double* z) {
+// one V-cycle z = M^-1 r in storage type T
+template <typename T>
+static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* r, T* z) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3();
-  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 0, 1);
-  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 1, 0);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 0, 1);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 1, 0);
   if (c->nlev > 1) {
-    LevelDev L1 = levdev(c, 1);
-    hipLaunchKernelGGL(k_restrict_fine, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, z, L1);
+    LevelDevT<T> L1 = levdev<T>(c, 1);
+    hipLaunchKernelGGL(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, (const T*)z, L1);
     // large coarse levels: one kernel per pass
     int l = 1;
     while (l < c->nlev - 1 && c->lev[l].N > TAIL_MAX) {
-      LevelDev L = levdev(c, l);
+      LevelDevT<T> L = levdev<T>(c, l);
       dim3 gl = lgrid(L.nx, L.ny, L.nz);
-      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 0, 1);
-      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 1, 0);
-      LevelDev C = levdev(c, l + 1);
-      hipLaunchKernelGGL(k_restrict_level, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
+      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 0, 1);
+      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 1, 0);
+      LevelDevT<T> C = levdev<T>(c, l + 1);
+      hipLaunchKernelGGL(k_restrict_level<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
       ++l;
     }
     // small levels l..nlev-1 (and the coarsest solve) in one workgroup
-    TailLevels T;
-    T.n = c->nlev - l;
-    for (int t = 0; t < T.n; ++t) T.L[t] = levdev(c, l + t);
-    hipLaunchKernelGGL(k_tail_vcycle, dim3(1), dim3(TAIL_THREADS), 0, c->stream, T, 6);
+    TailLevelsT<T> TL;
+    TL.n = c->nlev - l;
+    for (int t = 0; t < TL.n; ++t) TL.L[t] = levdev<T>(c, l + t);
+    hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), 0, c->stream, TL, 6);
     for (int q = l - 1; q >= 1; --q) {
-      LevelDev L = levdev(c, q);
-      LevelDev C = levdev(c, q + 1);
+      LevelDevT<T> L = levdev<T>(c, q);
+      LevelDevT<T> C = levdev<T>(c, q + 1);
       dim3 gl = lgrid(L.nx, L.ny, L.nz);
-      hipLaunchKernelGGL(k_prolong, gl, b, 0, c->stream, L.nx, L.ny, L.nz, L.dim, L.z, C);
-      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 1, 0);
-      hipLaunchKernelGGL(k_level_smooth, gl, b, 0, c->stream, L, 0, 0);
+      hipLaunchKernelGGL(k_prolong<T>, gl, b, 0, c->stream, L.nx, L.ny, L.nz, L.dim, L.z, C);
+      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 1, 0);
+      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 0, 0);
     }
-    hipLaunchKernelGGL(k_prolong, lgrid(P.nx, P.ny, P.nz), b, 0, c->stream, P.nx, P.ny, P.nz, P.dim, z, L1);
+    hipLaunchKernelGGL(k_prolong<T>, lgrid(P.nx, P.ny, P.nz), b, 0, c->stream, P.nx, P.ny, P.nz, P.dim, z, L1);
   }
-  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 1, 0);
-  hipLaunchKernelGGL(k_fine_smooth, g, b, 0, c->stream, P, O, r, z, 0, 0);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 1, 0);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 0, 0);
 }
 
+// coarse operators of every level from the FP64 fine operator
+template <typename T>
 static void build_levels(hfdib_ctx* c, const FineOp& O) {
   const Params& P = c->P;
   dim3 b = block3();
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
-    LevelDev Ld = levdev(c, l);
+    LevelDevT<T> Ld = levdev<T>(c, l);
+    T* cx = const_cast<T*>(Ld.cx);
+    T* cy = const_cast<T*>(Ld.cy);
+    T* cz = const_cast<T*>(Ld.cz);
     dim3 gf((L.nx + 1 + 63) / 64, (L.ny + 1 + 3) / 4, P.dim == 3 ? L.nz + 1 : 1);
     if (l == 1)
-      hipLaunchKernelGGL(k_coarsen_from_fine, gf, b, 0, c->stream, P, O, Ld, L.cx, L.cy, L.cz);
+      hipLaunchKernelGGL(k_coarsen_from_fine<T>, gf, b, 0, c->stream, P, O, Ld, cx, cy, cz);
     else
-      hipLaunchKernelGGL(k_coarsen_level, gf, b, 0, c->stream, levdev(c, l - 1), Ld, L.cx, L.cy, L.cz);
-    hipLaunchKernelGGL(k_level_diag, lgrid(L.nx, L.ny, L.nz), b, 0, c->stream, Ld, L.diag);
+      hipLaunchKernelGGL(k_coarsen_level<T>, gf, b, 0, c->stream, levdev<T>(c, l - 1), Ld, cx, cy, cz);
+    hipLaunchKernelGGL(k_level_diag<T>, lgrid(L.nx, L.ny, L.nz), b, 0, c->stream, Ld, const_cast<T*>(Ld.diag));
   }
 }
 
-int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol, int maxit, int* iters,
-                   double* relres, const double* xmean_dev) {
+// Preconditioned CG on the pressure system.  The preconditioner storage type
+// is T (FP64; FP32 under the mixed policy, where r32/z32 hold the FP32 copies
+// of the residual and of the preconditioned residual).
+template <typename T>
+static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const double* rhs, double* x, T* r_m, T* z_m,
+               float* r32, double rtol, int maxit, int* iters, double* relres, const double* xmean_dev) {
   const Params& P = c->P;
-  FineOp O{rAU, c->flags};
   dim3 g = grid3(P), b = block3();
   long long nblk3 = (long long)g.x * g.y * g.z;
   int nb1 = nblocks1(P.N);
   double* r = c->pr;
-  double* z = c->pz;
   double* d = c->pd;
   double* q = c->pq;
   double* S = c->scal + SCAL_PCG;
-  timer_begin(c, T_PSOLVE);
-  build_levels(c, O);
-  hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, O, rhs, x, r, xmean_dev, c->partials, c->pstride);
+  hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, O, rhs, x, r, r32, xmean_dev, c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [20]=rr0 [21]=bb [22..24]=residual sums
   // at least one PCG iteration is done; the host reads the residual after each
   // iteration (one synchronisation per iteration, none before the first)
-  vcycle(c, O, r, z);
-  hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
+  vcycle<T>(c, OM, r_m, z_m);
+  hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
+                     c->pstride);
   launch_finalize(c, nb1, 1, S_RZ, 3);
-  hipLaunchKernelGGL(k_copy_vec, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, z, d);
+  hipLaunchKernelGGL(k_copy_vec<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const T*)z_m, d);
   double hs[32];
   double rr = 0.0, bnorm = 1.0, target = 0.0;
   int it;
@@ -635,7 +667,7 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
     hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
     timer_end(c, T_PAPPLY);
     launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
-    hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, q, c->partials,
+    hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, r32, q, c->partials,
                        c->pstride);
     launch_finalize(c, nb1, 1, S_RR, 0);
     HFDIB_CHECK_LAUNCH(c, "pcg iteration");
@@ -652,27 +684,41 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
     rr = hs[S_RR];
     if (!std::isfinite(rr)) {
       c->err = "non-finite residual in the pressure solve";
-      timer_end(c, T_PSOLVE);
       return HFDIB_EDIVERGED;
     }
     if (sqrt(rr) <= target) break;
     if (it == maxit) break;
-    vcycle(c, O, r, z);
-    hipLaunchKernelGGL(k_dot, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, z, c->partials, c->pstride);
+    vcycle<T>(c, OM, r_m, z_m);
+    hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
+                       c->pstride);
     launch_finalize(c, nb1, 1, S_RZ, 2);
-    hipLaunchKernelGGL(k_xpby, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, z, d);
+    hipLaunchKernelGGL(k_xpby<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, (const T*)z_m, d);
   }
   if (it > maxit) it = maxit;
-  timer_end(c, T_PSOLVE);
   HFDIB_CHECK_LAUNCH(c, "pcg");
   if (iters) *iters = it;
   if (relres) *relres = sqrt(rr) / bnorm;
   return HFDIB_OK;
 }
 
-int mg_setup_levels(hfdib_ctx* c) {
-  (void)c;
-  return HFDIB_OK;
+int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol, int maxit, int* iters,
+                   double* relres, const double* xmean_dev) {
+  const Params& P = c->P;
+  FineOp O{rAU, c->flags};
+  int st;
+  timer_begin(c, T_PSOLVE);
+  if (P.precision == HFDIB_MIXED) {
+    // FP32 mirror of rAU for the fine smoother; coarse operators from FP64
+    hipLaunchKernelGGL(k_to_f32, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, rAU, c->rAU32);
+    build_levels<float>(c, O);
+    FineOpT<float> OM{c->rAU32, c->flags};
+    st = pcg<float>(c, O, OM, rhs, x, c->pr32, c->pz32, c->pr32, rtol, maxit, iters, relres, xmean_dev);
+  } else {
+    build_levels<double>(c, O);
+    st = pcg<double>(c, O, O, rhs, x, c->pr, c->pz, nullptr, rtol, maxit, iters, relres, xmean_dev);
+  }
+  timer_end(c, T_PSOLVE);
+  return st;
 }
 
 }  // namespace hfdib

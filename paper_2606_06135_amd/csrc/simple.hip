@@ -19,6 +19,22 @@ struct Mom {
   double* kw;  // grad k . grad omega of the previous iterate (SST)
 };
 
+// FP32 outputs of the momentum assembly under the mixed policy (all null under
+// FP64): the defect b - A u_old of each component, the relaxed diagonal and the
+// SST blending mirror used by the FP32 sweeps
+struct MixOut {
+  float* r[3];
+  float* a;
+  float* F1;
+};
+
+// FP32 coefficient mirrors read by the FP32 sweeps
+struct Mir32 {
+  const float* phi[3];
+  const float* nut;
+  const float* F1;
+};
+
 __device__ __forceinline__ double nut_wall(const Params& P, double yp) {
   if (!(yp > P.ylam)) return 0.0;
   double v = P.kappa * yp / log(P.E * yp) - 1.0;
@@ -204,7 +220,7 @@ __device__ __forceinline__ double nb_sum(const Params& P, const double (&anb)[6]
 // Assembly of the relaxed momentum rows with the explicit IB source
 // (discrete f_ib = alpha [M(u~) + grad p]), plus the normalised-residual sums
 // of the rows that are solved (alpha_u = 0).
-__global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
+__global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
                                const double* means, double* part, long long pstride) {
   double wmx = 0.0;  // max of omega/eps of the previous iterate over boundary and free-stream cells
   int i, j, k;
@@ -257,6 +273,7 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
     double urf = P.urf_u;
     double aPr = aP / urf;
     aPr_out[c] = aPr;
+    if (X.a) X.a[c] = (float)aPr;
     bool alpha = fl & F_ALPHA_U;
     double* rhs[3] = {rhs0, rhs1, rhs2};
 #pragma unroll
@@ -308,7 +325,7 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
         rh = (b0 - g) + r;
       }
       rhs[cc][c] = rh;
-      if (!alpha) {
+      if (!alpha || X.a) {
         double nb = 0.0, one = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
@@ -317,10 +334,15 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
           one += anb[q];
         }
         double Ax = aPr * uo - nb;
-        double Axb = (aPr - one) * means[cc];
-        red[3 * cc + 0] = fabs(rh - Ax);
-        red[3 * cc + 1] = fabs(Ax - Axb);
-        red[3 * cc + 2] = fabs(rh - Axb);
+        // mixed policy: FP64 defect of the row (every row is swept) for the
+        // FP32 correction
+        if (X.a) X.r[cc][c] = (float)(rh - Ax);
+        if (!alpha) {
+          double Axb = (aPr - one) * means[cc];
+          red[3 * cc + 0] = fabs(rh - Ax);
+          red[3 * cc + 1] = fabs(Ax - Axb);
+          red[3 * cc + 2] = fabs(rh - Axb);
+        }
       }
     }
     // turbulence inputs of the previous iterate (k, omega unchanged until the
@@ -346,6 +368,7 @@ __global__ void k_mom_assemble(Params P, Mom M, double* rhs0, double* rhs1, doub
       double arg1 = m1 < m2 ? m1 : m2;
       double a2 = arg1 * arg1;
       M.F1[c] = tanh(a2 * a2);
+      if (X.F1) X.F1[c] = (float)M.F1[c];
       M.kw[c] = kw;
     }
     if (P.model != HFDIB_LAMINAR && !(fl & F_IC)) wmx = M.w[c];
@@ -376,6 +399,78 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
   u0[c] = (rhs0[c] + nb_sum(P, anb, vm, u0, c)) / a;
   u1[c] = (rhs1[c] + nb_sum(P, anb, vm, u1, c)) / a;
   if (P.dim == 3) u2[c] = (rhs2[c] + nb_sum(P, anb, vm, u2, c)) / a;
+}
+
+// Mixed policy: one colour of a red-black Gauss-Seidel sweep of the FP32
+// correction d (A d = r, r the FP64 defect of the assembled rows, d = 0 before
+// the first sweep), coefficients from the FP32 mirrors.  init: first sweep
+// (cells of the other colour set to 0); fin: last sweep of this colour, which
+// also writes u <- u_old + d in FP64.  Equal to the FP64 sweeps from u_old in
+// exact arithmetic.
+__device__ __forceinline__ unsigned mom_anb32(const Params& P, const Mir32& M, float nuP, int i, int j, int k,
+                                              long long c, float (&anb)[6]) {
+  unsigned vm = 0u;
+  const float nu = (float)P.nu;
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sh = 0; sh < 2; ++sh) {
+      const int s = sh ? 1 : -1, q = 2 * d + sh;
+      anb[q] = 0.0f;
+      if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
+        long long n = c + s * stride(P, d);
+        long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
+        float F = s > 0 ? M.phi[d][f] : -M.phi[d][f];
+        float mf = -F;
+        anb[q] = 0.5f * (nuP + (nu + M.nut[n])) * (float)P.area[d] / (float)P.delta[d] + (mf > 0.0f ? mf : 0.0f);
+        vm |= 1u << q;
+      }
+    }
+  return vm;
+}
+
+__global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r1, const float* r2, const float* a32,
+                              float* d0, float* d1, float* d2, double* u0, double* u1, double* u2, int color, int init,
+                              int fin) {
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  bool mine = ((i + j + k) & 1) == color;
+  bool three = P.dim == 3;
+  if (init && !mine) {
+    d0[c] = 0.0f;
+    d1[c] = 0.0f;
+    if (three) d2[c] = 0.0f;
+    return;
+  }
+  if (!mine) return;
+  float a = a32[c];
+  float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
+  if (!init) {
+    float anb[6];
+    unsigned vm = mom_anb32(P, M, (float)P.nu + M.nut[c], i, j, k, c, anb);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      if (!(vm & (1u << q))) continue;
+      long long n = c + ((q & 1) ? 1 : -1) * stride(P, q >> 1);
+      n0 += anb[q] * d0[n];
+      n1 += anb[q] * d1[n];
+      if (three) n2 += anb[q] * d2[n];
+    }
+  }
+  float e0 = (r0[c] + n0) / a, e1 = (r1[c] + n1) / a;
+  d0[c] = e0;
+  d1[c] = e1;
+  if (fin) {
+    u0[c] = u0[c] + (double)e0;
+    u1[c] = u1[c] + (double)e1;
+  }
+  if (three) {
+    float e2 = (r2[c] + n2) / a;
+    d2[c] = e2;
+    if (fin) u2[c] = u2[c] + (double)e2;
+  }
 }
 
 // u <- u + alpha_u (u_ib - u) on forced cells (list kernels: boundary cells with
@@ -470,15 +565,23 @@ __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const d
 }
 
 // flux correction with the solved pressure and relaxation of p (into pnew)
+// (mixed policy: also the FP32 mirror of every face flux this cell owns)
+struct Phi32Out {
+  float* f[3];
+};
+
 __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, const double* pold,
-                               const uint8_t* flags, double* phx, double* phy, double* phz, double* pnew) {
+                               const uint8_t* flags, double* phx, double* phy, double* phz, double* pnew,
+                               Phi32Out m32) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   double* ph[3] = {phx, phy, phz};
   bool solid = flags[c] & F_SOLID;
-  for (int d = 0; d < P.dim; ++d) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d >= P.dim) continue;
     long long f = fidx(P, d, i, j, k);
     long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
     if (!on_bnd(P, d, +1, i, j, k)) {
@@ -491,6 +594,10 @@ __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, 
       double cb = solid ? 0.0 : rAU[c] * P.area[d] / (0.5 * P.delta[d]);
       long long ff = s > 0 ? f + fo : f;
       ph[d][ff] = ph[d][ff] + (double)s * cb * psol[c];
+    }
+    if (m32.f[0]) {
+      m32.f[d][f + fo] = (float)ph[d][f + fo];
+      if (on_bnd(P, d, -1, i, j, k)) m32.f[d][f] = (float)ph[d][f];
     }
   }
   pnew[c] = pold[c] + P.urf_p * (psol[c] - pold[c]);
@@ -579,7 +686,7 @@ int init_state(hfdib_ctx* c) {
     hipLaunchKernelGGL(k_init_ib, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_ic, c->ic_cells,
                        c->us[0], c->us[1], c->us[2], c->uib[0], c->uib[1], c->uib[2], c->kib);
   HFDIB_CHECK_LAUNCH(c, "init state");
-  return HFDIB_OK;
+  return refresh_mirrors(c);
 }
 
 __global__ void k_residuals(const double* S, int dim, int turb, double* out) {
@@ -599,6 +706,28 @@ __global__ void k_residuals(const double* S, int dim, int turb, double* out) {
     out[4] = 0.0;
     out[5] = 0.0;
   }
+}
+
+__global__ void k_to_f32_n(long long n, const double* a, float* b) {
+  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  if (c < n) b[c] = (float)a[c];
+}
+
+// mixed policy: FP32 mirrors of the sweep coefficients (face fluxes, nu_t, SST
+// blending) from the FP64 state, after initialisation or after the state was
+// set from outside; during iterations the producing kernels keep them current
+int refresh_mirrors(hfdib_ctx* c) {
+  const Params& P = c->P;
+  if (P.precision != HFDIB_MIXED) return HFDIB_OK;
+  long long nf[3] = {(long long)(P.nx + 1) * P.ny * P.nz, (long long)P.nx * (P.ny + 1) * P.nz,
+                     (long long)P.nx * P.ny * (P.nz + 1)};
+  for (int d = 0; d < 3; ++d)
+    hipLaunchKernelGGL(k_to_f32_n, dim3(nblocks1(nf[d])), dim3(NTHREADS), 0, c->stream, nf[d], c->phi[d],
+                       c->phi32[d]);
+  hipLaunchKernelGGL(k_to_f32_n, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, c->nut, c->nut32);
+  hipLaunchKernelGGL(k_to_f32_n, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, c->F1, c->F1_32);
+  HFDIB_CHECK_LAUNCH(c, "mirrors");
+  return HFDIB_OK;
 }
 
 int simple_step(hfdib_ctx* c, int it, double* res_host) {
@@ -625,19 +754,28 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                        c->wall_cells, c->wall_y, c->k, c->wall_utau, c->wall_yplus);
   // 2. momentum predictor
   Mom M = make_mom(c);
+  bool mixed = P.precision == HFDIB_MIXED;
+  MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
+  if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32, c->F1_32};
   timer_begin(c, T_MOMASM);
-  hipLaunchKernelGGL(k_mom_assemble, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
+  hipLaunchKernelGGL(k_mom_assemble, g, b, 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
                      S + SC_MEANS, c->partials, c->pstride);
   timer_end(c, T_MOMASM);
   launch_finalize(c, (int)nblk3, 9, SC_RESSUM, 0);
   if (P.model != HFDIB_LAMINAR) {
     launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4, 1.0, 9);  // partial row 9: omega maxima
   }
+  Mir32 M32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32, c->F1_32};
   for (int s = 0; s < P.n_sweeps; ++s)
     for (int color = 0; color < 2; ++color) {
       timer_begin(c, T_MOMSWEEP);
-      hipLaunchKernelGGL(k_mom_sweep, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
-                         c->u[1], c->u[2], color);
+      if (mixed)
+        hipLaunchKernelGGL(k_mom_sweep32, g, b, 0, c->stream, P, M32, c->r32[0], c->r32[1], c->r32[2], c->a32,
+                           c->d32[0], c->d32[1], c->d32[2], c->u[0], c->u[1], c->u[2], color,
+                           s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
+      else
+        hipLaunchKernelGGL(k_mom_sweep, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
+                           c->u[1], c->u[2], color);
       timer_end(c, T_MOMSWEEP);
     }
   // 3. u <- u + alpha_u (u_ib - u)
@@ -662,8 +800,10 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   c->stats[2] = iters > c->stats[2] ? iters : c->stats[2];
   c->stats[3] = relres;
   // 5. flux and velocity update
+  Phi32Out m32{{nullptr, nullptr, nullptr}};
+  if (mixed) m32 = Phi32Out{{c->phi32[0], c->phi32[1], c->phi32[2]}};
   hipLaunchKernelGGL(k_flux_correct, g, b, 0, c->stream, P, c->rAU, c->px, c->p, c->flags, c->phi[0], c->phi[1],
-                     c->phi[2], c->pnew);
+                     c->phi[2], c->pnew, m32);
   hipLaunchKernelGGL(k_vel_update, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->aPr, c->pnew,
                      c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1], c->u[2], c->p);
   double* tmp = c->p;

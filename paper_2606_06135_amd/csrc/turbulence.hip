@@ -128,8 +128,8 @@ __device__ __forceinline__ long long nb_index(const Params& P, int q, long long 
 
 // assembly of the omega (eps, eq = 0) or k (eq = 1) rows; rhs -> rhs_out,
 // relaxed diagonal -> aPr_out; residual sums of the solved rows
-__global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, const double* xmean,
-                                  double* part, long long pstride) {
+__global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, float* r32, float* a32,
+                                  const double* xmean, double* part, long long pstride) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   double red[3] = {0, 0, 0};
@@ -219,7 +219,9 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     }
     rhs_out[c] = rhs;
     aPr_out[c] = aPr;
-    if (!skip) {
+    // rows the sweeps update: all k rows; omega/eps rows outside alpha_omega
+    bool swept = eq == 1 || !(fl & F_ALPHA_W);
+    if (!skip || (a32 && swept)) {
       const double* xv = eq == 0 ? S.w : S.k;
       double nb = 0.0, one = 0.0;
 #pragma unroll
@@ -229,10 +231,18 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
         one += anb[q];
       }
       double Ax = aPr * x - nb;
-      double Axb = (aPr - one) * (*xmean);
-      red[0] = fabs(rhs - Ax);
-      red[1] = fabs(Ax - Axb);
-      red[2] = fabs(rhs - Axb);
+      if (!skip) {
+        double Axb = (aPr - one) * (*xmean);
+        red[0] = fabs(rhs - Ax);
+        red[1] = fabs(Ax - Axb);
+        red[2] = fabs(rhs - Axb);
+      }
+      // mixed policy: FP64 defect of the row for the FP32 correction
+      if (a32) r32[c] = (float)(rhs - Ax);
+    }
+    if (a32) {
+      a32[c] = (float)aPr;
+      if (!swept) r32[c] = 0.0f;
     }
   }
   block_sums_store<3>(red, part, pstride, block_linear());
@@ -256,6 +266,57 @@ __global__ void k_scalar_sweep(Params P, Scal S, int eq, const double* rhs, cons
   for (int q = 0; q < 6; ++q)
     if (vm & (1u << q)) nb += anb[q] * x[nb_index(P, q, c)];
   x[c] = (rhs[c] + nb) / aPr[c];
+}
+
+// Mixed policy: red-black sweep of the FP32 correction d of a scalar equation
+// (A d = r from d = 0; rows flagged `fixmask` keep d = 0), coefficients from
+// the FP32 mirrors; the last sweep of each colour writes x <- x_old + d (FP64).
+struct Scal32 {
+  const float* phi[3];
+  const float* nut;
+  const float* F1;
+};
+__device__ __forceinline__ float gam32(const Params& P, int eq, long long c, const float* nut, const float* F1) {
+  const float nu = (float)P.nu;
+  if (P.model == HFDIB_KEPS) return nu + nut[c] / (float)(eq == 0 ? P.sigma_eps : P.sigma_k);
+  float f = F1[c];
+  float a = (float)(eq == 0 ? P.sigma_w1 : P.sigma_k1), b = (float)(eq == 0 ? P.sigma_w2 : P.sigma_k2);
+  return nu + (f * a + (1.0f - f) * b) * nut[c];
+}
+
+__global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, int eq, const float* r, const float* a32,
+                                 float* dv, double* x, int color, uint8_t fixmask, int init, int fin) {
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  bool mine = ((i + j + k) & 1) == color;
+  bool fixed = flags[c] & fixmask;
+  if (init && (!mine || fixed)) {
+    dv[c] = 0.0f;
+    return;
+  }
+  if (!mine || fixed) return;
+  float nb = 0.0f;
+  if (!init) {
+    float gP = gam32(P, eq, c, S.nut, S.F1);
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int sh = 0; sh < 2; ++sh) {
+        const int s = sh ? 1 : -1;
+        if (d >= P.dim || on_bnd(P, d, s, i, j, k)) continue;
+        long long n = c + s * stride(P, d);
+        long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
+        float mf = s > 0 ? -S.phi[d][f] : S.phi[d][f];
+        float a = 0.5f * (gP + gam32(P, eq, n, S.nut, S.F1)) * (float)P.area[d] / (float)P.delta[d] +
+                  (mf > 0.0f ? mf : 0.0f);
+        nb += a * dv[n];
+      }
+  }
+  float e = (r[c] + nb) / a32[c];
+  dv[c] = e;
+  if (fin) x[c] = x[c] + (double)e;
 }
 
 // k_ib on boundary cells: quadratic along n_P with the wall-function surface
@@ -285,7 +346,7 @@ __global__ void k_kib(Params P, int nbc, const int* bc_cells, const uint8_t* fla
 // k <- k + alpha_k (k_ib - k), bounding, turbulent viscosity of the model
 // (in-solid cells 0); eps/omega is already bounded
 __global__ void k_turb_final(Params P, const uint8_t* flags, U3 U, const double* kib, double* k, const double* w,
-                             const double* dw, double* nut) {
+                             const double* dw, double* nut, float* nut32) {
   int i, j, kz;
   tile_ijk(P, i, j, kz);
   if (i >= P.nx || j >= P.ny) return;
@@ -314,16 +375,19 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, U3 U, const double*
   }
   if (fl & F_IC) nt = 0.0;
   nut[c] = nt;
+  if (nut32) nut32[c] = (float)nt;
 }
 
 // boundary cells on the logarithmic branch: log-law wall viscosity
-__global__ void k_nut_bc(Params P, int nbc, const int* bc_cells, const double* ypl, double* nut) {
+__global__ void k_nut_bc(Params P, int nbc, const int* bc_cells, const double* ypl, double* nut, float* nut32) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= nbc) return;
   double yp = ypl[b];
   if (!(yp > P.ylam)) return;
   double v = P.kappa * yp / log(P.E * yp) - 1.0;
-  nut[bc_cells[b]] = P.nu * (v > 0.0 ? v : 0.0);
+  double nt = P.nu * (v > 0.0 ? v : 0.0);
+  nut[bc_cells[b]] = nt;
+  if (nut32) nut32[bc_cells[b]] = (float)nt;
 }
 
 // velocity-based friction velocity from the log law by Newton's method
@@ -406,30 +470,40 @@ int turbulence_stage(hfdib_ctx* c) {
   Sc.w = c->w;
   Sc.wib = c->wib;
   Sc.kib = c->kib;
+  bool mixed = P.precision == HFDIB_MIXED;
+  float* r32 = mixed ? c->r32[0] : nullptr;
+  float* a32 = mixed ? c->a32 : nullptr;
+  Scal32 S32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32, c->F1_32};
+  // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
+  auto sweeps = [&](int eq, double* x, uint8_t fixmask) {
+    for (int s = 0; s < P.n_sweeps; ++s)
+      for (int color = 0; color < 2; ++color) {
+        if (mixed)
+          hipLaunchKernelGGL(k_scalar_sweep32, g, b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0], x, color,
+                             fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
+        else
+          hipLaunchKernelGGL(k_scalar_sweep, g, b, 0, c->stream, P, Sc, eq, c->t0, c->t1, x, color, fixmask);
+      }
+  };
   // omega / eps equation, alpha_omega rows fixed
-  hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, S + SC_MEANS + 5, c->partials,
-                     c->pstride);
+  hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, S + SC_MEANS + 5,
+                     c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
-  for (int s = 0; s < P.n_sweeps; ++s)
-    for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_scalar_sweep, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, c->w, color,
-                         (uint8_t)F_ALPHA_W);
+  sweeps(0, c->w, (uint8_t)F_ALPHA_W);
   // k_ib, then the k equation with S_ib (bounds omega/eps on the way)
   if (c->n_bc > 0)
     hipLaunchKernelGGL(k_kib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
                        c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->bc_yplus, c->bc_utau, c->k,
                        c->kib);
-  hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, S + SC_MEANS + 4, c->partials,
-                     c->pstride);
+  hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, S + SC_MEANS + 4,
+                     c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
-  for (int s = 0; s < P.n_sweeps; ++s)
-    for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_scalar_sweep, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, c->k, color, (uint8_t)0);
+  sweeps(1, c->k, (uint8_t)0);
   hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, U, c->kib, c->k, c->w,
-                     c->dw, c->nut);
+                     c->dw, c->nut, mixed ? c->nut32 : nullptr);
   if (c->n_bc > 0) {
     hipLaunchKernelGGL(k_nut_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
-                       c->bc_yplus, c->nut);
+                       c->bc_yplus, c->nut, mixed ? c->nut32 : nullptr);
     hipLaunchKernelGGL(k_loglaw, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
                        c->bc_n, c->bc_yeff, c->bc_yplus, c->bc_utau, c->u[0], c->u[1], c->u[2], c->us[0], c->us[1],
                        c->us[2], c->bc_utauU);

@@ -1,0 +1,134 @@
+"""The mixed-precision policy through the C ABI.
+
+Under the mixed policy the stencil sweeps solve for an FP32 correction of the
+FP64 defect and the multigrid preconditioner runs in FP32, while the state, the
+assembly, the residuals and every reduction stay FP64.  The converged state is
+therefore the FP64 fixed point: converged mixed fields must equal converged
+FP64 fields (which are tied to the oracle iteration by iteration) to a relative
+L2 of 1e-6, and reproduce the closed-form discrete Poiseuille solutions.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from parity_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _solver(spec, gpu, **kw):
+    import torch
+    from paper_2606_06135_amd import Solver
+    kw.setdefault("p_rtol", 1e-2)
+    kw.setdefault("p_maxit", 200)
+    s = Solver.from_spec(spec, device=gpu, **kw)
+    s.set_indicator(torch.from_numpy(spec.lam.ravel()))
+    return s
+
+
+CONVERGING = {
+    "channel_ib_laminar": lambda: synth.case_channel_ib(nx=32, n_fluid=8),
+    "block2d_laminar": lambda: synth.case_cavity_block(),
+    "box3d_sst": lambda: synth.case_small_body3d(model="sst", shape="box", nu=1e-5),
+    "ahmed_small_sst": lambda: synth.case_ahmed_small(),
+}
+FIELDS = ("ux", "uy", "uz", "p", "k", "w")
+
+
+@pytest.mark.parametrize("name", list(CONVERGING))
+def test_mixed_converges_to_the_fp64_fixed_point(gpu, name):
+    spec = CONVERGING[name]()
+    _say("mixed vs FP64 fixed point", name, spec.ncells)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        s = _solver(spec, gpu, precision=prec)
+        done, res = s.iterate(3000, 1e-9, 10)
+        assert done < 3000 and max(res) <= 1e-9, (prec, done, res)
+        out[prec] = {k: s.get_field(k).cpu().numpy() for k in FIELDS}
+        _say(f"  {prec}: {done} iterations, max residual {max(res):.2e}")
+    for k in FIELDS:
+        a, b = out["fp64"][k], out["mixed"][k]
+        if np.abs(a).max() == 0.0:
+            assert np.abs(b).max() == 0.0
+            continue
+        err = rel_l2(b, a)
+        _say(f"  {k}: {err:.2e}")
+        assert err <= 1e-6, (name, k, err)
+
+
+def test_mixed_immersed_poiseuille_closed_form(gpu):
+    # grid-aligned immersed walls, laminar: the converged discrete solution is the
+    # parabola u_j = G/(2 nu) y_j (H - y_j) through 0 at the wall lines, with
+    # G = 12 nu (Q/H) / (H^2 + D^2/2) for the flux Q through a cross-section
+    spec = synth.case_channel_ib(nx=96, n_fluid=8, n_solid=2, nu=0.1, U=1.0)
+    s = _solver(spec, gpu, precision="mixed", p_rtol=1e-6)
+    done, res = s.iterate(6000, 1e-12, 20)
+    _say(f"mixed Poiseuille: {done} iterations, max residual {max(res):.2e}")
+    assert max(res) <= 1e-12
+    H, D, nu, i = 1.0, 1.0 / 8, 0.1, 56
+    ny, nx = spec.ny, spec.nx
+    u = s.get_field("ux").cpu().numpy().reshape(ny, nx)[:, i]
+    p = s.get_field("p").cpu().numpy().reshape(ny, nx)
+    jm = ny // 2
+    G_ = -(p[jm, i + 1] - p[jm, i - 1]) / (2 * spec.dx)
+    y = spec.y0 + (np.arange(ny) + 0.5) * spec.dy
+    fl = (y > 0) & (y < H)
+    np.testing.assert_allclose(u[fl], G_ / (2 * nu) * y[fl] * (H - y[fl]), rtol=1e-8, atol=1e-11)
+    Q = s.get_field("phix").cpu().numpy().reshape(ny, nx + 1)[:, i].sum()
+    Gx = 12 * nu * (Q / H) / (H ** 2 + D ** 2 / 2)
+    assert abs(G_ / Gx - 1.0) < 1e-7
+
+
+def test_mixed_pressure_solve_reaches_fp64_accuracy(gpu):
+    # FP32 V-cycle inside FP64 CG: the residual recurrence and the operator are FP64,
+    # so tight tolerances stay reachable; the solution equals a direct sparse solve
+    import scipy.sparse.linalg as spla
+    from oracle.solver import Simple
+    spec = synth.case_small_body3d(nx=32, ny=16, nz=16)
+    s = _solver(spec, gpu, precision="mixed", p_rtol=1e-13, p_maxit=400)
+    rng = np.random.default_rng(7)
+    rAU = 10 ** rng.uniform(-3, -1, size=spec.ncells)
+    rAU[spec.lam.ravel() >= 0.5] = 0.0
+    rhs = rng.standard_normal(spec.ncells)
+    x, it, rr = s.pressure_solve(rAU, rhs, np.zeros(spec.ncells), rtol=1e-12, maxit=400)
+    A = Simple(spec).pressure_matrix(rAU.reshape(spec.shape))
+    ref = spla.spsolve(A.tocsc(), rhs)
+    err = rel_l2(x.cpu().numpy(), ref)
+    _say(f"mixed pressure solve: {it} iterations, relres {rr:.2e}, error {err:.2e}")
+    assert rr <= 1e-12
+    assert err <= 1e-9
+    assert it < 120
+
+
+def test_mixed_runs_are_deterministic(gpu):
+    spec = synth.case_ahmed_small()
+    a = _solver(spec, gpu, precision="mixed")
+    b = _solver(spec, gpu, precision="mixed")
+    a.iterate(8)
+    b.iterate(8)
+    for k in ("ux", "p", "k", "w", "nut", "phiz"):
+        np.testing.assert_array_equal(a.get_field(k).cpu().numpy(), b.get_field(k).cpu().numpy())
+
+
+def test_mixed_checkpoint_resume_is_bitwise(gpu):
+    # set_field refreshes the FP32 coefficient mirrors, so a resumed run continues
+    # exactly like the uninterrupted one
+    spec = synth.case_small_body3d(model="sst", nu=1e-4)
+    s1 = _solver(spec, gpu, precision="mixed")
+    s1.iterate(6)
+    keys = ("ux", "uy", "uz", "p", "k", "w", "nut", "phix", "phiy", "phiz")
+    saved = {k: s1.get_field(k).clone() for k in keys}
+    s1.iterate(5)
+    s2 = _solver(spec, gpu, precision="mixed")
+    for k, v in saved.items():
+        s2.set_field(k, v)
+    s2.iterate(5)
+    for k in keys:
+        np.testing.assert_array_equal(s1.get_field(k).cpu().numpy(), s2.get_field(k).cpu().numpy())

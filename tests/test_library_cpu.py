@@ -53,6 +53,19 @@ def test_workspace_bytes_scale_with_grid(hiplib):
     assert 40 * 8 * 6400 < n2 < 120 * 8 * 6400
 
 
+def test_mixed_workspace_adds_fp32_arrays(hiplib):
+    """The mixed policy adds FP32 defects, corrections and mirrors (about 16
+    N-sized FP32 arrays incl. faces) and stores the coarse levels in FP32."""
+    spec = synth.case_bfs(nx=160, ny=40)
+    d, c = B.make_desc_config(spec)
+    dm, cm = B.make_desc_config(spec, precision="mixed")
+    st, n64 = _ws(d, c)
+    stm, nmx = _ws(dm, cm)
+    assert st == 0 and stm == 0
+    N = spec.ncells
+    assert 12 * 4 * N < nmx - n64 < 20 * 4 * N
+
+
 @pytest.mark.parametrize("mutate", [
     lambda d, c: setattr(d, "dim", 4),
     lambda d, c: setattr(d, "nx", 2),
@@ -62,7 +75,7 @@ def test_workspace_bytes_scale_with_grid(hiplib):
     lambda d, c: setattr(c, "urf_u", 1.5),
     lambda d, c: setattr(c, "nu", 0.0),
     lambda d, c: setattr(c, "n_sweeps", 0),
-    lambda d, c: setattr(c, "precision", 1),
+    lambda d, c: setattr(c, "precision", 2),
     lambda d, c: setattr(c, "continuity", 7),
     lambda d, c: setattr(c, "abi_version", 99),
 ])
