@@ -7,6 +7,12 @@ velocity update, SST transport with the imposed omega/P_k, k_ib and k correction
 turbulent viscosity, residuals).  Workload: the Ahmed-like bluff body in a
 256 x 96 x 96 channel (2 359 296 cells), k-omega SST, FP64, synthetic lambda.
 
+Besides the throughput line it measures the mixed-precision policy against
+FP64 at equal residual: both runs start from identical initial conditions on
+the 512 x 192 x 192 Ahmed-like workload (18.9 M cells) and iterate until the
+maximum normalised residual reaches 1e-8; the wall time of each, the speedup
+and the relative L2 difference of the converged fields are reported.
+
 Prints one JSON line (see the fields below).  --gpus N > 1 is refused: the
 library runs on one GPU.
 """
@@ -45,6 +51,10 @@ def main():
     ap.add_argument("--p-rtol", type=float, default=1e-2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--mixed-case", default="ahmed2", choices=["ahmed", "ahmed2", "none"])
+    ap.add_argument("--mixed-tol", type=float, default=1e-8)
+    ap.add_argument("--mixed-maxit", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path",
@@ -67,7 +77,7 @@ def main():
     N = spec.ncells
     log(f"lambda ready in {time.time() - t0:.1f}s; cells {N}")
     dev = torch.device("cuda:0")
-    solver = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=100)
+    solver = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=100, precision=args.precision)
     lam = torch.from_numpy(spec.lam.ravel()).to(dev)
     t0 = time.time()
     solver.set_indicator(lam)
@@ -112,6 +122,11 @@ def main():
                     "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_cell": ALGO_BYTES[dom]}
 
     value = N * done / elapsed
+    del solver
+    torch.cuda.empty_cache()
+    mixed = None
+    if args.mixed_case != "none":
+        mixed = mixed_vs_fp64(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(spec, args.p_rtol)
@@ -127,17 +142,54 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f64+f32",
         "data": "synthetic",
         "config": {"workload": spec.name + "_" + spec.model, "cells": N, "model": "k-omega SST" if spec.model == "sst"
-                   else spec.model, "precision": "fp64", "p_rtol": args.p_rtol, "n_sweeps": spec.n_sweeps,
+                   else spec.model, "precision": args.precision, "p_rtol": args.p_rtol, "n_sweeps": spec.n_sweeps,
                    "boundary_cells": counts["bc"], "insolid_cells": counts["ic"],
                    "pcg_iters_per_step": round(stats[0] / max(done, 1), 2), "finite": bool(finite),
                    "final_residuals": [float(x) for x in res]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "mixed_vs_fp64": mixed,
     }
     print(json.dumps(out), flush=True)
+
+
+def mixed_vs_fp64(args):
+    """Time to the residual target in FP64 and under the mixed policy from the
+    same initial conditions, and the difference of the converged fields."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_06135_amd import Solver
+    spec = synth.case_ahmed(scale=2 if args.mixed_case == "ahmed2" else 1)
+    dev = torch.device("cuda:0")
+    lam = torch.from_numpy(spec.lam.ravel()).to(dev)
+    runs, fields = {}, {}
+    for prec in ("fp64", "mixed"):
+        s = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=100, precision=prec)
+        s.set_indicator(lam)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done, res = s.iterate(args.mixed_maxit, args.mixed_tol, 25)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        runs[prec] = {"iterations": done, "seconds": round(dt, 3), "max_residual": max(res),
+                      "ms_per_iteration": round(dt / done * 1e3, 3),
+                      "cell_iters_per_s": spec.ncells * done / dt, "converged": max(res) <= args.mixed_tol}
+        log(f"{spec.name} {prec}: {done} iterations to {max(res):.2e} in {dt:.2f}s")
+        fields[prec] = {k: s.get_field(k).cpu().numpy() for k in ("ux", "uy", "uz", "p", "k", "w")}
+        del s
+        torch.cuda.empty_cache()
+    err = {}
+    for k, a in fields["fp64"].items():
+        b = fields["mixed"][k]
+        err[k] = float(np.linalg.norm(b - a) / max(np.linalg.norm(a), 1e-300))
+    return {"workload": spec.name + "_" + spec.model, "cells": spec.ncells, "target_residual": args.mixed_tol,
+            "fp64": runs["fp64"], "mixed": runs["mixed"],
+            "speedup": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 4),
+            "rel_l2_mixed_vs_fp64": err}
 
 
 def cpu_baseline(spec, p_rtol):
@@ -151,10 +203,12 @@ def cpu_baseline(spec, p_rtol):
     sim = Simple(spec, p_solver="cg", p_rtol=p_rtol)
     log(f"cpu baseline: precompute {time.time() - t0:.1f}s; timing one iteration")
     n_it = 1
-    t0 = time.perf_counter()
-    for _ in range(n_it):
-        sim.step()
-    dt = time.perf_counter() - t0
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for _ in range(n_it):
+            sim.step()
+        dt = time.perf_counter() - t0
     return {"value": spec.ncells * n_it / dt, "unit": "cell-iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_it} SIMPLE iteration(s) of the same {spec.ncells}-cell workload from the initial "
                       f"conditions, pressure by SciPy CG (rtol {p_rtol}), {dt:.1f}s wall"}

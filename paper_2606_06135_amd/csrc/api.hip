@@ -338,6 +338,13 @@ static void fill_params(hfdib_ctx* c) {
   P.cd_floor = g.cd_floor;
   P.Cmu25 = std::pow(g.Cmu, 0.25);
   P.sqrtCmu = std::sqrt(g.Cmu);
+  for (int d = 0; d < 3; ++d) {
+    P.AoD[d] = P.area[d] / P.delta[d];
+    P.Ab[d] = P.area[d] / (0.5 * P.delta[d]);
+    P.idelta[d] = 1.0 / P.delta[d];
+  }
+  P.isig_k = 1.0 / g.sigma_k;
+  P.isig_eps = 1.0 / g.sigma_eps;
   P.recorrect = g.recorrect;
   P.continuity = g.continuity;
   P.precision = g.precision;

@@ -123,7 +123,7 @@ __device__ __forceinline__ double ggrad(const Params& P, const double* a, long l
   long long st = stride(P, d);
   double fp = on_bnd(P, d, +1, i, j, k) ? fb_p : 0.5 * (a[c] + a[c + st]);
   double fm = on_bnd(P, d, -1, i, j, k) ? fb_m : 0.5 * (a[c - st] + a[c]);
-  return (fp - fm) / P.delta[d];
+  return (fp - fm) * P.idelta[d];
 }
 // d u_jj / d x_ii at cell (i,j,k) (index c, lambda > 0 flag `solid`)
 __device__ __forceinline__ double gradu(const Params& P, const double* const* u, bool solid, int ii, int jj, int i,

@@ -41,6 +41,9 @@ struct Params {
   double sigma_k1, sigma_w1, beta_1, gamma_1, sigma_k2, sigma_w2, beta_2, gamma_2, a1, c_lim;
   double bound_frac, yperp_min_frac, cd_floor;
   double Cmu25, sqrtCmu;  // Cmu^(1/4), sqrt(Cmu) (host-computed)
+  // host-computed reciprocals (kernels multiply instead of dividing): |S_d|/d_d,
+  // |S_d|/(d_d/2) for boundary faces, 1/d_d, 1/sigma_k and 1/sigma_eps
+  double AoD[3], Ab[3], idelta[3], isig_k, isig_eps;
   int recorrect;
   int continuity;
   int precision;  // HFDIB_FP64 or HFDIB_MIXED

@@ -32,15 +32,14 @@ using FineOp = FineOpT<double>;
 template <typename T>
 __device__ __forceinline__ T fine_coef(const Params& P, const FineOpT<T>& O, long long c, int d, int s, int i, int j,
                                        int k, long long* nb) {
-  const T A = (T)P.area[d], D = (T)P.delta[d];
   if (on_bnd(P, d, s, i, j, k)) {
     *nb = -1;
-    if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID)) return O.rAU[c] * A / ((T)0.5 * D);
+    if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID)) return O.rAU[c] * (T)P.Ab[d];
     return (T)0;
   }
   long long n = c + s * stride(P, d);
   *nb = n;
-  return s > 0 ? (T)0.5 * (O.rAU[c] + O.rAU[n]) * A / D : (T)0.5 * (O.rAU[n] + O.rAU[c]) * A / D;
+  return (T)0.5 * (O.rAU[c] + O.rAU[n]) * (T)P.AoD[d];
 }
 
 // y = A x (and partial sums of x.y)

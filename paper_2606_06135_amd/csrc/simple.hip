@@ -44,7 +44,7 @@ __device__ __forceinline__ double nut_wall(const Params& P, double yp) {
 // interior neighbour coefficient a_nb = D_f + max(-F_f, 0) (upwind, bounded form)
 __device__ __forceinline__ double anb_coef(const Params& P, double gP, double gN, int d, double F) {
   double mf = -F;
-  return 0.5 * (gP + gN) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
+  return 0.5 * (gP + gN) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
 }
 
 __device__ __forceinline__ double p_bface(const Params& P, int d, int s, bool solid, double pP) {
@@ -60,7 +60,7 @@ __device__ __forceinline__ double gradp_V(const Params& P, const double* p, uint
   bool solid = fl & F_SOLID;
   double fp = on_bnd(P, cc, +1, i, j, k) ? p_bface(P, cc, +1, solid, pP) : 0.5 * (pP + p[c + st]);
   double fm = on_bnd(P, cc, -1, i, j, k) ? p_bface(P, cc, -1, solid, pP) : 0.5 * (p[c - st] + pP);
-  return P.V * ((fp - fm) / P.delta[cc]);
+  return P.V * ((fp - fm) * P.idelta[cc]);
 }
 
 // ---------------------------------------------------------------- state init
@@ -261,7 +261,7 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
         }
         double F = outward_flux(P, M.phi, d, s, i, j, k);
         double mf = -F;
-        double a = Gb * P.area[d] / (0.5 * P.delta[d]) + (mf > 0.0 ? mf : 0.0);
+        double a = Gb * P.Ab[d] + (mf > 0.0 ? mf : 0.0);
         aP += a;
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
@@ -422,7 +422,7 @@ __device__ __forceinline__ unsigned mom_anb32(const Params& P, const Mir32& M, f
         long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
         float F = s > 0 ? M.phi[d][f] : -M.phi[d][f];
         float mf = -F;
-        anb[q] = 0.5f * (nuP + (nu + M.nut[n])) * (float)P.area[d] / (float)P.delta[d] + (mf > 0.0f ? mf : 0.0f);
+        anb[q] = 0.5f * (nuP + (nu + M.nut[n])) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
         vm |= 1u << q;
       }
     }
@@ -586,12 +586,12 @@ __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, 
     long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
     if (!on_bnd(P, d, +1, i, j, k)) {
       long long n = c + stride(P, d);
-      double cf = 0.5 * (rAU[c] + rAU[n]) * P.area[d] / P.delta[d];
+      double cf = 0.5 * (rAU[c] + rAU[n]) * P.AoD[d];
       ph[d][f + fo] = ph[d][f + fo] - cf * (psol[n] - psol[c]);
     }
     for (int s = -1; s <= 1; s += 2) {
       if (!on_bnd(P, d, s, i, j, k) || face_kind(P, d, s) != HFDIB_BC_OUTLET) continue;
-      double cb = solid ? 0.0 : rAU[c] * P.area[d] / (0.5 * P.delta[d]);
+      double cb = solid ? 0.0 : rAU[c] * P.Ab[d];
       long long ff = s > 0 ? f + fo : f;
       ph[d][ff] = ph[d][ff] + (double)s * cb * psol[c];
     }

@@ -82,7 +82,7 @@ __global__ void k_sum1(long long n, const double* a, double* part, long long pst
 
 // diffusion coefficient of the transported scalar (0: omega/eps, 1: k)
 __device__ __forceinline__ double gam(const Params& P, int eq, long long c, const double* nut, const double* F1) {
-  if (P.model == HFDIB_KEPS) return P.nu + nut[c] / (eq == 0 ? P.sigma_eps : P.sigma_k);
+  if (P.model == HFDIB_KEPS) return P.nu + nut[c] * (eq == 0 ? P.isig_eps : P.isig_k);
   double f = F1[c];
   double sg = eq == 0 ? f * P.sigma_w1 + (1.0 - f) * P.sigma_w2 : f * P.sigma_k1 + (1.0 - f) * P.sigma_k2;
   return P.nu + sg * nut[c];
@@ -116,7 +116,7 @@ __device__ __forceinline__ unsigned scal_anb(const Params& P, const Scal& S, int
       if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
         long long n = c + s * stride(P, d);
         double mf = -outward_flux(P, S.phi, d, s, i, j, k);
-        anb[q] = 0.5 * (gP + gam(P, eq, n, S.nut, S.F1)) * P.area[d] / P.delta[d] + (mf > 0.0 ? mf : 0.0);
+        anb[q] = 0.5 * (gP + gam(P, eq, n, S.nut, S.F1)) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
         vm |= 1u << q;
       }
     }
@@ -154,7 +154,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
         if (d >= P.dim || !on_bnd(P, d, s, i, j, k) || solid || face_kind(P, d, s) != HFDIB_BC_INLET) continue;
         double F = outward_flux(P, S.phi, d, s, i, j, k);
         double mf = -F;
-        double a = gP * P.area[d] / (0.5 * P.delta[d]) + (mf > 0.0 ? mf : 0.0);
+        double a = gP * P.Ab[d] + (mf > 0.0 ? mf : 0.0);
         aP += a;
         b0 += a * vin;
       }
@@ -278,7 +278,7 @@ struct Scal32 {
 };
 __device__ __forceinline__ float gam32(const Params& P, int eq, long long c, const float* nut, const float* F1) {
   const float nu = (float)P.nu;
-  if (P.model == HFDIB_KEPS) return nu + nut[c] / (float)(eq == 0 ? P.sigma_eps : P.sigma_k);
+  if (P.model == HFDIB_KEPS) return nu + nut[c] * (float)(eq == 0 ? P.isig_eps : P.isig_k);
   float f = F1[c];
   float a = (float)(eq == 0 ? P.sigma_w1 : P.sigma_k1), b = (float)(eq == 0 ? P.sigma_w2 : P.sigma_k2);
   return nu + (f * a + (1.0f - f) * b) * nut[c];
@@ -309,7 +309,7 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, int e
         long long n = c + s * stride(P, d);
         long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
         float mf = s > 0 ? -S.phi[d][f] : S.phi[d][f];
-        float a = 0.5f * (gP + gam32(P, eq, n, S.nut, S.F1)) * (float)P.area[d] / (float)P.delta[d] +
+        float a = 0.5f * (gP + gam32(P, eq, n, S.nut, S.F1)) * (float)P.AoD[d] +
                   (mf > 0.0f ? mf : 0.0f);
         nb += a * dv[n];
       }
