@@ -163,6 +163,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
   long long ps = nblk3 > nb1 ? nblk3 : nb1;
   c->pstride = (ps + 63) / 64 * 64;
   c->partials = B.take<double>(16 * c->pstride);
+  c->partials2 = B.take<double>(16 * FIN2_STRIDE);
   c->scal = B.take<double>(512);
   c->iscal = B.take<int>(64);
   bool mixed = P.precision == HFDIB_MIXED;
@@ -342,6 +343,22 @@ static void fill_params(hfdib_ctx* c) {
     P.AoD[d] = P.area[d] / P.delta[d];
     P.Ab[d] = P.area[d] / (0.5 * P.delta[d]);
     P.idelta[d] = 1.0 / P.delta[d];
+  }
+  for (int f = 0; f < 6; ++f) {
+    int kind = d.bc[f], dn = f / 2;
+    for (int cc = 0; cc < 3; ++cc) {
+      double A = 1.0, Bv = 0.0;  // outlet, empty: zero gradient
+      if (kind == HFDIB_BC_INLET) {
+        A = 0.0;
+        Bv = d.u_in[cc];
+      } else if (kind == HFDIB_BC_NOSLIP || (kind == HFDIB_BC_SLIP && cc == dn)) {
+        A = 0.0;
+      }
+      P.ubA[f][cc] = A;
+      P.ubB[f][cc] = Bv;
+    }
+    P.sc_inlet[f] = kind == HFDIB_BC_INLET ? 1 : 0;
+    P.p_outlet[f] = kind == HFDIB_BC_OUTLET ? 1 : 0;
   }
   P.isig_k = 1.0 / g.sigma_k;
   P.isig_eps = 1.0 / g.sigma_eps;

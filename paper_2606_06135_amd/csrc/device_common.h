@@ -98,31 +98,53 @@ __device__ __forceinline__ void tile_ijk(const Params& P, int& i, int& j, int& k
   j = by * 4 + (int)threadIdx.y;
 }
 
+// Red-black half sweeps run on a grid of half the x extent: thread t of a row
+// handles the cell i = 2 t + ((j + k + color) & 1), the one of the active
+// colour (no idle lanes); same XCD-contiguous tile order as tile_ijk.
+__device__ __forceinline__ void tile_ijk_rb(const Params& P, int color, int& i, int& j, int& k) {
+  unsigned nb = gridDim.x, b = blockIdx.x;
+  unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, id = b >> 3;
+  unsigned L = x < r ? x * (q + 1) + id : r * (q + 1) + (x - r) * q + id;
+  int nxh = (P.nx + 1) >> 1;
+  int tx = (nxh + 63) >> 6, ty = (P.ny + 3) >> 2;
+  int bx = (int)(L % (unsigned)tx);
+  unsigned rest = L / (unsigned)tx;
+  int by = (int)(rest % (unsigned)ty);
+  k = (int)(rest / (unsigned)ty);
+  j = by * 4 + (int)threadIdx.y;
+  // t >= nxh gives i >= nx and i ^ 1 >= nx (both cells of the pair outside)
+  int t = bx * 64 + (int)threadIdx.x;
+  i = 2 * t + ((j + k + color) & 1);
+}
+
 __device__ __forceinline__ long long block_linear() {
   return (long long)blockIdx.x + (long long)gridDim.x * ((long long)blockIdx.y + (long long)gridDim.y * blockIdx.z);
 }
 
 // ---------------------------------------------------------------- gradients
 // Gauss face value of velocity component cc on the domain face (d, s)
+// (inlet u_in, no-slip 0, slip: normal component 0, outlet: owner value;
+// faces of cells with lambda > 0: owner value).  Branch free: affine map with
+// host-computed coefficients, exact for finite uP.
 __device__ __forceinline__ double u_bface(const Params& P, int cc, int d, int s, bool solid, double uP) {
-  if (solid) return uP;
-  int kind = face_kind(P, d, s);
-  if (kind == HFDIB_BC_INLET) return P.u_in[cc];
-  if (kind == HFDIB_BC_NOSLIP) return 0.0;
-  if (kind == HFDIB_BC_SLIP) return cc == d ? 0.0 : uP;
-  return uP;
+  const int f = 2 * d + (s > 0 ? 1 : 0);
+  double v = P.ubA[f][cc] * uP + P.ubB[f][cc];
+  return solid ? uP : v;
 }
 // Gauss face value of a transported scalar (inlet value at inlets, else zero gradient)
 __device__ __forceinline__ double sc_bface(const Params& P, int d, int s, bool solid, double vP, double vin) {
-  if (face_kind(P, d, s) == HFDIB_BC_INLET && !solid) return vin;
-  return vP;
+  const bool inl = P.sc_inlet[2 * d + (s > 0 ? 1 : 0)] != 0;
+  return (inl && !solid) ? vin : vP;
 }
 // (psi_+ - psi_-)/delta_d with linear face interpolation (Gauss gradient)
+// (loads from clamped indices: no branch around them)
 __device__ __forceinline__ double ggrad(const Params& P, const double* a, long long c, int d, int i, int j, int k,
                                        double fb_p, double fb_m) {
   long long st = stride(P, d);
-  double fp = on_bnd(P, d, +1, i, j, k) ? fb_p : 0.5 * (a[c] + a[c + st]);
-  double fm = on_bnd(P, d, -1, i, j, k) ? fb_m : 0.5 * (a[c - st] + a[c]);
+  const bool hi = on_bnd(P, d, +1, i, j, k), lo = on_bnd(P, d, -1, i, j, k);
+  double aP = a[c], ap = a[hi ? c : c + st], am = a[lo ? c : c - st];
+  double fp = hi ? fb_p : 0.5 * (aP + ap);
+  double fm = lo ? fb_m : 0.5 * (am + aP);
   return (fp - fm) * P.idelta[d];
 }
 // d u_jj / d x_ii at cell (i,j,k) (index c, lambda > 0 flag `solid`)
@@ -152,6 +174,66 @@ __device__ __forceinline__ double strain2(const double (&G)[3][3]) {
       S2 = S2 + 2.0 * sij * sij;
     }
   return S2;
+}
+
+// ---------------------------------------------------------------- neighbourhood
+// Clamped neighbour indices of a cell (the cell itself across a domain face)
+// and the mask of domain faces.  Stencil kernels load every neighbour value
+// unconditionally from these indices (always in bounds) and select boundary
+// values afterwards, so no load sits inside a divergent branch.  Face
+// q = 2 d + (s > 0) in the order W, E, S, N, B, T; faces beyond dim count as
+// domain faces.
+struct Nbr {
+  long long n[6];
+  unsigned bnd;  // bit q: face q is a domain face
+};
+__device__ __forceinline__ Nbr make_nbr(const Params& P, int i, int j, int k, long long c) {
+  Nbr N;
+  N.bnd = 0u;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    long long st = stride(P, d);
+    int a = comp(d, i, j, k);
+    bool lo = d >= P.dim || a == 0, hi = d >= P.dim || a == ncell(P, d) - 1;
+    N.n[2 * d] = lo ? c : c - st;
+    N.n[2 * d + 1] = hi ? c : c + st;
+    N.bnd |= (lo ? 1u : 0u) << (2 * d);
+    N.bnd |= (hi ? 1u : 0u) << (2 * d + 1);
+  }
+  return N;
+}
+__device__ __forceinline__ bool is_bnd(const Nbr& N, int q) { return (N.bnd >> q) & 1u; }
+
+// d u_jc / d x_a at cell x (Gauss, linear face interpolation) from clamped
+// loads; lo / hi: x lies on the low / high domain face along a; solid: lambda > 0
+__device__ __forceinline__ double gradu_bf(const Params& P, const double* uj, int jc, int a, long long x, bool lo,
+                                           bool hi, bool solid) {
+  long long st = stride(P, a);
+  double uP = uj[x];
+  double up = uj[hi ? x : x + st];
+  double um = uj[lo ? x : x - st];
+  double fp = hi ? u_bface(P, jc, a, +1, solid, uP) : 0.5 * (uP + up);
+  double fm = lo ? u_bface(P, jc, a, -1, solid, uP) : 0.5 * (um + uP);
+  return (fp - fm) * P.idelta[a];
+}
+// (psi_+ - psi_-)/delta_d of a scalar from clamped loads (boundary face values given)
+__device__ __forceinline__ double ggrad_bf(const Params& P, const double* a, const Nbr& N, long long c, int d,
+                                           double fb_p, double fb_m) {
+  double aP = a[c], ap = a[N.n[2 * d + 1]], am = a[N.n[2 * d]];
+  double fp = is_bnd(N, 2 * d + 1) ? fb_p : 0.5 * (aP + ap);
+  double fm = is_bnd(N, 2 * d) ? fb_m : 0.5 * (am + aP);
+  return (fp - fm) * P.idelta[d];
+}
+// full velocity gradient G[a][jc] = d u_jc / d x_a at a cell (zero outside dim)
+__device__ __forceinline__ void gradu_all_bf(const Params& P, const double* const* u, bool solid, const Nbr& N,
+                                             long long c, double (&G)[3][3]) {
+#pragma unroll
+  for (int jc = 0; jc < 3; ++jc)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      G[a][jc] = (a < P.dim && jc < P.dim)
+                     ? gradu_bf(P, u[jc], jc, a, c, is_bnd(N, 2 * a), is_bnd(N, 2 * a + 1), solid)
+                     : 0.0;
 }
 
 // ---------------------------------------------------------------- geometry

@@ -24,6 +24,7 @@ constexpr int NTHREADS = 256;
 constexpr int MAX_PARTIAL_BLOCKS = 2048;  // per reduction slot
 constexpr int NRED = 24;                  // reduction slots per pass
 constexpr int MAX_LEVELS = 12;
+constexpr int FIN2_STRIDE = 1024;         // second-stage partials per reduction row
 
 // Plain-old-data parameters passed by value to every kernel.
 struct Params {
@@ -44,6 +45,12 @@ struct Params {
   // host-computed reciprocals (kernels multiply instead of dividing): |S_d|/d_d,
   // |S_d|/(d_d/2) for boundary faces, 1/d_d, 1/sigma_k and 1/sigma_eps
   double AoD[3], Ab[3], idelta[3], isig_k, isig_eps;
+  // boundary face values as affine maps of the owner value (cells with
+  // lambda = 0): velocity component cc on face f = 2d + (s > 0) is
+  // ubA[f][cc] u_P + ubB[f][cc]; scalars take their inlet value where
+  // sc_inlet[f] != 0; the pressure is 0 where p_outlet[f] != 0
+  double ubA[6][3], ubB[6][3];
+  int sc_inlet[6], p_outlet[6];
   int recorrect;
   int continuity;
   int precision;  // HFDIB_FP64 or HFDIB_MIXED
@@ -106,6 +113,7 @@ struct hfdib_ctx {
   // --- reductions
   double* partials;  // 16 rows of pstride partial sums
   long long pstride;
+  double* partials2; // 16 rows of FIN2_STRIDE second-stage partials
   double* scal;      // 512 scalars
   int* iscal;        // 64 ints
   double* host_scal; // pinned? plain host mirror (filled by sync copies)
@@ -126,6 +134,10 @@ inline dim3 grid3(const Params& P) {
   return dim3((unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4) * P.nz), 1, 1);
 }
 inline dim3 block3() { return dim3(64, 4, 1); }
+// grid of the red-black half sweeps (half the x extent, see tile_ijk_rb)
+inline dim3 grid3_rb(const Params& P) {
+  return dim3((unsigned)((((P.nx + 1) / 2 + 63) / 64) * ((P.ny + 3) / 4) * P.nz), 1, 1);
+}
 inline int nblocks1(long long n) {
   long long b = (n + NTHREADS - 1) / NTHREADS;
   return (int)(b < 1 ? 1 : b);

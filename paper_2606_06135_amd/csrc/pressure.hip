@@ -42,6 +42,45 @@ __device__ __forceinline__ T fine_coef(const Params& P, const FineOpT<T>& O, lon
   return (T)0.5 * (O.rAU[c] + O.rAU[n]) * (T)P.AoD[d];
 }
 
+// The six face coefficients of a fine-level row from clamped loads (no branch
+// around a load): c_f = mean(rAU) |S|/d inside, rAU_P |S|/(d/2) on outlet faces
+// of cells with lambda = 0, 0 on other domain faces and beyond dim.
+template <typename T>
+__device__ __forceinline__ void fine_row(const Params& P, const FineOpT<T>& O, const Nbr& N, long long c,
+                                         T (&cf)[6]) {
+  const T rc = O.rAU[c];
+  const bool solid = O.flags[c] & F_SOLID;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int d = q >> 1;
+    cf[q] = (T)0;
+    if (d < P.dim) {
+      T inner = (T)0.5 * (rc + O.rAU[N.n[q]]) * (T)P.AoD[d];
+      T outl = (P.p_outlet[q] && !solid) ? rc * (T)P.Ab[d] : (T)0;
+      cf[q] = is_bnd(N, q) ? outl : inner;
+    }
+  }
+}
+
+// (A x)_c of a fine row and the sum of its coefficients (0: uncoupled row)
+template <typename T>
+__device__ __forceinline__ T fine_Ax(const T (&cf)[6], const Nbr& N, const T* x, long long c, T& dg,
+                                     T& bnd_sum) {
+  const T xc = x[c];
+  T acc = (T)0, bs = (T)0;
+  dg = (T)0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const bool b = is_bnd(N, q);
+    const T xn = x[N.n[q]];
+    acc += b ? cf[q] * xc : cf[q] * (xc - xn);
+    bs += b ? cf[q] : (T)0;
+    dg += cf[q];
+  }
+  bnd_sum = bs;
+  return acc;
+}
+
 // y = A x (and partial sums of x.y)
 __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, double* part, long long pstride) {
   int i, j, k;
@@ -49,15 +88,11 @@ __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, dou
   double v[1] = {0.0};
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
+    Nbr N = make_nbr(P, i, j, k, c);
+    double cf[6], dg, bs;
+    fine_row(P, O, N, c, cf);
     double xc = x[c];
-    double acc = 0.0, dg = 0.0;
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        long long n;
-        double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
-        acc += n < 0 ? cf * xc : cf * (xc - x[n]);
-        dg += cf;
-      }
+    double acc = fine_Ax(cf, N, x, c, dg, bs);
     if (dg == 0.0) acc = xc;  // uncoupled row: identity
     y[c] = acc;
     v[0] = xc * acc;
@@ -65,8 +100,9 @@ __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, dou
   block_sums_store<1>(v, part, pstride, block_linear());
 }
 
-// r = b - A x; partial sums of r.r, b.b and (for the SIMPLE residual) |r|,
-// |Ax - A xbar|, |b - A xbar| with xbar = *xmean (nullable)
+// r = b - A x (and its FP32 copy when r32 is given); partial sums of r.r, b.b
+// and (for the SIMPLE residual) |r|, |Ax - A xbar|, |b - A xbar| with
+// xbar = *xmean (nullable)
 __global__ void k_fine_residual(Params P, FineOp O, const double* b, const double* x, double* r, float* r32,
                                 const double* xmean, double* part, long long pstride) {
   int i, j, k;
@@ -74,22 +110,12 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
   double v[5] = {0, 0, 0, 0, 0};
   if (i < P.nx && j < P.ny) {
     long long c = cidx(P, i, j, k);
+    Nbr N = make_nbr(P, i, j, k, c);
+    double cf[6], dg, bnd;
+    fine_row(P, O, N, c, cf);
     double xc = x[c];
-    double acc = 0.0, bnd = 0.0, dg = 0.0;
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2) {
-        long long n;
-        double cf = fine_coef(P, O, c, d, s, i, j, k, &n);
-        dg += cf;
-        if (n < 0) {
-          acc += cf * xc;
-          bnd += cf;
-        } else {
-          acc += cf * (xc - x[n]);
-        }
-      }
-    bool ident = dg == 0.0;  // uncoupled row: identity
-    if (ident) {
+    double acc = fine_Ax(cf, N, x, c, dg, bnd);
+    if (dg == 0.0) {  // uncoupled row: identity
       acc = xc;
       bnd = 1.0;
     }
@@ -114,26 +140,24 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
 template <typename T>
 __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* r, T* z, int color, int init) {
   int i, j, k;
-  tile_ijk(P, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
-  long long c = cidx(P, i, j, k);
-  bool mine = ((i + j + k) & 1) == color;
-  if (init && !mine) {
-    z[c] = (T)0;
-    return;
+  tile_ijk_rb(P, color, i, j, k);
+  if (j >= P.ny) return;
+  if (init) {
+    // the partner cell of the other colour in this pair starts from z = 0
+    int io = i ^ 1;
+    if (io < P.nx) z[cidx(P, io, j, k)] = (T)0;
   }
-  if (!mine) return;
+  if (i >= P.nx) return;
+  long long c = cidx(P, i, j, k);
+  Nbr N = make_nbr(P, i, j, k, c);
+  T cf[6];
+  fine_row(P, O, N, c, cf);
   T diag = (T)0, nb = (T)0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int sh = 0; sh < 2; ++sh) {
-      if (d >= P.dim) continue;
-      long long n;
-      T cf = fine_coef(P, O, c, d, sh ? 1 : -1, i, j, k, &n);
-      diag += cf;
-      if (n >= 0 && !init) nb += cf * z[n];
-    }
+  for (int q = 0; q < 6; ++q) {
+    diag += cf[q];
+    if (!init) nb += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
+  }
   z[c] = diag == (T)0 ? r[c] : (r[c] + nb) / diag;
 }
 
@@ -312,25 +336,18 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* r, const T* z, 
   int J = blockIdx.y * blockDim.y + threadIdx.y;
   int K = blockIdx.z;
   if (I >= C.nx || J >= C.ny) return;
-  int nzs = C.dim == 3 ? 2 : 1;
+  const int nzs = C.dim == 3 ? 2 : 1;
   T s = (T)0;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = cidx(P, i, j, k);
-        T zc = z[c], acc = (T)0, dg = (T)0;
-#pragma unroll
-        for (int d = 0; d < 3; ++d)
-#pragma unroll
-          for (int sh = 0; sh < 2; ++sh) {
-            if (d >= P.dim) continue;
-            long long n;
-            T cf = fine_coef(P, O, c, d, sh ? 1 : -1, i, j, k, &n);
-            acc += n < 0 ? cf * zc : cf * (zc - z[n]);
-            dg += cf;
-          }
-        if (dg == (T)0) acc = zc;
+        Nbr N = make_nbr(P, i, j, k, c);
+        T cf[6], dg, bs;
+        fine_row(P, O, N, c, cf);
+        T acc = fine_Ax(cf, N, z, c, dg, bs);
+        if (dg == (T)0) acc = z[c];
         s += r[c] - acc;
       }
   C.r[lidx(C, I, J, K)] = s;
@@ -503,6 +520,30 @@ __global__ void k_to_f32(long long n, const double* a, float* b) {
   if (c < n) b[c] = (float)a[c];
 }
 
+// first stage of a large reduction: workgroup (b, v) reduces entries
+// [b chunk, (b+1) chunk) of partial row v (sum, or max when is_max) into
+// out[v * FIN2_STRIDE + b]
+constexpr int RED_THREADS = 256;
+constexpr int FIN2_CHUNKS = 512;
+__global__ void __launch_bounds__(RED_THREADS)
+k_reduce_chunks(const double* part, long long pstride, int nblk, int chunk, int is_max, double* out) {
+  __shared__ double lds[RED_THREADS / 64];
+  const double* row = part + (long long)blockIdx.y * pstride;
+  int b0 = blockIdx.x * chunk;
+  int b1 = b0 + chunk < nblk ? b0 + chunk : nblk;
+  double s = 0.0;
+  for (int b = b0 + (int)threadIdx.x; b < b1; b += RED_THREADS) s = is_max ? fmax(s, row[b]) : s + row[b];
+  s = is_max ? wave_max(s) : wave_sum(s);
+  int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) lds[wid] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = lds[0];
+    for (int w = 1; w < RED_THREADS / 64; ++w) t = is_max ? fmax(t, lds[w]) : t + lds[w];
+    out[(long long)blockIdx.y * FIN2_STRIDE + blockIdx.x] = t;
+  }
+}
+
 // finalize: reduces `nval` rows of per-block partials -> scal[out+v] (sums, or
 // maxima for op 4), then an optional PCG scalar update.  One workgroup of 1024
 // threads; fixed reduction order (deterministic).
@@ -570,16 +611,28 @@ static LevelDevT<T> levdev(hfdib_ctx* c, int l) {
 static dim3 lgrid(int nx, int ny, int nz) { return dim3((nx + 63) / 64, (ny + 3) / 4, nz); }
 
 // finalize helper; partial slots live in ctx->partials with row stride c->pstride
+// Large partial rows are first reduced in fixed chunks by many workgroups
+// (deterministic: fixed chunk boundaries and order), then by one workgroup.
 void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, c->stream, c->partials + (long long)row0 * c->pstride,
-                     c->pstride, nblk, nval, c->scal + SCAL_PCG, out, op, divisor);
+  const double* part = c->partials + (long long)row0 * c->pstride;
+  if (nblk > 4 * FIN_THREADS) {
+    int chunk = (nblk + FIN2_CHUNKS - 1) / FIN2_CHUNKS;
+    int nchunks = (nblk + chunk - 1) / chunk;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), 0, c->stream, part, c->pstride, nblk,
+                       chunk, op == 4 ? 1 : 0, c->partials2);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, c->stream, (const double*)c->partials2,
+                       (long long)FIN2_STRIDE, nchunks, nval, c->scal + SCAL_PCG, out, op, divisor);
+    return;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, c->stream, part, c->pstride, nblk, nval,
+                     c->scal + SCAL_PCG, out, op, divisor);
 }
 
 // one V-cycle z = M^-1 r in storage type T
 template <typename T>
 static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* r, T* z) {
   const Params& P = c->P;
-  dim3 g = grid3(P), b = block3();
+  dim3 g = grid3_rb(P), b = block3();
   hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 0, 1);
   hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 1, 0);
   if (c->nlev > 1) {

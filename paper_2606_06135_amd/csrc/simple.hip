@@ -48,18 +48,19 @@ __device__ __forceinline__ double anb_coef(const Params& P, double gP, double gN
 }
 
 __device__ __forceinline__ double p_bface(const Params& P, int d, int s, bool solid, double pP) {
-  if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !solid) return 0.0;
-  return pP;
+  const bool outl = P.p_outlet[2 * d + (s > 0 ? 1 : 0)] != 0;
+  return (outl && !solid) ? 0.0 : pP;
 }
 
 // V (grad p)_c at cell (i,j,k), Gauss with linear interpolation
 __device__ __forceinline__ double gradp_V(const Params& P, const double* p, uint8_t fl, int cc, int i, int j,
                                           int k, long long c) {
   long long st = stride(P, cc);
-  double pP = p[c];
   bool solid = fl & F_SOLID;
-  double fp = on_bnd(P, cc, +1, i, j, k) ? p_bface(P, cc, +1, solid, pP) : 0.5 * (pP + p[c + st]);
-  double fm = on_bnd(P, cc, -1, i, j, k) ? p_bface(P, cc, -1, solid, pP) : 0.5 * (p[c - st] + pP);
+  const bool hi = on_bnd(P, cc, +1, i, j, k), lo = on_bnd(P, cc, -1, i, j, k);
+  double pP = p[c], pp = p[hi ? c : c + st], pm = p[lo ? c : c - st];
+  double fp = hi ? p_bface(P, cc, +1, solid, pP) : 0.5 * (pP + pp);
+  double fm = lo ? p_bface(P, cc, -1, solid, pP) : 0.5 * (pm + pP);
   return P.V * ((fp - fm) * P.idelta[cc]);
 }
 
@@ -186,34 +187,28 @@ __global__ void k_wall_pre(Params P, int nw, const int* wall_cells, const double
 }
 
 // ---------------------------------------------------------------- momentum
-// Neighbour coefficients of a momentum row at an active cell: anb[q] for the
-// faces q = 2d + (s > 0) in the order W, E, S, N, B, T, bit q of the returned
-// mask set for interior faces (0 and clear on domain faces and beyond dim).
-// Loops are unrolled over three directions so that every index is static.
-__device__ __forceinline__ unsigned mom_anb(const Params& P, const Mom& M, double nuP, int i, int j, int k,
-                                            long long c, double (&anb)[6]) {
-  unsigned vm = 0u;
+// Neighbour coefficients of a momentum row: anb[q] for the faces q = 2d + (s>0)
+// in the order W, E, S, N, B, T, 0 on domain faces and beyond dim (loads from
+// clamped indices, no branches around them)
+__device__ __forceinline__ void mom_anb(const Params& P, const Mom& M, double nuP, const Nbr& N, int i, int j, int k,
+                                        double (&anb)[6]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int sh = 0; sh < 2; ++sh) {
       const int s = sh ? 1 : -1, q = 2 * d + sh;
       anb[q] = 0.0;
-      if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
-        long long n = c + s * stride(P, d);
-        anb[q] = anb_coef(P, nuP, P.nu + M.nut[n], d, outward_flux(P, M.phi, d, s, i, j, k));
-        vm |= 1u << q;
+      if (d < P.dim) {
+        double a = anb_coef(P, nuP, P.nu + M.nut[N.n[q]], d, outward_flux(P, M.phi, d, s, i, j, k));
+        anb[q] = is_bnd(N, q) ? 0.0 : a;
       }
     }
-  return vm;
 }
-// sum over interior faces of anb * x_nb, faces in the order W, E, S, N, B, T
-__device__ __forceinline__ double nb_sum(const Params& P, const double (&anb)[6], unsigned vm, const double* x,
-                                         long long c) {
+// sum over the faces of anb * x_nb (domain faces carry anb = 0), order W..T
+__device__ __forceinline__ double nb_sum(const double (&anb)[6], const Nbr& N, const double* x) {
   double nb = 0.0;
 #pragma unroll
-  for (int q = 0; q < 6; ++q)
-    if (vm & (1u << q)) nb += anb[q] * x[c + ((q & 1) ? 1 : -1) * stride(P, q >> 1)];
+  for (int q = 0; q < 6; ++q) nb += anb[q] * x[N.n[q]];
   return nb;
 }
 
@@ -229,15 +224,15 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
   double red[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (act) {
     long long c = cidx(P, i, j, k);
+    Nbr N = make_nbr(P, i, j, k, c);
     uint8_t fl = M.flags[c];
     bool solid = fl & F_SOLID;
     double nuP = P.nu + M.nut[c];
     double anb[6];
-    unsigned vm = mom_anb(P, M, nuP, i, j, k, c, anb);
+    mom_anb(P, M, nuP, N, i, j, k, anb);
     double aP = 0.0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      if (vm & (1u << q)) aP += anb[q];
+    for (int q = 0; q < 6; ++q) aP += anb[q];
     // Dirichlet domain faces (inlet, no-slip) of cells with lambda = 0
     double bsrc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -245,9 +240,9 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
 #pragma unroll
       for (int sh = 0; sh < 2; ++sh) {
         const int s = sh ? 1 : -1;
-        if (d >= P.dim || !on_bnd(P, d, s, i, j, k) || solid) continue;
         int kind = face_kind(P, d, s);
-        if (kind != HFDIB_BC_INLET && kind != HFDIB_BC_NOSLIP) continue;
+        if (d >= P.dim || (kind != HFDIB_BC_INLET && kind != HFDIB_BC_NOSLIP)) continue;
+        if (!is_bnd(N, 2 * d + sh) || solid) continue;
         double Gb = nuP;
         if (kind == HFDIB_BC_NOSLIP) {
           if (P.model == HFDIB_LAMINAR) {
@@ -276,30 +271,42 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
     if (X.a) X.a[c] = (float)aPr;
     bool alpha = fl & F_ALPHA_U;
     double* rhs[3] = {rhs0, rhs1, rhs2};
+    // neighbour data shared by the three components
+    bool solidN[6];
+    double nuN[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      solidN[q] = M.flags[N.n[q]] & F_SOLID;
+      nuN[q] = P.nu + M.nut[N.n[q]];
+    }
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       if (cc >= P.dim) continue;
       // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f, the
       // face gradient being the mean of the two cell (Gauss) gradients
+      const bool loP = is_bnd(N, 2 * cc), hiP = is_bnd(N, 2 * cc + 1);
       double T = 0.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         if (d >= P.dim) continue;
-        double GP = gradu(P, M.u, solid, cc, d, i, j, k, c);
+        double GP = gradu_bf(P, M.u[d], d, cc, c, loP, hiP, solid);
 #pragma unroll
         for (int sh = 0; sh < 2; ++sh) {
-          const int s = sh ? 1 : -1;
-          double nuf, gf;
-          if (on_bnd(P, d, s, i, j, k)) {
-            nuf = nuP;
-            gf = GP;
+          const int s = sh ? 1 : -1, q = 2 * d + sh;
+          const bool fb = is_bnd(N, q);
+          // domain faces of the neighbour along cc (all faces when it does not exist)
+          bool loN, hiN;
+          if (cc == d) {
+            int a = comp(d, i, j, k) + s;
+            loN = fb || a == 0;
+            hiN = fb || a == ncell(P, d) - 1;
           } else {
-            long long n = c + s * stride(P, d);
-            int in = i + (d == 0 ? s : 0), jn = j + (d == 1 ? s : 0), kn = k + (d == 2 ? s : 0);
-            double GN = gradu(P, M.u, (M.flags[n] & F_SOLID) != 0, cc, d, in, jn, kn, n);
-            nuf = 0.5 * (nuP + (P.nu + M.nut[n]));
-            gf = 0.5 * (GP + GN);
+            loN = fb || loP;
+            hiN = fb || hiP;
           }
+          double GN = gradu_bf(P, M.u[d], d, cc, N.n[q], loN, hiN, solidN[q]);
+          double nuf = fb ? nuP : 0.5 * (nuP + nuN[q]);
+          double gf = fb ? GP : 0.5 * (GP + GN);
           T += (double)s * P.area[d] * nuf * gf;
         }
       }
@@ -308,14 +315,14 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
       const double* u = M.u[cc];
       double uo = u[c];
       double r = (1.0 - urf) / urf * aP * uo;
+      double nb = nb_sum(anb, N, u);
       double rh;
       if (alpha) {
         const double* ub = M.uib[cc];
         double nbt = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          if (!(vm & (1u << q))) continue;
-          long long n = c + ((q & 1) ? 1 : -1) * stride(P, q >> 1);
+          long long n = N.n[q];
           double ut = (M.flags[n] & F_ALPHA_U) ? ub[n] : u[n];
           nbt += anb[q] * ut;
         }
@@ -325,24 +332,18 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
         rh = (b0 - g) + r;
       }
       rhs[cc][c] = rh;
-      if (!alpha || X.a) {
-        double nb = 0.0, one = 0.0;
+      double Ax = aPr * uo - nb;
+      // mixed policy: FP64 defect of the row (every row is swept) for the FP32
+      // correction
+      if (X.a) X.r[cc][c] = (float)(rh - Ax);
+      if (!alpha) {
+        double one = 0.0;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) {
-          if (!(vm & (1u << q))) continue;
-          nb += anb[q] * u[c + ((q & 1) ? 1 : -1) * stride(P, q >> 1)];
-          one += anb[q];
-        }
-        double Ax = aPr * uo - nb;
-        // mixed policy: FP64 defect of the row (every row is swept) for the
-        // FP32 correction
-        if (X.a) X.r[cc][c] = (float)(rh - Ax);
-        if (!alpha) {
-          double Axb = (aPr - one) * means[cc];
-          red[3 * cc + 0] = fabs(rh - Ax);
-          red[3 * cc + 1] = fabs(Ax - Axb);
-          red[3 * cc + 2] = fabs(rh - Axb);
-        }
+        for (int q = 0; q < 6; ++q) one += anb[q];
+        double Axb = (aPr - one) * means[cc];
+        red[3 * cc + 0] = fabs(rh - Ax);
+        red[3 * cc + 1] = fabs(Ax - Axb);
+        red[3 * cc + 2] = fabs(rh - Axb);
       }
     }
     // turbulence inputs of the previous iterate (k, omega unchanged until the
@@ -353,8 +354,8 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         if (d >= P.dim) continue;
-        gk[d] = ggrad(P, M.k, c, d, i, j, k, sc_bface(P, d, +1, solid, kk, P.k_in), sc_bface(P, d, -1, solid, kk, P.k_in));
-        gw[d] = ggrad(P, M.w, c, d, i, j, k, sc_bface(P, d, +1, solid, ww, P.w_in), sc_bface(P, d, -1, solid, ww, P.w_in));
+        gk[d] = ggrad_bf(P, M.k, N, c, d, sc_bface(P, d, +1, solid, kk, P.k_in), sc_bface(P, d, -1, solid, kk, P.k_in));
+        gw[d] = ggrad_bf(P, M.w, N, c, d, sc_bface(P, d, +1, solid, ww, P.w_in), sc_bface(P, d, -1, solid, ww, P.w_in));
       }
       double kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
       double dwc = M.dw[c];
@@ -388,17 +389,16 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
 __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
                             const double* aPr, double* u0, double* u1, double* u2, int color) {
   int i, j, k;
-  tile_ijk(P, i, j, k);
+  tile_ijk_rb(P, color, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
-  if (((i + j + k) & 1) != color) return;
   long long c = cidx(P, i, j, k);
-  double nuP = P.nu + M.nut[c];
+  Nbr N = make_nbr(P, i, j, k, c);
   double anb[6];
-  unsigned vm = mom_anb(P, M, nuP, i, j, k, c, anb);
+  mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
   double a = aPr[c];
-  u0[c] = (rhs0[c] + nb_sum(P, anb, vm, u0, c)) / a;
-  u1[c] = (rhs1[c] + nb_sum(P, anb, vm, u1, c)) / a;
-  if (P.dim == 3) u2[c] = (rhs2[c] + nb_sum(P, anb, vm, u2, c)) / a;
+  u0[c] = (rhs0[c] + nb_sum(anb, N, u0)) / a;
+  u1[c] = (rhs1[c] + nb_sum(anb, N, u1)) / a;
+  if (P.dim == 3) u2[c] = (rhs2[c] + nb_sum(anb, N, u2)) / a;
 }
 
 // Mixed policy: one colour of a red-black Gauss-Seidel sweep of the FP32
@@ -407,57 +407,46 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
 // (cells of the other colour set to 0); fin: last sweep of this colour, which
 // also writes u <- u_old + d in FP64.  Equal to the FP64 sweeps from u_old in
 // exact arithmetic.
-__device__ __forceinline__ unsigned mom_anb32(const Params& P, const Mir32& M, float nuP, int i, int j, int k,
-                                              long long c, float (&anb)[6]) {
-  unsigned vm = 0u;
-  const float nu = (float)P.nu;
-#pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int sh = 0; sh < 2; ++sh) {
-      const int s = sh ? 1 : -1, q = 2 * d + sh;
-      anb[q] = 0.0f;
-      if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
-        long long n = c + s * stride(P, d);
-        long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
-        float F = s > 0 ? M.phi[d][f] : -M.phi[d][f];
-        float mf = -F;
-        anb[q] = 0.5f * (nuP + (nu + M.nut[n])) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
-        vm |= 1u << q;
-      }
-    }
-  return vm;
-}
-
 __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r1, const float* r2, const float* a32,
                               float* d0, float* d1, float* d2, double* u0, double* u1, double* u2, int color, int init,
                               int fin) {
   int i, j, k;
-  tile_ijk(P, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
-  long long c = cidx(P, i, j, k);
-  bool mine = ((i + j + k) & 1) == color;
+  tile_ijk_rb(P, color, i, j, k);
+  if (j >= P.ny) return;
   bool three = P.dim == 3;
-  if (init && !mine) {
-    d0[c] = 0.0f;
-    d1[c] = 0.0f;
-    if (three) d2[c] = 0.0f;
-    return;
+  if (init) {
+    // the partner cell of the other colour in this pair starts from d = 0
+    int io = i ^ 1;
+    if (io < P.nx) {
+      long long co = cidx(P, io, j, k);
+      d0[co] = 0.0f;
+      d1[co] = 0.0f;
+      if (three) d2[co] = 0.0f;
+    }
   }
-  if (!mine) return;
+  if (i >= P.nx) return;
+  long long c = cidx(P, i, j, k);
   float a = a32[c];
   float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
   if (!init) {
-    float anb[6];
-    unsigned vm = mom_anb32(P, M, (float)P.nu + M.nut[c], i, j, k, c, anb);
+    Nbr N = make_nbr(P, i, j, k, c);
+    const float nu = (float)P.nu;
+    float nuP = nu + M.nut[c];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      if (!(vm & (1u << q))) continue;
-      long long n = c + ((q & 1) ? 1 : -1) * stride(P, q >> 1);
-      n0 += anb[q] * d0[n];
-      n1 += anb[q] * d1[n];
-      if (three) n2 += anb[q] * d2[n];
-    }
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int sh = 0; sh < 2; ++sh) {
+        const int s = sh ? 1 : -1, q = 2 * d + sh;
+        if (d >= P.dim) continue;
+        long long n = N.n[q];
+        long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
+        float mf = s > 0 ? -M.phi[d][f] : M.phi[d][f];
+        float an = 0.5f * (nuP + (nu + M.nut[n])) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
+        an = is_bnd(N, q) ? 0.0f : an;
+        n0 += an * d0[n];
+        n1 += an * d1[n];
+        if (three) n2 += an * d2[n];
+      }
   }
   float e0 = (r0[c] + n0) / a, e1 = (r1[c] + n1) / a;
   d0[c] = e0;
@@ -493,10 +482,10 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
   tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
-  double nuP = P.nu + M.nut[c];
+  Nbr N = make_nbr(P, i, j, k, c);
   uint8_t fl = M.flags[c];
   double anb[6];
-  unsigned vm = mom_anb(P, M, nuP, i, j, k, c, anb);
+  mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
   double a = aPr[c];
   const double* rr[3] = {rhs0, rhs1, rhs2};
   double* hh[3] = {h0, h1, h2};
@@ -506,7 +495,7 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
     if (cc >= P.dim) continue;
-    double nb = nb_sum(P, anb, vm, M.u[cc], c);
+    double nb = nb_sum(anb, N, M.u[cc]);
     double H = forced ? nb + rr[cc][c] : nb + rr[cc][c] + gradp_V(P, M.p, fl, cc, i, j, k, c);
     hh[cc][c] = H / a;
   }
@@ -770,11 +759,11 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
     for (int color = 0; color < 2; ++color) {
       timer_begin(c, T_MOMSWEEP);
       if (mixed)
-        hipLaunchKernelGGL(k_mom_sweep32, g, b, 0, c->stream, P, M32, c->r32[0], c->r32[1], c->r32[2], c->a32,
+        hipLaunchKernelGGL(k_mom_sweep32, grid3_rb(P), b, 0, c->stream, P, M32, c->r32[0], c->r32[1], c->r32[2], c->a32,
                            c->d32[0], c->d32[1], c->d32[2], c->u[0], c->u[1], c->u[2], color,
                            s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
       else
-        hipLaunchKernelGGL(k_mom_sweep, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
+        hipLaunchKernelGGL(k_mom_sweep, grid3_rb(P), b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
                            c->u[1], c->u[2], color);
       timer_end(c, T_MOMSWEEP);
     }

@@ -49,7 +49,7 @@ __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, c
   int i, j, k;
   cell_ijk(P, c, i, j, k);
   double G[3][3];
-  gradu_all(P, U.u, flags[c] & F_SOLID, i, j, k, c, G);
+  gradu_all_bf(P, U.u, flags[c] & F_SOLID, make_nbr(P, i, j, k, c), c, G);
   double yp = ypl[b], ut = utl[b], y = yv[b];
   double om = omega_ib(P, yp, y, ut);
   double kk = kold[c];
@@ -102,28 +102,22 @@ struct Scal {
   const double* kib;
 };
 
-// neighbour coefficients of a scalar row (faces W, E, S, N, B, T; bit q of the
-// returned mask set for interior faces), loops unrolled for static indexing
-__device__ __forceinline__ unsigned scal_anb(const Params& P, const Scal& S, int eq, double gP, int i, int j, int k,
-                                             long long c, double (&anb)[6]) {
-  unsigned vm = 0u;
+// neighbour coefficients of a scalar row (faces W, E, S, N, B, T; 0 on domain
+// faces and beyond dim), loads from clamped indices
+__device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq, double gP, const Nbr& N, int i, int j,
+                                         int k, double (&anb)[6]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
     for (int sh = 0; sh < 2; ++sh) {
       const int s = sh ? 1 : -1, q = 2 * d + sh;
       anb[q] = 0.0;
-      if (d < P.dim && !on_bnd(P, d, s, i, j, k)) {
-        long long n = c + s * stride(P, d);
+      if (d < P.dim) {
         double mf = -outward_flux(P, S.phi, d, s, i, j, k);
-        anb[q] = 0.5 * (gP + gam(P, eq, n, S.nut, S.F1)) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
-        vm |= 1u << q;
+        double a = 0.5 * (gP + gam(P, eq, N.n[q], S.nut, S.F1)) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
+        anb[q] = is_bnd(N, q) ? 0.0 : a;
       }
     }
-  return vm;
-}
-__device__ __forceinline__ long long nb_index(const Params& P, int q, long long c) {
-  return c + ((q & 1) ? 1 : -1) * stride(P, q >> 1);
 }
 
 // assembly of the omega (eps, eq = 0) or k (eq = 1) rows; rhs -> rhs_out,
@@ -138,12 +132,12 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     uint8_t fl = S.flags[c];
     bool solid = fl & F_SOLID;
     double gP = gam(P, eq, c, S.nut, S.F1);
+    Nbr N = make_nbr(P, i, j, k, c);
     double anb[6];
-    unsigned vm = scal_anb(P, S, eq, gP, i, j, k, c, anb);
+    scal_anb(P, S, eq, gP, N, i, j, k, anb);
     double aP = 0.0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      if (vm & (1u << q)) aP += anb[q];
+    for (int q = 0; q < 6; ++q) aP += anb[q];
     double vin = eq == 0 ? P.w_in : P.k_in;
     double b0 = 0.0;
 #pragma unroll
@@ -151,7 +145,8 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 #pragma unroll
       for (int sh = 0; sh < 2; ++sh) {
         const int s = sh ? 1 : -1;
-        if (d >= P.dim || !on_bnd(P, d, s, i, j, k) || solid || face_kind(P, d, s) != HFDIB_BC_INLET) continue;
+        if (d >= P.dim || face_kind(P, d, s) != HFDIB_BC_INLET) continue;
+        if (!is_bnd(N, 2 * d + sh) || solid) continue;
         double F = outward_flux(P, S.phi, d, s, i, j, k);
         double mf = -F;
         double a = gP * P.Ab[d] + (mf > 0.0 ? mf : 0.0);
@@ -170,7 +165,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
         Pc = S.Pk[c];
       } else {
         double G[3][3];
-        gradu_all(P, S.u, solid, i, j, k, c, G);
+        gradu_all_bf(P, S.u, solid, N, c, G);
         Pc = model_production(P, strain2(G), S.nut[c], kold, wo);
         S.Pk[c] = Pc;
       }
@@ -206,8 +201,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
         double nbt = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-          if (!(vm & (1u << q))) continue;
-          long long n = nb_index(P, q, c);
+          long long n = N.n[q];
           double kt = (S.flags[n] & F_ALPHA_U) ? S.kib[n] : S.k[n];
           nbt += anb[q] * kt;
         }
@@ -226,8 +220,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       double nb = 0.0, one = 0.0;
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
-        if (!(vm & (1u << q))) continue;
-        nb += anb[q] * xv[nb_index(P, q, c)];
+        nb += anb[q] * xv[N.n[q]];
         one += anb[q];
       }
       double Ax = aPr * x - nb;
@@ -253,18 +246,17 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 __global__ void k_scalar_sweep(Params P, Scal S, int eq, const double* rhs, const double* aPr, double* x, int color,
                                uint8_t fixmask) {
   int i, j, k;
-  tile_ijk(P, i, j, k);
+  tile_ijk_rb(P, color, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
-  if (((i + j + k) & 1) != color) return;
   long long c = cidx(P, i, j, k);
   if (S.flags[c] & fixmask) return;
   double gP = gam(P, eq, c, S.nut, S.F1);
+  Nbr N = make_nbr(P, i, j, k, c);
   double anb[6];
-  unsigned vm = scal_anb(P, S, eq, gP, i, j, k, c, anb);
+  scal_anb(P, S, eq, gP, N, i, j, k, anb);
   double nb = 0.0;
 #pragma unroll
-  for (int q = 0; q < 6; ++q)
-    if (vm & (1u << q)) nb += anb[q] * x[nb_index(P, q, c)];
+  for (int q = 0; q < 6; ++q) nb += anb[q] * x[N.n[q]];
   x[c] = (rhs[c] + nb) / aPr[c];
 }
 
@@ -287,31 +279,35 @@ __device__ __forceinline__ float gam32(const Params& P, int eq, long long c, con
 __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, int eq, const float* r, const float* a32,
                                  float* dv, double* x, int color, uint8_t fixmask, int init, int fin) {
   int i, j, k;
-  tile_ijk(P, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
+  tile_ijk_rb(P, color, i, j, k);
+  if (j >= P.ny) return;
+  if (init) {
+    // the partner cell of the other colour in this pair starts from d = 0
+    int io = i ^ 1;
+    if (io < P.nx) dv[cidx(P, io, j, k)] = 0.0f;
+  }
+  if (i >= P.nx) return;
   long long c = cidx(P, i, j, k);
-  bool mine = ((i + j + k) & 1) == color;
   bool fixed = flags[c] & fixmask;
-  if (init && (!mine || fixed)) {
-    dv[c] = 0.0f;
+  if (fixed) {
+    if (init) dv[c] = 0.0f;
     return;
   }
-  if (!mine || fixed) return;
   float nb = 0.0f;
   if (!init) {
     float gP = gam32(P, eq, c, S.nut, S.F1);
+    Nbr N = make_nbr(P, i, j, k, c);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
 #pragma unroll
       for (int sh = 0; sh < 2; ++sh) {
-        const int s = sh ? 1 : -1;
-        if (d >= P.dim || on_bnd(P, d, s, i, j, k)) continue;
-        long long n = c + s * stride(P, d);
+        const int s = sh ? 1 : -1, q = 2 * d + sh;
+        if (d >= P.dim) continue;
+        long long n = N.n[q];
         long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
         float mf = s > 0 ? -S.phi[d][f] : S.phi[d][f];
-        float a = 0.5f * (gP + gam32(P, eq, n, S.nut, S.F1)) * (float)P.AoD[d] +
-                  (mf > 0.0f ? mf : 0.0f);
-        nb += a * dv[n];
+        float a = 0.5f * (gP + gam32(P, eq, n, S.nut, S.F1)) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
+        nb += is_bnd(N, q) ? 0.0f : a * dv[n];
       }
   }
   float e = (r[c] + nb) / a32[c];
@@ -369,7 +365,7 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, U3 U, const double*
     double arg2 = a > bb ? a : bb;
     double F2 = tanh(arg2 * arg2);
     double G[3][3];
-    gradu_all(P, U.u, fl & F_SOLID, i, j, kz, c, G);
+    gradu_all_bf(P, U.u, fl & F_SOLID, make_nbr(P, i, j, kz, c), c, G);
     double den1 = P.a1 * ww, den2 = sqrt(strain2(G)) * F2;
     nt = P.a1 * kk / (den1 > den2 ? den1 : den2);
   }
@@ -479,10 +475,10 @@ int turbulence_stage(hfdib_ctx* c) {
     for (int s = 0; s < P.n_sweeps; ++s)
       for (int color = 0; color < 2; ++color) {
         if (mixed)
-          hipLaunchKernelGGL(k_scalar_sweep32, g, b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0], x, color,
+          hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0], x, color,
                              fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
         else
-          hipLaunchKernelGGL(k_scalar_sweep, g, b, 0, c->stream, P, Sc, eq, c->t0, c->t1, x, color, fixmask);
+          hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, eq, c->t0, c->t1, x, color, fixmask);
       }
   };
   // omega / eps equation, alpha_omega rows fixed
