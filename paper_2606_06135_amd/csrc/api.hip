@@ -126,6 +126,8 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->t0 = B.take<double>(N);
   c->t1 = B.take<double>(N);
   c->t2 = B.take<double>(N);
+  for (int q = 0; q < 9; ++q) c->G[q] = B.take<double>(N);
+  c->S2 = B.take<double>(N);
   c->rhs_p = B.take<double>(N);
   c->px = B.take<double>(N);
   c->pr = B.take<double>(N);
@@ -588,6 +590,7 @@ int hfdib_set_field(hfdib_ctx* c, int id, const double* src) {
   double* dst = field_ptr(c, id, &n);
   if (!dst) return HFDIB_EINVAL;
   HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "set_field");
+  c->grad_ok = 0;
   return hfdib::refresh_mirrors(c);
 }
 

@@ -90,6 +90,11 @@ struct hfdib_ctx {
   double *rhs[3], *aPr, *hbya[3], *rAU, *F1;
   double *uib[3], *kib, *wib, *Pk, *us[3];
   double *t0, *t1, *t2;  // scratch (turbulence rhs / diagonal)
+  // velocity gradient of the current u: G[3 a + jc] = d u_jc / d x_a, and 2 S:S
+  // (computed once per iteration after the velocity update; grad_ok = 0 when
+  // u changed otherwise)
+  double *G[9], *S2;
+  int grad_ok;
   double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
   uint8_t* flags;
   // --- face arrays
@@ -173,6 +178,7 @@ int refresh_mirrors(hfdib_ctx* c);
 // ctx->scal[SCAL_PCG + out + v]; op selects a PCG scalar update (pressure.hip)
 void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0);
 int turbulence_stage(hfdib_ctx* c);
+int velocity_gradient(hfdib_ctx* c);
 // offsets (relative to SCAL_PCG) of device scalars
 enum {
   SC_MEANS = 100,    // means of u, v, w, p, k (5) and of omega/eps after fixing (1)

@@ -15,6 +15,7 @@ struct Mom {
   const double* dw;
   const uint8_t* flags;
   const double* uib[3];
+  const double* G[9];  // stored velocity gradient of u (G[3 a + jc] = d u_jc / d x_a)
   double* F1;  // SST blending of the previous iterate (written by the assembly)
   double* kw;  // grad k . grad omega of the previous iterate (SST)
 };
@@ -271,40 +272,26 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
     if (X.a) X.a[c] = (float)aPr;
     bool alpha = fl & F_ALPHA_U;
     double* rhs[3] = {rhs0, rhs1, rhs2};
-    // neighbour data shared by the three components
-    bool solidN[6];
+    // neighbour viscosities shared by the three components
     double nuN[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      solidN[q] = M.flags[N.n[q]] & F_SOLID;
-      nuN[q] = P.nu + M.nut[N.n[q]];
-    }
+    for (int q = 0; q < 6; ++q) nuN[q] = P.nu + M.nut[N.n[q]];
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       if (cc >= P.dim) continue;
       // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f, the
       // face gradient being the mean of the two cell (Gauss) gradients
-      const bool loP = is_bnd(N, 2 * cc), hiP = is_bnd(N, 2 * cc + 1);
       double T = 0.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         if (d >= P.dim) continue;
-        double GP = gradu_bf(P, M.u[d], d, cc, c, loP, hiP, solid);
+        const double* Gd = M.G[3 * cc + d];
+        double GP = Gd[c];
 #pragma unroll
         for (int sh = 0; sh < 2; ++sh) {
           const int s = sh ? 1 : -1, q = 2 * d + sh;
           const bool fb = is_bnd(N, q);
-          // domain faces of the neighbour along cc (all faces when it does not exist)
-          bool loN, hiN;
-          if (cc == d) {
-            int a = comp(d, i, j, k) + s;
-            loN = fb || a == 0;
-            hiN = fb || a == ncell(P, d) - 1;
-          } else {
-            loN = fb || loP;
-            hiN = fb || hiP;
-          }
-          double GN = gradu_bf(P, M.u[d], d, cc, N.n[q], loN, hiN, solidN[q]);
+          double GN = Gd[N.n[q]];
           double nuf = fb ? nuP : 0.5 * (nuP + nuN[q]);
           double gf = fb ? GP : 0.5 * (GP + GN);
           T += (double)s * P.area[d] * nuf * gf;
@@ -631,6 +618,7 @@ static Mom make_mom(hfdib_ctx* c) {
     M.phi[q] = c->phi[q];
     M.uib[q] = c->uib[q];
   }
+  for (int q = 0; q < 9; ++q) M.G[q] = c->G[q];
   M.p = c->p;
   M.nut = c->nut;
   M.k = c->k;
@@ -675,6 +663,7 @@ int init_state(hfdib_ctx* c) {
     hipLaunchKernelGGL(k_init_ib, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_ic, c->ic_cells,
                        c->us[0], c->us[1], c->us[2], c->uib[0], c->uib[1], c->uib[2], c->kib);
   HFDIB_CHECK_LAUNCH(c, "init state");
+  c->grad_ok = 0;
   return refresh_mirrors(c);
 }
 
@@ -695,6 +684,37 @@ __global__ void k_residuals(const double* S, int dim, int turb, double* out) {
     out[4] = 0.0;
     out[5] = 0.0;
   }
+}
+
+// velocity gradient (Gauss, linear face interpolation) and 2 S:S of the current u
+struct GradOut {
+  double* G[9];
+};
+__global__ void k_grad(Params P, const double* u0, const double* u1, const double* u2, const uint8_t* flags, GradOut O,
+                       double* S2) {
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  const double* u[3] = {u0, u1, u2};
+  double G[3][3];
+  gradu_all_bf(P, u, flags[c] & F_SOLID, make_nbr(P, i, j, k, c), c, G);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int jc = 0; jc < 3; ++jc)
+      if (a < P.dim && jc < P.dim) O.G[3 * a + jc][c] = G[a][jc];
+  S2[c] = strain2(G);
+}
+
+int velocity_gradient(hfdib_ctx* c) {
+  const Params& P = c->P;
+  GradOut O;
+  for (int q = 0; q < 9; ++q) O.G[q] = c->G[q];
+  hipLaunchKernelGGL(k_grad, grid3(P), block3(), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
+  HFDIB_CHECK_LAUNCH(c, "velocity gradient");
+  c->grad_ok = 1;
+  return HFDIB_OK;
 }
 
 __global__ void k_to_f32_n(long long n, const double* a, float* b) {
@@ -741,7 +761,11 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   if (c->n_wall > 0)
     hipLaunchKernelGGL(k_wall_pre, dim3(nblocks1(c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_wall,
                        c->wall_cells, c->wall_y, c->k, c->wall_utau, c->wall_yplus);
-  // 2. momentum predictor
+  // 2. momentum predictor (needs the gradient of the current u)
+  if (!c->grad_ok) {
+    st = velocity_gradient(c);
+    if (st != HFDIB_OK) return st;
+  }
   Mom M = make_mom(c);
   bool mixed = P.precision == HFDIB_MIXED;
   MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
@@ -799,6 +823,10 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   c->p = c->pnew;
   c->pnew = tmp;
   HFDIB_CHECK_LAUNCH(c, "velocity update");
+  // gradient of the updated u: used by the turbulence stage and by the next
+  // momentum assembly (u does not change in between)
+  st = velocity_gradient(c);
+  if (st != HFDIB_OK) return st;
   // 6. turbulence
   if (P.model != HFDIB_LAMINAR) {
     st = turbulence_stage(c);

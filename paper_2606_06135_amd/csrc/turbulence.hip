@@ -7,17 +7,6 @@
 
 namespace hfdib {
 
-struct U3 {
-  const double* u[3];
-};
-
-__device__ __forceinline__ void cell_ijk(const Params& P, long long c, int& i, int& j, int& k) {
-  i = (int)(c % P.nx);
-  long long r = c / P.nx;
-  j = (int)(r % P.ny);
-  k = (int)(r / P.ny);
-}
-
 // production of k by the closure (k-eps: nu_t 2S:S; SST: limited by
 // c_lim beta* k omega), from the current velocity and the k, omega, nu_t
 // entering the turbulence stage
@@ -40,16 +29,21 @@ __device__ __forceinline__ double prod_ib(const Params& P, double yp, double Gk,
 
 // boundary cells (mode 0) and domain-wall cells (mode 1): imposed omega/eps and
 // production; the omega field takes its fixed value on these rows
+struct G9 {
+  const double* g[9];
+};
+
 __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, const double* nv, const double* ypl,
-                          const double* utl, const uint8_t* flags, U3 U, const double* kold, const double* nut,
+                          const double* utl, G9 Gs, const double* S2, const double* kold, const double* nut,
                           double* Pk, double* wib, double* w) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= n) return;
   int c = cells[b];
-  int i, j, k;
-  cell_ijk(P, c, i, j, k);
   double G[3][3];
-  gradu_all_bf(P, U.u, flags[c] & F_SOLID, make_nbr(P, i, j, k, c), c, G);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int jc = 0; jc < 3; ++jc) G[a][jc] = (a < P.dim && jc < P.dim) ? Gs.g[3 * a + jc][c] : 0.0;
   double yp = ypl[b], ut = utl[b], y = yv[b];
   double om = omega_ib(P, yp, y, ut);
   double kk = kold[c];
@@ -58,7 +52,7 @@ __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, c
   for (int jj = 0; jj < 3; ++jj)
     for (int ii = 0; ii < 3; ++ii) ng[jj] += nv[3 * b + ii] * G[ii][jj];
   double ng2 = ng[0] * ng[0] + ng[1] * ng[1] + ng[2] * ng[2];
-  double Pm = model_production(P, strain2(G), nut[c], kk, w[c]);
+  double Pm = model_production(P, S2[c], nut[c], kk, w[c]);
   Pk[c] = prod_ib(P, yp, Pm, ng2);
   wib[c] = val;
   w[c] = val;
@@ -90,7 +84,7 @@ __device__ __forceinline__ double gam(const Params& P, int eq, long long c, cons
 
 struct Scal {
   const double* phi[3];
-  const double* u[3];
+  const double* S2;  // 2 S:S of the current velocity
   const uint8_t* flags;
   const double* nut;
   const double* F1;
@@ -164,9 +158,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       if (fl & F_ALPHA_W) {
         Pc = S.Pk[c];
       } else {
-        double G[3][3];
-        gradu_all_bf(P, S.u, solid, N, c, G);
-        Pc = model_production(P, strain2(G), S.nut[c], kold, wo);
+        Pc = model_production(P, S.S2[c], S.nut[c], kold, wo);
         S.Pk[c] = Pc;
       }
       if (P.model == HFDIB_KEPS) {
@@ -341,8 +333,8 @@ __global__ void k_kib(Params P, int nbc, const int* bc_cells, const uint8_t* fla
 
 // k <- k + alpha_k (k_ib - k), bounding, turbulent viscosity of the model
 // (in-solid cells 0); eps/omega is already bounded
-__global__ void k_turb_final(Params P, const uint8_t* flags, U3 U, const double* kib, double* k, const double* w,
-                             const double* dw, double* nut, float* nut32) {
+__global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, const double* kib, double* k,
+                             const double* w, const double* dw, double* nut, float* nut32) {
   int i, j, kz;
   tile_ijk(P, i, j, kz);
   if (i >= P.nx || j >= P.ny) return;
@@ -364,9 +356,7 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, U3 U, const double*
     double bb = 500.0 * P.nu / (d * d * ww);
     double arg2 = a > bb ? a : bb;
     double F2 = tanh(arg2 * arg2);
-    double G[3][3];
-    gradu_all_bf(P, U.u, fl & F_SOLID, make_nbr(P, i, j, kz, c), c, G);
-    double den1 = P.a1 * ww, den2 = sqrt(strain2(G)) * F2;
+    double den1 = P.a1 * ww, den2 = sqrt(S2[c]) * F2;
     nt = P.a1 * kk / (den1 > den2 ? den1 : den2);
   }
   if (fl & F_IC) nt = 0.0;
@@ -435,17 +425,17 @@ int turbulence_stage(hfdib_ctx* c) {
   int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   double* wmax = S + SC_WMAX;
-  U3 U;
-  for (int q = 0; q < 3; ++q) U.u[q] = c->u[q];
+  G9 Gs;
+  for (int q = 0; q < 9; ++q) Gs.g[q] = c->G[q];
   // imposed omega/eps and production on boundary, wall and in-solid cells (the
   // maximum of omega/eps over cells outside the in-solid group was reduced in the momentum
   // assembly, before any omega/eps value changed)
   if (c->n_bc > 0)
     hipLaunchKernelGGL(k_turb_ib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
-                       c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau, c->flags, U, c->k, c->nut, c->Pk, c->wib, c->w);
+                       c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau, Gs, c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
   if (c->n_wall > 0)
     hipLaunchKernelGGL(k_turb_ib, dim3(nblocks1(c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_wall,
-                       c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau, c->flags, U, c->k, c->nut,
+                       c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau, Gs, c->S2, c->k, c->nut,
                        c->Pk, c->wib, c->w);
   if (c->n_ic > 0)
     hipLaunchKernelGGL(k_turb_ic, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, c->n_ic, c->ic_cells,
@@ -455,9 +445,9 @@ int turbulence_stage(hfdib_ctx* c) {
   Scal Sc;
   for (int q = 0; q < 3; ++q) {
     Sc.phi[q] = c->phi[q];
-    Sc.u[q] = c->u[q];
   }
   Sc.flags = c->flags;
+  Sc.S2 = c->S2;
   Sc.nut = c->nut;
   Sc.F1 = c->F1;
   Sc.kw = c->t2;
@@ -495,7 +485,7 @@ int turbulence_stage(hfdib_ctx* c) {
                      c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
-  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, U, c->kib, c->k, c->w,
+  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, c->kib, c->k, c->w,
                      c->dw, c->nut, mixed ? c->nut32 : nullptr);
   if (c->n_bc > 0) {
     hipLaunchKernelGGL(k_nut_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
