@@ -134,6 +134,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->pz = B.take<double>(N);
   c->pd = B.take<double>(N);
   c->pq = B.take<double>(N);
+  c->invD = B.take<double>(N);
   c->flags = B.take<uint8_t>(N);
   c->phi[0] = B.take<double>((long long)(P.nx + 1) * P.ny * P.nz);
   c->phi[1] = B.take<double>((long long)P.nx * (P.ny + 1) * P.nz);
@@ -193,7 +194,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
   }
   // FP32 arrays of the mixed policy
   for (int q = 0; q < 3; ++q) c->r32[q] = c->d32[q] = c->phi32[q] = nullptr;
-  c->a32 = c->nut32 = c->F1_32 = c->rAU32 = c->pr32 = c->pz32 = nullptr;
+  c->a32 = c->nut32 = c->F1_32 = c->rAU32 = c->pr32 = c->pz32 = c->invD32 = nullptr;
   if (mixed) {
     for (int q = 0; q < 3; ++q) c->r32[q] = B.take<float>(N);
     for (int q = 0; q < 3; ++q) c->d32[q] = B.take<float>(N);
@@ -206,6 +207,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
     c->rAU32 = B.take<float>(N);
     c->pr32 = B.take<float>(N);
     c->pz32 = B.take<float>(N);
+    c->invD32 = B.take<float>(N);
   }
   return B.off + 256;
 }

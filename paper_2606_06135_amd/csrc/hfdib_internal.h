@@ -96,6 +96,7 @@ struct hfdib_ctx {
   double *G[9], *S2;
   int grad_ok;
   double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
+  double* invD;  // inverse diagonal of the fine pressure operator (FP64 policy)
   uint8_t* flags;
   // --- face arrays
   double* phi[3];
@@ -104,7 +105,7 @@ struct hfdib_ctx {
   // (relaxed diagonal, face fluxes, nu_t, SST blending), pressure smoother
   // inputs (rAU) and the preconditioner residual / output
   float *r32[3], *d32[3], *a32, *phi32[3], *nut32, *F1_32;
-  float *rAU32, *pr32, *pz32;
+  float *rAU32, *pr32, *pz32, *invD32;
   // --- lists
   int cap;  // capacity of each list
   int *bc_cells, *ic_cells, *wall_cells;

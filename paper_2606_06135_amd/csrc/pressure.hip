@@ -135,30 +135,89 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
   block_sums_store<5>(v, part, pstride, block_linear());
 }
 
-// red-black Gauss-Seidel half sweep on the fine level; init != 0 means z was
-// zero before this (first red) sweep: red cells z = r/diag, black cells z = 0
+// Fine-level smoothing.  The V-cycle uses one red-black Gauss-Seidel sweep
+// before (red first, from z = 0) and one after (black first) the coarse
+// correction; the inverse diagonal D^-1 of the fine operator (1 for uncoupled
+// rows) is computed once per pressure solve.
+//
+// Inverse diagonal (and, under the mixed policy, the FP32 mirror of rAU).
 template <typename T>
-__global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* r, T* z, int color, int init) {
+__global__ void k_fine_invdiag(Params P, FineOp O, T* invD, float* rAU32) {
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  if (i >= P.nx || j >= P.ny) return;
+  long long c = cidx(P, i, j, k);
+  Nbr N = make_nbr(P, i, j, k, c);
+  double cf[6];
+  fine_row(P, O, N, c, cf);
+  double dg = 0.0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) dg += cf[q];
+  invD[c] = (T)(dg == 0.0 ? 1.0 : 1.0 / dg);
+  if (rAU32) rAU32[c] = (float)O.rAU[c];
+}
+
+// Pre-smoothing sweep in one pass: the red value of a cell is r D^-1 (its
+// neighbours are 0 before the sweep), so each thread takes one red/black pair
+// of a row, writes the red value and the black value
+// (r + sum_f c_f r_nb D^-1_nb) D^-1 from recomputed red neighbour values.
+template <typename T>
+__global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* z) {
+  int i, j, k;
+  tile_ijk_rb(P, 0, i, j, k);  // i: the red cell of the pair
+  if (j >= P.ny) return;
+  if (i < P.nx) {
+    long long c = cidx(P, i, j, k);
+    z[c] = r[c] * invD[c];
+  }
+  int ib = i ^ 1;  // the black cell of the pair
+  if (ib >= P.nx) return;
+  long long c = cidx(P, ib, j, k);
+  Nbr N = make_nbr(P, ib, j, k, c);
+  T cf[6];
+  fine_row(P, O, N, c, cf);
+  T nb = (T)0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    long long n = N.n[q];
+    nb += is_bnd(N, q) ? (T)0 : cf[q] * (r[n] * invD[n]);
+  }
+  z[c] = (r[c] + nb) * invD[c];
+}
+
+// One colour of a red-black half sweep (all neighbours are of the other
+// colour): z = (r + sum_f c_f z_nb) D^-1.  When zc is given (first sweep after
+// the coarse correction, black), the neighbour values are taken as
+// z_nb + zc(parent of nb): the prolongation is applied on the fly (the
+// prolonged values of this colour are overwritten, those of the other colour
+// are only read here and overwritten by the next sweep).
+template <typename T>
+__global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* z, int color, const T* zc,
+                              int cnx, int cny) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
-  if (j >= P.ny) return;
-  if (init) {
-    // the partner cell of the other colour in this pair starts from z = 0
-    int io = i ^ 1;
-    if (io < P.nx) z[cidx(P, io, j, k)] = (T)0;
-  }
-  if (i >= P.nx) return;
+  if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   Nbr N = make_nbr(P, i, j, k, c);
   T cf[6];
   fine_row(P, O, N, c, cf);
-  T diag = (T)0, nb = (T)0;
+  T nb = (T)0;
+  if (zc) {
+    const int i2 = i >> 1, j2 = j >> 1, k2 = P.dim == 3 ? k >> 1 : 0;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    diag += cf[q];
-    if (!init) nb += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
+    for (int q = 0; q < 6; ++q) {
+      const int d = q >> 1, s = (q & 1) ? 1 : -1;
+      if (is_bnd(N, q)) continue;
+      // parent of the neighbour: only its coordinate along d differs
+      int pi = d == 0 ? (i + s) >> 1 : i2, pj = d == 1 ? (j + s) >> 1 : j2, pk = d == 2 ? (k + s) >> 1 : k2;
+      long long pc = (long long)pi + (long long)cnx * ((long long)pj + (long long)cny * pk);
+      nb += cf[q] * (z[N.n[q]] + zc[pc]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nb += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
   }
-  z[c] = diag == (T)0 ? r[c] : (r[c] + nb) / diag;
+  z[c] = (r[c] + nb) * invD[c];
 }
 
 // ---------------------------------------------------------------- coarse levels
@@ -329,9 +388,12 @@ __global__ void k_level_smooth(LevelDevT<T> L, int color, int init) {
   L.z[c] = (L.r[c] + nb) / L.diag[c];
 }
 
-// restriction of the fine residual r - A z onto level 1 (sum over children)
+// Restriction of the fine residual onto level 1 (sum over the children) after
+// the pre-smoothing sweep: black rows are satisfied exactly, and a red row's
+// residual is r - D r D^-1 + sum_f c_f z_nb = sum_f c_f z_nb (its neighbours
+// are black), so only the red children contribute, each by that sum.
 template <typename T>
-__global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* r, const T* z, LevelDevT<T> C) {
+__global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T> C) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
   int J = blockIdx.y * blockDim.y + threadIdx.y;
   int K = blockIdx.z;
@@ -341,14 +403,14 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* r, const T* z, 
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
+        if ((a + b + e) & 1) continue;  // black child (2I+a+2J+b+2K+e odd)
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = cidx(P, i, j, k);
         Nbr N = make_nbr(P, i, j, k, c);
-        T cf[6], dg, bs;
+        T cf[6];
         fine_row(P, O, N, c, cf);
-        T acc = fine_Ax(cf, N, z, c, dg, bs);
-        if (dg == (T)0) acc = z[c];
-        s += r[c] - acc;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
       }
   C.r[lidx(C, I, J, K)] = s;
 }
@@ -515,10 +577,6 @@ __global__ void k_xpby(long long n, const double* scal, const TZ* z, double* d) 
   if (c < n) d[c] = (double)z[c] + scal[S_BETA] * d[c];
 }
 
-__global__ void k_to_f32(long long n, const double* a, float* b) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  if (c < n) b[c] = (float)a[c];
-}
 
 // first stage of a large reduction: workgroup (b, v) reduces entries
 // [b chunk, (b+1) chunk) of partial row v (sum, or max when is_max) into
@@ -630,14 +688,15 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
 
 // one V-cycle z = M^-1 r in storage type T
 template <typename T>
-static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* r, T* z) {
+static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z) {
   const Params& P = c->P;
   dim3 g = grid3_rb(P), b = block3();
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 0, 1);
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 1, 0);
+  hipLaunchKernelGGL(k_fine_presmooth<T>, g, b, 0, c->stream, P, O, invD, r, z);
+  const T* zc = nullptr;
+  int cnx = 0, cny = 0;
   if (c->nlev > 1) {
     LevelDevT<T> L1 = levdev<T>(c, 1);
-    hipLaunchKernelGGL(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, (const T*)z, L1);
+    hipLaunchKernelGGL(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, (const T*)z, L1);
     // large coarse levels: one kernel per pass
     int l = 1;
     while (l < c->nlev - 1 && c->lev[l].N > TAIL_MAX) {
@@ -662,10 +721,13 @@ static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* r, T* z) {
       hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 1, 0);
       hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 0, 0);
     }
-    hipLaunchKernelGGL(k_prolong<T>, lgrid(P.nx, P.ny, P.nz), b, 0, c->stream, P.nx, P.ny, P.nz, P.dim, z, L1);
+    zc = L1.z;
+    cnx = L1.nx;
+    cny = L1.ny;
   }
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 1, 0);
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, r, z, 0, 0);
+  // post-smoothing, black first (with the prolongation on the fly), then red
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0);
 }
 
 // coarse operators of every level from the FP64 fine operator
@@ -692,8 +754,9 @@ static void build_levels(hfdib_ctx* c, const FineOp& O) {
 // is T (FP64; FP32 under the mixed policy, where r32/z32 hold the FP32 copies
 // of the residual and of the preconditioned residual).
 template <typename T>
-static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const double* rhs, double* x, T* r_m, T* z_m,
-               float* r32, double rtol, int maxit, int* iters, double* relres, const double* xmean_dev) {
+static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* invD, const double* rhs, double* x,
+               T* r_m, T* z_m, float* r32, double rtol, int maxit, int* iters, double* relres,
+               const double* xmean_dev) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3();
   long long nblk3 = (long long)g.x * g.y * g.z;
@@ -706,7 +769,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const double
   launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [20]=rr0 [21]=bb [22..24]=residual sums
   // at least one PCG iteration is done; the host reads the residual after each
   // iteration (one synchronisation per iteration, none before the first)
-  vcycle<T>(c, OM, r_m, z_m);
+  vcycle<T>(c, OM, invD, r_m, z_m);
   hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
                      c->pstride);
   launch_finalize(c, nb1, 1, S_RZ, 3);
@@ -740,7 +803,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const double
     }
     if (sqrt(rr) <= target) break;
     if (it == maxit) break;
-    vcycle<T>(c, OM, r_m, z_m);
+    vcycle<T>(c, OM, invD, r_m, z_m);
     hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
                        c->pstride);
     launch_finalize(c, nb1, 1, S_RZ, 2);
@@ -760,14 +823,16 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
   int st;
   timer_begin(c, T_PSOLVE);
   if (P.precision == HFDIB_MIXED) {
-    // FP32 mirror of rAU for the fine smoother; coarse operators from FP64
-    hipLaunchKernelGGL(k_to_f32, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, rAU, c->rAU32);
+    // FP32 mirror of rAU and inverse diagonal for the fine smoother; coarse
+    // operators from the FP64 fine operator
+    hipLaunchKernelGGL(k_fine_invdiag<float>, grid3(P), block3(), 0, c->stream, P, O, c->invD32, c->rAU32);
     build_levels<float>(c, O);
     FineOpT<float> OM{c->rAU32, c->flags};
-    st = pcg<float>(c, O, OM, rhs, x, c->pr32, c->pz32, c->pr32, rtol, maxit, iters, relres, xmean_dev);
+    st = pcg<float>(c, O, OM, c->invD32, rhs, x, c->pr32, c->pz32, c->pr32, rtol, maxit, iters, relres, xmean_dev);
   } else {
+    hipLaunchKernelGGL(k_fine_invdiag<double>, grid3(P), block3(), 0, c->stream, P, O, c->invD, (float*)nullptr);
     build_levels<double>(c, O);
-    st = pcg<double>(c, O, O, rhs, x, c->pr, c->pz, nullptr, rtol, maxit, iters, relres, xmean_dev);
+    st = pcg<double>(c, O, O, c->invD, rhs, x, c->pr, c->pz, nullptr, rtol, maxit, iters, relres, xmean_dev);
   }
   timer_end(c, T_PSOLVE);
   return st;
