@@ -371,20 +371,71 @@ __device__ __forceinline__ T level_nbsum(const LevelDevT<T>& L, const T* z, int 
   return s;
 }
 
+// Coarse-level smoothing with the structure of the fine level: one pass for
+// the pre-smoothing sweep (red r/diag from zero, then black from the
+// recomputed red values), the restriction of the red rows' residuals only,
+// and the prolongation applied on the fly by the first post-smoothing sweep.
+// Thread t of a row (j, k) takes the pair of cells 2t, 2t+1.
 template <typename T>
-__global__ void k_level_smooth(LevelDevT<T> L, int color, int init) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
-  if (i >= L.nx || j >= L.ny) return;
+__device__ __forceinline__ bool level_pair(const LevelDevT<T>& L, int color, int& i, int& j, int& k) {
+  int t = blockIdx.x * blockDim.x + threadIdx.x;
+  j = blockIdx.y * blockDim.y + threadIdx.y;
+  k = blockIdx.z;
+  i = 2 * t + ((j + k + color) & 1);
+  return j < L.ny;
+}
+
+// sum_nb c_nb f(nb) at (i,j,k) of a stored level (f gives the neighbour value)
+template <typename T, typename F>
+__device__ __forceinline__ T level_nbsum_f(const LevelDevT<T>& L, int i, int j, int k, F f) {
   long long c = lidx(L, i, j, k);
-  bool mine = ((i + j + k) & 1) == color;
-  if (init && !mine) {
-    L.z[c] = (T)0;
-    return;
+  T s = (T)0;
+  if (i > 0) s += L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * f(c - 1, -1, 0, 0);
+  if (i < L.nx - 1)
+    s += L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * f(c + 1, 1, 0, 0);
+  if (j > 0) s += L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] * f(c - L.nx, 0, -1, 0);
+  if (j < L.ny - 1)
+    s += L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)] * f(c + L.nx, 0, 1, 0);
+  if (L.dim == 3) {
+    long long sz = (long long)L.nx * L.ny;
+    if (k > 0) s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] * f(c - sz, 0, 0, -1);
+    if (k < L.nz - 1)
+      s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))] * f(c + sz, 0, 0, 1);
   }
-  if (!mine) return;
-  T nb = init ? (T)0 : level_nbsum(L, L.z, i, j, k);
+  return s;
+}
+
+template <typename T>
+__global__ void k_level_presmooth(LevelDevT<T> L) {
+  int i, j, k;
+  if (!level_pair(L, 0, i, j, k)) return;  // i: the red cell of the pair
+  if (i < L.nx) {
+    long long c = lidx(L, i, j, k);
+    L.z[c] = L.r[c] / L.diag[c];
+  }
+  int ib = i ^ 1;
+  if (ib >= L.nx) return;
+  long long c = lidx(L, ib, j, k);
+  T nb = level_nbsum_f(L, ib, j, k, [&](long long n, int, int, int) { return L.r[n] / L.diag[n]; });
+  L.z[c] = (L.r[c] + nb) / L.diag[c];
+}
+
+// one colour of a half sweep; with zc (coarse correction of the next level),
+// the neighbour values are z_nb + zc(parent of nb)
+template <typename T>
+__global__ void k_level_smooth(LevelDevT<T> L, int color, LevelDevT<T> C, int prolong) {
+  int i, j, k;
+  if (!level_pair(L, color, i, j, k) || i >= L.nx) return;
+  long long c = lidx(L, i, j, k);
+  T nb;
+  if (prolong) {
+    const int k2 = L.dim == 3 ? k : 0;
+    nb = level_nbsum_f(L, i, j, k, [&](long long n, int di, int dj, int dk) {
+      return L.z[n] + C.z[lidx(C, (i + di) >> 1, (j + dj) >> 1, (k2 + dk) >> 1)];
+    });
+  } else {
+    nb = level_nbsum_f(L, i, j, k, [&](long long n, int, int, int) { return L.z[n]; });
+  }
   L.z[c] = (L.r[c] + nb) / L.diag[c];
 }
 
@@ -415,6 +466,9 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T>
   C.r[lidx(C, I, J, K)] = s;
 }
 
+// restriction after the pre-smoothing sweep of a stored level: the residual of
+// a red row is sum_nb c z_nb (black rows are satisfied), summed over the red
+// children of each coarse cell
 template <typename T>
 __global__ void k_restrict_level(LevelDevT<T> F, LevelDevT<T> C) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -426,23 +480,11 @@ __global__ void k_restrict_level(LevelDevT<T> F, LevelDevT<T> C) {
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
+        if ((a + b + e) & 1) continue;
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
-        long long c = lidx(F, i, j, k);
-        T Az = F.diag[c] * F.z[c] - level_nbsum(F, F.z, i, j, k);
-        s += F.r[c] - Az;
+        s += level_nbsum_f(F, i, j, k, [&](long long n, int, int, int) { return F.z[n]; });
       }
   C.r[lidx(C, I, J, K)] = s;
-}
-
-// z_fine += z_coarse(parent)
-template <typename T>
-__global__ void k_prolong(int fnx, int fny, int fnz, int dim, T* zf, LevelDevT<T> C) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
-  if (i >= fnx || j >= fny) return;
-  long long c = (long long)i + (long long)fnx * ((long long)j + (long long)fny * k);
-  zf[c] += C.z[lidx(C, i / 2, j / 2, dim == 3 ? k / 2 : 0)];
 }
 
 // ---------------------------------------------------------------- tail V-cycle
@@ -451,13 +493,17 @@ __global__ void k_prolong(int fnx, int fny, int fnz, int dim, T* zf, LevelDevT<T
 // post-smoothing with barriers between the passes (one launch instead of ~5 per
 // level).  Same arithmetic as the per-level kernels.  The coarsest solve is a
 // symmetric red-black Gauss-Seidel from zero (m forward then m backward colour
-// pairs) held in LDS.
+// pairs).  Two variants: every level staged in LDS (the normal case), and a
+// global-memory one for a coarsest level too large for LDS (grids whose
+// coarsening stops early).
 constexpr long long TAIL_MAX = 1024;
 constexpr int TAIL_LDS = 1024;
 constexpr int TAIL_THREADS = 1024;
+constexpr int TAIL_LDS_BYTES = 64 * 1024;  // the LDS tail keeps every tail level in LDS
 template <typename T>
 struct TailLevelsT {
   LevelDevT<T> L[MAX_LEVELS];
+  int off[MAX_LEVELS];  // LDS tail: element offset of each level's block r, z, diag, cx, cy, cz
   int n;
 };
 
@@ -478,7 +524,7 @@ __device__ __forceinline__ void tail_smooth(const LevelDevT<T>& L, int color, in
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL, int m) {
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle_global(TailLevelsT<T> TL, int m) {
   int n = TL.n;
   for (int t = 0; t < n - 1; ++t) {
     const LevelDevT<T>& F = TL.L[t];
@@ -539,6 +585,123 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
     tail_smooth(F, 1, 0);
     tail_smooth(F, 0, 0);
   }
+}
+
+// LDS tail: every tail level (r, z, diag, cx, cy, cz) staged in dynamic LDS,
+// 32-bit indices; the top level's r comes from the restriction above, its z
+// goes back to global memory for the prolongation.
+template <typename T>
+struct LdsLev {
+  int nx, ny, nz, dim, N;
+  T *r, *z, *diag, *cx, *cy, *cz;
+};
+template <typename T>
+__device__ __forceinline__ LdsLev<T> lds_lev(const TailLevelsT<T>& TL, int t, T* base) {
+  const LevelDevT<T>& L = TL.L[t];
+  LdsLev<T> v;
+  v.nx = L.nx;
+  v.ny = L.ny;
+  v.nz = L.nz;
+  v.dim = L.dim;
+  v.N = (int)L.N;
+  T* p = base + TL.off[t];
+  v.r = p;
+  v.z = p + v.N;
+  v.diag = p + 2 * v.N;
+  v.cx = p + 3 * v.N;
+  v.cy = v.cx + (v.nx + 1) * v.ny * v.nz;
+  v.cz = v.cy + v.nx * (v.ny + 1) * v.nz;
+  return v;
+}
+template <typename T>
+__device__ __forceinline__ T lds_nbsum(const LdsLev<T>& L, const T* z, int i, int j, int k) {
+  int c = i + L.nx * (j + L.ny * k);
+  T s = (T)0;
+  if (i > 0) s += L.cx[i + (L.nx + 1) * (j + L.ny * k)] * z[c - 1];
+  if (i < L.nx - 1) s += L.cx[i + 1 + (L.nx + 1) * (j + L.ny * k)] * z[c + 1];
+  if (j > 0) s += L.cy[i + L.nx * (j + (L.ny + 1) * k)] * z[c - L.nx];
+  if (j < L.ny - 1) s += L.cy[i + L.nx * (j + 1 + (L.ny + 1) * k)] * z[c + L.nx];
+  if (L.dim == 3) {
+    int sz = L.nx * L.ny;
+    if (k > 0) s += L.cz[i + L.nx * (j + L.ny * k)] * z[c - sz];
+    if (k < L.nz - 1) s += L.cz[i + L.nx * (j + L.ny * (k + 1))] * z[c + sz];
+  }
+  return s;
+}
+template <typename T>
+__device__ __forceinline__ void lds_smooth(const LdsLev<T>& L, int color, int init) {
+  for (int c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
+    int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    bool mine = ((i + j + k) & 1) == color;
+    if (init && !mine) {
+      L.z[c] = (T)0;
+      continue;
+    }
+    if (!mine) continue;
+    T nb = init ? (T)0 : lds_nbsum(L, (const T*)L.z, i, j, k);
+    L.z[c] = (L.r[c] + nb) / L.diag[c];
+  }
+  __syncthreads();
+}
+template <typename T>
+__device__ __forceinline__ void lds_copy(T* dst, const T* src, int n) {
+  for (int q = threadIdx.x; q < n; q += TAIL_THREADS) dst[q] = src[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL, int m) {
+  extern __shared__ unsigned char tail_lds_raw[];
+  T* base = reinterpret_cast<T*>(tail_lds_raw);
+  const int n = TL.n;
+  for (int t = 0; t < n; ++t) {
+    const LevelDevT<T>& G = TL.L[t];
+    LdsLev<T> L = lds_lev(TL, t, base);
+    if (t == 0) lds_copy(L.r, (const T*)G.r, L.N);
+    lds_copy(L.diag, G.diag, L.N);
+    lds_copy(L.cx, G.cx, (L.nx + 1) * L.ny * L.nz);
+    lds_copy(L.cy, G.cy, L.nx * (L.ny + 1) * L.nz);
+    if (L.dim == 3) lds_copy(L.cz, G.cz, L.nx * L.ny * (L.nz + 1));
+  }
+  __syncthreads();
+  for (int t = 0; t < n - 1; ++t) {
+    LdsLev<T> F = lds_lev(TL, t, base), C = lds_lev(TL, t + 1, base);
+    lds_smooth(F, 0, 1);
+    lds_smooth(F, 1, 0);
+    int nzs = C.dim == 3 ? 2 : 1;
+    for (int q = threadIdx.x; q < C.N; q += TAIL_THREADS) {
+      int I = q % C.nx, J = (q / C.nx) % C.ny, K = q / (C.nx * C.ny);
+      T sacc = (T)0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+          for (int e = 0; e < nzs; ++e) {
+            int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
+            int c = i + F.nx * (j + F.ny * k);
+            T Az = F.diag[c] * F.z[c] - lds_nbsum(F, (const T*)F.z, i, j, k);
+            sacc += F.r[c] - Az;
+          }
+      C.r[q] = sacc;
+    }
+    __syncthreads();
+  }
+  {
+    LdsLev<T> L = lds_lev(TL, n - 1, base);
+    for (int c = threadIdx.x; c < L.N; c += TAIL_THREADS) L.z[c] = (T)0;
+    __syncthreads();
+    for (int it = 0; it < 2 * m; ++it)
+      for (int h = 0; h < 2; ++h) lds_smooth(L, it < m ? h : 1 - h, 0);
+  }
+  for (int t = n - 2; t >= 0; --t) {
+    LdsLev<T> F = lds_lev(TL, t, base), C = lds_lev(TL, t + 1, base);
+    for (int c = threadIdx.x; c < F.N; c += TAIL_THREADS) {
+      int i = c % F.nx, j = (c / F.nx) % F.ny, k = c / (F.nx * F.ny);
+      F.z[c] += C.z[(i / 2) + C.nx * ((j / 2) + C.ny * (F.dim == 3 ? k / 2 : 0))];
+    }
+    __syncthreads();
+    lds_smooth(F, 1, 0);
+    lds_smooth(F, 0, 0);
+  }
+  LdsLev<T> L0 = lds_lev(TL, 0, base);
+  for (int c = threadIdx.x; c < L0.N; c += TAIL_THREADS) TL.L[0].z[c] = L0.z[c];
 }
 
 // ---------------------------------------------------------------- vector ops
@@ -667,13 +830,15 @@ static LevelDevT<T> levdev(hfdib_ctx* c, int l) {
   return LevelPick<T>::get(c, l);
 }
 static dim3 lgrid(int nx, int ny, int nz) { return dim3((nx + 63) / 64, (ny + 3) / 4, nz); }
+// pair-mapped grid of a stored level (half the x extent)
+static dim3 lgrid_rb(int nx, int ny, int nz) { return dim3(((nx + 1) / 2 + 63) / 64, (ny + 3) / 4, nz); }
 
 // finalize helper; partial slots live in ctx->partials with row stride c->pstride
 // Large partial rows are first reduced in fixed chunks by many workgroups
 // (deterministic: fixed chunk boundaries and order), then by one workgroup.
 void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0) {
   const double* part = c->partials + (long long)row0 * c->pstride;
-  if (nblk > 4 * FIN_THREADS) {
+  if (nblk > 32 * FIN_THREADS) {
     int chunk = (nblk + FIN2_CHUNKS - 1) / FIN2_CHUNKS;
     int nchunks = (nblk + chunk - 1) / chunk;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), 0, c->stream, part, c->pstride, nblk,
@@ -701,25 +866,34 @@ static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r,
     int l = 1;
     while (l < c->nlev - 1 && c->lev[l].N > TAIL_MAX) {
       LevelDevT<T> L = levdev<T>(c, l);
-      dim3 gl = lgrid(L.nx, L.ny, L.nz);
-      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 0, 1);
-      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 1, 0);
+      hipLaunchKernelGGL(k_level_presmooth<T>, lgrid_rb(L.nx, L.ny, L.nz), b, 0, c->stream, L);
       LevelDevT<T> C = levdev<T>(c, l + 1);
       hipLaunchKernelGGL(k_restrict_level<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
       ++l;
     }
-    // small levels l..nlev-1 (and the coarsest solve) in one workgroup
+    // small levels l..nlev-1 (and the coarsest solve) in one workgroup, staged
+    // in LDS when they fit
     TailLevelsT<T> TL;
     TL.n = c->nlev - l;
-    for (int t = 0; t < TL.n; ++t) TL.L[t] = levdev<T>(c, l + t);
-    hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), 0, c->stream, TL, 6);
+    long long elems = 0;
+    for (int t = 0; t < TL.n; ++t) {
+      TL.L[t] = levdev<T>(c, l + t);
+      const LevelDevT<T>& L = TL.L[t];
+      TL.off[t] = (int)elems;
+      elems += 3 * L.N + (long long)(L.nx + 1) * L.ny * L.nz + (long long)L.nx * (L.ny + 1) * L.nz +
+               (L.dim == 3 ? (long long)L.nx * L.ny * (L.nz + 1) : 0);
+    }
+    size_t lds = (size_t)elems * sizeof(T);
+    if (lds <= (size_t)TAIL_LDS_BYTES)
+      hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), lds, c->stream, TL, 6);
+    else
+      hipLaunchKernelGGL(k_tail_vcycle_global<T>, dim3(1), dim3(TAIL_THREADS), 0, c->stream, TL, 6);
     for (int q = l - 1; q >= 1; --q) {
       LevelDevT<T> L = levdev<T>(c, q);
       LevelDevT<T> C = levdev<T>(c, q + 1);
-      dim3 gl = lgrid(L.nx, L.ny, L.nz);
-      hipLaunchKernelGGL(k_prolong<T>, gl, b, 0, c->stream, L.nx, L.ny, L.nz, L.dim, L.z, C);
-      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 1, 0);
-      hipLaunchKernelGGL(k_level_smooth<T>, gl, b, 0, c->stream, L, 0, 0);
+      dim3 gr = lgrid_rb(L.nx, L.ny, L.nz);
+      hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 1, C, 1);
+      hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 0, C, 0);
     }
     zc = L1.z;
     cnx = L1.nx;
