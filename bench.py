@@ -30,12 +30,49 @@ sys.path.insert(0, HERE)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# algorithmic bytes per cell of the timed kernel classes (FP64 arrays read and
-# written once per launch; neighbours assumed reused on chip)
-#   fine pressure-operator apply: read x, rAU (8+8), flags (1); write y (8)
-#   momentum half sweep (one colour): read u,v,w,rhs(3),aPr,nut,phi(3) for the
-#   whole grid = 11*8, write u,v,w for half of the cells = 12
-ALGO_BYTES = {"p_apply": 25.0, "mom_sweep": 100.0}
+# Algorithmic bytes per cell and launch of the timed kernel classes (minimal
+# fused design: every FP64 array streamed once per pass, neighbours reused on
+# chip; per-pass figures of the byte model of one SIMPLE iteration):
+#   k / omega sweeps: 2 x 144 B/cell for n_s = 2 -> 36 per one-colour launch
+#   momentum sweeps: 224 B/cell for n_s = 2 -> 56 per one-colour launch
+#   momentum assembly: u,v,w,p,phi(3),nu_t (+flags) in, b(3), a_P out: 97
+#   omega and k assembly: 2 x 80 -> 80 per launch
+#   fine pressure-operator apply (SpMV): x, rAU in, y out: 24
+ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 97.0, "scalar_assemble": 80.0,
+              "p_apply": 24.0}
+KERNEL = {"scalar_sweep": "k_scalar_sweep", "mom_sweep": "k_mom_sweep", "mom_assemble": "k_mom_assemble",
+          "scalar_assemble": "k_scalar_assemble", "p_apply": "k_fine_apply"}
+KERNEL_SOURCES = {"k_scalar_sweep": "turbulence.hip", "k_scalar_assemble": "turbulence.hip",
+                  "k_mom_sweep": "simple.hip", "k_mom_assemble": "simple.hip", "k_fine_apply": "pressure.hip"}
+
+
+def kernel_source_hash(kernel):
+    """SHA-256 of the sources a kernel is built from (its file and the shared
+    device headers): a stored traffic measurement is valid only while equal."""
+    import hashlib
+    csrc = os.path.join(HERE, "paper_2606_06135_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCES[kernel], "device_common.h", "hfdib_internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel, workload):
+    """HBM-side traffic per launch (bytes) from the committed counter summary of
+    this kernel and workload, or None when absent or taken on other sources."""
+    path = os.path.join(HERE, "profiles", f"traffic_{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256") != kernel_source_hash(kernel):
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -104,7 +141,8 @@ def main():
     roof = None
     kern = {}
     if not args.no_timing:
-        for name in ("p_apply", "mom_sweep", "mom_assemble", "p_solve", "iteration"):
+        for name in ("p_apply", "mom_sweep", "mom_assemble", "scalar_sweep", "scalar_assemble", "p_solve",
+                     "iteration"):
             ms, cnt = solver.timing_query(name)
             kern[name] = (ms, cnt)
         solver.timing(False)
@@ -116,10 +154,15 @@ def main():
             ms, cnt = cand[dom]
             avg_s = ms / 1e3 / cnt
             achieved = ALGO_BYTES[dom] * N / avg_s / 1e9
+            kname = KERNEL[dom]
+            workload = spec.name + "_" + spec.model + "_" + args.precision
+            traffic = stored_traffic(kname, workload) if args.precision == "fp64" else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
-                    "kernel": {"p_apply": "k_fine_apply", "mom_sweep": "k_mom_sweep"}[dom],
-                    "avg_launch_us": round(avg_s * 1e6, 2), "bytes_per_cell": ALGO_BYTES[dom]}
+                    "frac": round(achieved / PEAK_HBM_GBS, 4),
+                    "traffic": None if traffic is None else round(traffic),
+                    "kernel": kname, "avg_launch_us": round(avg_s * 1e6, 2),
+                    "algorithmic_bytes_per_cell": ALGO_BYTES[dom],
+                    "share_of_iteration": round(ms / max(kern["iteration"][0], 1e-12), 4)}
 
     value = N * done / elapsed
     del solver
@@ -202,7 +245,7 @@ def cpu_baseline(spec, p_rtol):
     t0 = time.time()
     sim = Simple(spec, p_solver="cg", p_rtol=p_rtol)
     log(f"cpu baseline: precompute {time.time() - t0:.1f}s; timing one iteration")
-    n_it = 1
+    n_it = 2
     from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()

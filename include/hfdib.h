@@ -208,7 +208,8 @@ int hfdib_last_stats(hfdib_ctx* ctx, double* out8);
  * hfdib_timing_query); 0 stops.  Adds host overhead; off by default. */
 int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
 /* kernel_class: 0 pressure operator apply (fine level), 1 momentum sweep,
- * 2 momentum assembly, 3 whole pressure solve, 4 whole SIMPLE iteration.
+ * 2 momentum assembly, 3 whole pressure solve, 4 whole SIMPLE iteration,
+ * 5 k / eps-omega sweep (one colour), 6 turbulence scalar assembly.
  * Returns accumulated milliseconds and the launch count (host pointers).
  * Synchronises the stream. */
 int hfdib_timing_query(hfdib_ctx* ctx, int kernel_class, double* total_ms, long long* count);

@@ -23,7 +23,8 @@ FIELD = {"ux": 0, "uy": 1, "uz": 2, "p": 3, "k": 4, "w": 5, "nut": 6,
 IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "yeff": 5, "mode": 6,
       "lagrange": 7, "st1_idx": 8, "st1_w": 9, "st2_idx": 10, "st2_w": 11, "yplus": 12,
       "utau_loglaw": 13, "wall_y": 14}
-TIMER = {"p_apply": 0, "mom_sweep": 1, "mom_assemble": 2, "p_solve": 3, "iteration": 4}
+TIMER = {"p_apply": 0, "mom_sweep": 1, "mom_assemble": 2, "p_solve": 3, "iteration": 4, "scalar_sweep": 5,
+         "scalar_assemble": 6}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
           -4: "diverged", -5: "call out of order"}
 

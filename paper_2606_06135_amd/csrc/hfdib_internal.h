@@ -163,7 +163,8 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);
   } while (0)
 
 // timing classes
-enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_NCLASS = 5 };
+enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_SCALSWEEP = 5, T_SCALASM = 6,
+       T_NCLASS = 7 };
 void timer_begin(hfdib_ctx* c, int cls);
 void timer_end(hfdib_ctx* c, int cls);
 

@@ -464,16 +464,20 @@ int turbulence_stage(hfdib_ctx* c) {
   auto sweeps = [&](int eq, double* x, uint8_t fixmask) {
     for (int s = 0; s < P.n_sweeps; ++s)
       for (int color = 0; color < 2; ++color) {
+        timer_begin(c, T_SCALSWEEP);
         if (mixed)
           hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0], x, color,
                              fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
         else
           hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, eq, c->t0, c->t1, x, color, fixmask);
+        timer_end(c, T_SCALSWEEP);
       }
   };
   // omega / eps equation, alpha_omega rows fixed
+  timer_begin(c, T_SCALASM);
   hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, S + SC_MEANS + 5,
                      c->partials, c->pstride);
+  timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
   sweeps(0, c->w, (uint8_t)F_ALPHA_W);
   // k_ib, then the k equation with S_ib (bounds omega/eps on the way)
@@ -481,8 +485,10 @@ int turbulence_stage(hfdib_ctx* c) {
     hipLaunchKernelGGL(k_kib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
                        c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->bc_yplus, c->bc_utau, c->k,
                        c->kib);
+  timer_begin(c, T_SCALASM);
   hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, S + SC_MEANS + 4,
                      c->partials, c->pstride);
+  timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
   hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, c->kib, c->k, c->w,
