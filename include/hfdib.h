@@ -185,6 +185,32 @@ int hfdib_set_field(hfdib_ctx* ctx, int field_id, const double* src_dev);
 /* Sizes of the precomputed lists: counts[0] = n_bc, [1] = n_ic, [2] = n_wall. */
 int hfdib_get_counts(hfdib_ctx* ctx, int* counts);
 
+/* Force on the immersed body per unit density (kinematic) from the current
+ * state, for the drag and lift coefficients (Sec. "Flow over a cylinder", eq. of
+ * the drag coefficient; eq. of the lift coefficient).  The surface element of a
+ * cell is |grad lambda| V (central differences, one-sided at domain edges), its
+ * outward normal -grad lambda / |grad lambda|.  out8 (host, 8 doubles):
+ * [0..2] pressure force sum_cells p grad(lambda) V; [3..5] viscous force: the
+ * |grad lambda| V-weighted mean over boundary cells of tau_w t (t: direction of
+ * the tangential velocity relative to the solid; tau_w = u_tau^2 of the log-law
+ * Newton solve on logarithmic-branch cells, nu |u_t| / y_eff on viscous-branch
+ * cells) times the interface area; [6] interface area sum_cells |grad lambda| V;
+ * [7] the part of it on boundary cells.  C = 2 F.v / (|u_in|^2 A_ref).
+ * Synchronises the stream.  HFDIB_ESTATE before hfdib_set_indicator. */
+int hfdib_forces(hfdib_ctx* ctx, double* out8);
+
+/* Tile shape of the full-grid kernels: 256-thread tiles of width 32, 64 (the
+ * default), 128 or 256 cells along x.  hfdib_autotune_tiles times, for each
+ * width, reps rounds of the gradient pass, the momentum assembly and the
+ * pressure operator on the current state (none of them changes the state),
+ * keeps the fastest width and returns it in *best_width (nullable) with the
+ * average milliseconds per round of widths 32, 64, 128, 256 in ms4 (host,
+ * nullable).  The width changes only the order of partial sums in reductions.
+ * A batch captures the width in force when it is created.  HFDIB_EINVAL for
+ * other widths or reps < 1, HFDIB_ESTATE before hfdib_set_indicator. */
+int hfdib_autotune_tiles(hfdib_ctx* ctx, int reps, int* best_width, double* ms4);
+int hfdib_set_tile_width(hfdib_ctx* ctx, int width);
+
 /* Copies one per-boundary-cell record array (HFDIB_IB_*) to dst_dev. */
 int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);
 
@@ -215,6 +241,36 @@ int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
 int hfdib_timing_query(hfdib_ctx* ctx, int kernel_class, double* total_ms, long long* count);
 
 void hfdib_destroy(hfdib_ctx* ctx);
+
+/* ---------------------------------------------------------------- batches
+ * Independent contexts (for instance one section at many angles of attack, on
+ * grids of different sizes) iterated together by one HIP graph launch.  Each
+ * context must use its own non-null stream, distinct from the batch stream.
+ * hfdib_batch_create captures two SIMPLE iterations of every context, each on
+ * its stream between a fork and a join of the batch stream, with exactly
+ * pcg_iters PCG iterations per pressure solve and no host read; a device record
+ * per context counts iterations, keeps the first iteration whose maximum
+ * normalised residual is <= tol, and flags non-finite residuals.  It finishes
+ * the contexts' pending work; the graph references their workspaces, which
+ * must stay alive until hfdib_batch_destroy.  HFDIB_EINVAL: bad arguments,
+ * shared or null streams; HFDIB_ESTATE: a context without set_indicator;
+ * HFDIB_EDEVICE: capture or instantiation failed (hfdib_batch_last_error). */
+typedef struct hfdib_batch hfdib_batch;
+int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol, void* hip_stream,
+                       hfdib_batch** out);
+/* Launches the graph ceil(iters / 2) times on the batch stream (every context
+ * advances by two iterations per launch).  Returns after queueing; no host
+ * synchronisation with the device.  Work queued on the contexts' own streams
+ * before the call is waited for. */
+int hfdib_batch_run(hfdib_batch* b, int iters);
+/* Waits for the batch stream and copies, per context i (host arrays of n):
+ * iters_done[i], conv_iter[i] (first converged iteration counted from
+ * hfdib_batch_create, -1 if none) and res[6 i .. 6 i + 5] (last normalised
+ * residuals, as hfdib_simple_iterate).  Any array may be null.  Returns
+ * HFDIB_EDIVERGED if a context produced a non-finite residual. */
+int hfdib_batch_status(hfdib_batch* b, int* conv_iter, int* iters_done, double* res);
+const char* hfdib_batch_last_error(const hfdib_batch* b);
+void hfdib_batch_destroy(hfdib_batch* b);
 const char* hfdib_status_string(int status);
 const char* hfdib_last_error(const hfdib_ctx* ctx);
 

@@ -6,6 +6,7 @@ package only binds it.  See ``binding.Solver``.
 
 from .binding import (  # noqa: F401
     Solver,
+    Batch,
     HfdibError,
     make_desc_config,
     default_config,

@@ -89,9 +89,21 @@ def lib():
     L.hfdib_status_string.restype = C.c_char_p
     L.hfdib_last_error.argtypes = [vp]
     L.hfdib_last_error.restype = C.c_char_p
+    L.hfdib_forces.argtypes = [vp, C.POINTER(d)]
+    L.hfdib_autotune_tiles.argtypes = [vp, i, C.POINTER(i), C.POINTER(d)]
+    L.hfdib_set_tile_width.argtypes = [vp, i]
+    L.hfdib_batch_create.argtypes = [C.POINTER(vp), i, i, d, vp, C.POINTER(vp)]
+    L.hfdib_batch_run.argtypes = [vp, i]
+    L.hfdib_batch_status.argtypes = [vp, C.POINTER(i), C.POINTER(i), C.POINTER(d)]
+    L.hfdib_batch_last_error.argtypes = [vp]
+    L.hfdib_batch_last_error.restype = C.c_char_p
+    L.hfdib_batch_destroy.argtypes = [vp]
+    L.hfdib_batch_destroy.restype = None
     for fn in ("hfdib_workspace_bytes", "hfdib_init_grid", "hfdib_set_indicator", "hfdib_simple_iterate",
                "hfdib_get_field", "hfdib_set_field", "hfdib_get_counts", "hfdib_get_ib_array",
-               "hfdib_pressure_solve", "hfdib_last_stats", "hfdib_timing_enable", "hfdib_timing_query"):
+               "hfdib_pressure_solve", "hfdib_last_stats", "hfdib_timing_enable", "hfdib_timing_query",
+               "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
+               "hfdib_autotune_tiles", "hfdib_set_tile_width"):
         getattr(L, fn).restype = i
     if L.hfdib_abi_version() != ABI_VERSION:
         raise ImportError("libhfdib ABI version mismatch")
@@ -103,7 +115,8 @@ EXPORTED = ["hfdib_abi_version", "hfdib_default_config", "hfdib_workspace_bytes"
             "hfdib_set_indicator", "hfdib_simple_iterate", "hfdib_get_field", "hfdib_set_field",
             "hfdib_get_counts", "hfdib_get_ib_array", "hfdib_pressure_solve", "hfdib_last_stats",
             "hfdib_timing_enable", "hfdib_timing_query", "hfdib_destroy", "hfdib_status_string",
-            "hfdib_last_error"]
+            "hfdib_last_error", "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
+            "hfdib_batch_last_error", "hfdib_batch_destroy", "hfdib_autotune_tiles", "hfdib_set_tile_width"]
 
 
 def default_config():
@@ -178,9 +191,22 @@ class Solver:
         self.N = desc.nx * desc.ny * desc.nz
 
     @classmethod
-    def from_spec(cls, spec, device="cuda:0", **kw):
+    def from_spec(cls, spec, device="cuda:0", stream=None, **kw):
         d, c = make_desc_config(spec, **kw)
-        return cls(d, c, device=device)
+        return cls(d, c, device=device, stream=stream)
+
+    # stream ordering between torch's current stream and the solver's stream
+    def _sync_in(self):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def _sync_out(self, *tensors):
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            cur.wait_stream(self.stream)
+            for t in tensors:
+                t.record_stream(self.stream)
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -203,6 +229,7 @@ class Solver:
     def set_indicator(self, lam, solid_vel=None):
         self._lam = self._t(lam).reshape(-1)
         self._us = None if solid_vel is None else self._t(solid_vel).reshape(-1)
+        self._sync_in()
         st = lib().hfdib_set_indicator(self.ctx, C.c_void_p(self._lam.data_ptr()),
                                        C.c_void_p(self._us.data_ptr()) if self._us is not None else None)
         _check("hfdib_set_indicator", st, self.ctx)
@@ -226,14 +253,17 @@ class Solver:
 
     def get_field(self, name):
         out = self.torch.empty(self.field_size(name), dtype=self.torch.float64, device=self.device)
+        self._sync_in()
         _check("hfdib_get_field", lib().hfdib_get_field(self.ctx, FIELD[name], C.c_void_p(out.data_ptr())), self.ctx)
+        self._sync_out(out)
         return out
 
     def set_field(self, name, values):
         v = self._t(values).reshape(-1)
         assert v.numel() == self.field_size(name)
+        self._sync_in()
         _check("hfdib_set_field", lib().hfdib_set_field(self.ctx, FIELD[name], C.c_void_p(v.data_ptr())), self.ctx)
-        self.torch.cuda.current_stream(self.device).synchronize()
+        self.stream.synchronize()
 
     def counts(self):
         a = (C.c_int * 3)()
@@ -252,8 +282,10 @@ class Solver:
                  "wall_y": (n["wall"], t.float64)}
         cnt, dt = sizes[name]
         out = t.empty(max(cnt, 1), dtype=dt, device=self.device)
+        self._sync_in()
         _check("hfdib_get_ib_array", lib().hfdib_get_ib_array(self.ctx, IB[name], C.c_void_p(out.data_ptr())),
                self.ctx)
+        self._sync_out(out)
         return out[:cnt]
 
     def pressure_solve(self, rAU, rhs, p0, rtol=1e-12, maxit=200):
@@ -261,11 +293,40 @@ class Solver:
         p = self._t(p0).reshape(-1).clone()
         it = C.c_int(0)
         rr = C.c_double(0.0)
+        self._sync_in()
         st = lib().hfdib_pressure_solve(self.ctx, C.c_void_p(rAU.data_ptr()), C.c_void_p(rhs.data_ptr()),
                                         C.c_void_p(p.data_ptr()), float(rtol), int(maxit), C.byref(it),
                                         C.byref(rr))
         _check("hfdib_pressure_solve", st, self.ctx)
+        self._sync_out(p)
         return p, it.value, rr.value
+
+    def autotune_tiles(self, reps=5):
+        """Times the tile widths on the current state, keeps the fastest;
+        returns (width, {width: ms per round})."""
+        best = C.c_int(0)
+        ms = (C.c_double * 4)()
+        _check("hfdib_autotune_tiles", lib().hfdib_autotune_tiles(self.ctx, int(reps), C.byref(best), ms), self.ctx)
+        return best.value, {32 << q: ms[q] for q in range(4)}
+
+    def set_tile_width(self, width):
+        _check("hfdib_set_tile_width", lib().hfdib_set_tile_width(self.ctx, int(width)), self.ctx)
+
+    def forces(self):
+        """Force on the body per unit density: pressure part, viscous part,
+        interface area and its boundary-cell part (see hfdib_forces)."""
+        a = (C.c_double * 8)()
+        _check("hfdib_forces", lib().hfdib_forces(self.ctx, a), self.ctx)
+        return {"pressure": [a[0], a[1], a[2]], "viscous": [a[3], a[4], a[5]], "area": a[6], "bc_area": a[7]}
+
+    def coefficients(self, ref_area, u_ref=1.0, drag_dir=(1.0, 0.0, 0.0), lift_dir=(0.0, 1.0, 0.0)):
+        """Drag and lift coefficients C = 2 F.v / (|u|^2 A_ref) of the current state."""
+        f = self.forces()
+        tot = [f["pressure"][q] + f["viscous"][q] for q in range(3)]
+        q = 0.5 * u_ref * u_ref * ref_area
+        cd = sum(tot[i] * drag_dir[i] for i in range(3)) / q
+        cl = sum(tot[i] * lift_dir[i] for i in range(3)) / q
+        return cd, cl
 
     def stats(self):
         a = (C.c_double * 8)()
@@ -281,3 +342,49 @@ class Solver:
         _check("hfdib_timing_query", lib().hfdib_timing_query(self.ctx, TIMER[name], C.byref(ms), C.byref(cnt)),
                self.ctx)
         return ms.value, cnt.value
+
+
+class Batch:
+    """Independent solvers (each with its own stream) iterated together by one
+    HIP graph launch per two SIMPLE iterations (see hfdib_batch_create)."""
+
+    def __init__(self, solvers, pcg_iters=4, tol=1e-8, stream=None):
+        import torch
+        self.torch = torch
+        self.solvers = list(solvers)  # keeps the workspaces alive
+        dev = self.solvers[0].device
+        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
+        arr = (C.c_void_p * len(self.solvers))(*[s.ctx for s in self.solvers])
+        b = C.c_void_p()
+        st = lib().hfdib_batch_create(arr, len(self.solvers), int(pcg_iters), float(tol),
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(b))
+        if st != 0:
+            raise HfdibError("hfdib_batch_create", st, "")
+        self.b = b
+
+    def run(self, iters):
+        st = lib().hfdib_batch_run(self.b, int(iters))
+        if st != 0:
+            raise HfdibError("hfdib_batch_run", st, lib().hfdib_batch_last_error(self.b).decode())
+
+    def status(self):
+        n = len(self.solvers)
+        conv = (C.c_int * n)()
+        done = (C.c_int * n)()
+        res = (C.c_double * (6 * n))()
+        st = lib().hfdib_batch_status(self.b, conv, done, res)
+        if st not in (0, -4):
+            raise HfdibError("hfdib_batch_status", st, lib().hfdib_batch_last_error(self.b).decode())
+        return {"diverged": st == -4, "conv_iter": list(conv), "iters_done": list(done),
+                "residuals": [list(res[6 * i:6 * i + 6]) for i in range(n)]}
+
+    def close(self):
+        if getattr(self, "b", None):
+            lib().hfdib_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

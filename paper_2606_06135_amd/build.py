@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhfdib.so")
-SOURCES = ["api.hip", "geometry.hip", "simple.hip", "pressure.hip", "turbulence.hip"]
+SOURCES = ["api.hip", "geometry.hip", "simple.hip", "pressure.hip", "turbulence.hip", "forces.hip", "batch.hip"]
 
 
 def hipcc():

@@ -160,8 +160,15 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->wall_yplus = B.take<double>(cap);
   c->wall_utau = B.take<double>(cap);
   c->ipts = B.take<double>(3LL * cap);
-  dim3 g = grid3(P);
-  long long nblk3 = (long long)g.x * g.y * g.z;
+  // partial rows hold one entry per block of the largest tile-shape candidate
+  long long nblk3 = 0;
+  for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX; ++lx) {
+    Params Q = P;
+    Q.tx_log2 = lx;
+    dim3 g = grid3(Q);
+    long long nb = (long long)g.x * g.y * g.z;
+    nblk3 = nb > nblk3 ? nb : nblk3;
+  }
   long long nb1 = nblocks1(N);
   long long ps = nblk3 > nb1 ? nblk3 : nb1;
   c->pstride = (ps + 63) / 64 * 64;
@@ -369,6 +376,7 @@ static void fill_params(hfdib_ctx* c) {
   P.recorrect = g.recorrect;
   P.continuity = g.continuity;
   P.precision = g.precision;
+  P.tx_log2 = 6;
 }
 
 static int capacity_for(long long N, int requested) {
@@ -594,6 +602,62 @@ int hfdib_set_field(hfdib_ctx* c, int id, const double* src) {
   HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "set_field");
   c->grad_ok = 0;
   return hfdib::refresh_mirrors(c);
+}
+
+int hfdib_forces(hfdib_ctx* c, double* out8) {
+  if (!c || !out8) return HFDIB_EINVAL;
+  if (!c->ready) {
+    c->err = "hfdib_forces before hfdib_set_indicator";
+    return HFDIB_ESTATE;
+  }
+  return hfdib::body_forces(c, out8);
+}
+
+int hfdib_autotune_tiles(hfdib_ctx* c, int reps, int* best_width, double* ms_out) {
+  if (!c || reps < 1) return HFDIB_EINVAL;
+  if (!c->ready) {
+    c->err = "hfdib_autotune_tiles before hfdib_set_indicator";
+    return HFDIB_ESTATE;
+  }
+  hipEvent_t e0, e1;
+  HFDIB_CHECK(c, hipEventCreate(&e0), "autotune event");
+  HFDIB_CHECK(c, hipEventCreate(&e1), "autotune event");
+  int best = c->P.tx_log2;
+  double best_ms = 0.0;
+  int status = HFDIB_OK;
+  for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX && status == HFDIB_OK; ++lx) {
+    c->P.tx_log2 = lx;
+    status = tile_bench_round(c);  // warm-up
+    if (status != HFDIB_OK) break;
+    (void)hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && status == HFDIB_OK; ++r) status = tile_bench_round(c);
+    (void)hipEventRecord(e1, c->stream);
+    hipError_t e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) status = set_hip_error(c, e, "autotune timing");
+    double avg = (double)ms / reps;
+    if (ms_out) ms_out[lx - TILE_LOG2_MIN] = avg;
+    if (lx == TILE_LOG2_MIN || avg < best_ms) {
+      best_ms = avg;
+      best = lx;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->P.tx_log2 = best;
+  if (best_width) *best_width = 1 << best;
+  return status;
+}
+
+int hfdib_set_tile_width(hfdib_ctx* c, int width) {
+  if (!c) return HFDIB_EINVAL;
+  for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX; ++lx)
+    if (width == (1 << lx)) {
+      c->P.tx_log2 = lx;
+      return HFDIB_OK;
+    }
+  return HFDIB_EINVAL;
 }
 
 int hfdib_get_counts(hfdib_ctx* c, int* counts) {

@@ -446,7 +446,7 @@ int geometry_precompute(hfdib_ctx* c) {
     c->err = "lambda contains NaN or values outside [0,1]";
     return HFDIB_EINVAL;
   }
-  hipLaunchKernelGGL(k_classify, grid3(P), block3(), 0, c->stream, P, c->lam, c->flags);
+  hipLaunchKernelGGL(k_classify, grid3(P), block3(P), 0, c->stream, P, c->lam, c->flags);
   HFDIB_CHECK_LAUNCH(c, "classify");
   int st;
   if ((st = compact(c, F_BC, c->bc_cells, &c->n_bc)) != HFDIB_OK) return st;
@@ -462,7 +462,7 @@ int geometry_precompute(hfdib_ctx* c) {
   HFDIB_CHECK_LAUNCH(c, "bc geometry");
   if (P.model == HFDIB_KOMEGA_SST) {
     int* cnt = c->iscal + 16;
-    hipLaunchKernelGGL(k_iface_points, grid3(P), block3(), 0, c->stream, P, c->lam, c->flags, c->ipts, cnt,
+    hipLaunchKernelGGL(k_iface_points, grid3(P), block3(P), 0, c->stream, P, c->lam, c->flags, c->ipts, cnt,
                        c->cap);
     HFDIB_CHECK_LAUNCH(c, "interface points");
     int h = 0;

@@ -25,6 +25,7 @@ constexpr int MAX_PARTIAL_BLOCKS = 2048;  // per reduction slot
 constexpr int NRED = 24;                  // reduction slots per pass
 constexpr int MAX_LEVELS = 12;
 constexpr int FIN2_STRIDE = 1024;         // second-stage partials per reduction row
+constexpr int TILE_LOG2_MIN = 5, TILE_LOG2_MAX = 8;  // tile widths 32 .. 256 cells
 
 // Plain-old-data parameters passed by value to every kernel.
 struct Params {
@@ -54,6 +55,7 @@ struct Params {
   int recorrect;
   int continuity;
   int precision;  // HFDIB_FP64 or HFDIB_MIXED
+  int tx_log2;    // tile width of the full-grid kernels: 2^tx_log2 cells (5..8), 256 threads per tile
 };
 
 // Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).
@@ -126,6 +128,8 @@ struct hfdib_ctx {
   // --- multigrid
   int nlev;
   hfdib::Level lev[hfdib::MAX_LEVELS];
+  // --- graph mode (batched replay): fixed PCG iteration count, no host reads
+  int graph_mode, graph_pcg;
   // --- stats
   double stats[8];
   double last_pres[3];
@@ -136,14 +140,20 @@ struct hfdib_ctx {
 namespace hfdib {
 
 // launch helpers
+// Full-grid kernels run 256-thread tiles of 2^tx_log2 x 2^(8 - tx_log2) cells
+// (chosen by hfdib_autotune_tiles; 64 x 4 by default)
 inline dim3 grid3(const Params& P) {
-  return dim3((unsigned)(((P.nx + 63) / 64) * ((P.ny + 3) / 4) * P.nz), 1, 1);
+  const int TX = 1 << P.tx_log2, TY = 256 >> P.tx_log2;
+  return dim3((unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY) * P.nz), 1, 1);
 }
-inline dim3 block3() { return dim3(64, 4, 1); }
+inline dim3 block3(const Params& P) { return dim3(1u << P.tx_log2, 256u >> P.tx_log2, 1); }
 // grid of the red-black half sweeps (half the x extent, see tile_ijk_rb)
 inline dim3 grid3_rb(const Params& P) {
-  return dim3((unsigned)((((P.nx + 1) / 2 + 63) / 64) * ((P.ny + 3) / 4) * P.nz), 1, 1);
+  const int TX = 1 << P.tx_log2, TY = 256 >> P.tx_log2;
+  return dim3((unsigned)((((P.nx + 1) / 2 + TX - 1) / TX) * ((P.ny + TY - 1) / TY) * P.nz), 1, 1);
 }
+// blocks of the stored multigrid levels (3-D grids of 64 x 4 tiles)
+inline dim3 block_lv() { return dim3(64, 4, 1); }
 inline int nblocks1(long long n) {
   long long b = (n + NTHREADS - 1) / NTHREADS;
   return (int)(b < 1 ? 1 : b);
@@ -181,12 +191,17 @@ int refresh_mirrors(hfdib_ctx* c);
 void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0);
 int turbulence_stage(hfdib_ctx* c);
 int velocity_gradient(hfdib_ctx* c);
+int body_forces(hfdib_ctx* c, double* out8);
+int tile_bench_round(hfdib_ctx* c);
+void pressure_apply_bench(hfdib_ctx* c);
 // offsets (relative to SCAL_PCG) of device scalars
 enum {
   SC_MEANS = 100,    // means of u, v, w, p, k (5) and of omega/eps after fixing (1)
   SC_RESSUM = 120,   // residual sums: U 9, omega/eps 3, k 3
   SC_RES = 150,      // normalised residuals Ux, Uy, Uz, p, k, eps/omega
-  SC_WMAX = 160      // max of omega/eps over boundary and free-stream cells
+  SC_WMAX = 160,     // max of omega/eps over boundary and free-stream cells
+  SC_FORCE = 170,    // body-force sums (8)
+  SC_CONV = 180      // batched runs: iterations done, first converged iteration (-1), non-finite flag
 };
 constexpr int SCAL_PCG = 64;
 

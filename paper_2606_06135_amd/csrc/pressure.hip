@@ -855,8 +855,8 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
 template <typename T>
 static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z) {
   const Params& P = c->P;
-  dim3 g = grid3_rb(P), b = block3();
-  hipLaunchKernelGGL(k_fine_presmooth<T>, g, b, 0, c->stream, P, O, invD, r, z);
+  dim3 g = grid3_rb(P), bf = block3(P), b = block_lv();
+  hipLaunchKernelGGL(k_fine_presmooth<T>, g, bf, 0, c->stream, P, O, invD, r, z);
   const T* zc = nullptr;
   int cnx = 0, cny = 0;
   if (c->nlev > 1) {
@@ -900,15 +900,15 @@ static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r,
     cny = L1.ny;
   }
   // post-smoothing, black first (with the prolongation on the fly), then red
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny);
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, b, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0);
 }
 
 // coarse operators of every level from the FP64 fine operator
 template <typename T>
 static void build_levels(hfdib_ctx* c, const FineOp& O) {
   const Params& P = c->P;
-  dim3 b = block3();
+  dim3 b = block_lv();
   for (int l = 1; l < c->nlev; ++l) {
     Level& L = c->lev[l];
     LevelDevT<T> Ld = levdev<T>(c, l);
@@ -932,7 +932,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
                T* r_m, T* z_m, float* r32, double rtol, int maxit, int* iters, double* relres,
                const double* xmean_dev) {
   const Params& P = c->P;
-  dim3 g = grid3(P), b = block3();
+  dim3 g = grid3(P), b = block3(P);
   long long nblk3 = (long long)g.x * g.y * g.z;
   int nb1 = nblocks1(P.N);
   double* r = c->pr;
@@ -948,6 +948,28 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
                      c->pstride);
   launch_finalize(c, nb1, 1, S_RZ, 3);
   hipLaunchKernelGGL(k_copy_vec<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const T*)z_m, d);
+  if (c->graph_mode) {
+    // fixed iteration count, no host read (the step may be captured in a graph);
+    // the scalar updates guard zero denominators on the device
+    const int nit = c->graph_pcg;
+    for (int it = 1; it <= nit; ++it) {
+      hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
+      launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
+      hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, r32, q, c->partials,
+                         c->pstride);
+      launch_finalize(c, nb1, 1, S_RR, 0);
+      if (it == nit) break;
+      vcycle<T>(c, OM, invD, r_m, z_m);
+      hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
+                         c->pstride);
+      launch_finalize(c, nb1, 1, S_RZ, 2);
+      hipLaunchKernelGGL(k_xpby<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, (const T*)z_m, d);
+    }
+    HFDIB_CHECK_LAUNCH(c, "pcg (fixed)");
+    if (iters) *iters = nit;
+    if (relres) *relres = 0.0;
+    return HFDIB_OK;
+  }
   double hs[32];
   double rr = 0.0, bnorm = 1.0, target = 0.0;
   int it;
@@ -990,6 +1012,13 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
   return HFDIB_OK;
 }
 
+void pressure_apply_bench(hfdib_ctx* c) {
+  const Params& P = c->P;
+  FineOp O{c->rAU, c->flags};
+  hipLaunchKernelGGL(k_fine_apply, grid3(P), block3(P), 0, c->stream, P, O, (const double*)c->pd, c->pq, c->partials,
+                     c->pstride);
+}
+
 int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol, int maxit, int* iters,
                    double* relres, const double* xmean_dev) {
   const Params& P = c->P;
@@ -999,12 +1028,12 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
   if (P.precision == HFDIB_MIXED) {
     // FP32 mirror of rAU and inverse diagonal for the fine smoother; coarse
     // operators from the FP64 fine operator
-    hipLaunchKernelGGL(k_fine_invdiag<float>, grid3(P), block3(), 0, c->stream, P, O, c->invD32, c->rAU32);
+    hipLaunchKernelGGL(k_fine_invdiag<float>, grid3(P), block3(P), 0, c->stream, P, O, c->invD32, c->rAU32);
     build_levels<float>(c, O);
     FineOpT<float> OM{c->rAU32, c->flags};
     st = pcg<float>(c, O, OM, c->invD32, rhs, x, c->pr32, c->pz32, c->pr32, rtol, maxit, iters, relres, xmean_dev);
   } else {
-    hipLaunchKernelGGL(k_fine_invdiag<double>, grid3(P), block3(), 0, c->stream, P, O, c->invD, (float*)nullptr);
+    hipLaunchKernelGGL(k_fine_invdiag<double>, grid3(P), block3(P), 0, c->stream, P, O, c->invD, (float*)nullptr);
     build_levels<double>(c, O);
     st = pcg<double>(c, O, O, c->invD, rhs, x, c->pr, c->pz, nullptr, rtol, maxit, iters, relres, xmean_dev);
   }

@@ -653,7 +653,7 @@ int init_state(hfdib_ctx* c) {
   int nb = nblocks1(P.N);
   hipLaunchKernelGGL(k_init_cells, dim3(nb), dim3(NTHREADS), 0, c->stream, P, c->lam, c->us[0], c->us[1], c->us[2],
                      c->u[0], c->u[1], c->u[2], c->p, c->k, c->w, c->nut);
-  hipLaunchKernelGGL(k_interp_flux, grid3(P), block3(), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags,
+  hipLaunchKernelGGL(k_interp_flux, grid3(P), block3(P), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags,
                      c->phi[0], c->phi[1], c->phi[2]);
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->kib, 0.0);
   hipLaunchKernelGGL(k_fill, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, c->wib, 0.0);
@@ -711,9 +711,26 @@ int velocity_gradient(hfdib_ctx* c) {
   const Params& P = c->P;
   GradOut O;
   for (int q = 0; q < 9; ++q) O.G[q] = c->G[q];
-  hipLaunchKernelGGL(k_grad, grid3(P), block3(), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
+  hipLaunchKernelGGL(k_grad, grid3(P), block3(P), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
   HFDIB_CHECK_LAUNCH(c, "velocity gradient");
   c->grad_ok = 1;
+  return HFDIB_OK;
+}
+
+// One round of the kernels the tile autotuner times: the gradient pass, the
+// momentum assembly and the pressure operator.  None of them changes the state
+// (the gradient and the assembly outputs are recomputed from the same state by
+// the next iteration; the operator writes a PCG scratch vector).
+int tile_bench_round(hfdib_ctx* c) {
+  const Params& P = c->P;
+  int st = velocity_gradient(c);
+  if (st != HFDIB_OK) return st;
+  Mom M = make_mom(c);
+  MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
+  hipLaunchKernelGGL(k_mom_assemble, grid3(P), block3(P), 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2],
+                     c->aPr, c->scal + SCAL_PCG + SC_MEANS, c->partials, c->pstride);
+  pressure_apply_bench(c);
+  HFDIB_CHECK_LAUNCH(c, "tile bench");
   return HFDIB_OK;
 }
 
@@ -742,7 +759,7 @@ int refresh_mirrors(hfdib_ctx* c) {
 int simple_step(hfdib_ctx* c, int it, double* res_host) {
   (void)it;
   const Params& P = c->P;
-  dim3 g = grid3(P), b = block3();
+  dim3 g = grid3(P), b = block3(P);
   long long nblk3 = (long long)g.x * g.y * g.z;
   int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;

@@ -420,7 +420,7 @@ __global__ void k_set1(double* a, double v) {
 
 int turbulence_stage(hfdib_ctx* c) {
   const Params& P = c->P;
-  dim3 g = grid3(P), b = block3();
+  dim3 g = grid3(P), b = block3(P);
   long long nblk3 = (long long)g.x * g.y * g.z;
   int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;

@@ -19,6 +19,8 @@ from .cases import (  # noqa: F401
     case_cavity_block,
     case_small_body3d,
     case_uniform_duct,
+    case_naca,
+    naca_sweep_specs,
 )
 from .geometry import (  # noqa: F401
     lambda_from_sdf,
@@ -26,4 +28,6 @@ from .geometry import (  # noqa: F401
     sdf_ahmed_like,
     sdf_halfspace,
     sdf_sphere,
+    sdf_naca_symmetric,
+    naca4_half_thickness,
 )

@@ -227,3 +227,38 @@ def case_uniform_duct(nx=64, ny=4, model="keps", U=1.0, L=1.0):
               nu=1e-5, model=model)
     s.lam = np.zeros(s.shape)
     return s.validate()
+
+
+def case_naca(gamma_deg=4.0, nx=256, ny=128, model="sst", intensity=0.03):
+    """2D NACA 0012 section (chord 1, leading edge at the origin) pitched to the
+    angle of attack gamma about the quarter chord, in x in [-2, 6],
+    y in [-2, 2] (square cells: 256 x 128, 512 x 256 or 1024 x 512).
+    Re = 1e6 on the chord (nu = 1e-6, U = 1 along +x), inlet turbulence
+    intensity I (k = 1.5 I^2; default 3 %), omega_in = 5 U / c; inlet at
+    x = -2, outlet at x = 6, slip far-field top and bottom.  Lift is along +y,
+    drag along +x.  (With I = 0.1 % every near-wall cell starts on the viscous
+    branch and the iteration diverges on the two finer grids; the paper takes
+    its inlet values from a reference that is not available here.)"""
+    dx = 8.0 / nx
+    dy = 4.0 / ny
+    k = 1.5 * intensity ** 2
+    om = 5.0
+    eps = 0.09 * k * om
+    s = _spec(name=f"naca0012_a{gamma_deg:+.2f}_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+              x0=-2.0, y0=-2.0, z0=0.0, dx=dx, dy=dy, dz=1.0,
+              bc=("inlet", "outlet", "slip", "slip", "empty", "empty"),
+              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
+              nu=1e-6, model=model)
+    s.lam = G.lambda_from_sdf(G.sdf_naca_symmetric(0.12, 1.0, gamma_deg), s)
+    return s.validate()
+
+
+def naca_sweep_specs(n=64, gamma_min=-10.0, gamma_max=20.0, sizes=((256, 128), (512, 256), (1024, 512))):
+    """The batched sweep: n angles of attack uniformly spaced over
+    [gamma_min, gamma_max], instance j on grid sizes[j % len(sizes)]."""
+    out = []
+    for j in range(n):
+        g = gamma_min + (gamma_max - gamma_min) * j / max(n - 1, 1)
+        nx, ny = sizes[j % len(sizes)]
+        out.append(case_naca(g, nx, ny))
+    return out

@@ -163,3 +163,51 @@ def sdf_ahmed_like(x_front=0.0, length=1.044, width=0.389, height=0.288,
         d_slant = (x - ax) * nsx + (z - az) * nsz
         return np.maximum(np.maximum(d_xz, d_xy), np.maximum(d_rear, d_slant))
     return f
+
+
+def naca4_half_thickness(x, t):
+    """Half thickness of a symmetric NACA four-digit section of relative
+    thickness t at chord fraction x in [0, 1] (the standard polynomial)."""
+    return 5.0 * t * (0.2969 * np.sqrt(x) - 0.1260 * x - 0.3516 * x ** 2 + 0.2843 * x ** 3 - 0.1015 * x ** 4)
+
+
+def sdf_naca_symmetric(t=0.12, chord=1.0, gamma_deg=0.0, pivot=(0.25, 0.0), npts=4000):
+    """Signed distance (positive in fluid) to a symmetric NACA section with its
+    leading edge at the origin and the chord along +x, pitched nose-up by the
+    angle of attack gamma (the section is rotated by -gamma about the pivot, so
+    a flow along +x meets it at incidence gamma).  The magnitude is the
+    distance to a dense cosine-spaced polyline of the surface (npts points per
+    side), the sign comes from the exact thickness function."""
+    from scipy.spatial import cKDTree
+    beta = np.linspace(0.0, np.pi, npts)
+    xs = 0.5 * (1.0 - np.cos(beta))
+    ys = naca4_half_thickness(xs, t)
+    pts = np.concatenate([np.stack([xs, ys], 1), np.stack([xs[::-1], -ys[::-1]], 1)]) * chord
+    # densify along each segment so the point distance approximates the polyline distance
+    seg = np.diff(pts, axis=0)
+    dense = [pts[:-1] + seg * f for f in np.linspace(0.0, 1.0, 8, endpoint=False)]
+    tree = cKDTree(np.concatenate(dense + [pts[-1:]]))
+    g = np.deg2rad(gamma_deg)
+    cg, sg = np.cos(g), np.sin(g)
+    px, py = pivot
+
+    def f(x, y, z):
+        # world -> section frame: undo the rotation by -gamma about the pivot
+        X = np.asarray(x, dtype=np.float64) - px
+        Y = np.asarray(y, dtype=np.float64) - py
+        xa = cg * X - sg * Y + px
+        ya = sg * X + cg * Y + py
+        shape = np.broadcast(xa, ya).shape
+        xa = np.broadcast_to(xa, shape)
+        ya = np.broadcast_to(ya, shape)
+        xr, yr = xa.ravel(), ya.ravel()
+        # exact distances only near the section (far points are fluid and never
+        # part of a cut cell: any positive value serves)
+        near = (xr > -0.2 * chord) & (xr < 1.2 * chord) & (np.abs(yr) < 0.3 * chord)
+        dist = np.full(xr.shape, chord)
+        if near.any():
+            dist[near], _ = tree.query(np.stack([xr[near], yr[near]], 1))
+        xc = xr / chord
+        inside = (xc > 0.0) & (xc < 1.0) & (np.abs(yr) < chord * naca4_half_thickness(np.clip(xc, 0.0, 1.0), t))
+        return np.where(inside, -dist, dist).reshape(shape)
+    return f

@@ -1,0 +1,147 @@
+"""Body forces, tile shapes and batched graph execution through the C ABI.
+
+Forces are compared with the oracle's force integral on the same iterated
+states; tile widths and batching must not change the iteration (parity with
+the oracle, and bitwise equality between batched and isolated contexts)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.forces import body_force
+from oracle.solver import Simple
+from parity_util import compare
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _solver(spec, gpu, stream=None, **kw):
+    import torch
+    from paper_2606_06135_amd import Solver
+    kw.setdefault("p_rtol", 1e-13)
+    kw.setdefault("p_maxit", 300)
+    s = Solver.from_spec(spec, device=gpu, stream=stream, **kw)
+    s.set_indicator(torch.from_numpy(spec.lam.ravel()))
+    return s
+
+
+FORCE_CASES = {
+    "naca_128x64_sst": (lambda: synth.case_naca(6.0, 128, 64), 30),
+    "sphere3d_keps": (lambda: synth.case_small_body3d(model="keps", nu=1e-4), 20),
+    "channel_ib_laminar": (lambda: synth.case_channel_ib(nx=32, n_fluid=8), 30),
+}
+
+
+@pytest.mark.parametrize("name", list(FORCE_CASES))
+def test_forces_match_oracle(gpu, name):
+    mk, iters = FORCE_CASES[name]
+    spec = mk()
+    _say("forces", name, spec.ncells)
+    sim = Simple(spec)
+    for _ in range(iters):
+        sim.step()
+    s = _solver(spec, gpu)
+    s.iterate(iters)
+    F = body_force(sim)
+    G = s.forces()
+    for key in ("pressure", "viscous"):
+        a, b = np.asarray(F[key]), np.asarray(G[key])
+        scale = max(np.abs(a).max(), 1e-300)
+        _say(f"  {key}: oracle {a}, gpu {b}")
+        assert np.abs(a - b).max() <= 1e-8 * scale + 1e-15, (key, a, b)
+    assert abs(F["area"] - G["area"]) <= 1e-12 * F["area"]
+    assert abs(F["bc_area"] - G["bc_area"]) <= 1e-12 * max(F["bc_area"], 1e-300)
+
+
+@pytest.mark.parametrize("width", [32, 64, 128, 256])
+def test_tile_widths_keep_parity(gpu, width):
+    # odd extents: partial tiles in x and y for every width
+    spec = synth.case_small_body3d(nx=37, ny=13, nz=11, model="sst", nu=1e-4)
+    sim = Simple(spec)
+    for _ in range(15):
+        sim.step()
+    s = _solver(spec, gpu)
+    s.set_tile_width(width)
+    s.iterate(15)
+    c = compare(sim, s, dim=spec.dim, model=spec.model)
+    _say(f"width {width}:", {k: f"{v:.1e}" for k, v in c.items()})
+    for k, v in c.items():
+        assert v <= 1e-9, (width, k, v)
+
+
+def test_autotune_leaves_the_state_alone(gpu):
+    spec = synth.case_small_body3d(model="sst", nu=1e-4)
+    s = _solver(spec, gpu)
+    s.iterate(5)
+    keys = ("ux", "uy", "uz", "p", "k", "w", "nut", "phix")
+    before = {k: s.get_field(k).cpu().numpy() for k in keys}
+    width, ms = s.autotune_tiles(reps=2)
+    _say("autotune", width, ms)
+    assert width in (32, 64, 128, 256) and all(v > 0 for v in ms.values())
+    for k in keys:
+        np.testing.assert_array_equal(s.get_field(k).cpu().numpy(), before[k])
+
+
+def _batch_specs():
+    return [synth.case_naca(3.0, 64, 32), synth.case_naca(-5.0, 128, 64),
+            synth.case_small_body3d(model="keps", nu=1e-4)]
+
+
+def _batched(gpu, specs, iters, pcg_iters, tol=1e-8):
+    import torch
+    from paper_2606_06135_amd import Batch
+    solvers = [_solver(sp, gpu, stream=torch.cuda.Stream(gpu), p_rtol=1e-2, p_maxit=100) for sp in specs]
+    b = Batch(solvers, pcg_iters=pcg_iters, tol=tol)
+    b.run(iters)
+    st = b.status()
+    fields = [{k: s.get_field(k).cpu().numpy() for k in ("ux", "uy", "p", "k", "w", "nut")} for s in solvers]
+    b.close()
+    return st, fields, solvers
+
+
+def test_batched_contexts_match_isolated_ones_bitwise(gpu):
+    specs = _batch_specs()
+    st, together, _ = _batched(gpu, specs, 10, 4)
+    assert st["iters_done"] == [10, 10, 10] and not st["diverged"]
+    for q, sp in enumerate(specs):
+        st1, alone, _ = _batched(gpu, [sp], 10, 4)
+        for k in together[q]:
+            np.testing.assert_array_equal(together[q][k], alone[0][k])
+
+
+def test_batch_with_converged_pressure_matches_oracle(gpu):
+    spec = synth.case_naca(3.0, 64, 32)
+    sim = Simple(spec)
+    for _ in range(10):
+        sim.step()
+    st, fields, solvers = _batched(gpu, [spec], 10, 60)
+    c = compare(sim, solvers[0], dim=spec.dim, model=spec.model)
+    _say("batched vs oracle", {k: f"{v:.1e}" for k, v in c.items()})
+    for k, v in c.items():
+        assert v <= 1e-9, (k, v)
+
+
+def test_batch_device_convergence_flag(gpu):
+    spec = synth.case_small_body3d(model="sst", shape="box", nu=1e-5)
+    st, _, solvers = _batched(gpu, [spec], 400, 8, tol=1e-6)
+    _say("convergence flag", st)
+    assert 0 < st["conv_iter"][0] < 400
+    assert st["iters_done"][0] == 400
+    assert max(st["residuals"][0]) <= 1e-6
+
+
+def test_batch_rejects_shared_streams(gpu):
+    import torch
+    from paper_2606_06135_amd import Batch, HfdibError
+    st = torch.cuda.Stream(gpu)
+    a = _solver(synth.case_naca(0.0, 64, 32), gpu, stream=st)
+    b = _solver(synth.case_naca(2.0, 64, 32), gpu, stream=st)
+    with pytest.raises(HfdibError) as e:
+        Batch([a, b], pcg_iters=2)
+    assert e.value.status == -1
