@@ -13,6 +13,13 @@ the 512 x 192 x 192 Ahmed-like workload (18.9 M cells) and iterate until the
 maximum normalised residual reaches 1e-8; the wall time of each, the speedup
 and the relative L2 difference of the converged fields are reported.
 
+It also runs the batched angle-of-attack sweep: 64 NACA 0012 instances
+(-10..+20 degrees, grids of 256 x 128, 512 x 256 and 1024 x 512 cells) iterated
+together by one HIP graph (two SIMPLE iterations of every instance per launch,
+fixed PCG count, device-side convergence flags), with tile widths chosen per
+grid size by the autotuner, reporting instance-iterations per second and each
+instance's drag and lift coefficients.
+
 Prints one JSON line (see the fields below).  --gpus N > 1 is refused: the
 library runs on one GPU.
 """
@@ -92,6 +99,10 @@ def main():
     ap.add_argument("--mixed-case", default="ahmed2", choices=["ahmed", "ahmed2", "none"])
     ap.add_argument("--mixed-tol", type=float, default=1e-8)
     ap.add_argument("--mixed-maxit", type=int, default=5000)
+    ap.add_argument("--sweep-iters", type=int, default=600, help="iterations of the batched NACA sweep (0: skip)")
+    ap.add_argument("--sweep-pcg", type=int, default=4, help="PCG iterations per pressure solve in the sweep")
+    ap.add_argument("--sweep-warmup", type=int, default=20,
+                    help="iterations of each sweep instance on its own (adaptive PCG) before the batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the library has no multi-GPU path",
@@ -170,6 +181,9 @@ def main():
     mixed = None
     if args.mixed_case != "none":
         mixed = mixed_vs_fp64(args)
+    sweep = None
+    if args.sweep_iters > 0:
+        sweep = naca_sweep(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(spec, args.p_rtol)
@@ -195,6 +209,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "mixed_vs_fp64": mixed,
+        "naca_sweep": sweep,
     }
     print(json.dumps(out), flush=True)
 
@@ -233,6 +248,58 @@ def mixed_vs_fp64(args):
             "fp64": runs["fp64"], "mixed": runs["mixed"],
             "speedup": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 4),
             "rel_l2_mixed_vs_fp64": err}
+
+
+def naca_sweep(args):
+    """The batched angle-of-attack sweep (one graph for all instances)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_06135_amd import Solver, Batch
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    specs = synth.naca_sweep_specs(64)
+    log(f"naca sweep: indicators of {len(specs)} instances in {time.time() - t0:.1f}s")
+    solvers = []
+    for sp in specs:
+        s = Solver.from_spec(sp, device=dev, stream=torch.cuda.Stream(dev), p_rtol=args.p_rtol, p_maxit=100)
+        s.set_indicator(torch.from_numpy(sp.lam.ravel()))
+        solvers.append(s)
+    # the first iterations (large pressure corrections) on each instance's own
+    # stream with the adaptive PCG tolerance, then the fixed-count graph
+    for s in solvers:
+        s.iterate(args.sweep_warmup)
+    widths = {}
+    for s, sp in zip(solvers, specs):
+        key = f"{sp.nx}x{sp.ny}"
+        if key not in widths:
+            widths[key] = s.autotune_tiles(reps=3)[0]
+        else:
+            s.set_tile_width(widths[key])
+    torch.cuda.synchronize()
+    b = Batch(solvers, pcg_iters=args.sweep_pcg, tol=1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(args.sweep_iters)
+    st = b.status()
+    dt = time.perf_counter() - t0
+    b.close()
+    cells = sum(sp.ncells for sp in specs)
+    iters = st["iters_done"][0]
+    inst = []
+    for j, (s, sp) in enumerate(zip(solvers, specs)):
+        cd, cl = s.coefficients(ref_area=1.0)
+        g = -10.0 + 30.0 * j / (len(specs) - 1)
+        inst.append({"gamma_deg": round(g, 3), "grid": f"{sp.nx}x{sp.ny}", "cd": round(cd, 5), "cl": round(cl, 5),
+                     "thin_airfoil_cl": round(2 * np.pi * np.deg2rad(g), 5), "converged_at": st["conv_iter"][j],
+                     "max_residual": max(st["residuals"][j])})
+    log(f"naca sweep: {iters} iterations of {len(specs)} instances in {dt:.2f}s")
+    return {"workload": "naca0012_sweep_64", "instances": len(specs), "cells": cells, "iterations": iters,
+            "warmup_iterations_each": args.sweep_warmup, "pcg_iters": args.sweep_pcg, "seconds": round(dt, 3),
+            "instance_iterations_per_s": round(len(specs) * iters / dt, 1),
+            "instances_per_s": round(len(specs) / dt, 4), "cell_iters_per_s": cells * iters / dt,
+            "tile_widths": widths, "converged_1e-6": sum(1 for x in st["conv_iter"] if x > 0),
+            "diverged": st["diverged"], "per_instance": inst}
 
 
 def cpu_baseline(spec, p_rtol):

@@ -244,17 +244,20 @@ void hfdib_destroy(hfdib_ctx* ctx);
 
 /* ---------------------------------------------------------------- batches
  * Independent contexts (for instance one section at many angles of attack, on
- * grids of different sizes) iterated together by one HIP graph launch.  Each
- * context must use its own non-null stream, distinct from the batch stream.
- * hfdib_batch_create captures two SIMPLE iterations of every context, each on
- * its stream between a fork and a join of the batch stream, with exactly
+ * grids of different sizes) iterated together by one HIP graph launch.  The
+ * batch stream (nullable: the batch then creates and owns one) must differ
+ * from every context's stream; contexts may share streams.  hfdib_batch_create captures two SIMPLE iterations of every context,
+ * each on a capture stream of its own (created for the capture, released after
+ * it) between a fork and a join of the batch stream, with exactly
  * pcg_iters PCG iterations per pressure solve and no host read; a device record
  * per context counts iterations, keeps the first iteration whose maximum
  * normalised residual is <= tol, and flags non-finite residuals.  It finishes
  * the contexts' pending work; the graph references their workspaces, which
- * must stay alive until hfdib_batch_destroy.  HFDIB_EINVAL: bad arguments,
- * shared or null streams; HFDIB_ESTATE: a context without set_indicator;
- * HFDIB_EDEVICE: capture or instantiation failed (hfdib_batch_last_error). */
+ * must stay alive until hfdib_batch_destroy, and the contexts must not be
+ * iterated otherwise while a batch run is in flight.  HFDIB_EINVAL: bad
+ * arguments, a context listed twice, the batch stream used by a context;
+ * HFDIB_ESTATE: a context without set_indicator; HFDIB_EDEVICE: capture or
+ * instantiation failed (hfdib_batch_last_error). */
 typedef struct hfdib_batch hfdib_batch;
 int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol, void* hip_stream,
                        hfdib_batch** out);

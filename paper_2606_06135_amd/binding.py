@@ -352,12 +352,11 @@ class Batch:
         import torch
         self.torch = torch
         self.solvers = list(solvers)  # keeps the workspaces alive
-        dev = self.solvers[0].device
-        self.stream = stream if stream is not None else torch.cuda.Stream(dev)
+        self.stream = stream  # None: the batch creates and owns its launch stream
         arr = (C.c_void_p * len(self.solvers))(*[s.ctx for s in self.solvers])
         b = C.c_void_p()
-        st = lib().hfdib_batch_create(arr, len(self.solvers), int(pcg_iters), float(tol),
-                                      C.c_void_p(self.stream.cuda_stream), C.byref(b))
+        sp = None if stream is None else C.c_void_p(stream.cuda_stream)
+        st = lib().hfdib_batch_create(arr, len(self.solvers), int(pcg_iters), float(tol), sp, C.byref(b))
         if st != 0:
             raise HfdibError("hfdib_batch_create", st, "")
         self.b = b

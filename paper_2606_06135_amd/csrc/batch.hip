@@ -1,7 +1,8 @@
 // Batched SIMPLE iterations of independent contexts (e.g. one geometry at many
 // angles of attack, on grids of different sizes) as one HIP graph: the
-// iterations of every context are captured once, each context on its own
-// stream between a fork and a join event of the batch stream, with a fixed
+// iterations of every context are captured once, each context on a capture
+// stream of its own (created for the capture and released after it) between a
+// fork and a join event of the batch stream, with a fixed
 // PCG iteration count and no host read, so one graph launch advances all
 // contexts by two SIMPLE iterations with no host synchronisation.  A device
 // record per context counts the iterations and keeps the first iteration whose
@@ -16,6 +17,7 @@
 struct hfdib_batch {
   std::vector<hfdib_ctx*> ctx;
   hipStream_t stream;
+  int own_stream;  // created by the batch (no caller stream given)
   hipGraph_t graph;
   hipGraphExec_t exec;
   hipEvent_t fork;
@@ -63,19 +65,27 @@ extern "C" {
 
 int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol, void* hip_stream,
                        hfdib_batch** out) {
-  if (!ctxs || n < 1 || pcg_iters < 1 || !out || !hip_stream) return HFDIB_EINVAL;
+  if (!ctxs || n < 1 || pcg_iters < 1 || !out) return HFDIB_EINVAL;
   *out = nullptr;
   hipStream_t bs = (hipStream_t)hip_stream;
   for (int i = 0; i < n; ++i) {
     hfdib_ctx* c = ctxs[i];
     if (!c) return HFDIB_EINVAL;
     if (!c->ready) return HFDIB_ESTATE;
-    if (!c->stream || c->stream == bs) return HFDIB_EINVAL;
+    if (bs && c->stream == bs) return HFDIB_EINVAL;
     for (int j = 0; j < i; ++j)
-      if (ctxs[j] == c || ctxs[j]->stream == c->stream) return HFDIB_EINVAL;
+      if (ctxs[j] == c) return HFDIB_EINVAL;
   }
   hfdib_batch* b = new hfdib_batch();
   b->ctx.assign(ctxs, ctxs + n);
+  b->own_stream = 0;
+  if (!bs) {
+    if (hipStreamCreateWithFlags(&bs, hipStreamNonBlocking) != hipSuccess) {
+      delete b;
+      return HFDIB_EDEVICE;
+    }
+    b->own_stream = 1;
+  }
   b->stream = bs;
   b->graph = nullptr;
   b->exec = nullptr;
@@ -83,6 +93,7 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
   b->tol = tol;
   hipError_t e;
   if ((e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess) {
+    if (b->own_stream) (void)hipStreamDestroy(bs);
     delete b;
     return HFDIB_EDEVICE;
   }
@@ -91,6 +102,7 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
     if ((e = hipEventCreateWithFlags(&b->join[i], hipEventDisableTiming)) != hipSuccess) {
       for (int j = 0; j < i; ++j) (void)hipEventDestroy(b->join[j]);
       (void)hipEventDestroy(b->fork);
+      if (b->own_stream) (void)hipStreamDestroy(bs);
       delete b;
       return HFDIB_EDEVICE;
     }
@@ -114,9 +126,20 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
     hfdib_batch_destroy(b);
     return st;
   }
+  // one capture stream per context (default priority), so that every context
+  // becomes an independent branch of the graph
+  std::vector<hipStream_t> cs(n, nullptr);
+  for (int i = 0; i < n; ++i)
+    if ((e = hipStreamCreateWithFlags(&cs[i], hipStreamNonBlocking)) != hipSuccess) {
+      for (int j = 0; j < i; ++j) (void)hipStreamDestroy(cs[j]);
+      int st = batch_fail(b, "capture streams", e);
+      hfdib_batch_destroy(b);
+      return st;
+    }
   // capture two SIMPLE iterations of every context (the pressure buffers swap
   // each iteration, so two leave the host-side pointers as they were)
   if ((e = hipStreamBeginCapture(bs, hipStreamCaptureModeGlobal)) != hipSuccess) {
+    for (hipStream_t q : cs) (void)hipStreamDestroy(q);
     int st = batch_fail(b, "begin capture", e);
     hfdib_batch_destroy(b);
     return st;
@@ -125,6 +148,8 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
   (void)hipEventRecord(b->fork, bs);
   for (int i = 0; i < n && status == HFDIB_OK; ++i) {
     hfdib_ctx* c = b->ctx[i];
+    hipStream_t own = c->stream;
+    c->stream = cs[i];
     (void)hipStreamWaitEvent(c->stream, b->fork, 0);
     c->graph_mode = 1;
     c->graph_pcg = pcg_iters;
@@ -136,9 +161,11 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
     if (status != HFDIB_OK) b->err = c->err;
     (void)hipEventRecord(b->join[i], c->stream);
     (void)hipStreamWaitEvent(bs, b->join[i], 0);
+    c->stream = own;
   }
   hipGraph_t graph = nullptr;
   e = hipStreamEndCapture(bs, &graph);
+  for (hipStream_t q : cs) (void)hipStreamDestroy(q);
   if (status != HFDIB_OK || e != hipSuccess) {
     if (graph) (void)hipGraphDestroy(graph);
     if (status == HFDIB_OK) status = batch_fail(b, "end capture", e);
@@ -203,6 +230,10 @@ void hfdib_batch_destroy(hfdib_batch* b) {
   for (hipEvent_t ev : b->join)
     if (ev) (void)hipEventDestroy(ev);
   if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->own_stream && b->stream) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipStreamDestroy(b->stream);
+  }
   delete b;
 }
 

@@ -136,12 +136,25 @@ def test_batch_device_convergence_flag(gpu):
     assert max(st["residuals"][0]) <= 1e-6
 
 
-def test_batch_rejects_shared_streams(gpu):
+def test_batch_arguments_and_shared_streams(gpu):
+    # contexts may share a stream (each gets its own capture stream); a context
+    # listed twice or the batch stream used by a context is rejected
+    import ctypes as C
     import torch
-    from paper_2606_06135_amd import Batch, HfdibError
+    from paper_2606_06135_amd import Batch, HfdibError, lib
     st = torch.cuda.Stream(gpu)
-    a = _solver(synth.case_naca(0.0, 64, 32), gpu, stream=st)
-    b = _solver(synth.case_naca(2.0, 64, 32), gpu, stream=st)
+    specs = [synth.case_naca(0.0, 64, 32), synth.case_naca(2.0, 64, 32)]
+    a = _solver(specs[0], gpu, stream=st, p_rtol=1e-2, p_maxit=100)
+    b = _solver(specs[1], gpu, stream=st, p_rtol=1e-2, p_maxit=100)
+    bt = Batch([a, b], pcg_iters=3)
+    bt.run(6)
+    assert bt.status()["iters_done"] == [6, 6]
+    bt.close()
+    st2, alone, _ = _batched(gpu, [specs[1]], 6, 3)
+    np.testing.assert_array_equal(b.get_field("ux").cpu().numpy(), alone[0]["ux"])
     with pytest.raises(HfdibError) as e:
-        Batch([a, b], pcg_iters=2)
+        Batch([a, a], pcg_iters=2)
+    assert e.value.status == -1
+    with pytest.raises(HfdibError) as e:
+        Batch([a], pcg_iters=2, stream=st)
     assert e.value.status == -1
