@@ -109,7 +109,7 @@ class Simple:
             self.k = np.full(g.shape, sp_.k_in)
             self.w = np.full(g.shape, sp_.eps_in)
             self.nut = np.full(g.shape, self.C["Cmu"] * sp_.k_in ** 2 / sp_.eps_in)
-        elif sp_.model == "sst":
+        elif sp_.model in ("sst", "komega"):
             self.k = np.full(g.shape, sp_.k_in)
             self.w = np.full(g.shape, sp_.omega_in)
             self.nut = np.full(g.shape, sp_.k_in / sp_.omega_in)
@@ -443,6 +443,7 @@ class Simple:
         nu = sp_.nu
         bcc, icc = self.bc_cells, self.ic_cells
         keps = sp_.model == "keps"
+        sst = sp_.model == "sst"
         urf = sp_.urf_t
         Gu = self.grad_u(u)
         S2 = np.zeros(g.shape)  # 2 S:S
@@ -457,7 +458,7 @@ class Simple:
         alpha_w = alpha_w.reshape(g.shape)
         kin = sp_.k_in
         win = sp_.eps_in if keps else sp_.omega_in
-        if not keps:
+        if sst:
             gk = g.gauss_grad(k_old, self.scalar_face_value(kin))
             gw = g.gauss_grad(w_old, self.scalar_face_value(win))
             kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2]
@@ -514,8 +515,10 @@ class Simple:
         # omega (eps) equation, rows of alpha_omega cells fixed at the imposed value
         if keps:
             Gam = nu + nut_old / C["sigma_eps"]
-        else:
+        elif sst:
             Gam = nu + sig_w * nut_old
+        else:  # k-omega in the paper's form
+            Gam = nu + nut_old / C["sigma_w_kw"]
         anb = self.neighbor_coeffs(Gam, phi)
         aP = sum(anb.values())
         b0 = np.zeros(g.shape)
@@ -525,6 +528,10 @@ class Simple:
         if keps:
             aP = aP + C["C2"] * w_old / k_old * V
             b0 = b0 + C["C1"] * Pk * w_old / k_old * V
+        elif not sst:
+            # C_alpha1 (omega/k) P_k - C_beta1 omega^2, the sink linearised in omega
+            aP = aP + C["beta_kw"] * w_old * V
+            b0 = b0 + C["alpha_kw"] * (w_old / k_old) * Pk * V
         else:
             aP = aP + beta * w_old * V
             b0 = b0 + gamma * (w_old / k_old) * Pk * V
@@ -551,8 +558,10 @@ class Simple:
         # k equation with S_ib
         if keps:
             Gam = nu + nut_old / C["sigma_k"]
-        else:
+        elif sst:
             Gam = nu + sig_k * nut_old
+        else:
+            Gam = nu + nut_old / C["sigma_k_kw"]
         anb = self.neighbor_coeffs(Gam, phi)
         aP = sum(anb.values())
         b0 = np.zeros(g.shape)
@@ -577,6 +586,8 @@ class Simple:
         # turbulent viscosity
         if keps:
             nut = C["Cmu"] * k * k / w
+        elif not sst:
+            nut = k / w
         else:
             dw = geo.dw
             bs = C["Cmu"]
@@ -589,7 +600,7 @@ class Simple:
         nf[icc] = 0.0
         self.k, self.w, self.nut = k, w, nf.reshape(g.shape)
         self.last.update(dict(G=G, Pk=Pk, wib=wib, kib=kib, S2=S2, alpha_w=alpha_w))
-        if not keps:
+        if sst:
             self.last["F1"] = F1
 
     def run(self, n, tol=0.0, callback=None):

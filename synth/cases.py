@@ -17,7 +17,7 @@ from . import geometry as G
 
 FACES = ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax")
 BC_KINDS = ("inlet", "outlet", "noslip", "slip", "empty")
-MODELS = ("laminar", "keps", "sst")
+MODELS = ("laminar", "keps", "sst", "komega")
 
 # Model constants.  The paper defers their values to the turbulence-model
 # literature; these are the standard published values and both implementations
@@ -32,6 +32,9 @@ DEFAULT_CONSTANTS: Dict[str, float] = {
     "sigma_k1": 0.85, "sigma_w1": 0.5, "beta_1": 0.075, "gamma_1": 0.5532,
     "sigma_k2": 1.0, "sigma_w2": 0.856, "beta_2": 0.0828, "gamma_2": 0.4404,
     "a1": 0.31, "c_lim": 10.0,
+    # standard k-omega in the paper's form: nu + nu_t / sigma diffusion,
+    # C_alpha1 (omega/k) P_k - C_beta1 omega^2 (Wilcox's 2006 values; beta* = Cmu)
+    "sigma_k_kw": 1.0 / 0.6, "sigma_w_kw": 2.0, "alpha_kw": 0.52, "beta_kw": 0.0708,
     # numerical safeguards
     "bound_frac": 1e-10,      # k >= bound_frac*k_in, eps/omega >= bound_frac*inlet value
     "yperp_min_frac": 1e-6,   # y_perp >= yperp_min_frac*h

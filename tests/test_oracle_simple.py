@@ -202,3 +202,25 @@ def test_decaying_turbulence_first_order_convergence():
         errs.append(np.abs(sim.k[0, 1, :] - kx).max() / s.k_in)
     assert errs[1] < 0.05
     assert 1.6 < errs[0] / errs[1] < 2.6
+
+
+def test_decaying_turbulence_komega_first_order_convergence():
+    # the paper's k-omega form without shear: U dk/dx = -beta* k omega and
+    # U domega/dx = -C_beta1 omega^2, i.e. omega = omega0 / (1 + C_beta1 omega0 x / U)
+    # and k = k0 (1 + C_beta1 omega0 x / U)^(-beta*/C_beta1); upwind converges at
+    # first order
+    errs = []
+    for nx in (32, 64):
+        s = synth.case_uniform_duct(nx=nx, ny=4, model="komega")
+        sim = Simple(s)
+        _converge(sim, tol=1e-11, maxit=3000)
+        C = s.constants
+        x = sim.g.centers[0][0, 0, :]
+        t = 1.0 + C["beta_kw"] * s.omega_in * x / 1.0
+        wx = s.omega_in / t
+        kx = s.k_in * t ** (-C["Cmu"] / C["beta_kw"])
+        errs.append(max(np.abs(sim.k[0, 1, :] - kx).max() / s.k_in, np.abs(sim.w[0, 1, :] - wx).max() / s.omega_in))
+        # nu_t = k / omega exactly
+        np.testing.assert_allclose(sim.nut, sim.k / sim.w, rtol=1e-14)
+    assert errs[1] < 0.05
+    assert 1.6 < errs[0] / errs[1] < 2.6
