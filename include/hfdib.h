@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define HFDIB_ABI_VERSION 1
+#define HFDIB_ABI_VERSION 2
 
 typedef enum {
   HFDIB_OK = 0,
@@ -63,7 +63,10 @@ typedef enum {
   HFDIB_BC_EMPTY = 4   /* z faces of a 2D grid */
 } hfdib_bc_kind;
 
-typedef enum { HFDIB_LAMINAR = 0, HFDIB_KEPS = 1, HFDIB_KOMEGA_SST = 2 } hfdib_model;
+/* KOMEGA: the k-omega equations in the paper's form (diffusion nu + nu_t / sigma,
+ * omega sources C_alpha1 (omega/k) P_k - C_beta1 omega^2, sink beta* k omega with
+ * beta* = Cmu, nu_t = k / omega), wall treatment as for SST. */
+typedef enum { HFDIB_LAMINAR = 0, HFDIB_KEPS = 1, HFDIB_KOMEGA_SST = 2, HFDIB_KOMEGA = 3 } hfdib_model;
 typedef enum { HFDIB_FP64 = 0, HFDIB_MIXED = 1 } hfdib_precision;
 
 /* Grid and boundary data.  dim = 2 requires nz = 1 and EMPTY z faces.
@@ -105,6 +108,8 @@ typedef struct {
   double C1, C2, sigma_k, sigma_eps;
   /* Menter SST */
   double sigma_k1, sigma_w1, beta_1, gamma_1, sigma_k2, sigma_w2, beta_2, gamma_2, a1, c_lim;
+  /* standard k-omega (divisors sigma of nu_t, C_alpha1, C_beta1) */
+  double sigma_k_kw, sigma_w_kw, alpha_kw, beta_kw;
   /* safeguards */
   double bound_frac, yperp_min_frac, cd_floor;
 } hfdib_config;

@@ -14,10 +14,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhfdib.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 BC = {"inlet": 0, "outlet": 1, "noslip": 2, "slip": 3, "empty": 4}
-MODEL = {"laminar": 0, "keps": 1, "sst": 2}
+MODEL = {"laminar": 0, "keps": 1, "sst": 2, "komega": 3}
 FIELD = {"ux": 0, "uy": 1, "uz": 2, "p": 3, "k": 4, "w": 5, "nut": 6,
          "phix": 7, "phiy": 8, "phiz": 9, "lambda": 10, "class": 11, "alpha_u": 12, "walldist": 13}
 IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "yeff": 5, "mode": 6,
@@ -40,7 +40,8 @@ class GridDesc(C.Structure):
 _CONST_NAMES = ["Cmu", "kappa", "E", "beta1_wf", "Ceps2_wf", "C_wf", "ylam",
                 "C1", "C2", "sigma_k", "sigma_eps",
                 "sigma_k1", "sigma_w1", "beta_1", "gamma_1", "sigma_k2", "sigma_w2", "beta_2", "gamma_2",
-                "a1", "c_lim", "bound_frac", "yperp_min_frac", "cd_floor"]
+                "a1", "c_lim", "sigma_k_kw", "sigma_w_kw", "alpha_kw", "beta_kw",
+                "bound_frac", "yperp_min_frac", "cd_floor"]
 
 
 class Config(C.Structure):

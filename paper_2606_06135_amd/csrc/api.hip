@@ -268,7 +268,7 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "n_sweeps >= 1, p_maxit >= 1 and p_rtol > 0 are required";
     return HFDIB_EINVAL;
   }
-  if (c->model < HFDIB_LAMINAR || c->model > HFDIB_KOMEGA_SST) {
+  if (c->model < HFDIB_LAMINAR || c->model > HFDIB_KOMEGA) {
     *why = "invalid model";
     return HFDIB_EINVAL;
   }
@@ -317,7 +317,8 @@ static void fill_params(hfdib_ctx* c) {
   for (int f = 0; f < 6; ++f) P.bc[f] = d.bc[f];
   for (int q = 0; q < 3; ++q) P.u_in[q] = d.u_in[q];
   P.k_in = d.k_in;
-  P.w_in = g.model == HFDIB_KEPS ? d.eps_in : (g.model == HFDIB_KOMEGA_SST ? d.omega_in : 0.0);
+  P.w_in = g.model == HFDIB_KEPS ? d.eps_in
+                                 : ((g.model == HFDIB_KOMEGA_SST || g.model == HFDIB_KOMEGA) ? d.omega_in : 0.0);
   P.model = g.model;
   P.n_sweeps = g.n_sweeps;
   P.nu = g.nu;
@@ -345,6 +346,10 @@ static void fill_params(hfdib_ctx* c) {
   P.gamma_2 = g.gamma_2;
   P.a1 = g.a1;
   P.c_lim = g.c_lim;
+  P.alpha_kw = g.alpha_kw;
+  P.beta_kw = g.beta_kw;
+  P.isig_k_kw = 1.0 / g.sigma_k_kw;
+  P.isig_w_kw = 1.0 / g.sigma_w_kw;
   P.bound_frac = g.bound_frac;
   P.yperp_min_frac = g.yperp_min_frac;
   P.cd_floor = g.cd_floor;
@@ -442,6 +447,10 @@ void hfdib_default_config(hfdib_config* c) {
   c->gamma_2 = 0.4404;
   c->a1 = 0.31;
   c->c_lim = 10.0;
+  c->sigma_k_kw = 1.0 / 0.6;
+  c->sigma_w_kw = 2.0;
+  c->alpha_kw = 0.52;
+  c->beta_kw = 0.0708;
   c->bound_frac = 1e-10;
   c->yperp_min_frac = 1e-6;
   c->cd_floor = 1e-10;

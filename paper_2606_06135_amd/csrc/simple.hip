@@ -79,7 +79,7 @@ __global__ void k_init_cells(Params P, const double* lam, const double* us0, con
     k[c] = P.k_in;
     w[c] = P.w_in;
     nut[c] = P.Cmu * P.k_in * P.k_in / P.w_in;
-  } else if (P.model == HFDIB_KOMEGA_SST) {
+  } else if (P.model == HFDIB_KOMEGA_SST || P.model == HFDIB_KOMEGA) {
     k[c] = P.k_in;
     w[c] = P.w_in;
     nut[c] = P.k_in / P.w_in;

@@ -77,6 +77,7 @@ __global__ void k_sum1(long long n, const double* a, double* part, long long pst
 // diffusion coefficient of the transported scalar (0: omega/eps, 1: k)
 __device__ __forceinline__ double gam(const Params& P, int eq, long long c, const double* nut, const double* F1) {
   if (P.model == HFDIB_KEPS) return P.nu + nut[c] * (eq == 0 ? P.isig_eps : P.isig_k);
+  if (P.model == HFDIB_KOMEGA) return P.nu + nut[c] * (eq == 0 ? P.isig_w_kw : P.isig_k_kw);
   double f = F1[c];
   double sg = eq == 0 ? f * P.sigma_w1 + (1.0 - f) * P.sigma_w2 : f * P.sigma_k1 + (1.0 - f) * P.sigma_k2;
   return P.nu + sg * nut[c];
@@ -164,6 +165,10 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       if (P.model == HFDIB_KEPS) {
         aP = aP + P.C2 * wo / kold * V;
         b0 = b0 + P.C1 * Pc * wo / kold * V;
+      } else if (P.model == HFDIB_KOMEGA) {
+        // C_alpha1 (omega/k) P_k - C_beta1 omega^2, the sink linearised in omega
+        aP = aP + P.beta_kw * wo * V;
+        b0 = b0 + P.alpha_kw * (wo / kold) * Pc * V;
       } else {
         double f = S.F1[c];
         double beta = f * P.beta_1 + (1.0 - f) * P.beta_2;
@@ -263,6 +268,7 @@ struct Scal32 {
 __device__ __forceinline__ float gam32(const Params& P, int eq, long long c, const float* nut, const float* F1) {
   const float nu = (float)P.nu;
   if (P.model == HFDIB_KEPS) return nu + nut[c] * (float)(eq == 0 ? P.isig_eps : P.isig_k);
+  if (P.model == HFDIB_KOMEGA) return nu + nut[c] * (float)(eq == 0 ? P.isig_w_kw : P.isig_k_kw);
   float f = F1[c];
   float a = (float)(eq == 0 ? P.sigma_w1 : P.sigma_k1), b = (float)(eq == 0 ? P.sigma_w2 : P.sigma_k2);
   return nu + (f * a + (1.0f - f) * b) * nut[c];
@@ -349,6 +355,8 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, c
   double nt;
   if (P.model == HFDIB_KEPS) {
     nt = P.Cmu * kk * kk / ww;
+  } else if (P.model == HFDIB_KOMEGA) {
+    nt = kk / ww;
   } else {
     double d = dw[c];
     double bs = P.Cmu;

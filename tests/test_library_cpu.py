@@ -29,9 +29,9 @@ def test_every_declared_symbol_is_exported(hiplib):
 
 
 def test_abi_version_and_defaults(hiplib):
-    assert hiplib.hfdib_abi_version() == 1
+    assert hiplib.hfdib_abi_version() == 2
     c = B.default_config()
-    assert c.abi_version == 1 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
+    assert c.abi_version == 2 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
     assert (c.urf_u, c.urf_p, c.urf_t) == (0.7, 0.3, 0.85)
     assert (c.Cmu, c.kappa, c.E, c.ylam) == (0.09, 0.41, 9.8, 11.0)
 
