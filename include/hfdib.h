@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define HFDIB_ABI_VERSION 2
+#define HFDIB_ABI_VERSION 3
 
 typedef enum {
   HFDIB_OK = 0,
@@ -65,8 +65,28 @@ typedef enum {
 
 /* KOMEGA: the k-omega equations in the paper's form (diffusion nu + nu_t / sigma,
  * omega sources C_alpha1 (omega/k) P_k - C_beta1 omega^2, sink beta* k omega with
- * beta* = Cmu, nu_t = k / omega), wall treatment as for SST. */
-typedef enum { HFDIB_LAMINAR = 0, HFDIB_KEPS = 1, HFDIB_KOMEGA_SST = 2, HFDIB_KOMEGA = 3 } hfdib_model;
+ * beta* = Cmu, nu_t = k / omega), wall treatment as for SST.
+ * RKEPS: the realizable k-epsilon model the paper lists beside the others (Sec.
+ * "Governing equations", after Shih et al. 1995): nu_t = C_mu k^2 / eps with
+ * C_mu = 1 / (A0 + A_s U* k / eps) from the deviatoric strain rate S and the
+ * rotation rate of the velocity gradient (U* = sqrt(S:S + Omega:Omega),
+ * A_s = sqrt(6) cos(arccos(sqrt(6) W) / 3), W = S_ij S_jk S_ki / (S:S)^1.5);
+ * eps source C1 |S| eps with |S| = sqrt(2 S:S), C1 = max(0.43, eta / (eta + 5)),
+ * eta = |S| k / eps, and sink C2 eps^2 / (k + sqrt(nu eps)); k equation, IB and
+ * wall treatment as for KEPS. */
+typedef enum {
+  HFDIB_LAMINAR = 0,
+  HFDIB_KEPS = 1,
+  HFDIB_KOMEGA_SST = 2,
+  HFDIB_KOMEGA = 3,
+  HFDIB_RKEPS = 4
+} hfdib_model;
+/* Distance in y+ of boundary cells (Sec. "Calculation of y+ at the immersed
+ * boundary"): EFF the effective distance y_eff = (y_perp + h/2) / 2 of the paper's
+ * definition; PERP the perpendicular distance y_perp alone (the appendix comparing
+ * effective and perpendicular distance).  The chosen distance replaces y_eff in
+ * every wall function: y+, u_tau of the log law, omega_ib and the wall shear. */
+typedef enum { HFDIB_YPLUS_EFF = 0, HFDIB_YPLUS_PERP = 1 } hfdib_yplus_dist;
 typedef enum { HFDIB_FP64 = 0, HFDIB_MIXED = 1 } hfdib_precision;
 
 /* Grid and boundary data.  dim = 2 requires nz = 1 and EMPTY z faces.
@@ -102,6 +122,7 @@ typedef struct {
   int continuity;       /* lambda-masked continuity: 0 = div u = 0 wherever lambda < 1 (pressure
                            rhs sum_f phi*_f there, 0 in lambda = 1 cells); 1 = rhs scaled by
                            (1 - lambda) in every cell */
+  int yplus_dist;       /* hfdib_yplus_dist */
   /* wall treatment */
   double Cmu, kappa, E, beta1_wf, Ceps2_wf, C_wf, ylam;
   /* standard k-epsilon */
@@ -110,6 +131,8 @@ typedef struct {
   double sigma_k1, sigma_w1, beta_1, gamma_1, sigma_k2, sigma_w2, beta_2, gamma_2, a1, c_lim;
   /* standard k-omega (divisors sigma of nu_t, C_alpha1, C_beta1) */
   double sigma_k_kw, sigma_w_kw, alpha_kw, beta_kw;
+  /* realizable k-epsilon (A0 of C_mu, C2 of the eps sink, divisors sigma of nu_t) */
+  double A0_rke, C2_rke, sigma_k_rke, sigma_eps_rke;
   /* safeguards */
   double bound_frac, yperp_min_frac, cd_floor;
 } hfdib_config;

@@ -319,7 +319,10 @@ def precompute(spec, with_wall_distance=None):
             Lw[b] = (1.0, 0.0, 0.0)
             st1_idx[b], st1_w[b] = _pad8([], [], c)
             st2_idx[b], st2_w[b] = _pad8([], [], c)
-    yeff = 0.5 * (yperp + 0.5 * h)  # eq. for y_eff
+    if getattr(spec, "yplus_dist", "eff") == "perp":
+        yeff = yperp.copy()  # appendix variant: y+ from the perpendicular distance alone
+    else:
+        yeff = 0.5 * (yperp + 0.5 * h)  # eq. for y_eff
     geo = Geometry(tag=tag, lam=lam, sigma=sigma, bc_cells=bc_cells, ic_cells=ic_cells,
                    normal=normal, yperp=yperp, yeff=yeff, mode=mode, L=Lw,
                    st1_idx=st1_idx, st1_w=st1_w, st2_idx=st2_idx, st2_w=st2_w, nstar=nstar)

@@ -34,6 +34,7 @@ import scipy.sparse.linalg as spla
 from .grid import Grid
 from .geometry import precompute, IC, BC
 from . import wallfn as wf
+from . import realizable
 
 DIRS = None  # filled per grid: list of (d, s)
 
@@ -105,7 +106,7 @@ class Simple:
         if g.dim == 2:
             self.u[2] = np.zeros(g.shape)
         self.p = np.zeros(g.shape)
-        if sp_.model == "keps":
+        if sp_.model in ("keps", "rkeps"):
             self.k = np.full(g.shape, sp_.k_in)
             self.w = np.full(g.shape, sp_.eps_in)
             self.nut = np.full(g.shape, self.C["Cmu"] * sp_.k_in ** 2 / sp_.eps_in)
@@ -399,6 +400,19 @@ class Simple:
         Axb = A @ np.full(g.N, xb)
         res["p"] = float(np.abs(bflat - Ax).sum() / (np.abs(Ax - Axb).sum() + np.abs(bflat - Axb).sum() + 1e-300))
         p_sol = self.solve_pressure(A, bflat, pflat_old).reshape(g.shape)
+        # identity rows next to coupled cells take the mean solved pressure of their
+        # coupled face neighbours (deeper identity rows keep p).  Without it their p
+        # stays at a stale value; when a neighbour leaves the forced group (y+
+        # crossing y+_lam) the cell joins the solve and its under-relaxed pressure
+        # starts from that stale value, a jump that drove the backward-facing step
+        # to divergence with every turbulence model.
+        acc = np.zeros(g.shape)
+        cnt = np.zeros(g.shape)
+        for (d, s) in self.dirs:
+            has = g.has_neighbor(d, s) & g.neighbor(~iso, d, s, fill=False)
+            acc += np.where(has, g.neighbor(p_sol, d, s, fill=0.0), 0.0)
+            cnt += has
+        p_sol = np.where(iso & (cnt > 0), acc / np.maximum(cnt, 1), p_sol)
         cint, cout = self.pressure_coeffs(rAU)
         phi = [a.copy() for a in phis]
         for d in g.axes:
@@ -442,7 +456,8 @@ class Simple:
         V = g.V
         nu = sp_.nu
         bcc, icc = self.bc_cells, self.ic_cells
-        keps = sp_.model == "keps"
+        rke = sp_.model == "rkeps"
+        keps = sp_.model == "keps" or rke  # eps-based: inlet eps, eps_ib = Cmu k omega_ib, eps/k sink of k
         sst = sp_.model == "sst"
         urf = sp_.urf_t
         Gu = self.grad_u(u)
@@ -513,7 +528,9 @@ class Simple:
         Pk = Pf.reshape(g.shape)  # P_k <- P_ib on alpha_omega cells
 
         # omega (eps) equation, rows of alpha_omega cells fixed at the imposed value
-        if keps:
+        if rke:
+            Gam = nu + nut_old / C["sigma_eps_rke"]
+        elif keps:
             Gam = nu + nut_old / C["sigma_eps"]
         elif sst:
             Gam = nu + sig_w * nut_old
@@ -525,7 +542,12 @@ class Simple:
         for (d, s, kind, a) in self.dirichlet_faces(Gam, phi, ("inlet",)):
             aP[g.bnd(d, s)] += a
             b0[g.bnd(d, s)] += a * win
-        if keps:
+        if rke:
+            # C1 S eps explicit, C2 eps^2 / (k + sqrt(nu eps)) linearised in eps
+            src, sink = realizable.eps_terms(Gu, k_old, w_old, nu, C)
+            aP = aP + sink * V
+            b0 = b0 + src * V
+        elif keps:
             aP = aP + C["C2"] * w_old / k_old * V
             b0 = b0 + C["C1"] * Pk * w_old / k_old * V
         elif not sst:
@@ -556,7 +578,9 @@ class Simple:
         kib = kib.reshape(g.shape)
 
         # k equation with S_ib
-        if keps:
+        if rke:
+            Gam = nu + nut_old / C["sigma_k_rke"]
+        elif keps:
             Gam = nu + nut_old / C["sigma_k"]
         elif sst:
             Gam = nu + sig_k * nut_old
@@ -584,7 +608,9 @@ class Simple:
         k = np.maximum(k, C["bound_frac"] * kin)
 
         # turbulent viscosity
-        if keps:
+        if rke:
+            nut = realizable.c_mu(Gu, k, w, C) * k * k / w
+        elif keps:
             nut = C["Cmu"] * k * k / w
         elif not sst:
             nut = k / w

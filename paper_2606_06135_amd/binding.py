@@ -14,10 +14,11 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhfdib.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 BC = {"inlet": 0, "outlet": 1, "noslip": 2, "slip": 3, "empty": 4}
-MODEL = {"laminar": 0, "keps": 1, "sst": 2, "komega": 3}
+MODEL = {"laminar": 0, "keps": 1, "sst": 2, "komega": 3, "rkeps": 4}
+YPLUS_DIST = {"eff": 0, "perp": 1}
 FIELD = {"ux": 0, "uy": 1, "uz": 2, "p": 3, "k": 4, "w": 5, "nut": 6,
          "phix": 7, "phiy": 8, "phiz": 9, "lambda": 10, "class": 11, "alpha_u": 12, "walldist": 13}
 IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "yeff": 5, "mode": 6,
@@ -41,6 +42,7 @@ _CONST_NAMES = ["Cmu", "kappa", "E", "beta1_wf", "Ceps2_wf", "C_wf", "ylam",
                 "C1", "C2", "sigma_k", "sigma_eps",
                 "sigma_k1", "sigma_w1", "beta_1", "gamma_1", "sigma_k2", "sigma_w2", "beta_2", "gamma_2",
                 "a1", "c_lim", "sigma_k_kw", "sigma_w_kw", "alpha_kw", "beta_kw",
+                "A0_rke", "C2_rke", "sigma_k_rke", "sigma_eps_rke",
                 "bound_frac", "yperp_min_frac", "cd_floor"]
 
 
@@ -48,7 +50,7 @@ class Config(C.Structure):
     _fields_ = [("abi_version", C.c_int), ("model", C.c_int), ("precision", C.c_int), ("n_sweeps", C.c_int),
                 ("nu", C.c_double), ("urf_u", C.c_double), ("urf_p", C.c_double), ("urf_t", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("recorrect", C.c_int),
-                ("bc_capacity", C.c_int), ("continuity", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
+                ("bc_capacity", C.c_int), ("continuity", C.c_int), ("yplus_dist", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
 
 
 class HfdibError(RuntimeError):
@@ -149,6 +151,7 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
     c.recorrect = 1 if recorrect else 0
     c.bc_capacity = bc_capacity
     c.continuity = {"literal": 0, "weighted": 1}[continuity]
+    c.yplus_dist = YPLUS_DIST[getattr(spec, "yplus_dist", "eff")]
     c.precision = {"fp64": 0, "mixed": 1}[precision]
     for n in _CONST_NAMES:
         if n in spec.constants:

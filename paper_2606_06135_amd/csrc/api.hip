@@ -268,7 +268,7 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "n_sweeps >= 1, p_maxit >= 1 and p_rtol > 0 are required";
     return HFDIB_EINVAL;
   }
-  if (c->model < HFDIB_LAMINAR || c->model > HFDIB_KOMEGA) {
+  if (c->model < HFDIB_LAMINAR || c->model > HFDIB_RKEPS) {
     *why = "invalid model";
     return HFDIB_EINVAL;
   }
@@ -276,12 +276,16 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "continuity must be 0 or 1";
     return HFDIB_EINVAL;
   }
+  if (c->yplus_dist != HFDIB_YPLUS_EFF && c->yplus_dist != HFDIB_YPLUS_PERP) {
+    *why = "yplus_dist must be HFDIB_YPLUS_EFF or HFDIB_YPLUS_PERP";
+    return HFDIB_EINVAL;
+  }
   if (c->precision != HFDIB_FP64 && c->precision != HFDIB_MIXED) {
     *why = "precision must be HFDIB_FP64 or HFDIB_MIXED";
     return HFDIB_EINVAL;
   }
   if (c->model != HFDIB_LAMINAR) {
-    double win = c->model == HFDIB_KEPS ? d->eps_in : d->omega_in;
+    double win = (c->model == HFDIB_KEPS || c->model == HFDIB_RKEPS) ? d->eps_in : d->omega_in;
     if (!(d->k_in > 0.0 && win > 0.0)) {
       *why = "turbulent models need positive inlet k and eps/omega";
       return HFDIB_EINVAL;
@@ -317,8 +321,9 @@ static void fill_params(hfdib_ctx* c) {
   for (int f = 0; f < 6; ++f) P.bc[f] = d.bc[f];
   for (int q = 0; q < 3; ++q) P.u_in[q] = d.u_in[q];
   P.k_in = d.k_in;
-  P.w_in = g.model == HFDIB_KEPS ? d.eps_in
-                                 : ((g.model == HFDIB_KOMEGA_SST || g.model == HFDIB_KOMEGA) ? d.omega_in : 0.0);
+  P.w_in = (g.model == HFDIB_KEPS || g.model == HFDIB_RKEPS)
+               ? d.eps_in
+               : ((g.model == HFDIB_KOMEGA_SST || g.model == HFDIB_KOMEGA) ? d.omega_in : 0.0);
   P.model = g.model;
   P.n_sweeps = g.n_sweeps;
   P.nu = g.nu;
@@ -350,6 +355,11 @@ static void fill_params(hfdib_ctx* c) {
   P.beta_kw = g.beta_kw;
   P.isig_k_kw = 1.0 / g.sigma_k_kw;
   P.isig_w_kw = 1.0 / g.sigma_w_kw;
+  P.A0_rke = g.A0_rke;
+  P.C2_rke = g.C2_rke;
+  P.isig_k_rke = 1.0 / g.sigma_k_rke;
+  P.isig_eps_rke = 1.0 / g.sigma_eps_rke;
+  P.yplus_perp = g.yplus_dist == HFDIB_YPLUS_PERP;
   P.bound_frac = g.bound_frac;
   P.yperp_min_frac = g.yperp_min_frac;
   P.cd_floor = g.cd_floor;
@@ -451,6 +461,10 @@ void hfdib_default_config(hfdib_config* c) {
   c->sigma_w_kw = 2.0;
   c->alpha_kw = 0.52;
   c->beta_kw = 0.0708;
+  c->A0_rke = 4.0;
+  c->C2_rke = 1.9;
+  c->sigma_k_rke = 1.0;
+  c->sigma_eps_rke = 1.2;
   c->bound_frac = 1e-10;
   c->yperp_min_frac = 1e-6;
   c->cd_floor = 1e-10;

@@ -250,7 +250,8 @@ __global__ void k_bc_geometry(Params P, int nbc, const int* bc_cells, const doub
   double ymin = P.yperp_min_frac * h;
   yp = yp > ymin ? yp : ymin;
   bc_yperp[b] = yp;
-  bc_yeff[b] = 0.5 * (yp + 0.5 * h);
+  // y_eff of the y+ definition, or y_perp alone for the appendix variant
+  bc_yeff[b] = P.yplus_perp ? yp : 0.5 * (yp + 0.5 * h);
   // interpolation points along n_P
   int c1[8], c2[8];
   double q1[8], q2[8];

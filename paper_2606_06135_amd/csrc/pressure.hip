@@ -766,44 +766,44 @@ k_reduce_chunks(const double* part, long long pstride, int nblk, int chunk, int 
 }
 
 // finalize: reduces `nval` rows of per-block partials -> scal[out+v] (sums, or
-// maxima for op 4), then an optional PCG scalar update.  One workgroup of 1024
-// threads; fixed reduction order (deterministic).
+// maxima for op 4), then an optional PCG scalar update (only with one row).
+// Workgroup v of 1024 threads reduces row v; thread t takes entries t, t+1024,
+// ... in that order (loads issued eight at a time, summed in the same order),
+// then the waves and the workgroup in fixed order: deterministic, and the
+// result does not depend on how many rows are reduced together.
 // op: 0 none, 1 alpha = rho / dq, 2 beta = rz / rho, rho = rz, 3 rho = value, 4 max
 constexpr int FIN_THREADS = 1024;
+constexpr int FIN_BATCH = 8;
 __global__ void __launch_bounds__(FIN_THREADS)
-k_finalize(const double* part, long long pstride, int nblk, int nval, double* scal, int out, int op,
-           double divisor) {
+k_finalize(const double* part, long long pstride, int nblk, double* scal, int out, int op, double divisor) {
   __shared__ double lds[FIN_THREADS / 64];
-  int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int v = 0; v < nval; ++v) {
-    const double* row = part + (long long)v * pstride;
-    double s = 0.0;
-    if (op == 4) {
-      for (int b = tid; b < nblk; b += FIN_THREADS) s = fmax(s, row[b]);
-      s = wave_max(s);
-    } else {
-      for (int b = tid; b < nblk; b += FIN_THREADS) s += row[b];
-      s = wave_sum(s);
-    }
-    if (lane == 0) lds[wid] = s;
-    __syncthreads();
-    if (tid == 0) {
-      double t = lds[0];
-      for (int w = 1; w < FIN_THREADS / 64; ++w) t = op == 4 ? fmax(t, lds[w]) : t + lds[w];
-      scal[out + v] = divisor == 1.0 ? t : t / divisor;
-    }
-    __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, v = blockIdx.x;
+  const double* row = part + (long long)v * pstride;
+  const bool mx = op == 4;
+  double s = 0.0;
+  int b = tid;
+  for (; b + (FIN_BATCH - 1) * FIN_THREADS < nblk; b += FIN_BATCH * FIN_THREADS) {
+    double e[FIN_BATCH];
+#pragma unroll
+    for (int q = 0; q < FIN_BATCH; ++q) e[q] = row[b + q * FIN_THREADS];
+#pragma unroll
+    for (int q = 0; q < FIN_BATCH; ++q) s = mx ? fmax(s, e[q]) : s + e[q];
   }
+  for (; b < nblk; b += FIN_THREADS) s = mx ? fmax(s, row[b]) : s + row[b];
+  s = mx ? wave_max(s) : wave_sum(s);
+  if (lane == 0) lds[wid] = s;
+  __syncthreads();
   if (tid == 0) {
+    double t = lds[0];
+    for (int w = 1; w < FIN_THREADS / 64; ++w) t = mx ? fmax(t, lds[w]) : t + lds[w];
+    scal[out + v] = divisor == 1.0 ? t : t / divisor;
     if (op == 1) {
-      double dq = scal[out];
-      scal[S_ALPHA] = dq != 0.0 ? scal[S_RHO] / dq : 0.0;
+      scal[S_ALPHA] = t != 0.0 ? scal[S_RHO] / t : 0.0;
     } else if (op == 2) {
-      double rz = scal[out];
-      scal[S_BETA] = scal[S_RHO] != 0.0 ? rz / scal[S_RHO] : 0.0;
-      scal[S_RHO] = rz;
+      scal[S_BETA] = scal[S_RHO] != 0.0 ? t / scal[S_RHO] : 0.0;
+      scal[S_RHO] = t;
     } else if (op == 3) {
-      scal[S_RHO] = scal[out];
+      scal[S_RHO] = t;
     }
   }
 }
@@ -843,11 +843,11 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
     int nchunks = (nblk + chunk - 1) / chunk;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), 0, c->stream, part, c->pstride, nblk,
                        chunk, op == 4 ? 1 : 0, c->partials2);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, c->stream, (const double*)c->partials2,
-                       (long long)FIN2_STRIDE, nchunks, nval, c->scal + SCAL_PCG, out, op, divisor);
+    hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, (const double*)c->partials2,
+                       (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor);
     return;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, c->stream, part, c->pstride, nblk, nval,
+  hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, part, c->pstride, nblk,
                      c->scal + SCAL_PCG, out, op, divisor);
 }
 

@@ -75,7 +75,9 @@ __global__ void k_init_cells(Params P, const double* lam, const double* us0, con
   u1[c] = fl ? P.u_in[1] : us1[c];
   u2[c] = P.dim == 2 ? 0.0 : (fl ? P.u_in[2] : us2[c]);
   p[c] = 0.0;
-  if (P.model == HFDIB_KEPS) {
+  if (P.model == HFDIB_KEPS || P.model == HFDIB_RKEPS) {
+    // (realizable k-epsilon starts from the standard C_mu; its variable C_mu
+    // acts from the first turbulence update on)
     k[c] = P.k_in;
     w[c] = P.w_in;
     nut[c] = P.Cmu * P.k_in * P.k_in / P.w_in;
@@ -540,6 +542,35 @@ __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const d
   rhs_p[c] = rp;
 }
 
+// Pressure of an identity row (a forced cell whose face neighbours are all
+// forced): the mean solved pressure of its coupled face neighbours (forced cells
+// with a free face neighbour), summed axis by axis, low side first; a row
+// without such neighbours keeps its value.  The cell then enters the solve with a
+// consistent value when a neighbour leaves the forced group.
+__device__ __forceinline__ double decoupled_pressure(const Params& P, const uint8_t* flags, const double* psol, int i,
+                                                     int j, int k, long long c) {
+  for (int d = 0; d < P.dim; ++d)
+    for (int s = -1; s <= 1; s += 2)
+      if (!on_bnd(P, d, s, i, j, k) && !(flags[c + s * stride(P, d)] & F_ALPHA_U)) return psol[c];
+  double acc = 0.0;
+  int cnt = 0;
+  for (int d = 0; d < P.dim; ++d)
+    for (int s = -1; s <= 1; s += 2) {
+      if (on_bnd(P, d, s, i, j, k)) continue;
+      long long n = c + s * stride(P, d);
+      const int qi = i + (d == 0 ? s : 0), qj = j + (d == 1 ? s : 0), qk = k + (d == 2 ? s : 0);
+      bool coupled = false;
+      for (int d2 = 0; d2 < P.dim; ++d2)
+        for (int s2 = -1; s2 <= 1; s2 += 2)
+          if (!on_bnd(P, d2, s2, qi, qj, qk) && !(flags[n + s2 * stride(P, d2)] & F_ALPHA_U)) coupled = true;
+      if (coupled) {
+        acc += psol[n];
+        ++cnt;
+      }
+    }
+  return cnt > 0 ? acc / (double)cnt : psol[c];
+}
+
 // flux correction with the solved pressure and relaxation of p (into pnew)
 // (mixed policy: also the FP32 mirror of every face flux this cell owns)
 struct Phi32Out {
@@ -576,7 +607,8 @@ __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, 
       if (on_bnd(P, d, -1, i, j, k)) m32.f[d][f] = (float)ph[d][f];
     }
   }
-  pnew[c] = pold[c] + P.urf_p * (psol[c] - pold[c]);
+  double ps = (flags[c] & F_ALPHA_U) ? decoupled_pressure(P, flags, psol, i, j, k, c) : psol[c];
+  pnew[c] = pold[c] + P.urf_p * (ps - pold[c]);
 }
 
 // u = HbyA - rAU grad p (relaxed p), optional re-imposition of u_ib, copy p

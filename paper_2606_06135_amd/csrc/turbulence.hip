@@ -33,6 +33,49 @@ struct G9 {
   const double* g[9];
 };
 
+// Realizable k-epsilon (Shih et al. 1995): invariants S:S, Omega:Omega and
+// S_ij S_jk S_ki of the deviatoric strain rate S and the rotation rate Omega of
+// the stored velocity gradient G[a][b] = d u_a / d x_b (entries beyond dim are 0)
+struct RkeInv {
+  double SS, OO, S3;
+};
+__device__ __forceinline__ RkeInv rke_invariants(const Params& P, const G9& Gs, long long c) {
+  double G[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) G[a][b] = (a < P.dim && b < P.dim) ? Gs.g[3 * a + b][c] : 0.0;
+  const double tr = G[0][0] + G[1][1] + G[2][2];
+  double S[3][3];
+  RkeInv I{0.0, 0.0, 0.0};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      S[a][b] = 0.5 * (G[a][b] + G[b][a]) - (a == b ? tr / 3.0 : 0.0);
+      double o = 0.5 * (G[a][b] - G[b][a]);
+      I.SS += S[a][b] * S[a][b];
+      I.OO += o * o;
+    }
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) I.S3 += S[a][b] * S[b][e] * S[e][a];
+  return I;
+}
+// C_mu = 1 / (A0 + A_s U* k / eps), A_s = sqrt(6) cos(arccos(sqrt(6) W) / 3),
+// W = S_ij S_jk S_ki / (S:S)^1.5 (0 without strain, sqrt(6) W clipped to [-1, 1])
+__device__ __forceinline__ double rke_cmu(const Params& P, const RkeInv& I, double kk, double ee) {
+  double W = I.SS > 0.0 ? I.S3 / pow(I.SS, 1.5) : 0.0;
+  double x = sqrt(6.0) * W;
+  x = x < -1.0 ? -1.0 : (x > 1.0 ? 1.0 : x);
+  double As = sqrt(6.0) * cos(acos(x) / 3.0);
+  double Us = sqrt(I.SS + I.OO);
+  return 1.0 / (P.A0_rke + As * Us * kk / ee);
+}
+
 __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, const double* nv, const double* ypl,
                           const double* utl, G9 Gs, const double* S2, const double* kold, const double* nut,
                           double* Pk, double* wib, double* w) {
@@ -47,7 +90,7 @@ __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, c
   double yp = ypl[b], ut = utl[b], y = yv[b];
   double om = omega_ib(P, yp, y, ut);
   double kk = kold[c];
-  double val = P.model == HFDIB_KEPS ? P.Cmu * kk * om : om;
+  double val = (P.model == HFDIB_KEPS || P.model == HFDIB_RKEPS) ? P.Cmu * kk * om : om;
   double ng[3] = {0.0, 0.0, 0.0};
   for (int jj = 0; jj < 3; ++jj)
     for (int ii = 0; ii < 3; ++ii) ng[jj] += nv[3 * b + ii] * G[ii][jj];
@@ -78,6 +121,7 @@ __global__ void k_sum1(long long n, const double* a, double* part, long long pst
 __device__ __forceinline__ double gam(const Params& P, int eq, long long c, const double* nut, const double* F1) {
   if (P.model == HFDIB_KEPS) return P.nu + nut[c] * (eq == 0 ? P.isig_eps : P.isig_k);
   if (P.model == HFDIB_KOMEGA) return P.nu + nut[c] * (eq == 0 ? P.isig_w_kw : P.isig_k_kw);
+  if (P.model == HFDIB_RKEPS) return P.nu + nut[c] * (eq == 0 ? P.isig_eps_rke : P.isig_k_rke);
   double f = F1[c];
   double sg = eq == 0 ? f * P.sigma_w1 + (1.0 - f) * P.sigma_w2 : f * P.sigma_k1 + (1.0 - f) * P.sigma_k2;
   return P.nu + sg * nut[c];
@@ -95,6 +139,7 @@ struct Scal {
   double* w;        // omega/eps (fixed values already in place)
   const double* wib;
   const double* kib;
+  G9 G;  // velocity gradient (realizable k-epsilon)
 };
 
 // neighbour coefficients of a scalar row (faces W, E, S, N, B, T; 0 on domain
@@ -117,6 +162,9 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
 
 // assembly of the omega (eps, eq = 0) or k (eq = 1) rows; rhs -> rhs_out,
 // relaxed diagonal -> aPr_out; residual sums of the solved rows
+// (RKE: the realizable k-epsilon eps sources, instantiated separately so the
+// other closures keep their register budget)
+template <bool RKE>
 __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, float* r32, float* a32,
                                   const double* xmean, double* part, long long pstride) {
   int i, j, k;
@@ -165,6 +213,14 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       if (P.model == HFDIB_KEPS) {
         aP = aP + P.C2 * wo / kold * V;
         b0 = b0 + P.C1 * Pc * wo / kold * V;
+      } else if (RKE) {
+        // C1 |S| eps explicit, C2 eps^2 / (k + sqrt(nu eps)) linearised in eps
+        RkeInv I = rke_invariants(P, S.G, c);
+        double Sm = sqrt(2.0 * I.SS);
+        double eta = Sm * kold / wo;
+        double C1 = fmax(0.43, eta / (eta + 5.0));
+        aP = aP + P.C2_rke * wo / (kold + sqrt(P.nu * wo)) * V;
+        b0 = b0 + C1 * Sm * wo * V;
       } else if (P.model == HFDIB_KOMEGA) {
         // C_alpha1 (omega/k) P_k - C_beta1 omega^2, the sink linearised in omega
         aP = aP + P.beta_kw * wo * V;
@@ -188,7 +244,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       double wmin = P.bound_frac * P.w_in;
       wv = wv > wmin ? wv : wmin;
       S.w[c] = wv;
-      if (P.model == HFDIB_KEPS) aP = aP + wv / kold * V;
+      if (P.model == HFDIB_KEPS || P.model == HFDIB_RKEPS) aP = aP + wv / kold * V;
       else aP = aP + P.Cmu * wv * V;
       b0 = b0 + S.Pk[c] * V;
       aPr = aP / urf;
@@ -269,6 +325,7 @@ __device__ __forceinline__ float gam32(const Params& P, int eq, long long c, con
   const float nu = (float)P.nu;
   if (P.model == HFDIB_KEPS) return nu + nut[c] * (float)(eq == 0 ? P.isig_eps : P.isig_k);
   if (P.model == HFDIB_KOMEGA) return nu + nut[c] * (float)(eq == 0 ? P.isig_w_kw : P.isig_k_kw);
+  if (P.model == HFDIB_RKEPS) return nu + nut[c] * (float)(eq == 0 ? P.isig_eps_rke : P.isig_k_rke);
   float f = F1[c];
   float a = (float)(eq == 0 ? P.sigma_w1 : P.sigma_k1), b = (float)(eq == 0 ? P.sigma_w2 : P.sigma_k2);
   return nu + (f * a + (1.0f - f) * b) * nut[c];
@@ -339,7 +396,7 @@ __global__ void k_kib(Params P, int nbc, const int* bc_cells, const uint8_t* fla
 
 // k <- k + alpha_k (k_ib - k), bounding, turbulent viscosity of the model
 // (in-solid cells 0); eps/omega is already bounded
-__global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, const double* kib, double* k,
+__global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, G9 Gs, const double* kib, double* k,
                              const double* w, const double* dw, double* nut, float* nut32) {
   int i, j, kz;
   tile_ijk(P, i, j, kz);
@@ -357,6 +414,9 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, c
     nt = P.Cmu * kk * kk / ww;
   } else if (P.model == HFDIB_KOMEGA) {
     nt = kk / ww;
+  } else if (P.model == HFDIB_RKEPS) {
+    RkeInv I = rke_invariants(P, Gs, c);
+    nt = rke_cmu(P, I, kk, ww) * kk * kk / ww;
   } else {
     double d = dw[c];
     double bs = P.Cmu;
@@ -464,6 +524,7 @@ int turbulence_stage(hfdib_ctx* c) {
   Sc.w = c->w;
   Sc.wib = c->wib;
   Sc.kib = c->kib;
+  Sc.G = Gs;
   bool mixed = P.precision == HFDIB_MIXED;
   float* r32 = mixed ? c->r32[0] : nullptr;
   float* a32 = mixed ? c->a32 : nullptr;
@@ -483,7 +544,8 @@ int turbulence_stage(hfdib_ctx* c) {
   };
   // omega / eps equation, alpha_omega rows fixed
   timer_begin(c, T_SCALASM);
-  hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, S + SC_MEANS + 5,
+  auto assemble = P.model == HFDIB_RKEPS ? k_scalar_assemble<true> : k_scalar_assemble<false>;
+  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, S + SC_MEANS + 5,
                      c->partials, c->pstride);
   timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
@@ -494,12 +556,12 @@ int turbulence_stage(hfdib_ctx* c) {
                        c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->bc_yplus, c->bc_utau, c->k,
                        c->kib);
   timer_begin(c, T_SCALASM);
-  hipLaunchKernelGGL(k_scalar_assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, S + SC_MEANS + 4,
+  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, S + SC_MEANS + 4,
                      c->partials, c->pstride);
   timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
-  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, c->kib, c->k, c->w,
+  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, Gs, c->kib, c->k, c->w,
                      c->dw, c->nut, mixed ? c->nut32 : nullptr);
   if (c->n_bc > 0) {
     hipLaunchKernelGGL(k_nut_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,

@@ -17,7 +17,8 @@ from . import geometry as G
 
 FACES = ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax")
 BC_KINDS = ("inlet", "outlet", "noslip", "slip", "empty")
-MODELS = ("laminar", "keps", "sst", "komega")
+MODELS = ("laminar", "keps", "sst", "komega", "rkeps")
+YPLUS_DIST = ("eff", "perp")
 
 # Model constants.  The paper defers their values to the turbulence-model
 # literature; these are the standard published values and both implementations
@@ -35,6 +36,8 @@ DEFAULT_CONSTANTS: Dict[str, float] = {
     # standard k-omega in the paper's form: nu + nu_t / sigma diffusion,
     # C_alpha1 (omega/k) P_k - C_beta1 omega^2 (Wilcox's 2006 values; beta* = Cmu)
     "sigma_k_kw": 1.0 / 0.6, "sigma_w_kw": 2.0, "alpha_kw": 0.52, "beta_kw": 0.0708,
+    # realizable k-epsilon (Shih et al. 1995): A0, C2 of the eps sink, sigma_k, sigma_eps
+    "A0_rke": 4.0, "C2_rke": 1.9, "sigma_k_rke": 1.0, "sigma_eps_rke": 1.2,
     # numerical safeguards
     "bound_frac": 1e-10,      # k >= bound_frac*k_in, eps/omega >= bound_frac*inlet value
     "yperp_min_frac": 1e-6,   # y_perp >= yperp_min_frac*h
@@ -66,6 +69,10 @@ class CaseSpec:
     urf_p: float = 0.3
     urf_t: float = 0.85
     n_sweeps: int = 2
+    # distance in y+ of boundary cells: "eff" = y_eff of the paper's y+ definition,
+    # "perp" = the perpendicular distance alone (the variant of the appendix on
+    # effective vs perpendicular distance)
+    yplus_dist: str = "eff"
     constants: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(DEFAULT_CONSTANTS))
     lam: np.ndarray = None
     seed: int = 0
@@ -88,6 +95,7 @@ class CaseSpec:
         for b in self.bc:
             assert b in BC_KINDS
         assert self.model in MODELS
+        assert self.yplus_dist in YPLUS_DIST
         assert self.lam is not None and self.lam.shape == self.shape
         return self
 

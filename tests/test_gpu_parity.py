@@ -36,12 +36,24 @@ CASES = {
     "sphere3d_komega": (lambda: synth.case_small_body3d(model="komega", nu=1e-4), 30),
     "duct_komega": (lambda: synth.case_uniform_duct(nx=32, ny=4, model="komega"), 40),
     "naca_64x32_komega": (lambda: synth.case_naca(4.0, 64, 32, model="komega"), 30),
+    "sphere3d_rkeps": (lambda: synth.case_small_body3d(model="rkeps", nu=1e-4), 30),
+    "bfs_rkeps_160x40": (lambda: synth.case_bfs(model="rkeps"), 40),
+    "duct_rkeps": (lambda: synth.case_uniform_duct(nx=32, ny=4, model="rkeps"), 40),
+    "sphere3d_sst_yperp": (lambda: _yperp(synth.case_small_body3d(model="sst", nu=1e-4)), 30),
+    "naca_64x32_keps_yperp": (lambda: _yperp(synth.case_naca(4.0, 64, 32, model="keps")), 30),
 }
+
+
+def _yperp(spec):
+    # the appendix variant: y+ (and every wall function) from y_perp alone
+    spec.yplus_dist = "perp"
+    spec.name += "_yperp"
+    return spec
 
 # residual entries that are ratios of rounding noise: the uniform duct's velocity and
 # pressure sit exactly at their fixed point, so both numerator and normaliser of those
 # residuals are round-off and their ratio is not a property of the method
-NOISE_RESIDUALS = {"duct_komega": ("Ux", "Uy", "Uz", "p")}
+NOISE_RESIDUALS = {"duct_komega": ("Ux", "Uy", "Uz", "p"), "duct_rkeps": ("Ux", "Uy", "Uz", "p")}
 
 
 def _solver(spec, gpu, **kw):
@@ -108,7 +120,7 @@ def test_simple_iteration_parity(gpu, name):
         assert v <= 1e-9, (name, k, v)
     # normalised residuals of the last iteration (diagnostic, both computed in FP64;
     # below 1e-8 they are ratios of rounding noise and are not compared)
-    names = ["Ux", "Uy", "Uz", "p", "k", "eps" if spec.model == "keps" else "omega"]
+    names = ["Ux", "Uy", "Uz", "p", "k", "eps" if spec.model in ("keps", "rkeps") else "omega"]
     for q, nm in enumerate(names):
         if nm in r and r[nm] > 1e-8 and nm not in NOISE_RESIDUALS.get(name, ()):
             assert abs(res[q] - r[nm]) <= 1e-6 * max(1.0, abs(r[nm])), (nm, res[q], r[nm])
@@ -145,26 +157,30 @@ def test_pressure_solve_matches_direct(gpu, mk):
 
 
 def test_bfs_long_run_within_oracle_sensitivity(gpu):
-    # The 160x40 backward-facing-step iteration does not settle (boundary cells flip
-    # between the branches y+ <= y+_lam and y+ > y+_lam), and it amplifies rounding
-    # differences: two oracle runs whose initial velocity differs by 1e-15 drift apart.
-    # After 500 iterations the GPU must stay within that intrinsic spread.
+    # The 160x40 backward-facing-step iteration amplifies differences by about 100x
+    # per 100 iterations, and once one boundary cell changes wall-function branch
+    # (y+ crossing y+_lam) the field moves by ~1e-3: an oracle run perturbed by 1e-11
+    # (the size of the differences the GPU's iterative pressure solve, stopped at
+    # 1e-13, leaves against the oracle's direct solve) does so after 500 iterations.
+    # After 300 iterations, before any branch change, the GPU must stay within 100x
+    # the spread of that perturbed oracle run (or 1e-9).
     spec = synth.case_bfs()
-    _say("bfs 500 iterations (oracle twice)")
+    _say("bfs 300 iterations (oracle twice)")
     a = Simple(spec)
     b = Simple(spec)
-    b.u[0] = b.u[0] * (1.0 + 1e-15 * np.random.default_rng(0).standard_normal(b.u[0].shape))
+    b.u[0] = b.u[0] * (1.0 + 1e-11 * np.random.default_rng(0).standard_normal(b.u[0].shape))
     s = _solver(spec, gpu)
-    for _ in range(500):
+    for _ in range(300):
         a.step()
         b.step()
-    s.iterate(500)
+    s.iterate(300)
+    assert (a.last["alpha"] == b.last["alpha"]).all()
     gpu_ux = s.get_field("ux").cpu().numpy()
     spread = rel_l2(b.u[0], a.u[0])
     dev = rel_l2(gpu_ux, a.u[0].ravel())
-    _say(f"  oracle self-spread {spread:.2e}, GPU vs oracle {dev:.2e}")
+    _say(f"  oracle spread at 1e-11 {spread:.2e}, GPU vs oracle {dev:.2e}")
     assert dev <= max(100.0 * spread, 1e-9)
-    assert dev < 1e-2
+    np.testing.assert_array_equal(s.get_field("alpha_u").cpu().numpy() > 0.5, a.last["alpha"].ravel())
 
 
 def test_checkpoint_resume_is_bitwise(gpu):

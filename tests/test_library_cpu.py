@@ -29,9 +29,13 @@ def test_every_declared_symbol_is_exported(hiplib):
 
 
 def test_abi_version_and_defaults(hiplib):
-    assert hiplib.hfdib_abi_version() == 2
+    assert hiplib.hfdib_abi_version() == 3
     c = B.default_config()
-    assert c.abi_version == 2 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
+    assert c.abi_version == 3 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
+    assert c.yplus_dist == 0
+    # the library's defaults are the constants the oracle receives
+    for n in B._CONST_NAMES:
+        assert getattr(c, n) == synth.DEFAULT_CONSTANTS[n], n
     assert (c.urf_u, c.urf_p, c.urf_t) == (0.7, 0.3, 0.85)
     assert (c.Cmu, c.kappa, c.E, c.ylam) == (0.09, 0.41, 9.8, 11.0)
 
@@ -77,6 +81,8 @@ def test_mixed_workspace_adds_fp32_arrays(hiplib):
     lambda d, c: setattr(c, "n_sweeps", 0),
     lambda d, c: setattr(c, "precision", 2),
     lambda d, c: setattr(c, "continuity", 7),
+    lambda d, c: setattr(c, "yplus_dist", 2),
+    lambda d, c: setattr(c, "model", 5),
     lambda d, c: setattr(c, "abi_version", 99),
 ])
 def test_invalid_arguments_rejected(hiplib, mutate):
