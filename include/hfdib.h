@@ -87,6 +87,16 @@ typedef enum {
  * effective and perpendicular distance).  The chosen distance replaces y_eff in
  * every wall function: y+, u_tau of the log law, omega_ib and the wall shear. */
 typedef enum { HFDIB_YPLUS_EFF = 0, HFDIB_YPLUS_PERP = 1 } hfdib_yplus_dist;
+/* Convection scheme of the momentum equation (the paper's appendix on divergence
+ * schemes; upwind is the setting of its main results).  LINEAR_UPWIND and VANLEER
+ * enter as a deferred correction of the upwind rows from the previous iterate,
+ * -sum_f F_out (u_f - u_C) over interior faces (C upwind, D downwind cell):
+ * linear upwind u_f = u_C + (x_f - x_C).grad u_C; van Leer
+ * u_f = u_C + psi(r) (u_D - u_C)/2, psi(r) = (r + |r|)/(1 + |r|),
+ * r = 2 (x_D - x_C).grad u_C / (u_D - u_C) - 1, with grad u_C the Gauss cell
+ * gradient.  At a fixed point the discretisation is the higher-order one.  k and
+ * eps/omega stay upwind. */
+typedef enum { HFDIB_CONV_UPWIND = 0, HFDIB_CONV_LINEAR_UPWIND = 1, HFDIB_CONV_VANLEER = 2 } hfdib_conv_scheme;
 typedef enum { HFDIB_FP64 = 0, HFDIB_MIXED = 1 } hfdib_precision;
 
 /* Grid and boundary data.  dim = 2 requires nz = 1 and EMPTY z faces.
@@ -123,6 +133,7 @@ typedef struct {
                            rhs sum_f phi*_f there, 0 in lambda = 1 cells); 1 = rhs scaled by
                            (1 - lambda) in every cell */
   int yplus_dist;       /* hfdib_yplus_dist */
+  int conv_scheme;      /* hfdib_conv_scheme */
   /* wall treatment */
   double Cmu, kappa, E, beta1_wf, Ceps2_wf, C_wf, ylam;
   /* standard k-epsilon */

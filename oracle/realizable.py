@@ -32,8 +32,10 @@ import numpy as np
 
 
 def strain_invariants(Gu):
-    """Gu[i][j] = d u_i / d x_j.  Returns (S_ij S_ij, Omega_ij Omega_ij,
-    S_ij S_jk S_ki) of the deviatoric strain rate S and the rotation rate Omega."""
+    """Gu[i][j] = d u_j / d x_i (the solver's velocity gradient; the three
+    invariants are the same for the transposed tensor).  Returns (S_ij S_ij,
+    Omega_ij Omega_ij, S_ij S_jk S_ki) of the deviatoric strain rate S and the
+    rotation rate Omega."""
     tr = Gu[0][0] + Gu[1][1] + Gu[2][2]
     S = [[0.5 * (Gu[i][j] + Gu[j][i]) - (tr / 3.0 if i == j else 0.0) for j in range(3)] for i in range(3)]
     Om = [[0.5 * (Gu[i][j] - Gu[j][i]) for j in range(3)] for i in range(3)]

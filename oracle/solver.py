@@ -231,6 +231,44 @@ class Simple:
                 T[c] = T[c] + s * g.area[d] * nu_f * gf
         return T
 
+    def convection_correction(self, phi, u, G, scheme):
+        """Higher-order momentum convection (the schemes of the paper's appendix on
+        divergence schemes) as a deferred correction of the upwind matrix,
+        evaluated from the previous iterate: per cell
+        -sum over interior faces of F_out (u_f - u_C), with C the upwind and D the
+        downwind cell of the face and u_f the scheme's face value:
+          linear upwind: u_f = u_C + (x_f - x_C) . grad u_C;
+          van Leer:      u_f = u_C + psi(r) (u_D - u_C) / 2,
+                         psi(r) = (r + |r|) / (1 + |r|),
+                         r = 2 (x_D - x_C) . grad u_C / (u_D - u_C) - 1 (r = 0 where
+                         u_D = u_C; the face value is u_C there either way).
+        grad u_C is the cell's Gauss gradient G[d][c] = d u_c / d x_d.  At the
+        fixed point u = u_old the upwind terms cancel and the discretisation is
+        the higher-order one.  One array per velocity component."""
+        g = self.g
+        out = [np.zeros(g.shape) for _ in range(3)]
+        for c in g.axes:
+            for (d, s) in self.dirs:
+                has = g.has_neighbor(d, s)
+                F = g.outward_flux(phi, d, s)
+                up = F > 0.0  # this cell is upwind of the face
+                uC = np.where(up, u[c], g.neighbor(u[c], d, s))
+                uD = np.where(up, g.neighbor(u[c], d, s), u[c])
+                gC = np.where(up, G[d][c], g.neighbor(G[d][c], d, s))
+                dxC = np.where(up, s, -s) * 0.5 * g.delta[d]  # x_f - x_C along axis d
+                if scheme == "linear_upwind":
+                    uf = uC + dxC * gC
+                elif scheme == "vanleer":
+                    dCD = uD - uC
+                    nz = dCD != 0.0
+                    r = np.where(nz, 2.0 * (2.0 * dxC * gC) / np.where(nz, dCD, 1.0) - 1.0, 0.0)
+                    psi = (r + np.abs(r)) / (1.0 + np.abs(r))
+                    uf = uC + 0.5 * psi * dCD
+                else:
+                    raise ValueError(scheme)
+                out[c] = out[c] - np.where(has, F * (uf - uC), 0.0)
+        return out
+
     def pressure_gradient_V(self, p):
         """V (grad p)_P (Gauss; outlet faces p = 0, other faces zero gradient)"""
         gp = self.g.gauss_grad(p, self.p_face_value)
@@ -352,6 +390,10 @@ class Simple:
                 bsrc[c][g.bnd(d, s)] += a * ub
         Gu = self.grad_u(u_old)
         T = self.transpose_term(nuEff, Gu)
+        scheme = getattr(sp_, "conv_scheme", "upwind")
+        if scheme != "upwind":
+            Cc = self.convection_correction(phi_old, u_old, Gu, scheme)
+            T = [T[c] + Cc[c] for c in range(3)]
         gP = self.pressure_gradient_V(p_old)
         urf = sp_.urf_u
         aPr = aP / urf

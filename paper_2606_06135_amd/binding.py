@@ -19,6 +19,7 @@ ABI_VERSION = 3
 BC = {"inlet": 0, "outlet": 1, "noslip": 2, "slip": 3, "empty": 4}
 MODEL = {"laminar": 0, "keps": 1, "sst": 2, "komega": 3, "rkeps": 4}
 YPLUS_DIST = {"eff": 0, "perp": 1}
+CONV_SCHEME = {"upwind": 0, "linear_upwind": 1, "vanleer": 2}
 FIELD = {"ux": 0, "uy": 1, "uz": 2, "p": 3, "k": 4, "w": 5, "nut": 6,
          "phix": 7, "phiy": 8, "phiz": 9, "lambda": 10, "class": 11, "alpha_u": 12, "walldist": 13}
 IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "yeff": 5, "mode": 6,
@@ -50,7 +51,8 @@ class Config(C.Structure):
     _fields_ = [("abi_version", C.c_int), ("model", C.c_int), ("precision", C.c_int), ("n_sweeps", C.c_int),
                 ("nu", C.c_double), ("urf_u", C.c_double), ("urf_p", C.c_double), ("urf_t", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("recorrect", C.c_int),
-                ("bc_capacity", C.c_int), ("continuity", C.c_int), ("yplus_dist", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
+                ("bc_capacity", C.c_int), ("continuity", C.c_int), ("yplus_dist", C.c_int),
+                ("conv_scheme", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
 
 
 class HfdibError(RuntimeError):
@@ -152,6 +154,7 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
     c.bc_capacity = bc_capacity
     c.continuity = {"literal": 0, "weighted": 1}[continuity]
     c.yplus_dist = YPLUS_DIST[getattr(spec, "yplus_dist", "eff")]
+    c.conv_scheme = CONV_SCHEME[getattr(spec, "conv_scheme", "upwind")]
     c.precision = {"fp64": 0, "mixed": 1}[precision]
     for n in _CONST_NAMES:
         if n in spec.constants:

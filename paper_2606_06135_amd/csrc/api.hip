@@ -280,6 +280,10 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "yplus_dist must be HFDIB_YPLUS_EFF or HFDIB_YPLUS_PERP";
     return HFDIB_EINVAL;
   }
+  if (c->conv_scheme < HFDIB_CONV_UPWIND || c->conv_scheme > HFDIB_CONV_VANLEER) {
+    *why = "conv_scheme must be HFDIB_CONV_UPWIND, HFDIB_CONV_LINEAR_UPWIND or HFDIB_CONV_VANLEER";
+    return HFDIB_EINVAL;
+  }
   if (c->precision != HFDIB_FP64 && c->precision != HFDIB_MIXED) {
     *why = "precision must be HFDIB_FP64 or HFDIB_MIXED";
     return HFDIB_EINVAL;
@@ -360,6 +364,7 @@ static void fill_params(hfdib_ctx* c) {
   P.isig_k_rke = 1.0 / g.sigma_k_rke;
   P.isig_eps_rke = 1.0 / g.sigma_eps_rke;
   P.yplus_perp = g.yplus_dist == HFDIB_YPLUS_PERP;
+  P.conv = g.conv_scheme;
   P.bound_frac = g.bound_frac;
   P.yperp_min_frac = g.yperp_min_frac;
   P.cd_floor = g.cd_floor;

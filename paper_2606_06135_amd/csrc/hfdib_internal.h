@@ -44,6 +44,7 @@ struct Params {
   double alpha_kw, beta_kw, isig_k_kw, isig_w_kw;  // standard k-omega (1/sigma host-computed)
   double A0_rke, C2_rke, isig_k_rke, isig_eps_rke; // realizable k-epsilon
   int yplus_perp;                                  // 1: y+ from y_perp alone
+  int conv;                                        // momentum convection (hfdib_conv_scheme)
   double bound_frac, yperp_min_frac, cd_floor;
   double Cmu25, sqrtCmu;  // Cmu^(1/4), sqrt(Cmu) (host-computed)
   // host-computed reciprocals (kernels multiply instead of dividing): |S_d|/d_d,

@@ -218,6 +218,15 @@ __device__ __forceinline__ double nb_sum(const double (&anb)[6], const Nbr& N, c
 // Assembly of the relaxed momentum rows with the explicit IB source
 // (discrete f_ib = alpha [M(u~) + grad p]), plus the normalised-residual sums
 // of the rows that are solved (alpha_u = 0).
+// CONV: momentum convection 0 upwind, 1 linear upwind, 2 van Leer; the
+// higher-order schemes enter as a deferred correction of the upwind rows,
+// -sum_f F_out (u_f - u_C) from the previous iterate, with C the upwind cell of
+// the face, D the downwind one, and the face value
+//   linear upwind  u_f = u_C + (x_f - x_C) . grad u_C
+//   van Leer       u_f = u_C + psi(r) (u_D - u_C) / 2, psi(r) = (r + |r|) / (1 + |r|),
+//                  r = 2 (x_D - x_C) . grad u_C / (u_D - u_C) - 1 (0 where u_D = u_C)
+// (interior faces; grad u_C the stored Gauss gradient)
+template <int CONV>
 __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
                                const double* means, double* part, long long pstride) {
   double wmx = 0.0;  // max of omega/eps of the previous iterate over boundary and free-stream cells
@@ -299,9 +308,39 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
           T += (double)s * P.area[d] * nuf * gf;
         }
       }
+      const double* u = M.u[cc];
+      if (CONV != 0) {
+        double Cc = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          if (d >= P.dim) continue;
+          const double* Gc = M.G[3 * d + cc];  // d u_cc / d x_d
+#pragma unroll
+          for (int sh = 0; sh < 2; ++sh) {
+            const int s = sh ? 1 : -1, q = 2 * d + sh;
+            if (is_bnd(N, q)) continue;
+            const long long n = N.n[q];
+            const double F = outward_flux(P, M.phi, d, s, i, j, k);
+            const bool up = F > 0.0;
+            const double uC = up ? u[c] : u[n], uD = up ? u[n] : u[c];
+            const double gC = up ? Gc[c] : Gc[n];
+            const double dxC = (double)(up ? s : -s) * 0.5 * P.delta[d];
+            double uf;
+            if (CONV == 1) {
+              uf = uC + dxC * gC;
+            } else {
+              const double dCD = uD - uC;
+              const double r = dCD != 0.0 ? 2.0 * (2.0 * dxC * gC) / dCD - 1.0 : 0.0;
+              const double psi = (r + fabs(r)) / (1.0 + fabs(r));
+              uf = uC + 0.5 * psi * dCD;
+            }
+            Cc = Cc - F * (uf - uC);
+          }
+        }
+        T = T + Cc;
+      }
       double b0 = T + bsrc[cc];
       double g = gradp_V(P, M.p, fl, cc, i, j, k, c);
-      const double* u = M.u[cc];
       double uo = u[c];
       double r = (1.0 - urf) / urf * aP * uo;
       double nb = nb_sum(anb, N, u);
@@ -739,6 +778,15 @@ __global__ void k_grad(Params P, const double* u0, const double* u1, const doubl
   S2[c] = strain2(G);
 }
 
+// the momentum assembly instance of the configured convection scheme
+using MomAssembleFn = void (*)(Params, Mom, MixOut, double*, double*, double*, double*, const double*, double*,
+                               long long);
+static MomAssembleFn mom_assemble_kernel(const Params& P) {
+  if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1>;
+  if (P.conv == HFDIB_CONV_VANLEER) return k_mom_assemble<2>;
+  return k_mom_assemble<0>;
+}
+
 int velocity_gradient(hfdib_ctx* c) {
   const Params& P = c->P;
   GradOut O;
@@ -759,8 +807,8 @@ int tile_bench_round(hfdib_ctx* c) {
   if (st != HFDIB_OK) return st;
   Mom M = make_mom(c);
   MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
-  hipLaunchKernelGGL(k_mom_assemble, grid3(P), block3(P), 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2],
-                     c->aPr, c->scal + SCAL_PCG + SC_MEANS, c->partials, c->pstride);
+  hipLaunchKernelGGL(mom_assemble_kernel(P), grid3(P), block3(P), 0, c->stream, P, M, X, c->rhs[0], c->rhs[1],
+                     c->rhs[2], c->aPr, c->scal + SCAL_PCG + SC_MEANS, c->partials, c->pstride);
   pressure_apply_bench(c);
   HFDIB_CHECK_LAUNCH(c, "tile bench");
   return HFDIB_OK;
@@ -820,7 +868,7 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
   if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32, c->F1_32};
   timer_begin(c, T_MOMASM);
-  hipLaunchKernelGGL(k_mom_assemble, g, b, 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
+  hipLaunchKernelGGL(mom_assemble_kernel(P), g, b, 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
                      S + SC_MEANS, c->partials, c->pstride);
   timer_end(c, T_MOMASM);
   launch_finalize(c, (int)nblk3, 9, SC_RESSUM, 0);

@@ -35,7 +35,8 @@ struct G9 {
 
 // Realizable k-epsilon (Shih et al. 1995): invariants S:S, Omega:Omega and
 // S_ij S_jk S_ki of the deviatoric strain rate S and the rotation rate Omega of
-// the stored velocity gradient G[a][b] = d u_a / d x_b (entries beyond dim are 0)
+// the stored velocity gradient G[a][b] = d u_b / d x_a (entries beyond dim are 0;
+// the transposed tensor has the same invariants)
 struct RkeInv {
   double SS, OO, S3;
 };

@@ -19,6 +19,7 @@ FACES = ("xmin", "xmax", "ymin", "ymax", "zmin", "zmax")
 BC_KINDS = ("inlet", "outlet", "noslip", "slip", "empty")
 MODELS = ("laminar", "keps", "sst", "komega", "rkeps")
 YPLUS_DIST = ("eff", "perp")
+CONV_SCHEMES = ("upwind", "linear_upwind", "vanleer")
 
 # Model constants.  The paper defers their values to the turbulence-model
 # literature; these are the standard published values and both implementations
@@ -73,6 +74,9 @@ class CaseSpec:
     # "perp" = the perpendicular distance alone (the variant of the appendix on
     # effective vs perpendicular distance)
     yplus_dist: str = "eff"
+    # momentum convection: upwind (the paper's setting), or the higher-order schemes
+    # of its appendix on divergence schemes (linear upwind, van Leer)
+    conv_scheme: str = "upwind"
     constants: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(DEFAULT_CONSTANTS))
     lam: np.ndarray = None
     seed: int = 0
@@ -96,6 +100,7 @@ class CaseSpec:
             assert b in BC_KINDS
         assert self.model in MODELS
         assert self.yplus_dist in YPLUS_DIST
+        assert self.conv_scheme in CONV_SCHEMES
         assert self.lam is not None and self.lam.shape == self.shape
         return self
 

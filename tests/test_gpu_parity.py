@@ -41,7 +41,18 @@ CASES = {
     "duct_rkeps": (lambda: synth.case_uniform_duct(nx=32, ny=4, model="rkeps"), 40),
     "sphere3d_sst_yperp": (lambda: _yperp(synth.case_small_body3d(model="sst", nu=1e-4)), 30),
     "naca_64x32_keps_yperp": (lambda: _yperp(synth.case_naca(4.0, 64, 32, model="keps")), 30),
+    "bfs_keps_linear_upwind": (lambda: _conv(synth.case_bfs(), "linear_upwind"), 40),
+    "sphere3d_sst_vanleer": (lambda: _conv(synth.case_small_body3d(model="sst", nu=1e-4), "vanleer"), 30),
+    "block2d_laminar_vanleer": (lambda: _conv(synth.case_cavity_block(), "vanleer"), 30),
+    "naca_64x32_sst_linear_upwind": (lambda: _conv(synth.case_naca(4.0, 64, 32), "linear_upwind"), 30),
 }
+
+
+def _conv(spec, scheme):
+    # momentum convection by a higher-order scheme of the appendix on divergence schemes
+    spec.conv_scheme = scheme
+    spec.name += "_" + scheme
+    return spec
 
 
 def _yperp(spec):

@@ -32,7 +32,7 @@ def test_abi_version_and_defaults(hiplib):
     assert hiplib.hfdib_abi_version() == 3
     c = B.default_config()
     assert c.abi_version == 3 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
-    assert c.yplus_dist == 0
+    assert c.yplus_dist == 0 and c.conv_scheme == 0
     # the library's defaults are the constants the oracle receives
     for n in B._CONST_NAMES:
         assert getattr(c, n) == synth.DEFAULT_CONSTANTS[n], n
@@ -82,6 +82,7 @@ def test_mixed_workspace_adds_fp32_arrays(hiplib):
     lambda d, c: setattr(c, "precision", 2),
     lambda d, c: setattr(c, "continuity", 7),
     lambda d, c: setattr(c, "yplus_dist", 2),
+    lambda d, c: setattr(c, "conv_scheme", 3),
     lambda d, c: setattr(c, "model", 5),
     lambda d, c: setattr(c, "abi_version", 99),
 ])

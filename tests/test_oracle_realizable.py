@@ -15,8 +15,10 @@ A0 = C["A0_rke"]
 
 
 def _grad(m):
-    """uniform gradient d u_i / d x_j = m[i][j] as the oracle's nested lists of arrays"""
-    return [[np.array([float(m[i][j])]) for j in range(3)] for i in range(3)]
+    """uniform velocity gradient as the oracle's nested lists of arrays,
+    Gu[i][j] = d u_j / d x_i = m[j][i] (m[i][j] = d u_i / d x_j, as the comments
+    below write the flows)"""
+    return [[np.array([float(m[j][i])]) for j in range(3)] for i in range(3)]
 
 
 def _cmu(m, k=1.0, eps=1.0):
