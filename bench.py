@@ -49,8 +49,12 @@ ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 97.0, "sc
               "p_apply": 24.0}
 KERNEL = {"scalar_sweep": "k_scalar_sweep", "mom_sweep": "k_mom_sweep", "mom_assemble": "k_mom_assemble",
           "scalar_assemble": "k_scalar_assemble", "p_apply": "k_fine_apply"}
-KERNEL_SOURCES = {"k_scalar_sweep": "turbulence.hip", "k_scalar_assemble": "turbulence.hip",
-                  "k_mom_sweep": "simple.hip", "k_mom_assemble": "simple.hip", "k_fine_apply": "pressure.hip"}
+# the mixed policy's sweeps are one-colour launches of their own kernels
+ALGO_BYTES_MIXED = dict(ALGO_BYTES)
+KERNEL_MIXED = dict(KERNEL, scalar_sweep="k_scalar_sweep32", mom_sweep="k_mom_sweep32")
+KERNEL_SOURCES = {"k_scalar_sweep": "turbulence.hip", "k_scalar_sweep32": "turbulence.hip",
+                  "k_scalar_assemble": "turbulence.hip", "k_mom_sweep": "simple.hip",
+                  "k_mom_sweep32": "simple.hip", "k_mom_assemble": "simple.hip", "k_fine_apply": "pressure.hip"}
 
 
 def kernel_source_hash(kernel):
@@ -91,6 +95,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--tile", default="auto", choices=["auto", "default"],
+                    help="tile shape of the full-grid kernels: autotuned (width and depth) or 64 x 4 x 1")
     ap.add_argument("--case", default="ahmed", choices=["ahmed", "bfs", "ahmed2"])
     ap.add_argument("--p-rtol", type=float, default=1e-2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -133,6 +139,26 @@ def main():
     counts = solver.counts()
     log(f"set_indicator {time.time() - t0:.2f}s counts {counts}")
 
+    # tile shape (set-up, outside the timed region): for each depth that divides
+    # nz, the autotuner's fastest width; the fastest pair is kept
+    tile = {"width": 64, "depth": 1}
+    if args.tile == "auto":
+        best = None
+        for depth in (1, 2, 4):
+            if spec.dim != 3 or spec.nz % depth:
+                continue
+            solver.set_tile_width(64)
+            solver.set_tile_depth(depth)
+            w, ms = solver.autotune_tiles(reps=3)
+            log(f"tile depth {depth}: ms per round by width {ms}")
+            if best is None or ms[w] < best[0]:
+                best = (ms[w], w, depth)
+        solver.set_tile_width(64)
+        solver.set_tile_depth(best[2])
+        solver.set_tile_width(best[1])
+        tile = {"width": best[1], "depth": best[2]}
+    log(f"tile {tile}")
+
     done, res = solver.iterate(args.warmup)
     torch.cuda.synchronize()
     log(f"warmup {done} iterations, residuals {np.round(res, 5).tolist()}")
@@ -159,20 +185,21 @@ def main():
         solver.timing(False)
         log("kernel timing (ms total, launches): " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in kern.items()))
         # dominant single kernel among the timed classes with a byte model
-        cand = {k: kern[k] for k in ALGO_BYTES if kern[k][1] > 0}
+        algo, knames = (ALGO_BYTES, KERNEL) if args.precision == "fp64" else (ALGO_BYTES_MIXED, KERNEL_MIXED)
+        cand = {k: kern[k] for k in algo if kern[k][1] > 0}
         if cand:
             dom = max(cand, key=lambda k: cand[k][0])
             ms, cnt = cand[dom]
             avg_s = ms / 1e3 / cnt
-            achieved = ALGO_BYTES[dom] * N / avg_s / 1e9
-            kname = KERNEL[dom]
+            achieved = algo[dom] * N / avg_s / 1e9
+            kname = knames[dom]
             workload = spec.name + "_" + spec.model + "_" + args.precision
             traffic = stored_traffic(kname, workload) if args.precision == "fp64" else None
             roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": round(achieved / PEAK_HBM_GBS, 4),
                     "traffic": None if traffic is None else round(traffic),
                     "kernel": kname, "avg_launch_us": round(avg_s * 1e6, 2),
-                    "algorithmic_bytes_per_cell": ALGO_BYTES[dom],
+                    "algorithmic_bytes_per_cell": algo[dom],
                     "share_of_iteration": round(ms / max(kern["iteration"][0], 1e-12), 4)}
 
     value = N * done / elapsed
@@ -203,7 +230,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": spec.name + "_" + spec.model, "cells": N, "model": "k-omega SST" if spec.model == "sst"
                    else spec.model, "precision": args.precision, "p_rtol": args.p_rtol, "n_sweeps": spec.n_sweeps,
-                   "boundary_cells": counts["bc"], "insolid_cells": counts["ic"],
+                   "boundary_cells": counts["bc"], "insolid_cells": counts["ic"], "tile": tile,
                    "pcg_iters_per_step": round(stats[0] / max(done, 1), 2), "finite": bool(finite),
                    "final_residuals": [float(x) for x in res]},
         "roofline": roof,

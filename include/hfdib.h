@@ -125,7 +125,8 @@ typedef struct {
   int n_sweeps;         /* red-black Gauss-Seidel sweeps per transport solve (>= 1) */
   double nu;            /* kinematic viscosity (> 0) */
   double urf_u, urf_p, urf_t; /* under-relaxation of momentum, pressure, turbulence, in (0,1] */
-  double p_rtol;        /* relative residual target of the pressure PCG solve */
+  double p_rtol;        /* relative residual target of the pressure PCG solve (|r| <= p_rtol |b|, |b|
+                           over the coupled rows; see hfdib_pressure_solve) */
   int p_maxit;          /* PCG iteration cap per pressure solve */
   int recorrect;        /* 1: re-impose u_ib on forced cells after the velocity update */
   int bc_capacity;      /* max boundary (and in-solid, wall) cells; 0 = automatic */
@@ -249,6 +250,14 @@ int hfdib_forces(hfdib_ctx* ctx, double* out8);
  * other widths or reps < 1, HFDIB_ESTATE before hfdib_set_indicator. */
 int hfdib_autotune_tiles(hfdib_ctx* ctx, int reps, int* best_width, double* ms4);
 int hfdib_set_tile_width(hfdib_ctx* ctx, int width);
+/* Tile depth of the full-grid kernels: 1 (the default), 2 or 4 planes per
+ * 256-thread tile (the tile then spans 256 / (width * depth) rows), so the
+ * z-neighbour planes a stencil reads are shared by more cells of one tile.
+ * The depth must divide nz (3-D grids only) and width * depth must not exceed
+ * 256; otherwise HFDIB_EINVAL and the depth is unchanged.  Results are
+ * unchanged up to the order of partial sums in reductions.  hfdib_autotune_tiles
+ * times the widths at the current depth (ms4 entry -1 for a width too wide). */
+int hfdib_set_tile_depth(hfdib_ctx* ctx, int depth);
 
 /* Copies one per-boundary-cell record array (HFDIB_IB_*) to dst_dev. */
 int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);
@@ -258,7 +267,9 @@ int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);
  * c_b = rAU_P|S|/(d/2) on outlet faces of cells with lambda = 0 (requires
  * set_indicator).  rAU_dev, rhs_dev: N doubles; p_dev: initial guess in,
  * solution out.  Conjugate gradients preconditioned by one geometric-multigrid
- * V-cycle; stops at relative residual <= rtol or maxit iterations.
+ * V-cycle; stops at |r| <= rtol |b| or after maxit iterations, where |b| is taken
+ * over the coupled rows (an uncoupled row, all of whose coefficients are zero,
+ * is the identity p = rhs and its right-hand side does not enter |b|).
  * *iters and *relres (host, nullable) report the outcome.  Synchronises. */
 int hfdib_pressure_solve(hfdib_ctx* ctx, const double* rAU_dev, const double* rhs_dev,
                          double* p_dev, double rtol, int maxit, int* iters, double* relres);
@@ -269,8 +280,10 @@ int hfdib_pressure_solve(hfdib_ctx* ctx, const double* rAU_dev, const double* rh
 int hfdib_last_stats(hfdib_ctx* ctx, double* out8);
 
 /* Per-kernel timing with HIP events on the context stream.  enable != 0 starts
- * recording (events around every launch of the named kernel class, see
- * hfdib_timing_query); 0 stops.  Adds host overhead; off by default. */
+ * recording (an event pair around every launch of the named kernel class, or
+ * around the run of 2 n_sweeps consecutive launches of a red-black solve, which
+ * counts as that many launches; see hfdib_timing_query); 0 stops.  Adds host
+ * overhead; off by default. */
 int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
 /* kernel_class: 0 pressure operator apply (fine level), 1 momentum sweep,
  * 2 momentum assembly, 3 whole pressure solve, 4 whole SIMPLE iteration,

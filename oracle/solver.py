@@ -314,12 +314,14 @@ class Simple:
         A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(g.N, g.N))
         return A
 
-    def solve_pressure(self, A, b, x0):
+    def solve_pressure(self, A, b, x0, coupled=None):
         if self.p_solver == "direct":
             return spla.splu(A.tocsc()).solve(b)
         dinv = 1.0 / A.diagonal()
         M = spla.LinearOperator(A.shape, matvec=lambda v: dinv * v)
-        x, info = spla.cg(A, b, x0=x0, rtol=self.p_rtol, atol=0.0, M=M, maxiter=100000)
+        # the relative tolerance refers to |b| over the coupled rows
+        bn = np.linalg.norm(b if coupled is None else b[coupled])
+        x, info = spla.cg(A, b, x0=x0, rtol=0.0, atol=self.p_rtol * bn, M=M, maxiter=100000)
         return x
 
     # ------------------------------------------------------------ O3: iteration
@@ -440,8 +442,12 @@ class Simple:
         Ax = A @ pflat_old
         xb = pflat_old.mean()
         Axb = A @ np.full(g.N, xb)
-        res["p"] = float(np.abs(bflat - Ax).sum() / (np.abs(Ax - Axb).sum() + np.abs(bflat - Axb).sum() + 1e-300))
-        p_sol = self.solve_pressure(A, bflat, pflat_old).reshape(g.shape)
+        # normalised residual over the coupled rows (identity rows, whose right-hand
+        # side is a pressure value, are left out like the forced rows of u and k)
+        cp = ~iso.ravel()
+        res["p"] = float(np.abs(bflat - Ax)[cp].sum()
+                         / (np.abs(Ax - Axb)[cp].sum() + np.abs(bflat - Axb)[cp].sum() + 1e-300))
+        p_sol = self.solve_pressure(A, bflat, pflat_old, coupled=cp).reshape(g.shape)
         # identity rows next to coupled cells take the mean solved pressure of their
         # coupled face neighbours (deeper identity rows keep p).  Without it their p
         # stays at a stale value; when a neighbour leaves the forced group (y+

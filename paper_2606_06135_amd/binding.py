@@ -97,6 +97,7 @@ def lib():
     L.hfdib_forces.argtypes = [vp, C.POINTER(d)]
     L.hfdib_autotune_tiles.argtypes = [vp, i, C.POINTER(i), C.POINTER(d)]
     L.hfdib_set_tile_width.argtypes = [vp, i]
+    L.hfdib_set_tile_depth.argtypes = [vp, i]
     L.hfdib_batch_create.argtypes = [C.POINTER(vp), i, i, d, vp, C.POINTER(vp)]
     L.hfdib_batch_run.argtypes = [vp, i]
     L.hfdib_batch_status.argtypes = [vp, C.POINTER(i), C.POINTER(i), C.POINTER(d)]
@@ -108,7 +109,7 @@ def lib():
                "hfdib_get_field", "hfdib_set_field", "hfdib_get_counts", "hfdib_get_ib_array",
                "hfdib_pressure_solve", "hfdib_last_stats", "hfdib_timing_enable", "hfdib_timing_query",
                "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
-               "hfdib_autotune_tiles", "hfdib_set_tile_width"):
+               "hfdib_autotune_tiles", "hfdib_set_tile_width", "hfdib_set_tile_depth"):
         getattr(L, fn).restype = i
     if L.hfdib_abi_version() != ABI_VERSION:
         raise ImportError("libhfdib ABI version mismatch")
@@ -121,7 +122,8 @@ EXPORTED = ["hfdib_abi_version", "hfdib_default_config", "hfdib_workspace_bytes"
             "hfdib_get_counts", "hfdib_get_ib_array", "hfdib_pressure_solve", "hfdib_last_stats",
             "hfdib_timing_enable", "hfdib_timing_query", "hfdib_destroy", "hfdib_status_string",
             "hfdib_last_error", "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
-            "hfdib_batch_last_error", "hfdib_batch_destroy", "hfdib_autotune_tiles", "hfdib_set_tile_width"]
+            "hfdib_batch_last_error", "hfdib_batch_destroy", "hfdib_autotune_tiles", "hfdib_set_tile_width",
+            "hfdib_set_tile_depth"]
 
 
 def default_config():
@@ -318,6 +320,9 @@ class Solver:
 
     def set_tile_width(self, width):
         _check("hfdib_set_tile_width", lib().hfdib_set_tile_width(self.ctx, int(width)), self.ctx)
+
+    def set_tile_depth(self, depth):
+        _check("hfdib_set_tile_depth", lib().hfdib_set_tile_depth(self.ctx, int(depth)), self.ctx)
 
     def forces(self):
         """Force on the body per unit density: pressure part, viscous part,

@@ -20,7 +20,11 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where) {
 
 struct Timers {
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> pend[T_NCLASS];
+  struct Span {
+    hipEvent_t e0, e1;
+    int launches;
+  };
+  std::vector<Span> pend[T_NCLASS];
   hipEvent_t open[T_NCLASS] = {};
   double ms[T_NCLASS] = {};
   long long cnt[T_NCLASS] = {};
@@ -33,14 +37,14 @@ static void timers_flush(hfdib_ctx* c) {
   if (!any) return;
   (void)hipStreamSynchronize(c->stream);
   for (int k = 0; k < T_NCLASS; ++k) {
-    for (auto& pr : T->pend[k]) {
+    for (auto& sp : T->pend[k]) {
       float ms = 0.f;
-      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      if (hipEventElapsedTime(&ms, sp.e0, sp.e1) == hipSuccess) {
         T->ms[k] += ms;
-        T->cnt[k] += 1;
+        T->cnt[k] += sp.launches;
       }
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+      (void)hipEventDestroy(sp.e0);
+      (void)hipEventDestroy(sp.e1);
     }
     T->pend[k].clear();
   }
@@ -55,13 +59,13 @@ void timer_begin(hfdib_ctx* c, int cls) {
   T->open[cls] = e;
 }
 
-void timer_end(hfdib_ctx* c, int cls) {
+void timer_end(hfdib_ctx* c, int cls, int launches) {
   Timers* T = c->timers;
   if (!T || !T->on || !T->open[cls]) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
   (void)hipEventRecord(e, c->stream);
-  T->pend[cls].push_back({T->open[cls], e});
+  T->pend[cls].push_back({T->open[cls], e, launches});
   T->open[cls] = nullptr;
   if (T->pend[cls].size() > 4096) timers_flush(c);
 }
@@ -654,6 +658,10 @@ int hfdib_autotune_tiles(hfdib_ctx* c, int reps, int* best_width, double* ms_out
   double best_ms = 0.0;
   int status = HFDIB_OK;
   for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX && status == HFDIB_OK; ++lx) {
+    if (lx + c->P.tz_log2 > 8) {  // too wide for the current depth
+      if (ms_out) ms_out[lx - TILE_LOG2_MIN] = -1.0;
+      continue;
+    }
     c->P.tx_log2 = lx;
     status = tile_bench_round(c);  // warm-up
     if (status != HFDIB_OK) break;
@@ -666,7 +674,7 @@ int hfdib_autotune_tiles(hfdib_ctx* c, int reps, int* best_width, double* ms_out
     if (e != hipSuccess) status = set_hip_error(c, e, "autotune timing");
     double avg = (double)ms / reps;
     if (ms_out) ms_out[lx - TILE_LOG2_MIN] = avg;
-    if (lx == TILE_LOG2_MIN || avg < best_ms) {
+    if (best_ms == 0.0 || avg < best_ms) {
       best_ms = avg;
       best = lx;
     }
@@ -682,7 +690,25 @@ int hfdib_set_tile_width(hfdib_ctx* c, int width) {
   if (!c) return HFDIB_EINVAL;
   for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX; ++lx)
     if (width == (1 << lx)) {
+      if (lx + c->P.tz_log2 > 8) {
+        c->err = "tile width times depth exceeds 256 cells";
+        return HFDIB_EINVAL;
+      }
       c->P.tx_log2 = lx;
+      return HFDIB_OK;
+    }
+  return HFDIB_EINVAL;
+}
+
+int hfdib_set_tile_depth(hfdib_ctx* c, int depth) {
+  if (!c) return HFDIB_EINVAL;
+  for (int lz = 0; lz <= 2; ++lz)
+    if (depth == (1 << lz)) {
+      if (c->P.nz % depth != 0 || (lz > 0 && c->P.dim != 3) || c->P.tx_log2 + lz > 8) {
+        c->err = "tile depth must divide nz (3-D grids) and width times depth must not exceed 256";
+        return HFDIB_EINVAL;
+      }
+      c->P.tz_log2 = lz;
       return HFDIB_OK;
     }
   return HFDIB_EINVAL;

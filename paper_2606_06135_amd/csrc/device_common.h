@@ -81,7 +81,8 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[NV], double* 
   }
 }
 
-// Full-grid kernels run on a 1D grid of 256-thread tiles (grid3()).  Consecutive
+// Full-grid kernels run on a 1D grid of 256-thread tiles (grid3()) of
+// 2^tx_log2 x 2^(8 - tx_log2 - tz_log2) x 2^tz_log2 cells.  Consecutive
 // workgroups are dispatched round-robin over the 8 XCDs; the logical tile order
 // is remapped so that each XCD works on a contiguous run of tiles (x fastest,
 // then y, then z) and the y/z halo rows a tile needs stay in that XCD's L2.
@@ -89,12 +90,12 @@ __device__ __forceinline__ void tile_ijk(const Params& P, int& i, int& j, int& k
   unsigned nb = gridDim.x, b = blockIdx.x;
   unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, id = b >> 3;
   unsigned L = x < r ? x * (q + 1) + id : r * (q + 1) + (x - r) * q + id;
-  const int lx = P.tx_log2, ly = 8 - P.tx_log2;
+  const int lx = P.tx_log2, lz = P.tz_log2, ly = 8 - lx - lz;
   int tx = (P.nx + (1 << lx) - 1) >> lx, ty = (P.ny + (1 << ly) - 1) >> ly;
   int bx = (int)(L % (unsigned)tx);
   unsigned rest = L / (unsigned)tx;
   int by = (int)(rest % (unsigned)ty);
-  k = (int)(rest / (unsigned)ty);
+  k = ((int)(rest / (unsigned)ty) << lz) + (int)threadIdx.z;
   i = (bx << lx) + (int)threadIdx.x;
   j = (by << ly) + (int)threadIdx.y;
 }
@@ -107,12 +108,12 @@ __device__ __forceinline__ void tile_ijk_rb(const Params& P, int color, int& i, 
   unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, id = b >> 3;
   unsigned L = x < r ? x * (q + 1) + id : r * (q + 1) + (x - r) * q + id;
   int nxh = (P.nx + 1) >> 1;
-  const int lx = P.tx_log2, ly = 8 - P.tx_log2;
+  const int lx = P.tx_log2, lz = P.tz_log2, ly = 8 - lx - lz;
   int tx = (nxh + (1 << lx) - 1) >> lx, ty = (P.ny + (1 << ly) - 1) >> ly;
   int bx = (int)(L % (unsigned)tx);
   unsigned rest = L / (unsigned)tx;
   int by = (int)(rest % (unsigned)ty);
-  k = (int)(rest / (unsigned)ty);
+  k = ((int)(rest / (unsigned)ty) << lz) + (int)threadIdx.z;
   j = (by << ly) + (int)threadIdx.y;
   // t >= nxh gives i >= nx and i ^ 1 >= nx (both cells of the pair outside)
   int t = (bx << lx) + (int)threadIdx.x;

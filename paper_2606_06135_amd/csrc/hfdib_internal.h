@@ -60,6 +60,7 @@ struct Params {
   int continuity;
   int precision;  // HFDIB_FP64 or HFDIB_MIXED
   int tx_log2;    // tile width of the full-grid kernels: 2^tx_log2 cells (5..8), 256 threads per tile
+  int tz_log2;    // tile depth: 2^tz_log2 planes (0..2; 2^tz_log2 divides nz, tx_log2 + tz_log2 <= 8)
 };
 
 // Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).
@@ -144,17 +145,21 @@ struct hfdib_ctx {
 namespace hfdib {
 
 // launch helpers
-// Full-grid kernels run 256-thread tiles of 2^tx_log2 x 2^(8 - tx_log2) cells
-// (chosen by hfdib_autotune_tiles; 64 x 4 by default)
+// Full-grid kernels run 256-thread tiles of 2^tx_log2 x 2^(8 - tx_log2 - tz_log2)
+// cells (the width chosen by hfdib_autotune_tiles; 64 x 4 x 1 by default)
+// and 2^tz_log2 planes (a depth that divides nz: no tile reaches past the grid
+// in z, so the kernels only bound i and j)
 inline dim3 grid3(const Params& P) {
-  const int TX = 1 << P.tx_log2, TY = 256 >> P.tx_log2;
-  return dim3((unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY) * P.nz), 1, 1);
+  const int TX = 1 << P.tx_log2, TY = 256 >> (P.tx_log2 + P.tz_log2);
+  return dim3((unsigned)(((P.nx + TX - 1) / TX) * ((P.ny + TY - 1) / TY) * (P.nz >> P.tz_log2)), 1, 1);
 }
-inline dim3 block3(const Params& P) { return dim3(1u << P.tx_log2, 256u >> P.tx_log2, 1); }
+inline dim3 block3(const Params& P) {
+  return dim3(1u << P.tx_log2, 256u >> (P.tx_log2 + P.tz_log2), 1u << P.tz_log2);
+}
 // grid of the red-black half sweeps (half the x extent, see tile_ijk_rb)
 inline dim3 grid3_rb(const Params& P) {
-  const int TX = 1 << P.tx_log2, TY = 256 >> P.tx_log2;
-  return dim3((unsigned)((((P.nx + 1) / 2 + TX - 1) / TX) * ((P.ny + TY - 1) / TY) * P.nz), 1, 1);
+  const int TX = 1 << P.tx_log2, TY = 256 >> (P.tx_log2 + P.tz_log2);
+  return dim3((unsigned)((((P.nx + 1) / 2 + TX - 1) / TX) * ((P.ny + TY - 1) / TY) * (P.nz >> P.tz_log2)), 1, 1);
 }
 // blocks of the stored multigrid levels (3-D grids of 64 x 4 tiles)
 inline dim3 block_lv() { return dim3(64, 4, 1); }
@@ -180,7 +185,9 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);
 enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_SCALSWEEP = 5, T_SCALASM = 6,
        T_NCLASS = 7 };
 void timer_begin(hfdib_ctx* c, int cls);
-void timer_end(hfdib_ctx* c, int cls);
+// closes the open span of class cls, which covered `launches` consecutive
+// launches of that class (its per-launch average divides by them)
+void timer_end(hfdib_ctx* c, int cls, int launches = 1);
 
 // stages (each returns an hfdib_status)
 int geometry_precompute(hfdib_ctx* c);

@@ -115,21 +115,23 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
     fine_row(P, O, N, c, cf);
     double xc = x[c];
     double acc = fine_Ax(cf, N, x, c, dg, bnd);
-    if (dg == 0.0) {  // uncoupled row: identity
-      acc = xc;
-      bnd = 1.0;
-    }
+    const bool ident = dg == 0.0;  // uncoupled row: identity
+    if (ident) acc = xc;
     double bc = b[c];
     double rc = bc - acc;
     r[c] = rc;
     if (r32) r32[c] = (float)rc;
     v[0] = rc * rc;
-    v[1] = bc * bc;
-    if (xmean) {
-      double Axb = bnd * (*xmean);
-      v[2] = fabs(rc);
-      v[3] = fabs(acc - Axb);
-      v[4] = fabs(bc - Axb);
+    // |b| of the relative tolerance and the normalised residual: coupled rows only
+    // (an identity row's right-hand side is a pressure value, not a source)
+    if (!ident) {
+      v[1] = bc * bc;
+      if (xmean) {
+        double Axb = bnd * (*xmean);
+        v[2] = fabs(rc);
+        v[3] = fabs(acc - Axb);
+        v[4] = fabs(bc - Axb);
+      }
     }
   }
   block_sums_store<5>(v, part, pstride, block_linear());

@@ -77,24 +77,49 @@ __device__ __forceinline__ double rke_cmu(const Params& P, const RkeInv& I, doub
   return 1.0 / (P.A0_rke + As * Us * kk / ee);
 }
 
-__global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, const double* nv, const double* ypl,
-                          const double* utl, G9 Gs, const double* S2, const double* kold, const double* nut,
-                          double* Pk, double* wib, double* w) {
+// one list of wall-function cells: boundary cells, or free-stream cells at
+// no-slip domain faces (distance, normal, y+ and u_tau per entry)
+struct WallList {
+  int n;
+  const int* cells;
+  const double* y;
+  const double* nv;
+  const double* ypl;
+  const double* utl;
+};
+
+// imposed omega/eps and production on the boundary cells and the domain-wall
+// cells (one thread per list entry), and on the in-solid cells (omega/eps = the
+// maximum over the other cells, no production), in one launch
+__global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, const int* ic_cells, const double* wmax,
+                               G9 Gs, const double* S2, const double* kold, const double* nut, double* Pk,
+                               double* wib, double* w) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
-  if (b >= n) return;
-  int c = cells[b];
+  if (b >= L0.n + L1.n + nic) return;
+  if (b >= L0.n + L1.n) {
+    int c = ic_cells[b - L0.n - L1.n];
+    double m = *wmax;
+    Pk[c] = 0.0;
+    wib[c] = m;
+    w[c] = m;
+    return;
+  }
+  const bool first = b < L0.n;
+  const WallList& L = first ? L0 : L1;
+  if (!first) b -= L0.n;
+  int c = L.cells[b];
   double G[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int jc = 0; jc < 3; ++jc) G[a][jc] = (a < P.dim && jc < P.dim) ? Gs.g[3 * a + jc][c] : 0.0;
-  double yp = ypl[b], ut = utl[b], y = yv[b];
+  double yp = L.ypl[b], ut = L.utl[b], y = L.y[b];
   double om = omega_ib(P, yp, y, ut);
   double kk = kold[c];
   double val = (P.model == HFDIB_KEPS || P.model == HFDIB_RKEPS) ? P.Cmu * kk * om : om;
   double ng[3] = {0.0, 0.0, 0.0};
   for (int jj = 0; jj < 3; ++jj)
-    for (int ii = 0; ii < 3; ++ii) ng[jj] += nv[3 * b + ii] * G[ii][jj];
+    for (int ii = 0; ii < 3; ++ii) ng[jj] += L.nv[3 * b + ii] * G[ii][jj];
   double ng2 = ng[0] * ng[0] + ng[1] * ng[1] + ng[2] * ng[2];
   double Pm = model_production(P, S2[c], nut[c], kk, w[c]);
   Pk[c] = prod_ib(P, yp, Pm, ng2);
@@ -102,15 +127,6 @@ __global__ void k_turb_ib(Params P, int n, const int* cells, const double* yv, c
   w[c] = val;
 }
 
-__global__ void k_turb_ic(int n, const int* cells, const double* wmax, double* Pk, double* wib, double* w) {
-  int b = blockIdx.x * NTHREADS + threadIdx.x;
-  if (b >= n) return;
-  int c = cells[b];
-  double m = *wmax;
-  Pk[c] = 0.0;
-  wib[c] = m;
-  w[c] = m;
-}
 
 __global__ void k_sum1(long long n, const double* a, double* part, long long pstride) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
@@ -433,23 +449,14 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, G
   if (nut32) nut32[c] = (float)nt;
 }
 
-// boundary cells on the logarithmic branch: log-law wall viscosity
-__global__ void k_nut_bc(Params P, int nbc, const int* bc_cells, const double* ypl, double* nut, float* nut32) {
-  int b = blockIdx.x * NTHREADS + threadIdx.x;
-  if (b >= nbc) return;
-  double yp = ypl[b];
-  if (!(yp > P.ylam)) return;
-  double v = P.kappa * yp / log(P.E * yp) - 1.0;
-  double nt = P.nu * (v > 0.0 ? v : 0.0);
-  nut[bc_cells[b]] = nt;
-  if (nut32) nut32[bc_cells[b]] = (float)nt;
-}
 
-// velocity-based friction velocity from the log law by Newton's method
-// (boundary cells on the logarithmic branch; 0 elsewhere)
-__global__ void k_loglaw(Params P, int nbc, const int* bc_cells, const double* bc_n, const double* bc_yeff,
-                         const double* ypl, const double* utl, const double* u0, const double* u1, const double* u2,
-                         const double* us0, const double* us1, const double* us2, double* out) {
+// boundary cells on the logarithmic branch: the log-law wall viscosity, and the
+// velocity-based friction velocity from the log law by Newton's method (0 off
+// that branch)
+__global__ void k_wall_bc(Params P, int nbc, const int* bc_cells, const double* bc_n, const double* bc_yeff,
+                          const double* ypl, const double* utl, const double* u0, const double* u1, const double* u2,
+                          const double* us0, const double* us1, const double* us2, double* out, double* nut,
+                          float* nut32) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= nbc) return;
   double yp = ypl[b];
@@ -458,6 +465,12 @@ __global__ void k_loglaw(Params P, int nbc, const int* bc_cells, const double* b
     return;
   }
   int c = bc_cells[b];
+  {
+    double v = P.kappa * yp / log(P.E * yp) - 1.0;
+    double nt = P.nu * (v > 0.0 ? v : 0.0);
+    nut[c] = nt;
+    if (nut32) nut32[c] = (float)nt;
+  }
   double ur[3] = {u0[c] - us0[c], u1[c] - us1[c], u2[c] - us2[c]};
   double n[3] = {bc_n[3 * b], bc_n[3 * b + 1], bc_n[3 * b + 2]};
   double un = ur[0] * n[0] + ur[1] * n[1] + ur[2] * n[2];
@@ -499,16 +512,14 @@ int turbulence_stage(hfdib_ctx* c) {
   // imposed omega/eps and production on boundary, wall and in-solid cells (the
   // maximum of omega/eps over cells outside the in-solid group was reduced in the momentum
   // assembly, before any omega/eps value changed)
-  if (c->n_bc > 0)
-    hipLaunchKernelGGL(k_turb_ib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
-                       c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau, Gs, c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
-  if (c->n_wall > 0)
-    hipLaunchKernelGGL(k_turb_ib, dim3(nblocks1(c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_wall,
-                       c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau, Gs, c->S2, c->k, c->nut,
-                       c->Pk, c->wib, c->w);
-  if (c->n_ic > 0)
-    hipLaunchKernelGGL(k_turb_ic, dim3(nblocks1(c->n_ic)), dim3(NTHREADS), 0, c->stream, c->n_ic, c->ic_cells,
-                       wmax, c->Pk, c->wib, c->w);
+  {
+    WallList L0{c->n_bc, c->bc_cells, c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau};
+    WallList L1{c->n_wall, c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau};
+    int ntot = c->n_bc + c->n_wall + c->n_ic;
+    if (ntot > 0)
+      hipLaunchKernelGGL(k_turb_imposed, dim3(nblocks1(ntot)), dim3(NTHREADS), 0, c->stream, P, L0, L1, c->n_ic,
+                         c->ic_cells, wmax, Gs, c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
+  }
   hipLaunchKernelGGL(k_sum1, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, c->w, c->partials, c->pstride);
   launch_finalize(c, nb1, 1, SC_MEANS + 5, 0, (double)P.N);
   Scal Sc;
@@ -531,17 +542,19 @@ int turbulence_stage(hfdib_ctx* c) {
   float* a32 = mixed ? c->a32 : nullptr;
   Scal32 S32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32, c->F1_32};
   // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
+  // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
+  // (one timing span over the 2 n_s consecutive launches)
   auto sweeps = [&](int eq, double* x, uint8_t fixmask) {
+    timer_begin(c, T_SCALSWEEP);
     for (int s = 0; s < P.n_sweeps; ++s)
       for (int color = 0; color < 2; ++color) {
-        timer_begin(c, T_SCALSWEEP);
         if (mixed)
-          hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0], x, color,
-                             fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
+          hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0],
+                             x, color, fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
         else
           hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, eq, c->t0, c->t1, x, color, fixmask);
-        timer_end(c, T_SCALSWEEP);
       }
+    timer_end(c, T_SCALSWEEP, 2 * P.n_sweeps);
   };
   // omega / eps equation, alpha_omega rows fixed
   timer_begin(c, T_SCALASM);
@@ -565,11 +578,9 @@ int turbulence_stage(hfdib_ctx* c) {
   hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, Gs, c->kib, c->k, c->w,
                      c->dw, c->nut, mixed ? c->nut32 : nullptr);
   if (c->n_bc > 0) {
-    hipLaunchKernelGGL(k_nut_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
-                       c->bc_yplus, c->nut, mixed ? c->nut32 : nullptr);
-    hipLaunchKernelGGL(k_loglaw, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
+    hipLaunchKernelGGL(k_wall_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
                        c->bc_n, c->bc_yeff, c->bc_yplus, c->bc_utau, c->u[0], c->u[1], c->u[2], c->us[0], c->us[1],
-                       c->us[2], c->bc_utauU);
+                       c->us[2], c->bc_utauU, c->nut, mixed ? c->nut32 : nullptr);
   }
   HFDIB_CHECK_LAUNCH(c, "turbulence");
   return HFDIB_OK;

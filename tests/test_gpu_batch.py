@@ -79,6 +79,39 @@ def test_tile_widths_keep_parity(gpu, width):
         assert v <= 1e-9, (width, k, v)
 
 
+@pytest.mark.parametrize("width, depth", [(64, 2), (32, 4), (128, 2)])
+def test_tile_depths_keep_parity(gpu, width, depth):
+    # tiles spanning several planes (nz = 12 divisible by the depth), odd x and y extents
+    spec = synth.case_small_body3d(nx=37, ny=13, nz=12, model="sst", nu=1e-4)
+    spec.conv_scheme = "linear_upwind"
+    sim = Simple(spec)
+    for _ in range(15):
+        sim.step()
+    s = _solver(spec, gpu)
+    s.set_tile_depth(depth)
+    s.set_tile_width(width)
+    s.iterate(15)
+    c = compare(sim, s, dim=spec.dim, model=spec.model)
+    _say(f"width {width} depth {depth}:", {k: f"{v:.1e}" for k, v in c.items()})
+    for k, v in c.items():
+        assert v <= 1e-9, (width, depth, k, v)
+
+
+def test_invalid_tile_depth_rejected(gpu):
+    from paper_2606_06135_amd.binding import HfdibError
+    spec = synth.case_small_body3d(nx=24, ny=12, nz=10, model="laminar")
+    s = _solver(spec, gpu)
+    with pytest.raises(HfdibError):
+        s.set_tile_depth(4)  # does not divide nz = 10
+    with pytest.raises(HfdibError):
+        s.set_tile_depth(3)
+    s.set_tile_depth(2)
+    with pytest.raises(HfdibError):
+        s.set_tile_width(256)  # 256 x 2 > 256 cells
+    s.iterate(2)
+    assert np.isfinite(s.get_field("ux").cpu().numpy()).all()
+
+
 def test_autotune_leaves_the_state_alone(gpu):
     spec = synth.case_small_body3d(model="sst", nu=1e-4)
     s = _solver(spec, gpu)

@@ -45,7 +45,16 @@ CASES = {
     "sphere3d_sst_vanleer": (lambda: _conv(synth.case_small_body3d(model="sst", nu=1e-4), "vanleer"), 30),
     "block2d_laminar_vanleer": (lambda: _conv(synth.case_cavity_block(), "vanleer"), 30),
     "naca_64x32_sst_linear_upwind": (lambda: _conv(synth.case_naca(4.0, 64, 32), "linear_upwind"), 30),
+    "sphere3d_sst_1sweep": (lambda: _sweeps(synth.case_small_body3d(nx=37, ny=13, nz=11, model="sst", nu=1e-4), 1), 20),
+    "bfs_keps_3sweeps": (lambda: _sweeps(synth.case_bfs(), 3), 30),
 }
+
+
+def _sweeps(spec, n):
+    # an odd number of red-black sweeps per transport solve
+    spec.n_sweeps = n
+    spec.name += f"_{n}sweeps"
+    return spec
 
 
 def _conv(spec, scheme):
