@@ -117,8 +117,10 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->nut = B.take<double>(N);
   c->lam = B.take<double>(N);
   c->dw = B.take<double>(N);
-  for (int q = 0; q < 3; ++q) c->rhs[q] = B.take<double>(N);
-  c->aPr = B.take<double>(N);
+  // rhs and a'_P of the momentum rows, colour-split (see Params::nrb)
+  const long long nsplit_u = 2 * P.nrb > N ? 2 * P.nrb : N;
+  for (int q = 0; q < 3; ++q) c->rhs[q] = B.take<double>(nsplit_u);
+  c->aPr = B.take<double>(nsplit_u);
   for (int q = 0; q < 3; ++q) c->hbya[q] = B.take<double>(N);
   c->rAU = B.take<double>(N);
   c->F1 = B.take<double>(N);
@@ -127,8 +129,10 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->wib = B.take<double>(N);
   c->Pk = B.take<double>(N);
   for (int q = 0; q < 3; ++q) c->us[q] = B.take<double>(N);
-  c->t0 = B.take<double>(N);
-  c->t1 = B.take<double>(N);
+  // t0, t1: colour-split right-hand side and diagonal of the k and omega/eps rows
+  const long long nsplit = 2 * P.nrb > N ? 2 * P.nrb : N;
+  c->t0 = B.take<double>(nsplit);
+  c->t1 = B.take<double>(nsplit);
   c->t2 = B.take<double>(N);
   for (int q = 0; q < 9; ++q) c->G[q] = B.take<double>(N);
   c->S2 = B.take<double>(N);
@@ -312,6 +316,8 @@ static void fill_params(hfdib_ctx* c) {
   P.ny = d.ny;
   P.nz = d.nz;
   P.N = (long long)d.nx * d.ny * d.nz;
+  P.nxh = (d.nx + 1) / 2;
+  P.nrb = (long long)P.nxh * d.ny * d.nz;
   P.x0 = d.x0;
   P.y0 = d.y0;
   P.z0 = d.z0;

@@ -23,6 +23,10 @@ __device__ __forceinline__ long long stride(const Params& P, int d) {
 __device__ __forceinline__ int comp(int d, int i, int j, int k) { return d == 0 ? i : (d == 1 ? j : k); }
 
 // true when the cell touches the domain face (d, s)
+// index of cell (i, j, k) in a colour-split array (see Params::nrb)
+__device__ __forceinline__ long long rb_split(const Params& P, int i, int j, int k) {
+  return (long long)((i + j + k) & 1) * P.nrb + ((long long)k * P.ny + j) * P.nxh + (i >> 1);
+}
 __device__ __forceinline__ bool on_bnd(const Params& P, int d, int s, int i, int j, int k) {
   int a = comp(d, i, j, k);
   return s < 0 ? (a == 0) : (a == ncell(P, d) - 1);

@@ -31,6 +31,11 @@ constexpr int TILE_LOG2_MIN = 5, TILE_LOG2_MAX = 8;  // tile widths 32 .. 256 ce
 struct Params {
   int dim, nx, ny, nz;
   long long N;
+  // colour-split storage of per-row arrays of the red-black solves: colour
+  // (i+j+k)&1 first, then (k, j, i/2); nxh = (nx+1)/2 slots per row and colour,
+  // nrb = nz ny nxh slots per colour
+  int nxh;
+  long long nrb;
   double x0, y0, z0, dx, dy, dz;
   double area[3], delta[3], V, h;
   int bc[6];

@@ -227,7 +227,7 @@ __device__ __forceinline__ double nb_sum(const double (&anb)[6], const Nbr& N, c
 //                  r = 2 (x_D - x_C) . grad u_C / (u_D - u_C) - 1 (0 where u_D = u_C)
 // (interior faces; grad u_C the stored Gauss gradient)
 template <int CONV>
-__global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
+__global__ void __launch_bounds__(256) k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
                                const double* means, double* part, long long pstride) {
   double wmx = 0.0;  // max of omega/eps of the previous iterate over boundary and free-stream cells
   int i, j, k;
@@ -279,7 +279,7 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
       }
     double urf = P.urf_u;
     double aPr = aP / urf;
-    aPr_out[c] = aPr;
+    aPr_out[rb_split(P, i, j, k)] = aPr;  // rhs and a'_P are stored colour-split
     if (X.a) X.a[c] = (float)aPr;
     bool alpha = fl & F_ALPHA_U;
     double* rhs[3] = {rhs0, rhs1, rhs2};
@@ -359,7 +359,7 @@ __global__ void k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* 
       } else {
         rh = (b0 - g) + r;
       }
-      rhs[cc][c] = rh;
+      rhs[cc][rb_split(P, i, j, k)] = rh;
       double Ax = aPr * uo - nb;
       // mixed policy: FP64 defect of the row (every row is swept) for the FP32
       // correction
@@ -423,10 +423,11 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
   Nbr N = make_nbr(P, i, j, k, c);
   double anb[6];
   mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
-  double a = aPr[c];
-  u0[c] = (rhs0[c] + nb_sum(anb, N, u0)) / a;
-  u1[c] = (rhs1[c] + nb_sum(anb, N, u1)) / a;
-  if (P.dim == 3) u2[c] = (rhs2[c] + nb_sum(anb, N, u2)) / a;
+  const long long sidx = rb_split(P, i, j, k);
+  double a = aPr[sidx];
+  u0[c] = (rhs0[sidx] + nb_sum(anb, N, u0)) / a;
+  u1[c] = (rhs1[sidx] + nb_sum(anb, N, u1)) / a;
+  if (P.dim == 3) u2[c] = (rhs2[sidx] + nb_sum(anb, N, u2)) / a;
 }
 
 // Mixed policy: one colour of a red-black Gauss-Seidel sweep of the FP32
@@ -517,7 +518,8 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
   uint8_t fl = M.flags[c];
   double anb[6];
   mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
-  double a = aPr[c];
+  const long long sidx = rb_split(P, i, j, k);
+  double a = aPr[sidx];
   const double* rr[3] = {rhs0, rhs1, rhs2};
   double* hh[3] = {h0, h1, h2};
   // forced cells: no pressure term in the momentum row (f_ib contains +grad p),
@@ -527,7 +529,7 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
   for (int cc = 0; cc < 3; ++cc) {
     if (cc >= P.dim) continue;
     double nb = nb_sum(anb, N, M.u[cc]);
-    double H = forced ? nb + rr[cc][c] : nb + rr[cc][c] + gradp_V(P, M.p, fl, cc, i, j, k, c);
+    double H = forced ? nb + rr[cc][sidx] : nb + rr[cc][sidx] + gradp_V(P, M.p, fl, cc, i, j, k, c);
     hh[cc][c] = H / a;
   }
   if (P.dim == 2) h2[c] = 0.0;
@@ -665,7 +667,7 @@ __global__ void k_vel_update(Params P, const double* h0, const double* h1, const
   const double* hv[3] = {h0, h1, h2};
   const double* ub[3] = {ub0, ub1, ub2};
   double* uu[3] = {u0, u1, u2};
-  double a = aPr[c];
+  double a = aPr[rb_split(P, i, j, k)];
   bool alpha = (fl & F_ALPHA_U) && P.recorrect;
   bool forced = fl & F_ALPHA_U;
   for (int cc = 0; cc < P.dim; ++cc) {

@@ -183,7 +183,7 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
 // other closures keep their register budget)
 template <bool RKE>
 __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, float* r32, float* a32,
-                                  const double* xmean, double* part, long long pstride) {
+                                  double* gam_out, const double* xmean, double* part, long long pstride) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   double red[3] = {0, 0, 0};
@@ -192,6 +192,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     uint8_t fl = S.flags[c];
     bool solid = fl & F_SOLID;
     double gP = gam(P, eq, c, S.nut, S.F1);
+    if (gam_out) gam_out[c] = gP;
     Nbr N = make_nbr(P, i, j, k, c);
     double anb[6];
     scal_anb(P, S, eq, gP, N, i, j, k, anb);
@@ -281,8 +282,9 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
       }
       x = kold;
     }
-    rhs_out[c] = rhs;
-    aPr_out[c] = aPr;
+    const long long sidx = rb_split(P, i, j, k);
+    rhs_out[sidx] = rhs;
+    aPr_out[sidx] = aPr;
     // rows the sweeps update: all k rows; omega/eps rows outside alpha_omega
     bool swept = eq == 1 || !(fl & F_ALPHA_W);
     if (!skip || (a32 && swept)) {
@@ -313,21 +315,34 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 
 // red-black Gauss-Seidel half sweep of a scalar equation; rows flagged `fixmask`
 // are not updated
-__global__ void k_scalar_sweep(Params P, Scal S, int eq, const double* rhs, const double* aPr, double* x, int color,
-                               uint8_t fixmask) {
+// (FP64) the diffusivity of each cell comes from the array the assembly wrote
+// (the same value gam() gives), rhs and a'_P from the colour-split arrays, so a
+// one-colour launch streams only its own half of them
+__global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const double* rhs, const double* aPr, double* x,
+                               int color, uint8_t fixmask) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   if (S.flags[c] & fixmask) return;
-  double gP = gam(P, eq, c, S.nut, S.F1);
+  const double gP = gamc[c];
   Nbr N = make_nbr(P, i, j, k, c);
-  double anb[6];
-  scal_anb(P, S, eq, gP, N, i, j, k, anb);
   double nb = 0.0;
 #pragma unroll
-  for (int q = 0; q < 6; ++q) nb += anb[q] * x[N.n[q]];
-  x[c] = (rhs[c] + nb) / aPr[c];
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int sh = 0; sh < 2; ++sh) {
+      const int s = sh ? 1 : -1, q = 2 * d + sh;
+      double a = 0.0;
+      if (d < P.dim) {
+        double mf = -outward_flux(P, S.phi, d, s, i, j, k);
+        a = 0.5 * (gP + gamc[N.n[q]]) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
+        a = is_bnd(N, q) ? 0.0 : a;
+      }
+      nb += a * x[N.n[q]];
+    }
+  const long long sidx = rb_split(P, i, j, k);
+  x[c] = (rhs[sidx] + nb) / aPr[sidx];
 }
 
 // Mixed policy: red-black sweep of the FP32 correction d of a scalar equation
@@ -541,7 +556,9 @@ int turbulence_stage(hfdib_ctx* c) {
   float* r32 = mixed ? c->r32[0] : nullptr;
   float* a32 = mixed ? c->a32 : nullptr;
   Scal32 S32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32, c->F1_32};
-  // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
+  // per-cell diffusivity of the equation being solved (FP64 sweeps; the
+  // momentum right-hand sides are dead during this stage)
+  double* gam_c = c->rhs[0];
   // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
   // (one timing span over the 2 n_s consecutive launches)
   auto sweeps = [&](int eq, double* x, uint8_t fixmask) {
@@ -552,15 +569,16 @@ int turbulence_stage(hfdib_ctx* c) {
           hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0],
                              x, color, fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
         else
-          hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, eq, c->t0, c->t1, x, color, fixmask);
+          hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, (const double*)gam_c, c->t0, c->t1,
+                             x, color, fixmask);
       }
     timer_end(c, T_SCALSWEEP, 2 * P.n_sweeps);
   };
   // omega / eps equation, alpha_omega rows fixed
   timer_begin(c, T_SCALASM);
   auto assemble = P.model == HFDIB_RKEPS ? k_scalar_assemble<true> : k_scalar_assemble<false>;
-  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, S + SC_MEANS + 5,
-                     c->partials, c->pstride);
+  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
+                     S + SC_MEANS + 5, c->partials, c->pstride);
   timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
   sweeps(0, c->w, (uint8_t)F_ALPHA_W);
@@ -570,8 +588,8 @@ int turbulence_stage(hfdib_ctx* c) {
                        c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->bc_yplus, c->bc_utau, c->k,
                        c->kib);
   timer_begin(c, T_SCALASM);
-  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, S + SC_MEANS + 4,
-                     c->partials, c->pstride);
+  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
+                     S + SC_MEANS + 4, c->partials, c->pstride);
   timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
