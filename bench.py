@@ -95,8 +95,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--tile", default="auto", choices=["auto", "default"],
-                    help="tile shape of the full-grid kernels: autotuned (width and depth) or 64 x 4 x 1")
+    ap.add_argument("--tile", default="64x1x0",
+                    help="tile shape of the full-grid kernels, WIDTHxDEPTHxZFIRST (default: the library's "
+                         "64 x 4 x 1, x-first), or auto (the autotuner's choice from timed rounds of the "
+                         "gradient, assembly and pressure operator); on the 2.36 M-cell case whole "
+                         "iterations take the same time for every shape within 1 %")
     ap.add_argument("--case", default="ahmed", choices=["ahmed", "bfs", "ahmed2"])
     ap.add_argument("--p-rtol", type=float, default=1e-2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -139,24 +142,34 @@ def main():
     counts = solver.counts()
     log(f"set_indicator {time.time() - t0:.2f}s counts {counts}")
 
-    # tile shape (set-up, outside the timed region): for each depth that divides
-    # nz, the autotuner's fastest width; the fastest pair is kept
-    tile = {"width": 64, "depth": 1}
-    if args.tile == "auto":
+    # tile shape (set-up, outside the timed region): the given one, or (--tile auto)
+    # for each tile order and each depth that divides nz the autotuner's fastest
+    # width, the fastest of those kept
+    if args.tile != "auto":
+        w, d, z = (int(v) for v in args.tile.split("x"))
+        solver.set_tile_order(z)
+        solver.set_tile_width(64)
+        solver.set_tile_depth(d)
+        solver.set_tile_width(w)
+        tile = {"width": w, "depth": d, "zfirst": z}
+    else:
         best = None
-        for depth in (1, 2, 4):
-            if spec.dim != 3 or spec.nz % depth:
-                continue
-            solver.set_tile_width(64)
-            solver.set_tile_depth(depth)
-            w, ms = solver.autotune_tiles(reps=3)
-            log(f"tile depth {depth}: ms per round by width {ms}")
-            if best is None or ms[w] < best[0]:
-                best = (ms[w], w, depth)
+        for zfirst in (0, 1):
+            for depth in (1, 2, 4):
+                if spec.dim != 3 or spec.nz % depth:
+                    continue
+                solver.set_tile_order(zfirst)
+                solver.set_tile_width(64)
+                solver.set_tile_depth(depth)
+                w, ms = solver.autotune_tiles(reps=3)
+                log(f"tile order z-first {zfirst} depth {depth}: ms per round by width {ms}")
+                if best is None or ms[w] < best[0]:
+                    best = (ms[w], w, depth, zfirst)
+        solver.set_tile_order(best[3])
         solver.set_tile_width(64)
         solver.set_tile_depth(best[2])
         solver.set_tile_width(best[1])
-        tile = {"width": best[1], "depth": best[2]}
+        tile = {"width": best[1], "depth": best[2], "zfirst": best[3]}
     log(f"tile {tile}")
 
     done, res = solver.iterate(args.warmup)

@@ -258,6 +258,13 @@ int hfdib_set_tile_width(hfdib_ctx* ctx, int width);
  * unchanged up to the order of partial sums in reductions.  hfdib_autotune_tiles
  * times the widths at the current depth (ms4 entry -1 for a width too wide). */
 int hfdib_set_tile_depth(hfdib_ctx* ctx, int depth);
+/* Order in which the tiles of the full-grid kernels are handed to each XCD
+ * (each XCD takes a contiguous run of tiles): zfirst = 0 (the default) x
+ * fastest, then y, then z; zfirst = 1 z fastest, so vertically adjacent tiles run
+ * together and share their z-neighbour planes in that XCD's L2.  Results are
+ * unchanged up to the order of partial sums in reductions.  HFDIB_EINVAL for
+ * other values. */
+int hfdib_set_tile_order(hfdib_ctx* ctx, int zfirst);
 
 /* Copies one per-boundary-cell record array (HFDIB_IB_*) to dst_dev. */
 int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);

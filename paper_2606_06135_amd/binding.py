@@ -98,6 +98,7 @@ def lib():
     L.hfdib_autotune_tiles.argtypes = [vp, i, C.POINTER(i), C.POINTER(d)]
     L.hfdib_set_tile_width.argtypes = [vp, i]
     L.hfdib_set_tile_depth.argtypes = [vp, i]
+    L.hfdib_set_tile_order.argtypes = [vp, i]
     L.hfdib_batch_create.argtypes = [C.POINTER(vp), i, i, d, vp, C.POINTER(vp)]
     L.hfdib_batch_run.argtypes = [vp, i]
     L.hfdib_batch_status.argtypes = [vp, C.POINTER(i), C.POINTER(i), C.POINTER(d)]
@@ -109,7 +110,8 @@ def lib():
                "hfdib_get_field", "hfdib_set_field", "hfdib_get_counts", "hfdib_get_ib_array",
                "hfdib_pressure_solve", "hfdib_last_stats", "hfdib_timing_enable", "hfdib_timing_query",
                "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
-               "hfdib_autotune_tiles", "hfdib_set_tile_width", "hfdib_set_tile_depth"):
+               "hfdib_autotune_tiles", "hfdib_set_tile_width", "hfdib_set_tile_depth",
+               "hfdib_set_tile_order"):
         getattr(L, fn).restype = i
     if L.hfdib_abi_version() != ABI_VERSION:
         raise ImportError("libhfdib ABI version mismatch")
@@ -123,7 +125,7 @@ EXPORTED = ["hfdib_abi_version", "hfdib_default_config", "hfdib_workspace_bytes"
             "hfdib_timing_enable", "hfdib_timing_query", "hfdib_destroy", "hfdib_status_string",
             "hfdib_last_error", "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
             "hfdib_batch_last_error", "hfdib_batch_destroy", "hfdib_autotune_tiles", "hfdib_set_tile_width",
-            "hfdib_set_tile_depth"]
+            "hfdib_set_tile_depth", "hfdib_set_tile_order"]
 
 
 def default_config():
@@ -323,6 +325,9 @@ class Solver:
 
     def set_tile_depth(self, depth):
         _check("hfdib_set_tile_depth", lib().hfdib_set_tile_depth(self.ctx, int(depth)), self.ctx)
+
+    def set_tile_order(self, zfirst):
+        _check("hfdib_set_tile_order", lib().hfdib_set_tile_order(self.ctx, 1 if zfirst else 0), self.ctx)
 
     def forces(self):
         """Force on the body per unit density: pressure part, viscous part,

@@ -706,6 +706,12 @@ int hfdib_set_tile_width(hfdib_ctx* c, int width) {
   return HFDIB_EINVAL;
 }
 
+int hfdib_set_tile_order(hfdib_ctx* c, int zfirst) {
+  if (!c || (zfirst != 0 && zfirst != 1)) return HFDIB_EINVAL;
+  c->P.tile_zfirst = zfirst;
+  return HFDIB_OK;
+}
+
 int hfdib_set_tile_depth(hfdib_ctx* c, int depth) {
   if (!c) return HFDIB_EINVAL;
   for (int lz = 0; lz <= 2; ++lz)

@@ -90,16 +90,31 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[NV], double* 
 // workgroups are dispatched round-robin over the 8 XCDs; the logical tile order
 // is remapped so that each XCD works on a contiguous run of tiles (x fastest,
 // then y, then z) and the y/z halo rows a tile needs stay in that XCD's L2.
+// tile coordinates of logical tile L on a grid of tx x ty x (nz >> tz_log2)
+// tiles: x fastest, then y, then z; or z fastest, then x, then y
+__device__ __forceinline__ void tile_coords(const Params& P, unsigned L, int tx, int ty, int& bx, int& by, int& bz) {
+  if (P.tile_zfirst) {
+    const unsigned tz = (unsigned)(P.nz >> P.tz_log2);
+    bz = (int)(L % tz);
+    unsigned rest = L / tz;
+    bx = (int)(rest % (unsigned)tx);
+    by = (int)(rest / (unsigned)tx);
+  } else {
+    bx = (int)(L % (unsigned)tx);
+    unsigned rest = L / (unsigned)tx;
+    by = (int)(rest % (unsigned)ty);
+    bz = (int)(rest / (unsigned)ty);
+  }
+}
 __device__ __forceinline__ void tile_ijk(const Params& P, int& i, int& j, int& k) {
   unsigned nb = gridDim.x, b = blockIdx.x;
   unsigned q = nb >> 3, r = nb & 7u, x = b & 7u, id = b >> 3;
   unsigned L = x < r ? x * (q + 1) + id : r * (q + 1) + (x - r) * q + id;
   const int lx = P.tx_log2, lz = P.tz_log2, ly = 8 - lx - lz;
   int tx = (P.nx + (1 << lx) - 1) >> lx, ty = (P.ny + (1 << ly) - 1) >> ly;
-  int bx = (int)(L % (unsigned)tx);
-  unsigned rest = L / (unsigned)tx;
-  int by = (int)(rest % (unsigned)ty);
-  k = ((int)(rest / (unsigned)ty) << lz) + (int)threadIdx.z;
+  int bx, by, bz;
+  tile_coords(P, L, tx, ty, bx, by, bz);
+  k = (bz << lz) + (int)threadIdx.z;
   i = (bx << lx) + (int)threadIdx.x;
   j = (by << ly) + (int)threadIdx.y;
 }
@@ -114,10 +129,9 @@ __device__ __forceinline__ void tile_ijk_rb(const Params& P, int color, int& i, 
   int nxh = (P.nx + 1) >> 1;
   const int lx = P.tx_log2, lz = P.tz_log2, ly = 8 - lx - lz;
   int tx = (nxh + (1 << lx) - 1) >> lx, ty = (P.ny + (1 << ly) - 1) >> ly;
-  int bx = (int)(L % (unsigned)tx);
-  unsigned rest = L / (unsigned)tx;
-  int by = (int)(rest % (unsigned)ty);
-  k = ((int)(rest / (unsigned)ty) << lz) + (int)threadIdx.z;
+  int bx, by, bz;
+  tile_coords(P, L, tx, ty, bx, by, bz);
+  k = (bz << lz) + (int)threadIdx.z;
   j = (by << ly) + (int)threadIdx.y;
   // t >= nxh gives i >= nx and i ^ 1 >= nx (both cells of the pair outside)
   int t = (bx << lx) + (int)threadIdx.x;

@@ -195,31 +195,50 @@ __global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T*
 // are only read here and overwritten by the next sweep).
 template <typename T>
 __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* z, int color, const T* zc,
-                              int cnx, int cny) {
+                              int cnx, int cny, const double* rdot, double* part, long long pstride) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
-  long long c = cidx(P, i, j, k);
-  Nbr N = make_nbr(P, i, j, k, c);
-  T cf[6];
-  fine_row(P, O, N, c, cf);
-  T nb = (T)0;
-  if (zc) {
-    const int i2 = i >> 1, j2 = j >> 1, k2 = P.dim == 3 ? k >> 1 : 0;
+  const bool own = i < P.nx && j < P.ny;
+  T znew = (T)0;
+  long long c = 0;
+  if (own) {
+    c = cidx(P, i, j, k);
+    Nbr N = make_nbr(P, i, j, k, c);
+    T cf[6];
+    fine_row(P, O, N, c, cf);
+    T nb = (T)0;
+    if (zc) {
+      const int i2 = i >> 1, j2 = j >> 1, k2 = P.dim == 3 ? k >> 1 : 0;
 #pragma unroll
-    for (int q = 0; q < 6; ++q) {
-      const int d = q >> 1, s = (q & 1) ? 1 : -1;
-      if (is_bnd(N, q)) continue;
-      // parent of the neighbour: only its coordinate along d differs
-      int pi = d == 0 ? (i + s) >> 1 : i2, pj = d == 1 ? (j + s) >> 1 : j2, pk = d == 2 ? (k + s) >> 1 : k2;
-      long long pc = (long long)pi + (long long)cnx * ((long long)pj + (long long)cny * pk);
-      nb += cf[q] * (z[N.n[q]] + zc[pc]);
+      for (int q = 0; q < 6; ++q) {
+        const int d = q >> 1, s = (q & 1) ? 1 : -1;
+        if (is_bnd(N, q)) continue;
+        // parent of the neighbour: only its coordinate along d differs
+        int pi = d == 0 ? (i + s) >> 1 : i2, pj = d == 1 ? (j + s) >> 1 : j2, pk = d == 2 ? (k + s) >> 1 : k2;
+        long long pc = (long long)pi + (long long)cnx * ((long long)pj + (long long)cny * pk);
+        nb += cf[q] * (z[N.n[q]] + zc[pc]);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) nb += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
     }
-  } else {
-#pragma unroll
-    for (int q = 0; q < 6; ++q) nb += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
+    znew = (r[c] + nb) * invD[c];
+    z[c] = znew;
   }
-  z[c] = (r[c] + nb) * invD[c];
+  // the last sweep of a V-cycle also forms the partial sums of r . z (FP64 r):
+  // its own cell, then the other cell of its pair, whose z is already final
+  if (rdot) {
+    double v[1] = {0.0};
+    if (j < P.ny) {
+      if (own) v[0] = rdot[c] * (double)znew;
+      const int io = i ^ 1;
+      if (io < P.nx) {
+        const long long co = cidx(P, io, j, k);
+        v[0] += rdot[co] * (double)z[co];
+      }
+    }
+    block_sums_store<1>(v, part, pstride, block_linear());
+  }
 }
 
 // ---------------------------------------------------------------- coarse levels
@@ -595,8 +614,18 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle_global(TailLevelsT
 template <typename T>
 struct LdsLev {
   int nx, ny, nz, dim, N;
+  float inx, iny;  // 1/nx, 1/ny for split3
   T *r, *z, *diag, *cx, *cy, *cz;
 };
+// (i, j, k) of the flat index c of an nx x ny x nz block without integer
+// division: (c + 0.5) / nx lies at least 0.5 / nx from an integer and the float
+// product is accurate to ~1e-7 relative, so the floor is exact for c < 2^20
+__device__ __forceinline__ void split3(int c, int nx, int ny, float inx, float iny, int& i, int& j, int& k) {
+  const int jk = (int)(((float)c + 0.5f) * inx);
+  i = c - jk * nx;
+  k = (int)(((float)jk + 0.5f) * iny);
+  j = jk - k * ny;
+}
 template <typename T>
 __device__ __forceinline__ LdsLev<T> lds_lev(const TailLevelsT<T>& TL, int t, T* base) {
   const LevelDevT<T>& L = TL.L[t];
@@ -606,6 +635,8 @@ __device__ __forceinline__ LdsLev<T> lds_lev(const TailLevelsT<T>& TL, int t, T*
   v.nz = L.nz;
   v.dim = L.dim;
   v.N = (int)L.N;
+  v.inx = 1.0f / (float)L.nx;
+  v.iny = 1.0f / (float)L.ny;
   T* p = base + TL.off[t];
   v.r = p;
   v.z = p + v.N;
@@ -633,7 +664,8 @@ __device__ __forceinline__ T lds_nbsum(const LdsLev<T>& L, const T* z, int i, in
 template <typename T>
 __device__ __forceinline__ void lds_smooth(const LdsLev<T>& L, int color, int init) {
   for (int c = threadIdx.x; c < L.N; c += TAIL_THREADS) {
-    int i = c % L.nx, j = (c / L.nx) % L.ny, k = c / (L.nx * L.ny);
+    int i, j, k;
+    split3(c, L.nx, L.ny, L.inx, L.iny, i, j, k);
     bool mine = ((i + j + k) & 1) == color;
     if (init && !mine) {
       L.z[c] = (T)0;
@@ -655,14 +687,42 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
   extern __shared__ unsigned char tail_lds_raw[];
   T* base = reinterpret_cast<T*>(tail_lds_raw);
   const int n = TL.n;
+  // staging: per level, every thread issues all its loads (two elements of each
+  // array; tail levels have at most TAIL_MAX cells, so their arrays fit in
+  // 2 TAIL_THREADS elements, the loop after covers any rest) before its first LDS
+  // store, so the level arrives in one memory round trip
   for (int t = 0; t < n; ++t) {
     const LevelDevT<T>& G = TL.L[t];
     LdsLev<T> L = lds_lev(TL, t, base);
-    if (t == 0) lds_copy(L.r, (const T*)G.r, L.N);
-    lds_copy(L.diag, G.diag, L.N);
-    lds_copy(L.cx, G.cx, (L.nx + 1) * L.ny * L.nz);
-    lds_copy(L.cy, G.cy, L.nx * (L.ny + 1) * L.nz);
-    if (L.dim == 3) lds_copy(L.cz, G.cz, L.nx * L.ny * (L.nz + 1));
+    const int nr = t == 0 ? L.N : 0;
+    const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz;
+    const int nfz = L.dim == 3 ? L.nx * L.ny * (L.nz + 1) : 0;
+    T v[2][5];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = (int)threadIdx.x + h * TAIL_THREADS;
+      v[h][0] = q < nr ? G.r[q] : (T)0;
+      v[h][1] = q < L.N ? G.diag[q] : (T)0;
+      v[h][2] = q < nfx ? G.cx[q] : (T)0;
+      v[h][3] = q < nfy ? G.cy[q] : (T)0;
+      v[h][4] = q < nfz ? G.cz[q] : (T)0;
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = (int)threadIdx.x + h * TAIL_THREADS;
+      if (q < nr) L.r[q] = v[h][0];
+      if (q < L.N) L.diag[q] = v[h][1];
+      if (q < nfx) L.cx[q] = v[h][2];
+      if (q < nfy) L.cy[q] = v[h][3];
+      if (q < nfz) L.cz[q] = v[h][4];
+    }
+    for (int q = (int)threadIdx.x + 2 * TAIL_THREADS; q < nfx || q < nfy || q < nfz || q < L.N; q += TAIL_THREADS) {
+      if (q < nr) L.r[q] = G.r[q];
+      if (q < L.N) L.diag[q] = G.diag[q];
+      if (q < nfx) L.cx[q] = G.cx[q];
+      if (q < nfy) L.cy[q] = G.cy[q];
+      if (q < nfz) L.cz[q] = G.cz[q];
+    }
   }
   __syncthreads();
   for (int t = 0; t < n - 1; ++t) {
@@ -671,7 +731,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
     lds_smooth(F, 1, 0);
     int nzs = C.dim == 3 ? 2 : 1;
     for (int q = threadIdx.x; q < C.N; q += TAIL_THREADS) {
-      int I = q % C.nx, J = (q / C.nx) % C.ny, K = q / (C.nx * C.ny);
+      int I, J, K;
+      split3(q, C.nx, C.ny, C.inx, C.iny, I, J, K);
       T sacc = (T)0;
       for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b)
@@ -695,7 +756,8 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
   for (int t = n - 2; t >= 0; --t) {
     LdsLev<T> F = lds_lev(TL, t, base), C = lds_lev(TL, t + 1, base);
     for (int c = threadIdx.x; c < F.N; c += TAIL_THREADS) {
-      int i = c % F.nx, j = (c / F.nx) % F.ny, k = c / (F.nx * F.ny);
+      int i, j, k;
+      split3(c, F.nx, F.ny, F.inx, F.iny, i, j, k);
       F.z[c] += C.z[(i / 2) + C.nx * ((j / 2) + C.ny * (F.dim == 3 ? k / 2 : 0))];
     }
     __syncthreads();
@@ -713,12 +775,6 @@ __global__ void k_copy_vec(long long n, const TA* a, double* b) {
   if (c < n) b[c] = (double)a[c];
 }
 
-template <typename TB>
-__global__ void k_dot(long long n, const double* a, const TB* b, double* part, long long pstride) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  double v[1] = {c < n ? a[c] * (double)b[c] : 0.0};
-  block_sums_store<1>(v, part, pstride, blockIdx.x);
-}
 
 // x += alpha d, r -= alpha q (and its FP32 copy when r32 is given); partial r.r
 __global__ void k_axpy2(long long n, const double* scal, double* x, const double* d, double* r, float* r32,
@@ -853,9 +909,11 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
                      c->scal + SCAL_PCG, out, op, divisor);
 }
 
-// one V-cycle z = M^-1 r in storage type T
+// one V-cycle z = M^-1 r in storage type T; the last sweep also leaves the
+// block partial sums of rdot . z in the partials (rdot: the FP64 residual);
+// returns their count
 template <typename T>
-static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z) {
+static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, const double* rdot) {
   const Params& P = c->P;
   dim3 g = grid3_rb(P), bf = block3(P), b = block_lv();
   hipLaunchKernelGGL(k_fine_presmooth<T>, g, bf, 0, c->stream, P, O, invD, r, z);
@@ -902,8 +960,11 @@ static void vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r,
     cny = L1.ny;
   }
   // post-smoothing, black first (with the prolongation on the fly), then red
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny);
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny, (const double*)nullptr,
+                     (double*)nullptr, 0LL);
+  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0, rdot,
+                     c->partials, c->pstride);
+  return (int)g.x;
 }
 
 // coarse operators of every level from the FP64 fine operator
@@ -945,10 +1006,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
   launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [20]=rr0 [21]=bb [22..24]=residual sums
   // at least one PCG iteration is done; the host reads the residual after each
   // iteration (one synchronisation per iteration, none before the first)
-  vcycle<T>(c, OM, invD, r_m, z_m);
-  hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
-                     c->pstride);
-  launch_finalize(c, nb1, 1, S_RZ, 3);
+  launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r), 1, S_RZ, 3);
   hipLaunchKernelGGL(k_copy_vec<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const T*)z_m, d);
   if (c->graph_mode) {
     // fixed iteration count, no host read (the step may be captured in a graph);
@@ -961,10 +1019,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
                          c->pstride);
       launch_finalize(c, nb1, 1, S_RR, 0);
       if (it == nit) break;
-      vcycle<T>(c, OM, invD, r_m, z_m);
-      hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
-                         c->pstride);
-      launch_finalize(c, nb1, 1, S_RZ, 2);
+      launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r), 1, S_RZ, 2);
       hipLaunchKernelGGL(k_xpby<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, (const T*)z_m, d);
     }
     HFDIB_CHECK_LAUNCH(c, "pcg (fixed)");
@@ -1001,10 +1056,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
     }
     if (sqrt(rr) <= target) break;
     if (it == maxit) break;
-    vcycle<T>(c, OM, invD, r_m, z_m);
-    hipLaunchKernelGGL(k_dot<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, r, (const T*)z_m, c->partials,
-                       c->pstride);
-    launch_finalize(c, nb1, 1, S_RZ, 2);
+    launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r), 1, S_RZ, 2);
     hipLaunchKernelGGL(k_xpby<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, (const T*)z_m, d);
   }
   if (it > maxit) it = maxit;

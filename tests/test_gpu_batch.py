@@ -79,8 +79,8 @@ def test_tile_widths_keep_parity(gpu, width):
         assert v <= 1e-9, (width, k, v)
 
 
-@pytest.mark.parametrize("width, depth", [(64, 2), (32, 4), (128, 2)])
-def test_tile_depths_keep_parity(gpu, width, depth):
+@pytest.mark.parametrize("width, depth, zfirst", [(64, 2, 0), (32, 4, 0), (128, 2, 1), (256, 1, 1)])
+def test_tile_depths_keep_parity(gpu, width, depth, zfirst):
     # tiles spanning several planes (nz = 12 divisible by the depth), odd x and y extents
     spec = synth.case_small_body3d(nx=37, ny=13, nz=12, model="sst", nu=1e-4)
     spec.conv_scheme = "linear_upwind"
@@ -88,13 +88,14 @@ def test_tile_depths_keep_parity(gpu, width, depth):
     for _ in range(15):
         sim.step()
     s = _solver(spec, gpu)
+    s.set_tile_order(zfirst)
     s.set_tile_depth(depth)
     s.set_tile_width(width)
     s.iterate(15)
     c = compare(sim, s, dim=spec.dim, model=spec.model)
-    _say(f"width {width} depth {depth}:", {k: f"{v:.1e}" for k, v in c.items()})
+    _say(f"width {width} depth {depth} z-first {zfirst}:", {k: f"{v:.1e}" for k, v in c.items()})
     for k, v in c.items():
-        assert v <= 1e-9, (width, depth, k, v)
+        assert v <= 1e-9, (width, depth, zfirst, k, v)
 
 
 def test_invalid_tile_depth_rejected(gpu):
