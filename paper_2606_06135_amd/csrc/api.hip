@@ -244,6 +244,10 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "grid too small (>= 4 cells per active axis; nz = 1 in 2D)";
     return HFDIB_EINVAL;
   }
+  if ((long long)d->nx * d->ny * d->nz >= (1LL << 31)) {
+    *why = "grid too large (at most 2^31 - 1 cells)";
+    return HFDIB_EINVAL;
+  }
   if (!(d->dx > 0.0 && d->dy > 0.0 && d->dz > 0.0)) {
     *why = "cell sizes must be positive";
     return HFDIB_EINVAL;

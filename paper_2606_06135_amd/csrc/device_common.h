@@ -91,20 +91,22 @@ __device__ __forceinline__ void block_sums_store(const double (&v)[NV], double* 
 // is remapped so that each XCD works on a contiguous run of tiles (x fastest,
 // then y, then z) and the y/z halo rows a tile needs stay in that XCD's L2.
 // tile coordinates of logical tile L on a grid of tx x ty x (nz >> tz_log2)
-// tiles: x fastest, then y, then z; or z fastest, then x, then y
-__device__ __forceinline__ void tile_coords(const Params& P, unsigned L, int tx, int ty, int& bx, int& by, int& bz) {
-  if (P.tile_zfirst) {
-    const unsigned tz = (unsigned)(P.nz >> P.tz_log2);
-    bz = (int)(L % tz);
-    unsigned rest = L / tz;
-    bx = (int)(rest % (unsigned)tx);
-    by = (int)(rest / (unsigned)tx);
-  } else {
-    bx = (int)(L % (unsigned)tx);
-    unsigned rest = L / (unsigned)tx;
-    by = (int)(rest % (unsigned)ty);
-    bz = (int)(rest / (unsigned)ty);
-  }
+// tiles: x fastest, then y, then z; or z fastest, then x, then y.  Written with
+// selects on the (uniform) order flag so the three results stay in registers.
+struct TileXYZ {
+  int x, y, z;
+};
+__device__ __forceinline__ TileXYZ tile_coords(const Params& P, unsigned L, int tx, int ty) {
+  const bool zf = P.tile_zfirst != 0;
+  const unsigned m0 = zf ? (unsigned)(P.nz >> P.tz_log2) : (unsigned)tx;
+  const unsigned m1 = zf ? (unsigned)tx : (unsigned)ty;
+  const unsigned a = L % m0, rest = L / m0;
+  const unsigned b = rest % m1, c = rest / m1;
+  TileXYZ t;
+  t.x = (int)(zf ? b : a);
+  t.y = (int)(zf ? c : b);
+  t.z = (int)(zf ? a : c);
+  return t;
 }
 __device__ __forceinline__ void tile_ijk(const Params& P, int& i, int& j, int& k) {
   unsigned nb = gridDim.x, b = blockIdx.x;
@@ -112,11 +114,10 @@ __device__ __forceinline__ void tile_ijk(const Params& P, int& i, int& j, int& k
   unsigned L = x < r ? x * (q + 1) + id : r * (q + 1) + (x - r) * q + id;
   const int lx = P.tx_log2, lz = P.tz_log2, ly = 8 - lx - lz;
   int tx = (P.nx + (1 << lx) - 1) >> lx, ty = (P.ny + (1 << ly) - 1) >> ly;
-  int bx, by, bz;
-  tile_coords(P, L, tx, ty, bx, by, bz);
-  k = (bz << lz) + (int)threadIdx.z;
-  i = (bx << lx) + (int)threadIdx.x;
-  j = (by << ly) + (int)threadIdx.y;
+  const TileXYZ t = tile_coords(P, L, tx, ty);
+  k = (t.z << lz) + (int)threadIdx.z;
+  i = (t.x << lx) + (int)threadIdx.x;
+  j = (t.y << ly) + (int)threadIdx.y;
 }
 
 // Red-black half sweeps run on a grid of half the x extent: thread t of a row
@@ -129,13 +130,12 @@ __device__ __forceinline__ void tile_ijk_rb(const Params& P, int color, int& i, 
   int nxh = (P.nx + 1) >> 1;
   const int lx = P.tx_log2, lz = P.tz_log2, ly = 8 - lx - lz;
   int tx = (nxh + (1 << lx) - 1) >> lx, ty = (P.ny + (1 << ly) - 1) >> ly;
-  int bx, by, bz;
-  tile_coords(P, L, tx, ty, bx, by, bz);
-  k = (bz << lz) + (int)threadIdx.z;
-  j = (by << ly) + (int)threadIdx.y;
+  const TileXYZ t = tile_coords(P, L, tx, ty);
+  k = (t.z << lz) + (int)threadIdx.z;
+  j = (t.y << ly) + (int)threadIdx.y;
   // t >= nxh gives i >= nx and i ^ 1 >= nx (both cells of the pair outside)
-  int t = (bx << lx) + (int)threadIdx.x;
-  i = 2 * t + ((j + k + color) & 1);
+  int tp = (t.x << lx) + (int)threadIdx.x;
+  i = 2 * tp + ((j + k + color) & 1);
 }
 
 __device__ __forceinline__ long long block_linear() {
@@ -205,7 +205,7 @@ __device__ __forceinline__ double strain2(const double (&G)[3][3]) {
 // q = 2 d + (s > 0) in the order W, E, S, N, B, T; faces beyond dim count as
 // domain faces.
 struct Nbr {
-  long long n[6];
+  int n[6];      // neighbour cell indices (grids hold fewer than 2^31 cells; 32-bit to save registers)
   unsigned bnd;  // bit q: face q is a domain face
 };
 __device__ __forceinline__ Nbr make_nbr(const Params& P, int i, int j, int k, long long c) {
@@ -216,8 +216,8 @@ __device__ __forceinline__ Nbr make_nbr(const Params& P, int i, int j, int k, lo
     long long st = stride(P, d);
     int a = comp(d, i, j, k);
     bool lo = d >= P.dim || a == 0, hi = d >= P.dim || a == ncell(P, d) - 1;
-    N.n[2 * d] = lo ? c : c - st;
-    N.n[2 * d + 1] = hi ? c : c + st;
+    N.n[2 * d] = (int)(lo ? c : c - st);
+    N.n[2 * d + 1] = (int)(hi ? c : c + st);
     N.bnd |= (lo ? 1u : 0u) << (2 * d);
     N.bnd |= (hi ? 1u : 0u) << (2 * d + 1);
   }
