@@ -209,16 +209,18 @@ static size_t layout(hfdib_ctx* c, char* base) {
   }
   // FP32 arrays of the mixed policy
   for (int q = 0; q < 3; ++q) c->r32[q] = c->d32[q] = c->phi32[q] = nullptr;
-  c->a32 = c->nut32 = c->F1_32 = c->rAU32 = c->pr32 = c->pz32 = c->invD32 = nullptr;
+  c->a32 = c->nut32 = c->rAU32 = c->pr32 = c->pz32 = c->invD32 = c->gam32 = nullptr;
   if (mixed) {
-    for (int q = 0; q < 3; ++q) c->r32[q] = B.take<float>(N);
+    // FP32 defects and relaxed diagonals, colour-split like their FP64 counterparts
+    const long long n32 = 2 * P.nrb > N ? 2 * P.nrb : N;
+    for (int q = 0; q < 3; ++q) c->r32[q] = B.take<float>(n32);
     for (int q = 0; q < 3; ++q) c->d32[q] = B.take<float>(N);
-    c->a32 = B.take<float>(N);
+    c->a32 = B.take<float>(n32);
+    c->gam32 = B.take<float>(N);
     c->phi32[0] = B.take<float>((long long)(P.nx + 1) * P.ny * P.nz);
     c->phi32[1] = B.take<float>((long long)P.nx * (P.ny + 1) * P.nz);
     c->phi32[2] = B.take<float>((long long)P.nx * P.ny * (P.nz + 1));
     c->nut32 = B.take<float>(N);
-    c->F1_32 = B.take<float>(N);
     c->rAU32 = B.take<float>(N);
     c->pr32 = B.take<float>(N);
     c->pz32 = B.take<float>(N);

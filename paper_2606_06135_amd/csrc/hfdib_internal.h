@@ -117,8 +117,9 @@ struct hfdib_ctx {
   // corrections of the stencil solves, mirrors of the sweep coefficients
   // (relaxed diagonal, face fluxes, nu_t, SST blending), pressure smoother
   // inputs (rAU) and the preconditioner residual / output
-  float *r32[3], *d32[3], *a32, *phi32[3], *nut32, *F1_32;
+  float *r32[3], *d32[3], *a32, *phi32[3], *nut32;
   float *rAU32, *pr32, *pz32, *invD32;
+  float* gam32;  // FP32 diffusivity of the scalar being solved (mixed policy)
   // --- lists
   int cap;  // capacity of each list
   int *bc_cells, *ic_cells, *wall_cells;

@@ -195,7 +195,7 @@ __global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T*
 // are only read here and overwritten by the next sweep).
 template <typename T>
 __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* z, int color, const T* zc,
-                              int cnx, int cny, const double* rdot, double* part, long long pstride) {
+                              int cnx, int cny, const double* rdot, double* part, long long pstride, double* dcopy) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
   const bool own = i < P.nx && j < P.ny;
@@ -226,15 +226,21 @@ __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r,
     z[c] = znew;
   }
   // the last sweep of a V-cycle also forms the partial sums of r . z (FP64 r):
-  // its own cell, then the other cell of its pair, whose z is already final
+  // its own cell, then the other cell of its pair, whose z is already final;
+  // optionally it copies both cells' z to the FP64 search direction (dcopy)
   if (rdot) {
     double v[1] = {0.0};
     if (j < P.ny) {
-      if (own) v[0] = rdot[c] * (double)znew;
+      if (own) {
+        v[0] = rdot[c] * (double)znew;
+        if (dcopy) dcopy[c] = (double)znew;
+      }
       const int io = i ^ 1;
       if (io < P.nx) {
         const long long co = cidx(P, io, j, k);
-        v[0] += rdot[co] * (double)z[co];
+        const T zo = z[co];
+        v[0] += rdot[co] * (double)zo;
+        if (dcopy) dcopy[co] = (double)zo;
       }
     }
     block_sums_store<1>(v, part, pstride, block_linear());
@@ -262,36 +268,33 @@ __device__ __forceinline__ long long lidx(const LevelDevT<T>& L, int i, int j, i
 // coefficients of level 1 from the fine operator (always evaluated in FP64 from
 // rAU, then stored as T): sum of the fine face coefficients on each coarse
 // face, halved (rediscretisation on the 2h grid)
+// Coarse operator of level L in one pass per cell: its six face coefficients
+// (half the sum of the fine faces they cover, each interior face computed alike by
+// both cells that share it), stored as the low faces of each cell plus the high
+// faces on the domain boundary, and the diagonal (sum of the six; an uncoupled
+// cell gets 1).  From the fine operator (FROM_FINE) or from level F.
 template <typename T>
-__global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDevT<T> L, T* cx, T* cy, T* cz) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  int J = blockIdx.y * blockDim.y + threadIdx.y;
-  int K = blockIdx.z;
-  int nzs = L.dim == 3 ? 2 : 1;
-  // x faces: I in [0, nx]
-  if (I <= L.nx && J < L.ny && K < L.nz) {
-    double s = 0.0;
+__device__ __forceinline__ T cface_fine(const Params& P, const FineOp& O, const LevelDevT<T>& L, int d, int I, int J,
+                                        int K) {
+  const int nzs = L.dim == 3 ? 2 : 1;
+  double s = 0.0;
+  long long n;
+  if (d == 0) {
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
         int j = 2 * J + b, k = L.dim == 3 ? 2 * K + e : 0;
         if (I < L.nx) {
           int i = 2 * I;
-          long long n;
           s += fine_coef(P, O, cidx(P, i, j, k), 0, -1, i, j, k, &n);
         } else {
           int i = 2 * I - 1;
-          long long n;
           s += fine_coef(P, O, cidx(P, i, j, k), 0, +1, i, j, k, &n);
         }
       }
-    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = (T)(0.5 * s);
-  }
-  if (I < L.nx && J <= L.ny && K < L.nz) {
-    double s = 0.0;
+  } else if (d == 1) {
     for (int a = 0; a < 2; ++a)
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, k = L.dim == 3 ? 2 * K + e : 0;
-        long long n;
         if (J < L.ny) {
           int j = 2 * J;
           s += fine_coef(P, O, cidx(P, i, j, k), 1, -1, i, j, k, &n);
@@ -300,15 +303,10 @@ __global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDevT<T> L, T* cx, T
           s += fine_coef(P, O, cidx(P, i, j, k), 1, +1, i, j, k, &n);
         }
       }
-    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = (T)(0.5 * s);
-  }
-  if (L.dim == 3 && I < L.nx && J < L.ny && K <= L.nz) {
-    // z faces K in [0, nz]: the launch has nz+1 planes
-    double s = 0.0;
+  } else {
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
         int i = 2 * I + a, j = 2 * J + b;
-        long long n;
         if (K < L.nz) {
           int k = 2 * K;
           s += fine_coef(P, O, cidx(P, i, j, k), 2, -1, i, j, k, &n);
@@ -317,61 +315,63 @@ __global__ void k_coarsen_from_fine(Params P, FineOp O, LevelDevT<T> L, T* cx, T
           s += fine_coef(P, O, cidx(P, i, j, k), 2, +1, i, j, k, &n);
         }
       }
-    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = (T)(0.5 * s);
   }
+  return (T)(0.5 * s);
 }
-
-// coefficients of level l+1 from the stored coefficients of level l (F)
 template <typename T>
-__global__ void k_coarsen_level(LevelDevT<T> F, LevelDevT<T> L, T* cx, T* cy, T* cz) {
-  int I = blockIdx.x * blockDim.x + threadIdx.x;
-  int J = blockIdx.y * blockDim.y + threadIdx.y;
-  int K = blockIdx.z;
-  int nzs = L.dim == 3 ? 2 : 1;
-  if (I <= L.nx && J < L.ny && K < L.nz) {
-    T s = (T)0;
+__device__ __forceinline__ T cface_level(const LevelDevT<T>& F, const LevelDevT<T>& L, int d, int I, int J, int K) {
+  const int nzs = L.dim == 3 ? 2 : 1;
+  T s = (T)0;
+  if (d == 0) {
     for (int b = 0; b < 2; ++b)
       for (int e = 0; e < nzs; ++e) {
         int j = 2 * J + b, k = L.dim == 3 ? 2 * K + e : 0;
         s += F.cx[(long long)(2 * I) + (long long)(F.nx + 1) * ((long long)j + (long long)F.ny * k)];
       }
-    cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = (T)0.5 * s;
-  }
-  if (I < L.nx && J <= L.ny && K < L.nz) {
-    T s = (T)0;
+  } else if (d == 1) {
     for (int a = 0; a < 2; ++a)
       for (int e = 0; e < nzs; ++e) {
         int i = 2 * I + a, k = L.dim == 3 ? 2 * K + e : 0;
         s += F.cy[(long long)i + (long long)F.nx * ((long long)(2 * J) + (long long)(F.ny + 1) * k)];
       }
-    cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = (T)0.5 * s;
-  }
-  if (L.dim == 3 && I < L.nx && J < L.ny && K <= L.nz) {
-    T s = (T)0;
+  } else {
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) {
         int i = 2 * I + a, j = 2 * J + b;
         s += F.cz[(long long)i + (long long)F.nx * ((long long)j + (long long)F.ny * (2 * K))];
       }
-    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = (T)0.5 * s;
   }
+  return (T)0.5 * s;
+}
+template <typename T, bool FROM_FINE>
+__global__ void k_coarsen_diag(Params P, FineOp O, LevelDevT<T> F, LevelDevT<T> L, T* cx, T* cy, T* cz, T* diag) {
+  const int I = blockIdx.x * blockDim.x + threadIdx.x;
+  const int J = blockIdx.y * blockDim.y + threadIdx.y;
+  const int K = blockIdx.z;
+  if (I >= L.nx || J >= L.ny) return;
+  auto face = [&](int d, int a, int b, int e) {
+    return FROM_FINE ? cface_fine<T>(P, O, L, d, a, b, e) : cface_level<T>(F, L, d, a, b, e);
+  };
+  const T xl = face(0, I, J, K), xh = face(0, I + 1, J, K);
+  const T yl = face(1, I, J, K), yh = face(1, I, J + 1, K);
+  const bool d3 = L.dim == 3;
+  const T zl = d3 ? face(2, I, J, K) : (T)0, zh = d3 ? face(2, I, J, K + 1) : (T)0;
+  cx[(long long)I + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = xl;
+  if (I == L.nx - 1) cx[(long long)L.nx + (long long)(L.nx + 1) * ((long long)J + (long long)L.ny * K)] = xh;
+  cy[(long long)I + (long long)L.nx * ((long long)J + (long long)(L.ny + 1) * K)] = yl;
+  if (J == L.ny - 1) cy[(long long)I + (long long)L.nx * ((long long)L.ny + (long long)(L.ny + 1) * K)] = yh;
+  if (d3) {
+    cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * K)] = zl;
+    if (K == L.nz - 1) cz[(long long)I + (long long)L.nx * ((long long)J + (long long)L.ny * L.nz)] = zh;
+  }
+  T sd = xl + xh + yl + yh;
+  if (d3) sd += zl + zh;
+  diag[lidx(L, I, J, K)] = sd == (T)0 ? (T)1 : sd;  // uncoupled coarse cells: identity
 }
 
-template <typename T>
-__global__ void k_level_diag(LevelDevT<T> L, T* diag) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int j = blockIdx.y * blockDim.y + threadIdx.y;
-  int k = blockIdx.z;
-  if (i >= L.nx || j >= L.ny) return;
-  T s = L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
-        L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] +
-        L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] +
-        L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)];
-  if (L.dim == 3)
-    s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] +
-         L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))];
-  diag[lidx(L, i, j, k)] = s == (T)0 ? (T)1 : s;  // uncoupled coarse cells: identity
-}
+
+// coefficients of level l+1 from the stored coefficients of level l (F)
+
 
 // off-diagonal sum sum_nb c z_nb at (i,j,k) of a stored level
 template <typename T>
@@ -769,11 +769,6 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
 }
 
 // ---------------------------------------------------------------- vector ops
-template <typename TA>
-__global__ void k_copy_vec(long long n, const TA* a, double* b) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  if (c < n) b[c] = (double)a[c];
-}
 
 
 // x += alpha d, r -= alpha q (and its FP32 copy when r32 is given); partial r.r
@@ -910,10 +905,11 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
 }
 
 // one V-cycle z = M^-1 r in storage type T; the last sweep also leaves the
-// block partial sums of rdot . z in the partials (rdot: the FP64 residual);
-// returns their count
+// block partial sums of rdot . z in the partials (rdot: the FP64 residual) and,
+// with dcopy, writes z to that FP64 vector as well; returns the partial count
 template <typename T>
-static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, const double* rdot) {
+static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, const double* rdot,
+                  double* dcopy = nullptr) {
   const Params& P = c->P;
   dim3 g = grid3_rb(P), bf = block3(P), b = block_lv();
   hipLaunchKernelGGL(k_fine_presmooth<T>, g, bf, 0, c->stream, P, O, invD, r, z);
@@ -961,9 +957,9 @@ static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, 
   }
   // post-smoothing, black first (with the prolongation on the fly), then red
   hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny, (const double*)nullptr,
-                     (double*)nullptr, 0LL);
+                     (double*)nullptr, 0LL, (double*)nullptr);
   hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0, rdot,
-                     c->partials, c->pstride);
+                     c->partials, c->pstride, dcopy);
   return (int)g.x;
 }
 
@@ -978,12 +974,13 @@ static void build_levels(hfdib_ctx* c, const FineOp& O) {
     T* cx = const_cast<T*>(Ld.cx);
     T* cy = const_cast<T*>(Ld.cy);
     T* cz = const_cast<T*>(Ld.cz);
-    dim3 gf((L.nx + 1 + 63) / 64, (L.ny + 1 + 3) / 4, P.dim == 3 ? L.nz + 1 : 1);
+    T* dg = const_cast<T*>(Ld.diag);
     if (l == 1)
-      hipLaunchKernelGGL(k_coarsen_from_fine<T>, gf, b, 0, c->stream, P, O, Ld, cx, cy, cz);
+      hipLaunchKernelGGL((k_coarsen_diag<T, true>), lgrid(L.nx, L.ny, L.nz), b, 0, c->stream, P, O, Ld, Ld, cx, cy, cz,
+                         dg);
     else
-      hipLaunchKernelGGL(k_coarsen_level<T>, gf, b, 0, c->stream, levdev<T>(c, l - 1), Ld, cx, cy, cz);
-    hipLaunchKernelGGL(k_level_diag<T>, lgrid(L.nx, L.ny, L.nz), b, 0, c->stream, Ld, const_cast<T*>(Ld.diag));
+      hipLaunchKernelGGL((k_coarsen_diag<T, false>), lgrid(L.nx, L.ny, L.nz), b, 0, c->stream, P, O,
+                         levdev<T>(c, l - 1), Ld, cx, cy, cz, dg);
   }
 }
 
@@ -1006,8 +1003,7 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
   launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [20]=rr0 [21]=bb [22..24]=residual sums
   // at least one PCG iteration is done; the host reads the residual after each
   // iteration (one synchronisation per iteration, none before the first)
-  launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r), 1, S_RZ, 3);
-  hipLaunchKernelGGL(k_copy_vec<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const T*)z_m, d);
+  launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r, d), 1, S_RZ, 3);  // d = z
   if (c->graph_mode) {
     // fixed iteration count, no host read (the step may be captured in a graph);
     // the scalar updates guard zero denominators on the device

@@ -21,19 +21,17 @@ struct Mom {
 };
 
 // FP32 outputs of the momentum assembly under the mixed policy (all null under
-// FP64): the defect b - A u_old of each component, the relaxed diagonal and the
-// SST blending mirror used by the FP32 sweeps
+// FP64): the defect b - A u_old of each component and the relaxed diagonal used
+// by the FP32 sweeps (colour-split)
 struct MixOut {
   float* r[3];
   float* a;
-  float* F1;
 };
 
 // FP32 coefficient mirrors read by the FP32 sweeps
 struct Mir32 {
   const float* phi[3];
   const float* nut;
-  const float* F1;
 };
 
 __device__ __forceinline__ double nut_wall(const Params& P, double yp) {
@@ -280,7 +278,7 @@ __global__ void __launch_bounds__(256) k_mom_assemble(Params P, Mom M, MixOut X,
     double urf = P.urf_u;
     double aPr = aP / urf;
     aPr_out[rb_split(P, i, j, k)] = aPr;  // rhs and a'_P are stored colour-split
-    if (X.a) X.a[c] = (float)aPr;
+    if (X.a) X.a[rb_split(P, i, j, k)] = (float)aPr;
     bool alpha = fl & F_ALPHA_U;
     double* rhs[3] = {rhs0, rhs1, rhs2};
     // neighbour viscosities shared by the three components
@@ -363,7 +361,7 @@ __global__ void __launch_bounds__(256) k_mom_assemble(Params P, Mom M, MixOut X,
       double Ax = aPr * uo - nb;
       // mixed policy: FP64 defect of the row (every row is swept) for the FP32
       // correction
-      if (X.a) X.r[cc][c] = (float)(rh - Ax);
+      if (X.a) X.r[cc][rb_split(P, i, j, k)] = (float)(rh - Ax);
       if (!alpha) {
         double one = 0.0;
 #pragma unroll
@@ -397,7 +395,6 @@ __global__ void __launch_bounds__(256) k_mom_assemble(Params P, Mom M, MixOut X,
       double arg1 = m1 < m2 ? m1 : m2;
       double a2 = arg1 * arg1;
       M.F1[c] = tanh(a2 * a2);
-      if (X.F1) X.F1[c] = (float)M.F1[c];
       M.kw[c] = kw;
     }
     if (P.model != HFDIB_LAMINAR && !(fl & F_IC)) wmx = M.w[c];
@@ -455,7 +452,8 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
   }
   if (i >= P.nx) return;
   long long c = cidx(P, i, j, k);
-  float a = a32[c];
+  const long long sidx = rb_split(P, i, j, k);  // defects and diagonal are colour-split
+  float a = a32[sidx];
   float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
   if (!init) {
     Nbr N = make_nbr(P, i, j, k, c);
@@ -477,7 +475,7 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
         if (three) n2 += an * d2[n];
       }
   }
-  float e0 = (r0[c] + n0) / a, e1 = (r1[c] + n1) / a;
+  float e0 = (r0[sidx] + n0) / a, e1 = (r1[sidx] + n1) / a;
   d0[c] = e0;
   d1[c] = e1;
   if (fin) {
@@ -485,7 +483,7 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
     u1[c] = u1[c] + (double)e1;
   }
   if (three) {
-    float e2 = (r2[c] + n2) / a;
+    float e2 = (r2[sidx] + n2) / a;
     d2[c] = e2;
     if (fin) u2[c] = u2[c] + (double)e2;
   }
@@ -811,7 +809,7 @@ int tile_bench_round(hfdib_ctx* c) {
   int st = velocity_gradient(c);
   if (st != HFDIB_OK) return st;
   Mom M = make_mom(c);
-  MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
+  MixOut X{{nullptr, nullptr, nullptr}, nullptr};
   hipLaunchKernelGGL(mom_assemble_kernel(P), grid3(P), block3(P), 0, c->stream, P, M, X, c->rhs[0], c->rhs[1],
                      c->rhs[2], c->aPr, c->scal + SCAL_PCG + SC_MEANS, c->partials, c->pstride);
   pressure_apply_bench(c);
@@ -836,7 +834,6 @@ int refresh_mirrors(hfdib_ctx* c) {
     hipLaunchKernelGGL(k_to_f32_n, dim3(nblocks1(nf[d])), dim3(NTHREADS), 0, c->stream, nf[d], c->phi[d],
                        c->phi32[d]);
   hipLaunchKernelGGL(k_to_f32_n, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, c->nut, c->nut32);
-  hipLaunchKernelGGL(k_to_f32_n, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, c->F1, c->F1_32);
   HFDIB_CHECK_LAUNCH(c, "mirrors");
   return HFDIB_OK;
 }
@@ -870,8 +867,8 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   }
   Mom M = make_mom(c);
   bool mixed = P.precision == HFDIB_MIXED;
-  MixOut X{{nullptr, nullptr, nullptr}, nullptr, nullptr};
-  if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32, c->F1_32};
+  MixOut X{{nullptr, nullptr, nullptr}, nullptr};
+  if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32};
   timer_begin(c, T_MOMASM);
   hipLaunchKernelGGL(mom_assemble_kernel(P), g, b, 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
                      S + SC_MEANS, c->partials, c->pstride);
@@ -880,7 +877,7 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   if (P.model != HFDIB_LAMINAR) {
     launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4, 1.0, 9);  // partial row 9: omega maxima
   }
-  Mir32 M32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32, c->F1_32};
+  Mir32 M32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32};
   // (one timing span over the 2 n_s consecutive launches)
   timer_begin(c, T_MOMSWEEP);
   for (int s = 0; s < P.n_sweeps; ++s)

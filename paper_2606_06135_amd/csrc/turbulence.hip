@@ -183,7 +183,8 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
 // other closures keep their register budget)
 template <bool RKE>
 __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, float* r32, float* a32,
-                                  double* gam_out, const double* xmean, double* part, long long pstride) {
+                                  double* gam_out, float* gam_out32, const double* xmean, double* part,
+                                  long long pstride) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   double red[3] = {0, 0, 0};
@@ -193,6 +194,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     bool solid = fl & F_SOLID;
     double gP = gam(P, eq, c, S.nut, S.F1);
     if (gam_out) gam_out[c] = gP;
+    if (gam_out32) gam_out32[c] = (float)gP;
     Nbr N = make_nbr(P, i, j, k, c);
     double anb[6];
     scal_anb(P, S, eq, gP, N, i, j, k, anb);
@@ -303,11 +305,11 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
         red[2] = fabs(rhs - Axb);
       }
       // mixed policy: FP64 defect of the row for the FP32 correction
-      if (a32) r32[c] = (float)(rhs - Ax);
+      if (a32) r32[sidx] = (float)(rhs - Ax);
     }
     if (a32) {
-      a32[c] = (float)aPr;
-      if (!swept) r32[c] = 0.0f;
+      a32[sidx] = (float)aPr;
+      if (!swept) r32[sidx] = 0.0f;
     }
   }
   block_sums_store<3>(red, part, pstride, block_linear());
@@ -350,21 +352,13 @@ __global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const doubl
 // the FP32 mirrors; the last sweep of each colour writes x <- x_old + d (FP64).
 struct Scal32 {
   const float* phi[3];
-  const float* nut;
-  const float* F1;
 };
-__device__ __forceinline__ float gam32(const Params& P, int eq, long long c, const float* nut, const float* F1) {
-  const float nu = (float)P.nu;
-  if (P.model == HFDIB_KEPS) return nu + nut[c] * (float)(eq == 0 ? P.isig_eps : P.isig_k);
-  if (P.model == HFDIB_KOMEGA) return nu + nut[c] * (float)(eq == 0 ? P.isig_w_kw : P.isig_k_kw);
-  if (P.model == HFDIB_RKEPS) return nu + nut[c] * (float)(eq == 0 ? P.isig_eps_rke : P.isig_k_rke);
-  float f = F1[c];
-  float a = (float)(eq == 0 ? P.sigma_w1 : P.sigma_k1), b = (float)(eq == 0 ? P.sigma_w2 : P.sigma_k2);
-  return nu + (f * a + (1.0f - f) * b) * nut[c];
-}
 
-__global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, int eq, const float* r, const float* a32,
-                                 float* dv, double* x, int color, uint8_t fixmask, int init, int fin) {
+// (the diffusivity of each cell from the FP32 array the assembly stored; defect
+// and diagonal colour-split)
+__global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, const float* gamc, const float* r,
+                                 const float* a32, float* dv, double* x, int color, uint8_t fixmask, int init,
+                                 int fin) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
   if (j >= P.ny) return;
@@ -382,7 +376,7 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, int e
   }
   float nb = 0.0f;
   if (!init) {
-    float gP = gam32(P, eq, c, S.nut, S.F1);
+    float gP = gamc[c];
     Nbr N = make_nbr(P, i, j, k, c);
 #pragma unroll
     for (int d = 0; d < 3; ++d)
@@ -393,11 +387,12 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, int e
         long long n = N.n[q];
         long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
         float mf = s > 0 ? -S.phi[d][f] : S.phi[d][f];
-        float a = 0.5f * (gP + gam32(P, eq, n, S.nut, S.F1)) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
+        float a = 0.5f * (gP + gamc[n]) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
         nb += is_bnd(N, q) ? 0.0f : a * dv[n];
       }
   }
-  float e = (r[c] + nb) / a32[c];
+  const long long sidx = rb_split(P, i, j, k);
+  float e = (r[sidx] + nb) / a32[sidx];
   dv[c] = e;
   if (fin) x[c] = x[c] + (double)e;
 }
@@ -555,7 +550,7 @@ int turbulence_stage(hfdib_ctx* c) {
   bool mixed = P.precision == HFDIB_MIXED;
   float* r32 = mixed ? c->r32[0] : nullptr;
   float* a32 = mixed ? c->a32 : nullptr;
-  Scal32 S32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32, c->F1_32};
+  Scal32 S32{{c->phi32[0], c->phi32[1], c->phi32[2]}};
   // per-cell diffusivity of the equation being solved (FP64 sweeps; the
   // momentum right-hand sides are dead during this stage)
   double* gam_c = c->rhs[0];
@@ -566,8 +561,9 @@ int turbulence_stage(hfdib_ctx* c) {
     for (int s = 0; s < P.n_sweeps; ++s)
       for (int color = 0; color < 2; ++color) {
         if (mixed)
-          hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, eq, r32, a32, c->d32[0],
-                             x, color, fixmask, s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
+          hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, (const float*)c->gam32,
+                             r32, a32, c->d32[0], x, color, fixmask, s == 0 && color == 0 ? 1 : 0,
+                             s == P.n_sweeps - 1 ? 1 : 0);
         else
           hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, (const double*)gam_c, c->t0, c->t1,
                              x, color, fixmask);
@@ -578,7 +574,7 @@ int turbulence_stage(hfdib_ctx* c) {
   timer_begin(c, T_SCALASM);
   auto assemble = P.model == HFDIB_RKEPS ? k_scalar_assemble<true> : k_scalar_assemble<false>;
   hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
-                     S + SC_MEANS + 5, c->partials, c->pstride);
+                     mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride);
   timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
   sweeps(0, c->w, (uint8_t)F_ALPHA_W);
@@ -589,7 +585,7 @@ int turbulence_stage(hfdib_ctx* c) {
                        c->kib);
   timer_begin(c, T_SCALASM);
   hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
-                     S + SC_MEANS + 4, c->partials, c->pstride);
+                     mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride);
   timer_end(c, T_SCALASM);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
