@@ -222,6 +222,15 @@ def main():
             # ... and every timed kernel class, by share (the two largest are close)
             roof_all = [roofline_of(k) for k in sorted(cand, key=lambda k: -cand[k][0])]
 
+    # whole-iteration %HBM peak with the per-iteration byte model of the minimal
+    # fused design (3-D SST, FP64): 1178 B/cell for everything but the pressure
+    # solve, 190 B/cell per CG iteration (N_cg measured over the timed region)
+    n_cg = stats[0] / max(done, 1)
+    bpc = 1178.0 + 190.0 * n_cg
+    ach = bpc * N * done / elapsed / 1e9
+    iteration_hbm = {"bytes_per_cell": round(bpc, 1), "cg_iters_per_step": round(n_cg, 3),
+                     "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(ach / PEAK_HBM_GBS, 4)}
     value = N * done / elapsed
     del solver
     torch.cuda.empty_cache()
@@ -255,6 +264,7 @@ def main():
                    "final_residuals": [float(x) for x in res]},
         "roofline": roof,
         "roofline_kernels": roof_all,
+        "iteration_hbm": iteration_hbm,
         "cpu_baseline": cpu,
         "mixed_vs_fp64": mixed,
         "naca_sweep": sweep,
