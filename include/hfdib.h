@@ -195,7 +195,9 @@ int hfdib_workspace_bytes(const hfdib_grid_desc* d, const hfdib_config* c, size_
 
 /* Creates a context.  Copies d and c, lays out the caller's workspace (device
  * pointer, >= hfdib_workspace_bytes, 256-byte aligned) and records the stream
- * (a hipStream_t, NULL for the default stream).  No device work is enqueued. */
+ * (a hipStream_t, NULL for the default stream).  No device work is enqueued
+ * and no HIP call is made.  Errors: EINVAL for a bad descriptor or workspace
+ * pointer, ENOMEM for a workspace below hfdib_workspace_bytes. */
 int hfdib_init_grid(const hfdib_grid_desc* d, const hfdib_config* c, void* workspace,
                     size_t bytes, void* hip_stream, hfdib_ctx** out);
 
@@ -211,10 +213,12 @@ int hfdib_set_indicator(hfdib_ctx* ctx, const double* lambda_dev, const double* 
 
 /* Runs up to max_iters SIMPLE iterations (the paper's extended loop).  Stops
  * early when tol > 0 and the largest normalised residual <= tol (checked every
- * check_every iterations, which is where the host synchronises).  tol <= 0 runs
- * exactly max_iters.  *iters_done (nullable) receives the count; res_out
- * (nullable, host, 6 doubles) the residuals of Ux, Uy, Uz, p, k, eps/omega of the
- * last iteration.  Returns EDIVERGED on NaN/Inf. */
+ * check_every iterations and after the last one, with a host synchronisation).
+ * tol <= 0 runs exactly max_iters.  The pressure solve of every iteration also
+ * synchronises once per PCG iteration (see hfdib_pressure_solve).
+ * *iters_done (nullable) receives the count; res_out (nullable, host, 6 doubles)
+ * the residuals of Ux, Uy, Uz, p, k, eps/omega of the last iteration.  Returns
+ * EDIVERGED on NaN/Inf. */
 int hfdib_simple_iterate(hfdib_ctx* ctx, int max_iters, double tol, int check_every,
                          int* iters_done, double* res_out);
 
@@ -277,7 +281,10 @@ int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);
  * V-cycle; stops at |r| <= rtol |b| or after maxit iterations, where |b| is taken
  * over the coupled rows (an uncoupled row, all of whose coefficients are zero,
  * is the identity p = rhs and its right-hand side does not enter |b|).
- * *iters and *relres (host, nullable) report the outcome.  Synchronises. */
+ * *iters and *relres (host, nullable) report the outcome.  Synchronises the
+ * host once per PCG iteration: the device writes the convergence scalars to a
+ * 200-byte pinned host buffer that the context allocates on its first solve
+ * (EDEVICE if that fails) and frees in hfdib_destroy. */
 int hfdib_pressure_solve(hfdib_ctx* ctx, const double* rAU_dev, const double* rhs_dev,
                          double* p_dev, double rtol, int maxit, int* iters, double* relres);
 
@@ -286,11 +293,14 @@ int hfdib_pressure_solve(hfdib_ctx* ctx, const double* rAU_dev, const double* rh
  * solve, [3] last pressure relative residual. */
 int hfdib_last_stats(hfdib_ctx* ctx, double* out8);
 
-/* Per-kernel timing with HIP events on the context stream.  enable != 0 starts
- * recording (an event pair around every launch of the named kernel class, or
- * around the run of 2 n_sweeps consecutive launches of a red-black solve, which
- * counts as that many launches; see hfdib_timing_query); 0 stops.  Adds host
- * overhead; off by default. */
+/* Per-kernel timing with HIP events on the context stream.  enable > 0 starts
+ * recording in every enable-th SIMPLE iteration (1: every iteration; calls
+ * outside hfdib_simple_iterate are always recorded): the kernel's own start and
+ * end are stamped on every launch of the named kernel class, or on the first
+ * and last of the 2 n_sweeps consecutive launches of a red-black solve, which
+ * count as that many launches (see hfdib_timing_query).  0 stops.  Recording
+ * adds a few microseconds per timed launch; off by default.  EINVAL for
+ * enable < 0. */
 int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
 /* kernel_class: 0 pressure operator apply (fine level), 1 momentum sweep,
  * 2 momentum assembly, 3 whole pressure solve, 4 whole SIMPLE iteration,

@@ -350,8 +350,9 @@ class Solver:
         _check("hfdib_last_stats", lib().hfdib_last_stats(self.ctx, a), self.ctx)
         return list(a)
 
-    def timing(self, enable):
-        _check("hfdib_timing_enable", lib().hfdib_timing_enable(self.ctx, 1 if enable else 0), self.ctx)
+    def timing(self, enable, every=1):
+        """Kernel timing on (recording every `every`-th SIMPLE iteration) or off."""
+        _check("hfdib_timing_enable", lib().hfdib_timing_enable(self.ctx, int(every) if enable else 0), self.ctx)
 
     def timing_query(self, name):
         ms = C.c_double(0.0)

@@ -20,6 +20,9 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where) {
 
 struct Timers {
   bool on = false;
+  int every = 1;      // record every `every`-th SIMPLE iteration
+  long long n_it = 0; // SIMPLE iterations seen while on
+  bool skip = false;  // the current iteration is not recorded
   struct Span {
     hipEvent_t e0, e1;
     int launches;
@@ -28,6 +31,24 @@ struct Timers {
   hipEvent_t open[T_NCLASS] = {};
   double ms[T_NCLASS] = {};
   long long cnt[T_NCLASS] = {};
+  // events whose spans were read back, reused by later spans (creating an event
+  // per span would cost a runtime call inside the timed iterations)
+  std::vector<hipEvent_t> pool;
+  hipEvent_t take() {
+    hipEvent_t e = nullptr;
+    if (!pool.empty()) {
+      e = pool.back();
+      pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+    }
+    return e;
+  }
+  ~Timers() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (hipEvent_t e : open)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 static void timers_flush(hfdib_ctx* c) {
@@ -43,31 +64,52 @@ static void timers_flush(hfdib_ctx* c) {
         T->ms[k] += ms;
         T->cnt[k] += sp.launches;
       }
-      (void)hipEventDestroy(sp.e0);
-      (void)hipEventDestroy(sp.e1);
+      T->pool.push_back(sp.e0);
+      T->pool.push_back(sp.e1);
     }
     T->pend[k].clear();
   }
 }
 
-void timer_begin(hfdib_ctx* c, int cls) {
+void timer_iteration(hfdib_ctx* c, bool begin) {
   Timers* T = c->timers;
   if (!T || !T->on) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
-  (void)hipEventRecord(e, c->stream);
-  T->open[cls] = e;
+  T->skip = begin && (T->n_it++ % T->every) != 0;
+}
+
+void timer_begin(hfdib_ctx* c, int cls) {
+  Timers* T = c->timers;
+  if (!T || !T->on || T->skip) return;
+  if (!T->open[cls]) T->open[cls] = T->take();
+  if (T->open[cls]) (void)hipEventRecord(T->open[cls], c->stream);
 }
 
 void timer_end(hfdib_ctx* c, int cls, int launches) {
   Timers* T = c->timers;
   if (!T || !T->on || !T->open[cls]) return;
-  hipEvent_t e;
-  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEvent_t e = T->take();
+  if (!e) return;
   (void)hipEventRecord(e, c->stream);
   T->pend[cls].push_back({T->open[cls], e, launches});
   T->open[cls] = nullptr;
   if (T->pend[cls].size() > 4096) timers_flush(c);
+}
+
+LaunchEv timer_launch(hfdib_ctx* c, int cls, bool first, bool last, int launches) {
+  LaunchEv ev{nullptr, nullptr};
+  Timers* T = c->timers;
+  if (!T || !T->on || T->skip) return ev;
+  if (first) {
+    if (T->pend[cls].size() > 4096) timers_flush(c);
+    if (!T->open[cls]) T->open[cls] = T->take();
+    ev.start = T->open[cls];
+  }
+  if (last && T->open[cls]) {
+    ev.stop = T->take();
+    if (ev.stop) T->pend[cls].push_back({T->open[cls], ev.stop, launches});
+    T->open[cls] = nullptr;
+  }
+  return ev;
 }
 
 // ---------------------------------------------------------------- layout
@@ -575,7 +617,9 @@ int hfdib_simple_iterate(hfdib_ctx* c, int max_iters, double tol, int check_ever
   int status = HFDIB_OK;
   for (int it = 0; it < max_iters; ++it) {
     bool check = (tol > 0.0 && check_every > 0 && (it + 1) % check_every == 0) || it == max_iters - 1;
+    timer_iteration(c, true);
     int st = simple_step(c, it, check ? res : nullptr);
+    timer_iteration(c, false);
     ++done;
     if (st != HFDIB_OK) {
       status = st;
@@ -790,9 +834,12 @@ int hfdib_last_stats(hfdib_ctx* c, double* out8) {
 }
 
 int hfdib_timing_enable(hfdib_ctx* c, int enable) {
-  if (!c || !c->timers) return HFDIB_EINVAL;
+  if (!c || !c->timers || enable < 0) return HFDIB_EINVAL;
   if (!enable) timers_flush(c);
   c->timers->on = enable != 0;
+  c->timers->every = enable > 0 ? enable : 1;
+  c->timers->n_it = 0;
+  c->timers->skip = false;
   return HFDIB_OK;
 }
 
@@ -810,6 +857,7 @@ void hfdib_destroy(hfdib_ctx* c) {
     timers_flush(c);
     delete c->timers;
   }
+  if (c->hmir) (void)hipHostFree(c->hmir);
   delete c;
 }
 

@@ -1,6 +1,7 @@
 // Internal declarations of the HFDIB SIMPLE library (gfx950, HIP).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <string>
@@ -136,7 +137,10 @@ struct hfdib_ctx {
   double* partials2; // 16 rows of FIN2_STRIDE second-stage partials
   double* scal;      // 512 scalars
   int* iscal;        // 64 ints
-  double* host_scal; // pinned? plain host mirror (filled by sync copies)
+  // pinned, host-coherent mirror of the first NMIR PCG scalars, written by the
+  // device after each PCG iteration (the host reads it after a stream sync)
+  double* hmir;
+  double* hmir_dev;  // its device address
   // --- multigrid
   int nlev;
   hfdib::Level lev[hfdib::MAX_LEVELS];
@@ -192,9 +196,30 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);
 enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_SCALSWEEP = 5, T_SCALASM = 6,
        T_NCLASS = 7 };
 void timer_begin(hfdib_ctx* c, int cls);
+// brackets one SIMPLE iteration (begin = true at its start, false at its end):
+// with a recording period n > 1 only every n-th iteration is recorded
+void timer_iteration(hfdib_ctx* c, bool begin);
 // closes the open span of class cls, which covered `launches` consecutive
 // launches of that class (its per-launch average divides by them)
 void timer_end(hfdib_ctx* c, int cls, int launches = 1);
+// events of one kernel launch in a timed span of class cls, for
+// hipExtLaunchKernelGGL (the runtime stamps them with the kernel's own start
+// and end, no marker packets): `start` when the launch opens the span, `stop`
+// when it closes a span of `launches` consecutive launches; null when timing is
+// off or for launches inside the span
+struct LaunchEv {
+  hipEvent_t start, stop;
+};
+LaunchEv timer_launch(hfdib_ctx* c, int cls, bool first, bool last, int launches = 1);
+// launch with the span events of timer_launch (a plain launch when it has none,
+// e.g. with timing off or under graph capture)
+template <typename K, typename... A>
+inline void launch_ev(K kernel, dim3 grid, dim3 block, hipStream_t stream, LaunchEv ev, A... args) {
+  if (ev.start || ev.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, ev.start, ev.stop, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+}
 
 // stages (each returns an hfdib_status)
 int geometry_precompute(hfdib_ctx* c);
@@ -206,7 +231,9 @@ int refresh_mirrors(hfdib_ctx* c);
 
 // deterministic reduction of `nval` rows of per-block partial sums into
 // ctx->scal[SCAL_PCG + out + v]; op selects a PCG scalar update (pressure.hip)
-void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0);
+// (hmir: after the update, copy scal[SCAL_PCG .. SCAL_PCG + NMIR) to that host mirror)
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0,
+                     double* hmir = nullptr);
 int turbulence_stage(hfdib_ctx* c);
 int velocity_gradient(hfdib_ctx* c);
 int body_forces(hfdib_ctx* c, double* out8);
@@ -222,5 +249,6 @@ enum {
   SC_CONV = 180      // batched runs: iterations done, first converged iteration (-1), non-finite flag
 };
 constexpr int SCAL_PCG = 64;
+constexpr int NMIR = 25;  // PCG scalars mirrored to the host (S_RR, S_BB, the residual sums)
 
 }  // namespace hfdib

@@ -828,7 +828,8 @@ k_reduce_chunks(const double* part, long long pstride, int nblk, int chunk, int 
 constexpr int FIN_THREADS = 1024;
 constexpr int FIN_BATCH = 8;
 __global__ void __launch_bounds__(FIN_THREADS)
-k_finalize(const double* part, long long pstride, int nblk, double* scal, int out, int op, double divisor) {
+k_finalize(const double* part, long long pstride, int nblk, double* scal, int out, int op, double divisor,
+           double* hmir) {
   __shared__ double lds[FIN_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, v = blockIdx.x;
   const double* row = part + (long long)v * pstride;
@@ -857,6 +858,10 @@ k_finalize(const double* part, long long pstride, int nblk, double* scal, int ou
       scal[S_RHO] = t;
     } else if (op == 3) {
       scal[S_RHO] = t;
+    }
+    if (hmir) {
+      for (int q = 0; q < NMIR; ++q) hmir[q] = scal[q];
+      __threadfence_system();
     }
   }
 }
@@ -889,7 +894,7 @@ static dim3 lgrid_rb(int nx, int ny, int nz) { return dim3(((nx + 1) / 2 + 63) /
 // finalize helper; partial slots live in ctx->partials with row stride c->pstride
 // Large partial rows are first reduced in fixed chunks by many workgroups
 // (deterministic: fixed chunk boundaries and order), then by one workgroup.
-void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0) {
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0, double* hmir) {
   const double* part = c->partials + (long long)row0 * c->pstride;
   if (nblk > 32 * FIN_THREADS) {
     int chunk = (nblk + FIN2_CHUNKS - 1) / FIN2_CHUNKS;
@@ -897,11 +902,11 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), 0, c->stream, part, c->pstride, nblk,
                        chunk, op == 4 ? 1 : 0, c->partials2);
     hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, (const double*)c->partials2,
-                       (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor);
+                       (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor, hmir);
     return;
   }
   hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, part, c->pstride, nblk,
-                     c->scal + SCAL_PCG, out, op, divisor);
+                     c->scal + SCAL_PCG, out, op, divisor, hmir);
 }
 
 // one V-cycle z = M^-1 r in storage type T; the last sweep also leaves the
@@ -1023,20 +1028,32 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
     if (relres) *relres = 0.0;
     return HFDIB_OK;
   }
-  double hs[32];
+  if (!c->hmir) {
+    // host-coherent pinned mirror of the PCG scalars, allocated on first use
+    void *hm = nullptr, *hm_dev = nullptr;
+    HFDIB_CHECK(c, hipHostMalloc(&hm, NMIR * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent),
+                "pinned scalar mirror");
+    hipError_t e = hipHostGetDevicePointer(&hm_dev, hm, 0);
+    if (e != hipSuccess) {
+      (void)hipHostFree(hm);
+      return set_hip_error(c, e, "pinned scalar mirror");
+    }
+    c->hmir = (double*)hm;
+    c->hmir_dev = (double*)hm_dev;
+  }
   double rr = 0.0, bnorm = 1.0, target = 0.0;
   int it;
   for (it = 1; it <= maxit; ++it) {
-    timer_begin(c, T_PAPPLY);
-    hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
-    timer_end(c, T_PAPPLY);
+    LaunchEv ev = timer_launch(c, T_PAPPLY, true, true);
+    launch_ev(k_fine_apply, g, b, c->stream, ev, P, O, d, q, c->partials, c->pstride);
     launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
     hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, r32, q, c->partials,
                        c->pstride);
-    launch_finalize(c, nb1, 1, S_RR, 0);
+    // the reduction of r.r also writes the scalars to the pinned host mirror
+    launch_finalize(c, nb1, 1, S_RR, 0, 1.0, 0, c->hmir_dev);
     HFDIB_CHECK_LAUNCH(c, "pcg iteration");
-    HFDIB_CHECK(c, hipMemcpyAsync(hs, S, 25 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
     HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
+    const double* hs = c->hmir;
     if (it == 1) {
       double bb = hs[S_BB + 17];
       bnorm = sqrt(bb) > 0.0 ? sqrt(bb) : 1.0;

@@ -10,14 +10,10 @@ struct Mom {
   const double* p;
   const double* phi[3];
   const double* nut;
-  const double* k;
-  const double* w;
-  const double* dw;
+  const double* k;  // (wall functions of no-slip domain faces)
   const uint8_t* flags;
   const double* uib[3];
   const double* G[9];  // stored velocity gradient of u (G[3 a + jc] = d u_jc / d x_a)
-  double* F1;  // SST blending of the previous iterate (written by the assembly)
-  double* kw;  // grad k . grad omega of the previous iterate (SST)
 };
 
 // FP32 outputs of the momentum assembly under the mixed policy (all null under
@@ -225,9 +221,9 @@ __device__ __forceinline__ double nb_sum(const double (&anb)[6], const Nbr& N, c
 //                  r = 2 (x_D - x_C) . grad u_C / (u_D - u_C) - 1 (0 where u_D = u_C)
 // (interior faces; grad u_C the stored Gauss gradient)
 template <int CONV>
-__global__ void __launch_bounds__(256) k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
-                               const double* means, double* part, long long pstride) {
-  double wmx = 0.0;  // max of omega/eps of the previous iterate over boundary and free-stream cells
+__global__ void __launch_bounds__(256)
+k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
+               const double* means, double* part, long long pstride) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   bool act = i < P.nx && j < P.ny;
@@ -372,42 +368,8 @@ __global__ void __launch_bounds__(256) k_mom_assemble(Params P, Mom M, MixOut X,
         red[3 * cc + 2] = fabs(rh - Axb);
       }
     }
-    // turbulence inputs of the previous iterate (k, omega unchanged until the
-    // turbulence stage): SST blending F1 and grad k . grad omega; omega maximum
-    if (P.model == HFDIB_KOMEGA_SST) {
-      double kk = M.k[c], ww = M.w[c];
-      double gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (d >= P.dim) continue;
-        gk[d] = ggrad_bf(P, M.k, N, c, d, sc_bface(P, d, +1, solid, kk, P.k_in), sc_bface(P, d, -1, solid, kk, P.k_in));
-        gw[d] = ggrad_bf(P, M.w, N, c, d, sc_bface(P, d, +1, solid, ww, P.w_in), sc_bface(P, d, -1, solid, ww, P.w_in));
-      }
-      double kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
-      double dwc = M.dw[c];
-      double bs = P.Cmu;
-      double cd = 2.0 * P.sigma_w2 / ww * kw;
-      cd = cd > P.cd_floor ? cd : P.cd_floor;
-      double a = sqrt(kk) / (bs * ww * dwc);
-      double bb = 500.0 * P.nu / (dwc * dwc * ww);
-      double m1 = a > bb ? a : bb;
-      double m2 = 4.0 * P.sigma_w2 * kk / (cd * dwc * dwc);
-      double arg1 = m1 < m2 ? m1 : m2;
-      double a2 = arg1 * arg1;
-      M.F1[c] = tanh(a2 * a2);
-      M.kw[c] = kw;
-    }
-    if (P.model != HFDIB_LAMINAR && !(fl & F_IC)) wmx = M.w[c];
   }
   block_sums_store<9>(red, part, pstride, block_linear());
-  if (P.model != HFDIB_LAMINAR) {
-    __shared__ double lmax[4];
-    double m = wave_max(wmx);
-    int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-    if ((tid & 63) == 0) lmax[tid >> 6] = m;
-    __syncthreads();
-    if (tid == 0) part[9 * pstride + block_linear()] = fmax(fmax(lmax[0], lmax[1]), fmax(lmax[2], lmax[3]));
-  }
 }
 
 // one colour of a red-black Gauss-Seidel sweep over the three components
@@ -696,11 +658,7 @@ static Mom make_mom(hfdib_ctx* c) {
   M.p = c->p;
   M.nut = c->nut;
   M.k = c->k;
-  M.w = c->w;
-  M.dw = c->dw;
   M.flags = c->flags;
-  M.F1 = c->F1;
-  M.kw = c->t2;
   return M;
 }
 
@@ -846,10 +804,11 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   int st;
-  timer_begin(c, T_ITER);
-  // means of the previous iterate (residual normalisation)
-  hipLaunchKernelGGL(k_sums5, dim3(nb1), dim3(NTHREADS), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->p, c->k,
-                     c->partials, c->pstride);
+  // means of the previous iterate (residual normalisation); opens the timing
+  // span of the iteration
+  LaunchEv ev = timer_launch(c, T_ITER, true, false);
+  launch_ev(k_sums5, dim3(nb1), dim3(NTHREADS), c->stream, ev, P, c->u[0], c->u[1], c->u[2], c->p, c->k, c->partials,
+            c->pstride);
   launch_finalize(c, nb1, 5, SC_MEANS, 0, (double)P.N);
   // 1. IB-pre
   if (c->n_bc > 0)
@@ -869,28 +828,24 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   bool mixed = P.precision == HFDIB_MIXED;
   MixOut X{{nullptr, nullptr, nullptr}, nullptr};
   if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32};
-  timer_begin(c, T_MOMASM);
-  hipLaunchKernelGGL(mom_assemble_kernel(P), g, b, 0, c->stream, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
-                     S + SC_MEANS, c->partials, c->pstride);
-  timer_end(c, T_MOMASM);
+  ev = timer_launch(c, T_MOMASM, true, true);
+  launch_ev(mom_assemble_kernel(P), g, b, c->stream, ev, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, S + SC_MEANS,
+            c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 9, SC_RESSUM, 0);
-  if (P.model != HFDIB_LAMINAR) {
-    launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4, 1.0, 9);  // partial row 9: omega maxima
-  }
   Mir32 M32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32};
   // (one timing span over the 2 n_s consecutive launches)
-  timer_begin(c, T_MOMSWEEP);
   for (int s = 0; s < P.n_sweeps; ++s)
     for (int color = 0; color < 2; ++color) {
+      const bool first = s == 0 && color == 0, last = s == P.n_sweeps - 1 && color == 1;
+      ev = timer_launch(c, T_MOMSWEEP, first, last, 2 * P.n_sweeps);
       if (mixed)
-        hipLaunchKernelGGL(k_mom_sweep32, grid3_rb(P), b, 0, c->stream, P, M32, c->r32[0], c->r32[1], c->r32[2], c->a32,
-                           c->d32[0], c->d32[1], c->d32[2], c->u[0], c->u[1], c->u[2], color,
-                           s == 0 && color == 0 ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
+        launch_ev(k_mom_sweep32, grid3_rb(P), b, c->stream, ev, P, M32, c->r32[0], c->r32[1], c->r32[2], c->a32,
+                  c->d32[0], c->d32[1], c->d32[2], c->u[0], c->u[1], c->u[2], color, first ? 1 : 0,
+                  s == P.n_sweeps - 1 ? 1 : 0);
       else
-        hipLaunchKernelGGL(k_mom_sweep, grid3_rb(P), b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
-                           c->u[0], c->u[1], c->u[2], color);
+        launch_ev(k_mom_sweep, grid3_rb(P), b, c->stream, ev, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
+                  c->u[1], c->u[2], color);
     }
-  timer_end(c, T_MOMSWEEP, 2 * P.n_sweeps);
   // 3. u <- u + alpha_u (u_ib - u)
   if (c->n_bc + c->n_ic > 0)
     hipLaunchKernelGGL(k_correct_list, dim3(nblocks1(c->n_bc + c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_bc,
@@ -930,9 +885,8 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
     st = turbulence_stage(c);
     if (st != HFDIB_OK) return st;
   }
-  hipLaunchKernelGGL(k_residuals, dim3(1), dim3(64), 0, c->stream, S, P.dim, P.model != HFDIB_LAMINAR ? 1 : 0,
-                     S + SC_RES);
-  timer_end(c, T_ITER);
+  ev = timer_launch(c, T_ITER, false, true);
+  launch_ev(k_residuals, dim3(1), dim3(64), c->stream, ev, S, P.dim, P.model != HFDIB_LAMINAR ? 1 : 0, S + SC_RES);
   HFDIB_CHECK_LAUNCH(c, "residuals");
   if (res_host) {
     HFDIB_CHECK(c, hipMemcpyAsync(res_host, S + SC_RES, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream),

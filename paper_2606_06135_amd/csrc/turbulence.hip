@@ -88,6 +88,53 @@ struct WallList {
   const double* utl;
 };
 
+// Turbulence inputs of the previous iterate, taken before this stage changes
+// any k or omega/eps value: the SST blending F1 and grad k . grad omega (the
+// cross-diffusion term), and per block the maximum of omega/eps over the cells
+// outside the in-solid group (the value imposed on in-solid cells)
+__global__ void __launch_bounds__(256)
+k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv, const double* dw, double* F1,
+              double* kwo, double* part) {
+  double wmx = 0.0;
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  if (i < P.nx && j < P.ny) {
+    const long long c = cidx(P, i, j, k);
+    const uint8_t fl = flags[c];
+    if (P.model == HFDIB_KOMEGA_SST) {
+      const Nbr N = make_nbr(P, i, j, k, c);
+      const bool solid = fl & F_SOLID;
+      const double kk = kv[c], ww = wv[c];
+      double gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if (d >= P.dim) continue;
+        gk[d] = ggrad_bf(P, kv, N, c, d, sc_bface(P, d, +1, solid, kk, P.k_in), sc_bface(P, d, -1, solid, kk, P.k_in));
+        gw[d] = ggrad_bf(P, wv, N, c, d, sc_bface(P, d, +1, solid, ww, P.w_in), sc_bface(P, d, -1, solid, ww, P.w_in));
+      }
+      const double kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
+      const double dwc = dw[c];
+      double cd = 2.0 * P.sigma_w2 / ww * kw;
+      cd = cd > P.cd_floor ? cd : P.cd_floor;
+      const double a = sqrt(kk) / (P.Cmu * ww * dwc);
+      const double bb = 500.0 * P.nu / (dwc * dwc * ww);
+      const double m1 = a > bb ? a : bb;
+      const double m2 = 4.0 * P.sigma_w2 * kk / (cd * dwc * dwc);
+      const double arg1 = m1 < m2 ? m1 : m2;
+      const double a2 = arg1 * arg1;
+      F1[c] = tanh(a2 * a2);
+      kwo[c] = kw;
+    }
+    if (!(fl & F_IC)) wmx = wv[c];
+  }
+  __shared__ double lmax[4];
+  const double m = wave_max(wmx);
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  if ((tid & 63) == 0) lmax[tid >> 6] = m;
+  __syncthreads();
+  if (tid == 0) part[block_linear()] = fmax(fmax(lmax[0], lmax[1]), fmax(lmax[2], lmax[3]));
+}
+
 // imposed omega/eps and production on the boundary cells and the domain-wall
 // cells (one thread per list entry), and on the in-solid cells (omega/eps = the
 // maximum over the other cells, no production), in one launch
@@ -519,9 +566,12 @@ int turbulence_stage(hfdib_ctx* c) {
   double* wmax = S + SC_WMAX;
   G9 Gs;
   for (int q = 0; q < 9; ++q) Gs.g[q] = c->G[q];
-  // imposed omega/eps and production on boundary, wall and in-solid cells (the
-  // maximum of omega/eps over cells outside the in-solid group was reduced in the momentum
-  // assembly, before any omega/eps value changed)
+  // SST blending and cross diffusion of the previous iterate, maximum of
+  // omega/eps over cells outside the in-solid group
+  hipLaunchKernelGGL(k_turb_inputs, g, b, 0, c->stream, P, (const uint8_t*)c->flags, (const double*)c->k,
+                     (const double*)c->w, (const double*)c->dw, c->F1, c->t2, c->partials);
+  launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4);
+  // imposed omega/eps and production on boundary, wall and in-solid cells
   {
     WallList L0{c->n_bc, c->bc_cells, c->bc_yeff, c->bc_n, c->bc_yplus, c->bc_utau};
     WallList L1{c->n_wall, c->wall_cells, c->wall_y, c->wall_n, c->wall_yplus, c->wall_utau};
@@ -557,25 +607,22 @@ int turbulence_stage(hfdib_ctx* c) {
   // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
   // (one timing span over the 2 n_s consecutive launches)
   auto sweeps = [&](int eq, double* x, uint8_t fixmask) {
-    timer_begin(c, T_SCALSWEEP);
     for (int s = 0; s < P.n_sweeps; ++s)
       for (int color = 0; color < 2; ++color) {
+        const bool first = s == 0 && color == 0, last = s == P.n_sweeps - 1 && color == 1;
+        LaunchEv ev = timer_launch(c, T_SCALSWEEP, first, last, 2 * P.n_sweeps);
         if (mixed)
-          hipLaunchKernelGGL(k_scalar_sweep32, grid3_rb(P), b, 0, c->stream, P, S32, c->flags, (const float*)c->gam32,
-                             r32, a32, c->d32[0], x, color, fixmask, s == 0 && color == 0 ? 1 : 0,
-                             s == P.n_sweeps - 1 ? 1 : 0);
+          launch_ev(k_scalar_sweep32, grid3_rb(P), b, c->stream, ev, P, S32, c->flags, c->gam32, r32, a32, c->d32[0], x,
+                    color, fixmask, first ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
         else
-          hipLaunchKernelGGL(k_scalar_sweep, grid3_rb(P), b, 0, c->stream, P, Sc, (const double*)gam_c, c->t0, c->t1,
-                             x, color, fixmask);
+          launch_ev(k_scalar_sweep, grid3_rb(P), b, c->stream, ev, P, Sc, gam_c, c->t0, c->t1, x, color, fixmask);
       }
-    timer_end(c, T_SCALSWEEP, 2 * P.n_sweeps);
   };
   // omega / eps equation, alpha_omega rows fixed
-  timer_begin(c, T_SCALASM);
   auto assemble = P.model == HFDIB_RKEPS ? k_scalar_assemble<true> : k_scalar_assemble<false>;
-  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 0, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
-                     mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride);
-  timer_end(c, T_SCALASM);
+  LaunchEv ev = timer_launch(c, T_SCALASM, true, true);
+  launch_ev(assemble, g, b, c->stream, ev, P, Sc, 0, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
+            mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
   sweeps(0, c->w, (uint8_t)F_ALPHA_W);
   // k_ib, then the k equation with S_ib (bounds omega/eps on the way)
@@ -583,10 +630,9 @@ int turbulence_stage(hfdib_ctx* c) {
     hipLaunchKernelGGL(k_kib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
                        c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->bc_yplus, c->bc_utau, c->k,
                        c->kib);
-  timer_begin(c, T_SCALASM);
-  hipLaunchKernelGGL(assemble, g, b, 0, c->stream, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
-                     mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride);
-  timer_end(c, T_SCALASM);
+  ev = timer_launch(c, T_SCALASM, true, true);
+  launch_ev(assemble, g, b, c->stream, ev, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
+            mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
   hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, Gs, c->kib, c->k, c->w,
