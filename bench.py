@@ -20,6 +20,10 @@ fixed PCG count, device-side convergence flags), with tile widths chosen per
 grid size by the autotuner, reporting instance-iterations per second and each
 instance's drag and lift coefficients.
 
+The same 256 x 96 x 96 workload is also timed under the other closures
+(k-epsilon, k-omega, realizable k-epsilon), with y+ from y_perp alone, and with
+the linear-upwind and van Leer momentum convection ("variants").
+
 Prints one JSON line (see the fields below).  --gpus N > 1 is refused: the
 library runs on one GPU.
 """
@@ -28,6 +32,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -110,6 +115,9 @@ def main():
     ap.add_argument("--mixed-case", default="ahmed2", choices=["ahmed", "ahmed2", "none"])
     ap.add_argument("--mixed-tol", type=float, default=1e-8)
     ap.add_argument("--mixed-maxit", type=int, default=5000)
+    ap.add_argument("--variant-steps", type=int, default=30,
+                    help="timed iterations of each closure / scheme variant (0: skip)")
+    ap.add_argument("--variant-warmup", type=int, default=10)
     ap.add_argument("--sweep-iters", type=int, default=600, help="iterations of the batched NACA sweep (0: skip)")
     ap.add_argument("--sweep-pcg", type=int, default=4, help="PCG iterations per pressure solve in the sweep")
     ap.add_argument("--sweep-warmup", type=int, default=20,
@@ -241,6 +249,9 @@ def main():
     mixed = None
     if args.mixed_case != "none":
         mixed = mixed_vs_fp64(args)
+    var = None
+    if args.variant_steps > 0 and args.case == "ahmed":
+        var = variants(args, elapsed / done * 1e3)
     sweep = None
     if args.sweep_iters > 0:
         sweep = naca_sweep(args)
@@ -272,6 +283,7 @@ def main():
         "cpu_baseline": cpu,
         "mixed_vs_fp64": mixed,
         "naca_sweep": sweep,
+        "variants": var,
     }
     print(json.dumps(out), flush=True)
 
@@ -310,6 +322,48 @@ def mixed_vs_fp64(args):
             "fp64": runs["fp64"], "mixed": runs["mixed"],
             "speedup": round(runs["fp64"]["seconds"] / runs["mixed"]["seconds"], 4),
             "rel_l2_mixed_vs_fp64": err}
+
+
+VARIANTS = (("keps", "upwind", "eff"), ("komega", "upwind", "eff"), ("rkeps", "upwind", "eff"),
+            ("sst", "upwind", "perp"), ("sst", "linear_upwind", "eff"), ("sst", "vanleer", "eff"))
+
+
+def variants(args, base_ms):
+    """The same workload under the other closures, the y_perp variant of y+ and
+    the higher-order convection schemes: time per iteration and the momentum /
+    scalar assembly kernel averages over a short timed run each."""
+    import torch
+    import synth
+    from paper_2606_06135_amd import Solver
+    dev = torch.device("cuda:0")
+    out = []
+    for model, conv, ydist in VARIANTS:
+        spec = synth.case_ahmed(scale=1, model=model)
+        spec.conv_scheme = conv
+        spec.yplus_dist = ydist
+        s = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=200)
+        s.set_indicator(torch.from_numpy(spec.lam.ravel()).to(dev))
+        s.iterate(args.variant_warmup)
+        torch.cuda.synchronize()
+        s.timing(True, args.timing_every)
+        t0 = time.perf_counter()
+        done, res = s.iterate(args.variant_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        rec = {"model": model, "convection": conv, "yplus_distance": ydist, "iterations": done,
+               "ms_per_iteration": round(dt / done * 1e3, 4),
+               "pcg_iters_per_step": round(s.stats()[0] / max(done, 1), 2),
+               "finite": bool(all(math.isfinite(x) for x in res))}
+        for cls in ("mom_assemble", "scalar_assemble"):
+            ms, cnt = s.timing_query(cls)
+            rec[cls + "_avg_us"] = round(ms / cnt * 1e3, 2) if cnt else None
+        s.timing(False)
+        log(f"variant {model}/{conv}/{ydist}: {rec['ms_per_iteration']} ms per iteration")
+        out.append(rec)
+        del s
+        torch.cuda.empty_cache()
+    return {"workload": "ahmed_256x96x96", "warmup": args.variant_warmup, "steps": args.variant_steps,
+            "reference_sst_upwind_ms_per_iteration": round(base_ms, 4), "runs": out}
 
 
 def naca_sweep(args):

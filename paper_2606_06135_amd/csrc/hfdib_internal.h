@@ -137,10 +137,12 @@ struct hfdib_ctx {
   double* partials2; // 16 rows of FIN2_STRIDE second-stage partials
   double* scal;      // 512 scalars
   int* iscal;        // 64 ints
-  // pinned, host-coherent mirror of the first NMIR PCG scalars, written by the
-  // device after each PCG iteration (the host reads it after a stream sync)
+  // pinned, host-coherent mirror of the first NMIR PCG scalars and, after
+  // them, the sequence number of the CG step that wrote them (the host waits
+  // for it instead of synchronising the stream)
   double* hmir;
-  double* hmir_dev;  // its device address
+  double* hmir_dev;    // its device address
+  long long mir_seq;   // sequence number of the last CG step enqueued
   // --- multigrid
   int nlev;
   hfdib::Level lev[hfdib::MAX_LEVELS];
@@ -231,9 +233,10 @@ int refresh_mirrors(hfdib_ctx* c);
 
 // deterministic reduction of `nval` rows of per-block partial sums into
 // ctx->scal[SCAL_PCG + out + v]; op selects a PCG scalar update (pressure.hip)
-// (hmir: after the update, copy scal[SCAL_PCG .. SCAL_PCG + NMIR) to that host mirror)
+// (hmir: after the update, copy scal[SCAL_PCG .. SCAL_PCG + NMIR) to that host
+// mirror, then write seq to hmir[NMIR])
 void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0,
-                     double* hmir = nullptr);
+                     double* hmir = nullptr, double seq = 0.0);
 int turbulence_stage(hfdib_ctx* c);
 int velocity_gradient(hfdib_ctx* c);
 int body_forces(hfdib_ctx* c, double* out8);

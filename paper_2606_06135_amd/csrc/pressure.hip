@@ -829,7 +829,7 @@ constexpr int FIN_THREADS = 1024;
 constexpr int FIN_BATCH = 8;
 __global__ void __launch_bounds__(FIN_THREADS)
 k_finalize(const double* part, long long pstride, int nblk, double* scal, int out, int op, double divisor,
-           double* hmir) {
+           double* hmir, double seq) {
   __shared__ double lds[FIN_THREADS / 64];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, v = blockIdx.x;
   const double* row = part + (long long)v * pstride;
@@ -860,7 +860,11 @@ k_finalize(const double* part, long long pstride, int nblk, double* scal, int ou
       scal[S_RHO] = t;
     }
     if (hmir) {
+      // the scalars, then (once they are visible to the host) the sequence
+      // number the host waits for
       for (int q = 0; q < NMIR; ++q) hmir[q] = scal[q];
+      __threadfence_system();
+      *(volatile double*)(hmir + NMIR) = seq;
       __threadfence_system();
     }
   }
@@ -894,7 +898,8 @@ static dim3 lgrid_rb(int nx, int ny, int nz) { return dim3(((nx + 1) / 2 + 63) /
 // finalize helper; partial slots live in ctx->partials with row stride c->pstride
 // Large partial rows are first reduced in fixed chunks by many workgroups
 // (deterministic: fixed chunk boundaries and order), then by one workgroup.
-void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0, double* hmir) {
+void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor, int row0, double* hmir,
+                     double seq) {
   const double* part = c->partials + (long long)row0 * c->pstride;
   if (nblk > 32 * FIN_THREADS) {
     int chunk = (nblk + FIN2_CHUNKS - 1) / FIN2_CHUNKS;
@@ -902,22 +907,31 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), 0, c->stream, part, c->pstride, nblk,
                        chunk, op == 4 ? 1 : 0, c->partials2);
     hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, (const double*)c->partials2,
-                       (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor, hmir);
+                       (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor, hmir, seq);
     return;
   }
   hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, part, c->pstride, nblk,
-                     c->scal + SCAL_PCG, out, op, divisor, hmir);
+                     c->scal + SCAL_PCG, out, op, divisor, hmir, seq);
+}
+
+// the first pass of a V-cycle: fine-level pre-smoothing of z from zero (it
+// writes z alone)
+template <typename T>
+static void vcycle_presmooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z) {
+  const Params& P = c->P;
+  hipLaunchKernelGGL(k_fine_presmooth<T>, grid3_rb(P), block3(P), 0, c->stream, P, O, invD, r, z);
 }
 
 // one V-cycle z = M^-1 r in storage type T; the last sweep also leaves the
 // block partial sums of rdot . z in the partials (rdot: the FP64 residual) and,
-// with dcopy, writes z to that FP64 vector as well; returns the partial count
+// with dcopy, writes z to that FP64 vector as well; returns the partial count.
+// presmoothed: the first pass (vcycle_presmooth) is already enqueued.
 template <typename T>
 static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, const double* rdot,
-                  double* dcopy = nullptr) {
+                  double* dcopy = nullptr, bool presmoothed = false) {
   const Params& P = c->P;
   dim3 g = grid3_rb(P), bf = block3(P), b = block_lv();
-  hipLaunchKernelGGL(k_fine_presmooth<T>, g, bf, 0, c->stream, P, O, invD, r, z);
+  if (!presmoothed) vcycle_presmooth<T>(c, O, invD, r, z);
   const T* zc = nullptr;
   int cnx = 0, cny = 0;
   if (c->nlev > 1) {
@@ -993,45 +1007,178 @@ static void build_levels(hfdib_ctx* c, const FineOp& O) {
 // is T (FP64; FP32 under the mixed policy, where r32/z32 hold the FP32 copies
 // of the residual and of the preconditioned residual).
 template <typename T>
-static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* invD, const double* rhs, double* x,
-               T* r_m, T* z_m, float* r32, double rtol, int maxit, int* iters, double* relres,
-               const double* xmean_dev) {
+struct PcgSet {
+  FineOp O;         // FP64 fine operator (residual, operator apply)
+  FineOpT<T> OM;    // fine operator of the preconditioner
+  const T* invD;    // its inverse diagonal
+  T* r_m;           // preconditioner input (the residual, or its FP32 copy)
+  T* z_m;           // preconditioner output
+  float* r32;       // FP32 copy of the residual (mixed policy) or null
+};
+template <typename T>
+static PcgSet<T> pcg_set(hfdib_ctx* c, const double* rAU);
+template <>
+PcgSet<double> pcg_set<double>(hfdib_ctx* c, const double* rAU) {
+  return PcgSet<double>{FineOp{rAU, c->flags}, FineOp{rAU, c->flags}, c->invD, c->pr, c->pz, nullptr};
+}
+template <>
+PcgSet<float> pcg_set<float>(hfdib_ctx* c, const double* rAU) {
+  return PcgSet<float>{FineOp{rAU, c->flags}, FineOpT<float>{c->rAU32, c->flags}, c->invD32, c->pr32, c->pz32,
+                       c->pr32};
+}
+
+// inverse diagonal of the fine smoother (and, mixed, the FP32 copy of rAU) and
+// the coarse operators from the FP64 fine operator
+template <typename T>
+static void pcg_operators(hfdib_ctx* c, const PcgSet<T>& A) {
+  const Params& P = c->P;
+  hipLaunchKernelGGL(k_fine_invdiag<T>, grid3(P), block3(P), 0, c->stream, P, A.O, const_cast<T*>(A.invD),
+                     sizeof(T) == sizeof(float) ? c->rAU32 : (float*)nullptr);
+  build_levels<T>(c, A.O);
+}
+
+// r = b - A x, |b| and the SIMPLE residual sums, then d = z = M^-1 r
+template <typename T>
+static void pcg_start(hfdib_ctx* c, const PcgSet<T>& A, const double* rhs, double* x, const double* xmean_dev) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3(P);
-  long long nblk3 = (long long)g.x * g.y * g.z;
-  int nb1 = nblocks1(P.N);
-  double* r = c->pr;
-  double* d = c->pd;
-  double* q = c->pq;
+  hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, A.O, rhs, x, c->pr, A.r32, xmean_dev, c->partials,
+                     c->pstride);
+  // [20] = rr0, [21] = bb, [22..24] = residual sums
+  launch_finalize(c, (int)((long long)g.x * g.y * g.z), 5, S_BB + 16, 0);
+  launch_finalize(c, vcycle<T>(c, A.OM, A.invD, A.r_m, A.z_m, c->pr, c->pd), 1, S_RZ, 3);  // d = z
+}
+
+// one CG step: q = A d, alpha, x += alpha d, r -= alpha q, r.r (the reduction of
+// r.r also copies the PCG scalars to the pinned host mirror hmir when given)
+template <typename T>
+static void pcg_step(hfdib_ctx* c, const PcgSet<T>& A, double* x, double* hmir) {
+  const Params& P = c->P;
+  dim3 g = grid3(P), b = block3(P);
+  const int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
-  hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, O, rhs, x, r, r32, xmean_dev, c->partials, c->pstride);
-  launch_finalize(c, (int)nblk3, 5, S_BB + 16, 0);  // [20]=rr0 [21]=bb [22..24]=residual sums
-  // at least one PCG iteration is done; the host reads the residual after each
-  // iteration (one synchronisation per iteration, none before the first)
-  launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r, d), 1, S_RZ, 3);  // d = z
-  if (c->graph_mode) {
-    // fixed iteration count, no host read (the step may be captured in a graph);
-    // the scalar updates guard zero denominators on the device
-    const int nit = c->graph_pcg;
-    for (int it = 1; it <= nit; ++it) {
-      hipLaunchKernelGGL(k_fine_apply, g, b, 0, c->stream, P, O, d, q, c->partials, c->pstride);
-      launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
-      hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, r32, q, c->partials,
-                         c->pstride);
-      launch_finalize(c, nb1, 1, S_RR, 0);
-      if (it == nit) break;
-      launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r), 1, S_RZ, 2);
-      hipLaunchKernelGGL(k_xpby<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, (const T*)z_m, d);
+  LaunchEv ev = timer_launch(c, T_PAPPLY, true, true);
+  launch_ev(k_fine_apply, g, b, c->stream, ev, P, A.O, (const double*)c->pd, c->pq, c->partials, c->pstride);
+  launch_finalize(c, (int)((long long)g.x * g.y * g.z), 1, S_DQ, 1);
+  hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const double*)S, x, (const double*)c->pd,
+                     c->pr, A.r32, (const double*)c->pq, c->partials, c->pstride);
+  launch_finalize(c, nb1, 1, S_RR, 0, 1.0, 0, hmir, hmir ? (double)++c->mir_seq : 0.0);
+}
+
+// z = M^-1 r, beta = r.z / rho, d = z + beta d
+template <typename T>
+static void pcg_direction(hfdib_ctx* c, const PcgSet<T>& A, bool presmoothed = false) {
+  const Params& P = c->P;
+  double* S = c->scal + SCAL_PCG;
+  launch_finalize(c, vcycle<T>(c, A.OM, A.invD, A.r_m, A.z_m, c->pr, nullptr, presmoothed), 1, S_RZ, 2);
+  hipLaunchKernelGGL(k_xpby<T>, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, (const double*)S,
+                     (const T*)A.z_m, c->pd);
+}
+
+// The adaptive solve in the pieces between which the host reads the
+// convergence scalars: the set-up with the first CG step, and each further
+// step (both end with the reduction that writes the pinned host mirror).
+// While the host waits for a step's scalars the first pass of the next
+// V-cycle is already queued (it only writes the preconditioner output z, so it
+// is harmless when the solve has converged): the device does not idle for the
+// host's round trip.
+template <typename T>
+static void pcg_begin_t(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, const double* xmean_dev) {
+  PcgSet<T> A = pcg_set<T>(c, rAU);
+  pcg_operators<T>(c, A);
+  pcg_start<T>(c, A, rhs, x, xmean_dev);
+  pcg_step<T>(c, A, x, c->hmir_dev);
+}
+template <typename T>
+static void pcg_ahead_t(hfdib_ctx* c, const double* rAU) {
+  PcgSet<T> A = pcg_set<T>(c, rAU);
+  vcycle_presmooth<T>(c, A.OM, A.invD, A.r_m, A.z_m);
+}
+template <typename T>
+static void pcg_continue_t(hfdib_ctx* c, const double* rAU, double* x, bool presmoothed) {
+  PcgSet<T> A = pcg_set<T>(c, rAU);
+  pcg_direction<T>(c, A, presmoothed);
+  pcg_step<T>(c, A, x, c->hmir_dev);
+}
+static void pcg_begin(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, const double* xmean_dev) {
+  if (c->P.precision == HFDIB_MIXED)
+    pcg_begin_t<float>(c, rAU, rhs, x, xmean_dev);
+  else
+    pcg_begin_t<double>(c, rAU, rhs, x, xmean_dev);
+}
+static void pcg_ahead(hfdib_ctx* c, const double* rAU) {
+  if (c->P.precision == HFDIB_MIXED)
+    pcg_ahead_t<float>(c, rAU);
+  else
+    pcg_ahead_t<double>(c, rAU);
+}
+static void pcg_continue(hfdib_ctx* c, const double* rAU, double* x, bool presmoothed) {
+  if (c->P.precision == HFDIB_MIXED)
+    pcg_continue_t<float>(c, rAU, x, presmoothed);
+  else
+    pcg_continue_t<double>(c, rAU, x, presmoothed);
+}
+
+// Waits until the host mirror holds the scalars of the last CG step: spins on
+// its sequence number (the device writes it after the scalars), checking the
+// stream now and then so that a device error ends the wait.
+static int wait_mirror(hfdib_ctx* c) {
+  volatile const double* m = c->hmir;
+  const double want = (double)c->mir_seq;
+  for (unsigned long n = 1; m[NMIR] != want; ++n) {
+    if ((n & 255) == 0) {
+      hipError_t e = hipStreamQuery(c->stream);
+      if (e == hipErrorNotReady) continue;
+      if (e != hipSuccess) return set_hip_error(c, e, "pcg wait");
+      if (m[NMIR] == want) break;
+      c->err = "pcg wait: the stream is idle but the scalars of the last step did not arrive";
+      return HFDIB_EDEVICE;
     }
+  }
+  return HFDIB_OK;
+}
+
+// fixed iteration count, no host read (the step may be captured in a graph);
+// the scalar updates guard zero denominators on the device
+template <typename T>
+static void pcg_fixed(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, const double* xmean_dev,
+                      int nit) {
+  PcgSet<T> A = pcg_set<T>(c, rAU);
+  pcg_operators<T>(c, A);
+  pcg_start<T>(c, A, rhs, x, xmean_dev);
+  for (int it = 1; it <= nit; ++it) {
+    pcg_step<T>(c, A, x, nullptr);
+    if (it == nit) break;
+    pcg_direction<T>(c, A);
+  }
+}
+
+void pressure_apply_bench(hfdib_ctx* c) {
+  const Params& P = c->P;
+  FineOp O{c->rAU, c->flags};
+  hipLaunchKernelGGL(k_fine_apply, grid3(P), block3(P), 0, c->stream, P, O, (const double*)c->pd, c->pq, c->partials,
+                     c->pstride);
+}
+
+int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol, int maxit, int* iters,
+                   double* relres, const double* xmean_dev) {
+  const Params& P = c->P;
+  timer_begin(c, T_PSOLVE);
+  if (c->graph_mode) {
+    if (P.precision == HFDIB_MIXED)
+      pcg_fixed<float>(c, rAU, rhs, x, xmean_dev, c->graph_pcg);
+    else
+      pcg_fixed<double>(c, rAU, rhs, x, xmean_dev, c->graph_pcg);
     HFDIB_CHECK_LAUNCH(c, "pcg (fixed)");
-    if (iters) *iters = nit;
+    timer_end(c, T_PSOLVE);
+    if (iters) *iters = c->graph_pcg;
     if (relres) *relres = 0.0;
     return HFDIB_OK;
   }
   if (!c->hmir) {
     // host-coherent pinned mirror of the PCG scalars, allocated on first use
     void *hm = nullptr, *hm_dev = nullptr;
-    HFDIB_CHECK(c, hipHostMalloc(&hm, NMIR * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent),
+    HFDIB_CHECK(c, hipHostMalloc(&hm, (NMIR + 1) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent),
                 "pinned scalar mirror");
     hipError_t e = hipHostGetDevicePointer(&hm_dev, hm, 0);
     if (e != hipSuccess) {
@@ -1040,20 +1187,21 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
     }
     c->hmir = (double*)hm;
     c->hmir_dev = (double*)hm_dev;
+    c->hmir[NMIR] = 0.0;
+    c->mir_seq = 0;
   }
+  // at least one CG step is done; the host reads the residual after each step
+  // (one synchronisation per step, none before the first)
   double rr = 0.0, bnorm = 1.0, target = 0.0;
   int it;
+  pcg_begin(c, rAU, rhs, x, xmean_dev);
+  HFDIB_CHECK_LAUNCH(c, "pcg set-up");
   for (it = 1; it <= maxit; ++it) {
-    LaunchEv ev = timer_launch(c, T_PAPPLY, true, true);
-    launch_ev(k_fine_apply, g, b, c->stream, ev, P, O, d, q, c->partials, c->pstride);
-    launch_finalize(c, (int)nblk3, 1, S_DQ, 1);
-    hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, x, d, r, r32, q, c->partials,
-                       c->pstride);
-    // the reduction of r.r also writes the scalars to the pinned host mirror
-    launch_finalize(c, nb1, 1, S_RR, 0, 1.0, 0, c->hmir_dev);
-    HFDIB_CHECK_LAUNCH(c, "pcg iteration");
-    HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "sync");
-    const double* hs = c->hmir;
+    if (it < maxit) pcg_ahead(c, rAU);
+    HFDIB_CHECK_LAUNCH(c, "pcg look-ahead");
+    int st = wait_mirror(c);
+    if (st != HFDIB_OK) return st;
+    const volatile double* hs = c->hmir;
     if (it == 1) {
       double bb = hs[S_BB + 17];
       bnorm = sqrt(bb) > 0.0 ? sqrt(bb) : 1.0;
@@ -1067,45 +1215,15 @@ static int pcg(hfdib_ctx* c, const FineOp& O, const FineOpT<T>& OM, const T* inv
       c->err = "non-finite residual in the pressure solve";
       return HFDIB_EDIVERGED;
     }
-    if (sqrt(rr) <= target) break;
-    if (it == maxit) break;
-    launch_finalize(c, vcycle<T>(c, OM, invD, r_m, z_m, r), 1, S_RZ, 2);
-    hipLaunchKernelGGL(k_xpby<T>, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, S, (const T*)z_m, d);
+    if (sqrt(rr) <= target || it == maxit) break;
+    pcg_continue(c, rAU, x, true);
+    HFDIB_CHECK_LAUNCH(c, "pcg iteration");
   }
   if (it > maxit) it = maxit;
-  HFDIB_CHECK_LAUNCH(c, "pcg");
+  timer_end(c, T_PSOLVE);
   if (iters) *iters = it;
   if (relres) *relres = sqrt(rr) / bnorm;
   return HFDIB_OK;
-}
-
-void pressure_apply_bench(hfdib_ctx* c) {
-  const Params& P = c->P;
-  FineOp O{c->rAU, c->flags};
-  hipLaunchKernelGGL(k_fine_apply, grid3(P), block3(P), 0, c->stream, P, O, (const double*)c->pd, c->pq, c->partials,
-                     c->pstride);
-}
-
-int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, double rtol, int maxit, int* iters,
-                   double* relres, const double* xmean_dev) {
-  const Params& P = c->P;
-  FineOp O{rAU, c->flags};
-  int st;
-  timer_begin(c, T_PSOLVE);
-  if (P.precision == HFDIB_MIXED) {
-    // FP32 mirror of rAU and inverse diagonal for the fine smoother; coarse
-    // operators from the FP64 fine operator
-    hipLaunchKernelGGL(k_fine_invdiag<float>, grid3(P), block3(P), 0, c->stream, P, O, c->invD32, c->rAU32);
-    build_levels<float>(c, O);
-    FineOpT<float> OM{c->rAU32, c->flags};
-    st = pcg<float>(c, O, OM, c->invD32, rhs, x, c->pr32, c->pz32, c->pr32, rtol, maxit, iters, relres, xmean_dev);
-  } else {
-    hipLaunchKernelGGL(k_fine_invdiag<double>, grid3(P), block3(P), 0, c->stream, P, O, c->invD, (float*)nullptr);
-    build_levels<double>(c, O);
-    st = pcg<double>(c, O, O, c->invD, rhs, x, c->pr, c->pz, nullptr, rtol, maxit, iters, relres, xmean_dev);
-  }
-  timer_end(c, T_PSOLVE);
-  return st;
 }
 
 }  // namespace hfdib
