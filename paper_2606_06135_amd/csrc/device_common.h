@@ -204,6 +204,15 @@ __device__ __forceinline__ double strain2(const double (&G)[3][3]) {
 // values afterwards, so no load sits inside a divergent branch.  Face
 // q = 2 d + (s > 0) in the order W, E, S, N, B, T; faces beyond dim count as
 // domain faces.
+// b ? x : y with both operands evaluated before the choice.  Stencil code
+// writes its conditional terms this way: a conditional expression whose arms
+// contain a load is emitted as a branch around the load, and the loads of a
+// stencil then wait one after another instead of being in flight together.
+template <typename T>
+__device__ __forceinline__ T sel(bool b, T x, T y) {
+  return b ? x : y;
+}
+
 struct Nbr {
   int n[6];      // neighbour cell indices (grids hold fewer than 2^31 cells; 32-bit to save registers)
   unsigned bnd;  // bit q: face q is a domain face

@@ -49,16 +49,16 @@ template <typename T>
 __device__ __forceinline__ void fine_row(const Params& P, const FineOpT<T>& O, const Nbr& N, long long c,
                                          T (&cf)[6]) {
   const T rc = O.rAU[c];
+  T rn[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) rn[q] = O.rAU[N.n[q]];  // all six (clamped) loads in flight together
   const bool solid = O.flags[c] & F_SOLID;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const int d = q >> 1;
-    cf[q] = (T)0;
-    if (d < P.dim) {
-      T inner = (T)0.5 * (rc + O.rAU[N.n[q]]) * (T)P.AoD[d];
-      T outl = (P.p_outlet[q] && !solid) ? rc * (T)P.Ab[d] : (T)0;
-      cf[q] = is_bnd(N, q) ? outl : inner;
-    }
+    const T inner = (T)0.5 * (rc + rn[q]) * (T)P.AoD[d];
+    const T outl = sel(P.p_outlet[q] != 0 && !solid, rc * (T)P.Ab[d], (T)0);
+    cf[q] = sel(d < P.dim, sel(is_bnd(N, q), outl, inner), (T)0);
   }
 }
 
@@ -67,14 +67,16 @@ template <typename T>
 __device__ __forceinline__ T fine_Ax(const T (&cf)[6], const Nbr& N, const T* x, long long c, T& dg,
                                      T& bnd_sum) {
   const T xc = x[c];
+  T xn[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) xn[q] = x[N.n[q]];
   T acc = (T)0, bs = (T)0;
   dg = (T)0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     const bool b = is_bnd(N, q);
-    const T xn = x[N.n[q]];
-    acc += b ? cf[q] * xc : cf[q] * (xc - xn);
-    bs += b ? cf[q] : (T)0;
+    acc = sel(b, acc + cf[q] * xc, acc + cf[q] * (xc - xn[q]));
+    bs = sel(b, bs + cf[q], bs);
     dg += cf[q];
   }
   bnd_sum = bs;
@@ -178,12 +180,15 @@ __global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T*
   Nbr N = make_nbr(P, ib, j, k, c);
   T cf[6];
   fine_row(P, O, N, c, cf);
-  T nb = (T)0;
+  T rn[6], dn[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
-    long long n = N.n[q];
-    nb += is_bnd(N, q) ? (T)0 : cf[q] * (r[n] * invD[n]);
+    rn[q] = r[N.n[q]];
+    dn[q] = invD[N.n[q]];
   }
+  T nb = (T)0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) nb = sel(is_bnd(N, q), nb, nb + cf[q] * (rn[q] * dn[q]));
   z[c] = (r[c] + nb) * invD[c];
 }
 
@@ -207,20 +212,27 @@ __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r,
     T cf[6];
     fine_row(P, O, N, c, cf);
     T nb = (T)0;
+    T zn[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) zn[q] = z[N.n[q]];
     if (zc) {
       const int i2 = i >> 1, j2 = j >> 1, k2 = P.dim == 3 ? k >> 1 : 0;
+      T zp[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) {
         const int d = q >> 1, s = (q & 1) ? 1 : -1;
-        if (is_bnd(N, q)) continue;
-        // parent of the neighbour: only its coordinate along d differs
-        int pi = d == 0 ? (i + s) >> 1 : i2, pj = d == 1 ? (j + s) >> 1 : j2, pk = d == 2 ? (k + s) >> 1 : k2;
-        long long pc = (long long)pi + (long long)cnx * ((long long)pj + (long long)cny * pk);
-        nb += cf[q] * (z[N.n[q]] + zc[pc]);
+        // parent of the neighbour: only its coordinate along d differs (the
+        // own parent for a domain face, whose term is not used)
+        const bool b = is_bnd(N, q);
+        const int pi = (d == 0 && !b) ? (i + s) >> 1 : i2, pj = (d == 1 && !b) ? (j + s) >> 1 : j2;
+        const int pk = (d == 2 && !b) ? (k + s) >> 1 : k2;
+        zp[q] = zc[(long long)pi + (long long)cnx * ((long long)pj + (long long)cny * pk)];
       }
+#pragma unroll
+      for (int q = 0; q < 6; ++q) nb = sel(is_bnd(N, q), nb, nb + cf[q] * (zn[q] + zp[q]));
     } else {
 #pragma unroll
-      for (int q = 0; q < 6; ++q) nb += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
+      for (int q = 0; q < 6; ++q) nb = sel(is_bnd(N, q), nb, nb + cf[q] * zn[q]);
     }
     znew = (r[c] + nb) * invD[c];
     z[c] = znew;
@@ -479,10 +491,12 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T>
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = cidx(P, i, j, k);
         Nbr N = make_nbr(P, i, j, k, c);
-        T cf[6];
+        T cf[6], zn[6];
         fine_row(P, O, N, c, cf);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) s += is_bnd(N, q) ? (T)0 : cf[q] * z[N.n[q]];
+        for (int q = 0; q < 6; ++q) zn[q] = z[N.n[q]];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) s = sel(is_bnd(N, q), s, s + cf[q] * zn[q]);
       }
   C.r[lidx(C, I, J, K)] = s;
 }
