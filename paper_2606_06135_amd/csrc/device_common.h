@@ -157,6 +157,15 @@ __device__ __forceinline__ double sc_bface(const Params& P, int d, int s, bool s
   const bool inl = P.sc_inlet[2 * d + (s > 0 ? 1 : 0)] != 0;
   return (inl && !solid) ? vin : vP;
 }
+// b ? x : y with both operands evaluated before the choice.  Stencil code
+// writes its conditional terms this way: a conditional expression whose arms
+// contain a load is emitted as a branch around the load, and the loads of a
+// stencil then wait one after another instead of being in flight together.
+template <typename T>
+__device__ __forceinline__ T sel(bool b, T x, T y) {
+  return b ? x : y;
+}
+
 // (psi_+ - psi_-)/delta_d with linear face interpolation (Gauss gradient)
 // (loads from clamped indices: no branch around them)
 __device__ __forceinline__ double ggrad(const Params& P, const double* a, long long c, int d, int i, int j, int k,
@@ -164,8 +173,8 @@ __device__ __forceinline__ double ggrad(const Params& P, const double* a, long l
   long long st = stride(P, d);
   const bool hi = on_bnd(P, d, +1, i, j, k), lo = on_bnd(P, d, -1, i, j, k);
   double aP = a[c], ap = a[hi ? c : c + st], am = a[lo ? c : c - st];
-  double fp = hi ? fb_p : 0.5 * (aP + ap);
-  double fm = lo ? fb_m : 0.5 * (am + aP);
+  double fp = sel(hi, fb_p, 0.5 * (aP + ap));
+  double fm = sel(lo, fb_m, 0.5 * (am + aP));
   return (fp - fm) * P.idelta[d];
 }
 // d u_jj / d x_ii at cell (i,j,k) (index c, lambda > 0 flag `solid`)
@@ -182,7 +191,7 @@ __device__ __forceinline__ void gradu_all(const Params& P, const double* const* 
   for (int jj = 0; jj < 3; ++jj)
 #pragma unroll
     for (int ii = 0; ii < 3; ++ii)
-      G[ii][jj] = (ii < P.dim && jj < P.dim) ? gradu(P, u, solid, ii, jj, i, j, k, c) : 0.0;
+      G[ii][jj] = sel(ii < P.dim && jj < P.dim, gradu(P, u, solid, ii, jj, i, j, k, c), 0.0);
 }
 // 2 S:S with S the symmetric part of G (summed over all nine entries)
 __device__ __forceinline__ double strain2(const double (&G)[3][3]) {
@@ -204,15 +213,6 @@ __device__ __forceinline__ double strain2(const double (&G)[3][3]) {
 // values afterwards, so no load sits inside a divergent branch.  Face
 // q = 2 d + (s > 0) in the order W, E, S, N, B, T; faces beyond dim count as
 // domain faces.
-// b ? x : y with both operands evaluated before the choice.  Stencil code
-// writes its conditional terms this way: a conditional expression whose arms
-// contain a load is emitted as a branch around the load, and the loads of a
-// stencil then wait one after another instead of being in flight together.
-template <typename T>
-__device__ __forceinline__ T sel(bool b, T x, T y) {
-  return b ? x : y;
-}
-
 struct Nbr {
   int n[6];      // neighbour cell indices (grids hold fewer than 2^31 cells; 32-bit to save registers)
   unsigned bnd;  // bit q: face q is a domain face
@@ -242,16 +242,16 @@ __device__ __forceinline__ double gradu_bf(const Params& P, const double* uj, in
   double uP = uj[x];
   double up = uj[hi ? x : x + st];
   double um = uj[lo ? x : x - st];
-  double fp = hi ? u_bface(P, jc, a, +1, solid, uP) : 0.5 * (uP + up);
-  double fm = lo ? u_bface(P, jc, a, -1, solid, uP) : 0.5 * (um + uP);
+  double fp = sel(hi, u_bface(P, jc, a, +1, solid, uP), 0.5 * (uP + up));
+  double fm = sel(lo, u_bface(P, jc, a, -1, solid, uP), 0.5 * (um + uP));
   return (fp - fm) * P.idelta[a];
 }
 // (psi_+ - psi_-)/delta_d of a scalar from clamped loads (boundary face values given)
 __device__ __forceinline__ double ggrad_bf(const Params& P, const double* a, const Nbr& N, long long c, int d,
                                            double fb_p, double fb_m) {
   double aP = a[c], ap = a[N.n[2 * d + 1]], am = a[N.n[2 * d]];
-  double fp = is_bnd(N, 2 * d + 1) ? fb_p : 0.5 * (aP + ap);
-  double fm = is_bnd(N, 2 * d) ? fb_m : 0.5 * (am + aP);
+  double fp = sel(is_bnd(N, 2 * d + 1), fb_p, 0.5 * (aP + ap));
+  double fm = sel(is_bnd(N, 2 * d), fb_m, 0.5 * (am + aP));
   return (fp - fm) * P.idelta[d];
 }
 // full velocity gradient G[a][jc] = d u_jc / d x_a at a cell (zero outside dim)
@@ -261,9 +261,8 @@ __device__ __forceinline__ void gradu_all_bf(const Params& P, const double* cons
   for (int jc = 0; jc < 3; ++jc)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      G[a][jc] = (a < P.dim && jc < P.dim)
-                     ? gradu_bf(P, u[jc], jc, a, c, is_bnd(N, 2 * a), is_bnd(N, 2 * a + 1), solid)
-                     : 0.0;
+      G[a][jc] = sel(a < P.dim && jc < P.dim,
+                     gradu_bf(P, u[jc], jc, a, c, is_bnd(N, 2 * a), is_bnd(N, 2 * a + 1), solid), 0.0);
 }
 
 // ---------------------------------------------------------------- geometry

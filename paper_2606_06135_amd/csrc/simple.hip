@@ -194,11 +194,10 @@ __device__ __forceinline__ void mom_anb(const Params& P, const Mom& M, double nu
 #pragma unroll
     for (int sh = 0; sh < 2; ++sh) {
       const int s = sh ? 1 : -1, q = 2 * d + sh;
-      anb[q] = 0.0;
-      if (d < P.dim) {
-        double a = anb_coef(P, nuP, P.nu + M.nut[N.n[q]], d, outward_flux(P, M.phi, d, s, i, j, k));
-        anb[q] = is_bnd(N, q) ? 0.0 : a;
-      }
+      // loads from clamped indices for every face (also beyond dim: the face-flux
+      // arrays have their nz + 1 planes in 2-D as well), chosen with selects
+      const double a = anb_coef(P, nuP, P.nu + M.nut[N.n[q]], d, outward_flux(P, M.phi, d, s, i, j, k));
+      anb[q] = sel(d < P.dim && !is_bnd(N, q), a, 0.0);
     }
 }
 // sum over the faces of anb * x_nb (domain faces carry anb = 0), order W..T
@@ -220,7 +219,7 @@ __device__ __forceinline__ double nb_sum(const double (&anb)[6], const Nbr& N, c
 //   van Leer       u_f = u_C + psi(r) (u_D - u_C) / 2, psi(r) = (r + |r|) / (1 + |r|),
 //                  r = 2 (x_D - x_C) . grad u_C / (u_D - u_C) - 1 (0 where u_D = u_C)
 // (interior faces; grad u_C the stored Gauss gradient)
-template <int CONV>
+template <int CONV, int DIM>
 __global__ void __launch_bounds__(256)
 k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
                const double* means, double* part, long long pstride) {
@@ -231,142 +230,162 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
   if (act) {
     long long c = cidx(P, i, j, k);
     Nbr N = make_nbr(P, i, j, k, c);
-    uint8_t fl = M.flags[c];
-    bool solid = fl & F_SOLID;
-    double nuP = P.nu + M.nut[c];
+    // the stencil's loads first, with no store in between (a store could alias
+    // a later load and would hold it back); conditional terms are selects
+    const uint8_t fl = M.flags[c];
+    const bool solid = fl & F_SOLID;
+    const double nuP = P.nu + M.nut[c];
+    double nuN[6], fo[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      nuN[q] = P.nu + M.nut[N.n[q]];
+      fo[q] = outward_flux(P, M.phi, q >> 1, (q & 1) ? 1 : -1, i, j, k);
+    }
+    double uc[DIM], un[DIM][6];
+#pragma unroll
+    for (int cc = 0; cc < DIM; ++cc) {
+      uc[cc] = M.u[cc][c];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) un[cc][q] = M.u[cc][N.n[q]];
+    }
     double anb[6];
-    mom_anb(P, M, nuP, N, i, j, k, anb);
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      anb[q] = sel((q >> 1) < DIM && !is_bnd(N, q), anb_coef(P, nuP, nuN[q], q >> 1, fo[q]), 0.0);
     double aP = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) aP += anb[q];
     // Dirichlet domain faces (inlet, no-slip) of cells with lambda = 0
     double bsrc[3] = {0.0, 0.0, 0.0};
+    const double kc = P.model == HFDIB_LAMINAR ? 0.0 : M.k[c];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int d = 0; d < DIM; ++d)
 #pragma unroll
       for (int sh = 0; sh < 2; ++sh) {
         const int s = sh ? 1 : -1;
         int kind = face_kind(P, d, s);
-        if (d >= P.dim || (kind != HFDIB_BC_INLET && kind != HFDIB_BC_NOSLIP)) continue;
+        if (kind != HFDIB_BC_INLET && kind != HFDIB_BC_NOSLIP) continue;
         if (!is_bnd(N, 2 * d + sh) || solid) continue;
         double Gb = nuP;
         if (kind == HFDIB_BC_NOSLIP) {
           if (P.model == HFDIB_LAMINAR) {
             Gb = P.nu;
           } else {
-            double kk = M.k[c];
-            double ut = P.Cmu25 * sqrt(kk > 0.0 ? kk : 0.0);
+            double ut = P.Cmu25 * sqrt(kc > 0.0 ? kc : 0.0);
             double ypf = 0.5 * P.delta[d] * ut / P.nu;
             Gb = P.nu + nut_wall(P, ypf);
           }
         }
-        double F = outward_flux(P, M.phi, d, s, i, j, k);
-        double mf = -F;
+        double mf = -fo[2 * d + sh];
         double a = Gb * P.Ab[d] + (mf > 0.0 ? mf : 0.0);
         aP += a;
 #pragma unroll
-        for (int cc = 0; cc < 3; ++cc) {
-          if (cc >= P.dim) continue;
+        for (int cc = 0; cc < DIM; ++cc) {
           double ubv = kind == HFDIB_BC_INLET ? P.u_in[cc] : 0.0;
           bsrc[cc] += a * ubv;
         }
       }
-    double urf = P.urf_u;
-    double aPr = aP / urf;
-    aPr_out[rb_split(P, i, j, k)] = aPr;  // rhs and a'_P are stored colour-split
-    if (X.a) X.a[rb_split(P, i, j, k)] = (float)aPr;
-    bool alpha = fl & F_ALPHA_U;
-    double* rhs[3] = {rhs0, rhs1, rhs2};
-    // neighbour viscosities shared by the three components
-    double nuN[6];
+    const double urf = P.urf_u;
+    const double aPr = aP / urf;
+    const bool alpha = fl & F_ALPHA_U;
+    double rh[DIM], Ax[DIM];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) nuN[q] = P.nu + M.nut[N.n[q]];
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      if (cc >= P.dim) continue;
+    for (int cc = 0; cc < DIM; ++cc) {
       // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f, the
       // face gradient being the mean of the two cell (Gauss) gradients
       double T = 0.0;
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        if (d >= P.dim) continue;
+      for (int d = 0; d < DIM; ++d) {
         const double* Gd = M.G[3 * cc + d];
-        double GP = Gd[c];
+        const double GP = Gd[c];
 #pragma unroll
         for (int sh = 0; sh < 2; ++sh) {
           const int s = sh ? 1 : -1, q = 2 * d + sh;
           const bool fb = is_bnd(N, q);
-          double GN = Gd[N.n[q]];
-          double nuf = fb ? nuP : 0.5 * (nuP + nuN[q]);
-          double gf = fb ? GP : 0.5 * (GP + GN);
+          const double GN = Gd[N.n[q]];
+          const double nuf = sel(fb, nuP, 0.5 * (nuP + nuN[q]));
+          const double gf = sel(fb, GP, 0.5 * (GP + GN));
           T += (double)s * P.area[d] * nuf * gf;
         }
       }
-      const double* u = M.u[cc];
       if (CONV != 0) {
         double Cc = 0.0;
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          if (d >= P.dim) continue;
+        for (int d = 0; d < DIM; ++d) {
           const double* Gc = M.G[3 * d + cc];  // d u_cc / d x_d
+          const double gP = Gc[c];
 #pragma unroll
           for (int sh = 0; sh < 2; ++sh) {
             const int s = sh ? 1 : -1, q = 2 * d + sh;
-            if (is_bnd(N, q)) continue;
-            const long long n = N.n[q];
-            const double F = outward_flux(P, M.phi, d, s, i, j, k);
+            const double gN = Gc[N.n[q]];
+            const double F = fo[q];
             const bool up = F > 0.0;
-            const double uC = up ? u[c] : u[n], uD = up ? u[n] : u[c];
-            const double gC = up ? Gc[c] : Gc[n];
-            const double dxC = (double)(up ? s : -s) * 0.5 * P.delta[d];
+            const double uC = sel(up, uc[cc], un[cc][q]), uD = sel(up, un[cc][q], uc[cc]);
+            const double gC = sel(up, gP, gN);
+            const double dxC = (double)s * 0.5 * P.delta[d] * sel(up, 1.0, -1.0);
             double uf;
             if (CONV == 1) {
               uf = uC + dxC * gC;
             } else {
               const double dCD = uD - uC;
-              const double r = dCD != 0.0 ? 2.0 * (2.0 * dxC * gC) / dCD - 1.0 : 0.0;
+              const double r = sel(dCD != 0.0, 2.0 * (2.0 * dxC * gC) / dCD - 1.0, 0.0);
               const double psi = (r + fabs(r)) / (1.0 + fabs(r));
               uf = uC + 0.5 * psi * dCD;
             }
-            Cc = Cc - F * (uf - uC);
+            Cc = sel(is_bnd(N, q), Cc, Cc - F * (uf - uC));
           }
         }
         T = T + Cc;
       }
-      double b0 = T + bsrc[cc];
-      double g = gradp_V(P, M.p, fl, cc, i, j, k, c);
-      double uo = u[c];
-      double r = (1.0 - urf) / urf * aP * uo;
-      double nb = nb_sum(anb, N, u);
-      double rh;
+      const double b0 = T + bsrc[cc];
+      // V (grad p)_c, Gauss with linear interpolation
+      const double pP = M.p[c], pp = M.p[N.n[2 * cc + 1]], pm = M.p[N.n[2 * cc]];
+      const double fp = sel(is_bnd(N, 2 * cc + 1), p_bface(P, cc, +1, solid, pP), 0.5 * (pP + pp));
+      const double fm = sel(is_bnd(N, 2 * cc), p_bface(P, cc, -1, solid, pP), 0.5 * (pm + pP));
+      const double g = P.V * ((fp - fm) * P.idelta[cc]);
+      const double uo = uc[cc];
+      const double r = (1.0 - urf) / urf * aP * uo;
+      double nb = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) nb += anb[q] * un[cc][q];
+      double rr;
       if (alpha) {
         const double* ub = M.uib[cc];
         double nbt = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
           long long n = N.n[q];
-          double ut = (M.flags[n] & F_ALPHA_U) ? ub[n] : u[n];
+          double ut = (M.flags[n] & F_ALPHA_U) ? ub[n] : un[cc][q];
           nbt += anb[q] * ut;
         }
         double ut = ub[c];
-        rh = (aP * ut - nbt) + r;
+        rr = (aP * ut - nbt) + r;
       } else {
-        rh = (b0 - g) + r;
+        rr = (b0 - g) + r;
       }
-      rhs[cc][rb_split(P, i, j, k)] = rh;
-      double Ax = aPr * uo - nb;
-      // mixed policy: FP64 defect of the row (every row is swept) for the FP32
-      // correction
-      if (X.a) X.r[cc][rb_split(P, i, j, k)] = (float)(rh - Ax);
+      rh[cc] = rr;
+      Ax[cc] = aPr * uo - nb;
       if (!alpha) {
         double one = 0.0;
 #pragma unroll
         for (int q = 0; q < 6; ++q) one += anb[q];
         double Axb = (aPr - one) * means[cc];
-        red[3 * cc + 0] = fabs(rh - Ax);
-        red[3 * cc + 1] = fabs(Ax - Axb);
-        red[3 * cc + 2] = fabs(rh - Axb);
+        red[3 * cc + 0] = fabs(rr - Ax[cc]);
+        red[3 * cc + 1] = fabs(Ax[cc] - Axb);
+        red[3 * cc + 2] = fabs(rr - Axb);
       }
+    }
+    // rhs and a'_P are stored colour-split; under the mixed policy also the FP64
+    // defect of every row (all rows are swept) for the FP32 correction
+    const long long sidx = rb_split(P, i, j, k);
+    aPr_out[sidx] = aPr;
+    double* rhs[3] = {rhs0, rhs1, rhs2};
+#pragma unroll
+    for (int cc = 0; cc < DIM; ++cc) rhs[cc][sidx] = rh[cc];
+    if (X.a) {
+      X.a[sidx] = (float)aPr;
+#pragma unroll
+      for (int cc = 0; cc < DIM; ++cc) X.r[cc][sidx] = (float)(rh[cc] - Ax[cc]);
     }
   }
   block_sums_store<9>(red, part, pstride, block_linear());
@@ -380,13 +399,26 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   Nbr N = make_nbr(P, i, j, k, c);
+  const long long sidx = rb_split(P, i, j, k);
+  // every load of the three rows before the first store (the stores could
+  // alias later loads otherwise, which would serialise the components)
+  double un[3][6];
+  const double* u[3] = {u0, u1, u2};
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) un[cc][q] = u[cc][N.n[q]];
+  const double b0 = rhs0[sidx], b1 = rhs1[sidx], b2 = rhs2[sidx], a = aPr[sidx];
   double anb[6];
   mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
-  const long long sidx = rb_split(P, i, j, k);
-  double a = aPr[sidx];
-  u0[c] = (rhs0[sidx] + nb_sum(anb, N, u0)) / a;
-  u1[c] = (rhs1[sidx] + nb_sum(anb, N, u1)) / a;
-  if (P.dim == 3) u2[c] = (rhs2[sidx] + nb_sum(anb, N, u2)) / a;
+  double nb[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nb[cc] += anb[q] * un[cc][q];
+  u0[c] = (b0 + nb[0]) / a;
+  u1[c] = (b1 + nb[1]) / a;
+  if (P.dim == 3) u2[c] = (b2 + nb[2]) / a;
 }
 
 // Mixed policy: one colour of a red-black Gauss-Seidel sweep of the FP32
@@ -743,9 +775,14 @@ __global__ void k_grad(Params P, const double* u0, const double* u1, const doubl
 using MomAssembleFn = void (*)(Params, Mom, MixOut, double*, double*, double*, double*, const double*, double*,
                                long long);
 static MomAssembleFn mom_assemble_kernel(const Params& P) {
-  if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1>;
-  if (P.conv == HFDIB_CONV_VANLEER) return k_mom_assemble<2>;
-  return k_mom_assemble<0>;
+  if (P.dim == 2) {
+    if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1, 2>;
+    if (P.conv == HFDIB_CONV_VANLEER) return k_mom_assemble<2, 2>;
+    return k_mom_assemble<0, 2>;
+  }
+  if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1, 3>;
+  if (P.conv == HFDIB_CONV_VANLEER) return k_mom_assemble<2, 3>;
+  return k_mom_assemble<0, 3>;
 }
 
 int velocity_gradient(hfdib_ctx* c) {

@@ -215,12 +215,10 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
 #pragma unroll
     for (int sh = 0; sh < 2; ++sh) {
       const int s = sh ? 1 : -1, q = 2 * d + sh;
-      anb[q] = 0.0;
-      if (d < P.dim) {
-        double mf = -outward_flux(P, S.phi, d, s, i, j, k);
-        double a = 0.5 * (gP + gam(P, eq, N.n[q], S.nut, S.F1)) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
-        anb[q] = is_bnd(N, q) ? 0.0 : a;
-      }
+      // loads from clamped indices for every face, chosen with selects
+      const double mf = -outward_flux(P, S.phi, d, s, i, j, k);
+      const double a = 0.5 * (gP + gam(P, eq, N.n[q], S.nut, S.F1)) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
+      anb[q] = sel(d < P.dim && !is_bnd(N, q), a, 0.0);
     }
 }
 
@@ -373,25 +371,29 @@ __global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const doubl
   tile_ijk_rb(P, color, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
-  if (S.flags[c] & fixmask) return;
-  const double gP = gamc[c];
-  Nbr N = make_nbr(P, i, j, k, c);
+  const Nbr N = make_nbr(P, i, j, k, c);
+  const long long sidx = rb_split(P, i, j, k);
+  // every load of the row is issued before any is used (also for fixed rows,
+  // which then store nothing)
+  const uint8_t fl = S.flags[c];
+  const double gP = gamc[c], b = rhs[sidx], ap = aPr[sidx];
+  double gn[6], xn[6], fo[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    gn[q] = gamc[N.n[q]];
+    xn[q] = x[N.n[q]];
+    fo[q] = outward_flux(P, S.phi, q >> 1, (q & 1) ? 1 : -1, i, j, k);
+  }
   double nb = 0.0;
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
-#pragma unroll
-    for (int sh = 0; sh < 2; ++sh) {
-      const int s = sh ? 1 : -1, q = 2 * d + sh;
-      double a = 0.0;
-      if (d < P.dim) {
-        double mf = -outward_flux(P, S.phi, d, s, i, j, k);
-        a = 0.5 * (gP + gamc[N.n[q]]) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
-        a = is_bnd(N, q) ? 0.0 : a;
-      }
-      nb += a * x[N.n[q]];
-    }
-  const long long sidx = rb_split(P, i, j, k);
-  x[c] = (rhs[sidx] + nb) / aPr[sidx];
+  for (int q = 0; q < 6; ++q) {
+    const int d = q >> 1;
+    const double mf = -fo[q];
+    double a = 0.5 * (gP + gn[q]) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
+    a = sel(d < P.dim && !is_bnd(N, q), a, 0.0);
+    nb += a * xn[q];
+  }
+  if (!(fl & fixmask)) x[c] = (b + nb) / ap;
 }
 
 // Mixed policy: red-black sweep of the FP32 correction d of a scalar equation
