@@ -59,6 +59,15 @@ __device__ __forceinline__ double gradp_V(const Params& P, const double* p, uint
   return P.V * ((fp - fm) * P.idelta[cc]);
 }
 
+// the same from preloaded values: pP = p_c, pn[q] = p at the (clamped) face
+// neighbour q of N
+__device__ __forceinline__ double gradp_V_nb(const Params& P, bool solid, int cc, const Nbr& N, double pP,
+                                             const double (&pn)[6]) {
+  const double fp = sel(is_bnd(N, 2 * cc + 1), p_bface(P, cc, +1, solid, pP), 0.5 * (pP + pn[2 * cc + 1]));
+  const double fm = sel(is_bnd(N, 2 * cc), p_bface(P, cc, -1, solid, pP), 0.5 * (pn[2 * cc] + pP));
+  return P.V * ((fp - fm) * P.idelta[cc]);
+}
+
 // ---------------------------------------------------------------- state init
 __global__ void k_init_cells(Params P, const double* lam, const double* us0, const double* us1, const double* us2,
                              double* u0, double* u1, double* u2, double* p, double* k, double* w, double* nut) {
@@ -507,24 +516,36 @@ __global__ void k_hbya(Params P, Mom M, const double* rhs0, const double* rhs1, 
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
   Nbr N = make_nbr(P, i, j, k, c);
-  uint8_t fl = M.flags[c];
+  const long long sidx = rb_split(P, i, j, k);
+  // loads of the three rows first, stores last
+  const uint8_t fl = M.flags[c];
+  double un[3][6], pn[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    un[0][q] = M.u[0][N.n[q]];
+    un[1][q] = M.u[1][N.n[q]];
+    un[2][q] = M.u[2][N.n[q]];
+    pn[q] = M.p[N.n[q]];
+  }
+  const double pP = M.p[c], a = aPr[sidx];
+  const double b[3] = {rhs0[sidx], rhs1[sidx], rhs2[sidx]};
   double anb[6];
   mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
-  const long long sidx = rb_split(P, i, j, k);
-  double a = aPr[sidx];
-  const double* rr[3] = {rhs0, rhs1, rhs2};
-  double* hh[3] = {h0, h1, h2};
   // forced cells: no pressure term in the momentum row (f_ib contains +grad p),
   // hence no pressure-velocity coupling (rAU = 0)
-  bool forced = fl & F_ALPHA_U;
+  const bool forced = fl & F_ALPHA_U;
+  const bool solid = fl & F_SOLID;
+  double H[3];
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc) {
-    if (cc >= P.dim) continue;
-    double nb = nb_sum(anb, N, M.u[cc]);
-    double H = forced ? nb + rr[cc][sidx] : nb + rr[cc][sidx] + gradp_V(P, M.p, fl, cc, i, j, k, c);
-    hh[cc][c] = H / a;
+    double nb = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) nb += anb[q] * un[cc][q];
+    H[cc] = sel(forced, nb + b[cc], nb + b[cc] + gradp_V_nb(P, solid, cc, N, pP, pn));
   }
-  if (P.dim == 2) h2[c] = 0.0;
+  h0[c] = H[0] / a;
+  h1[c] = H[1] / a;
+  h2[c] = P.dim == 3 ? H[2] / a : 0.0;
   rAU[c] = forced ? 0.0 : P.V / a;
 }
 
@@ -537,45 +558,59 @@ __global__ void k_flux_rhs(Params P, const double* h0, const double* h1, const d
   tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
+  const Nbr N = make_nbr(P, i, j, k, c);
   const double* hv[3] = {h0, h1, h2};
   double* ph[3] = {phx, phy, phz};
-  bool solid = flags[c] & F_SOLID;
-  double div = 0.0;
-  for (int d = 0; d < P.dim; ++d) {
-    double A = P.area[d];
-    long long f = fidx(P, d, i, j, k);
-    long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
-    for (int s = -1; s <= 1; s += 2) {
-      double val;
-      if (!on_bnd(P, d, s, i, j, k)) {
-        long long n = c + s * stride(P, d);
-        val = s > 0 ? 0.5 * (hv[d][c] + hv[d][n]) * A : 0.5 * (hv[d][n] + hv[d][c]) * A;
-        if (s > 0) ph[d][f + fo] = val;
-      } else {
-        int kind = face_kind(P, d, s);
-        if (kind == HFDIB_BC_INLET) val = P.u_in[d] * A;
-        else if (kind == HFDIB_BC_OUTLET) val = hv[d][c] * A;
-        else val = 0.0;
-        if (solid) val = 0.0;
-        ph[d][s > 0 ? f + fo : f] = val;
-      }
-      div += s > 0 ? val : -val;
+  // loads first (clamped neighbours), stores last
+  const uint8_t fl = flags[c];
+  const double l = lam[c], po = pold[c];
+  double hc[3], hlo[3], hhi[3];
+  uint8_t fn[6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    hc[d] = hv[d][c];
+    hlo[d] = hv[d][N.n[2 * d]];
+    hhi[d] = hv[d][N.n[2 * d + 1]];
+  }
+#pragma unroll
+  for (int q = 0; q < 6; ++q) fn[q] = flags[N.n[q]];
+  const bool solid = fl & F_SOLID;
+  double div = 0.0, vlo[3], vhi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double A = P.area[d];
+    double vb[2];
+#pragma unroll
+    for (int sh = 0; sh < 2; ++sh) {
+      const int kind = face_kind(P, d, sh ? 1 : -1);
+      double v = kind == HFDIB_BC_INLET ? P.u_in[d] * A : (kind == HFDIB_BC_OUTLET ? hc[d] * A : 0.0);
+      vb[sh] = solid ? 0.0 : v;
     }
+    vlo[d] = sel(is_bnd(N, 2 * d), vb[0], 0.5 * (hlo[d] + hc[d]) * A);
+    vhi[d] = sel(is_bnd(N, 2 * d + 1), vb[1], 0.5 * (hc[d] + hhi[d]) * A);
+    if (d < P.dim) {
+      div -= vlo[d];
+      div += vhi[d];
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (d >= P.dim) continue;
+    const long long f = fidx(P, d, i, j, k);
+    const long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+    ph[d][f + fo] = vhi[d];
+    if (is_bnd(N, 2 * d)) ph[d][f] = vlo[d];
   }
   // lambda-masked continuity (1 - lambda) div u = 0: either div u = 0 wherever
   // lambda < 1, or the predictor divergence weighted by (1 - lambda)
-  double l = lam[c];
   double rp = P.continuity == 0 ? (l < 1.0 ? -div : 0.0) : -(1.0 - l) * div;
   // a forced cell whose face neighbours are all forced has no pressure coupling:
   // identity row, p unchanged
-  if (flags[c] & F_ALPHA_U) {
-    bool iso = true;
-    for (int d = 0; d < P.dim; ++d)
-      for (int s = -1; s <= 1; s += 2)
-        if (!on_bnd(P, d, s, i, j, k) && !(flags[c + s * stride(P, d)] & F_ALPHA_U)) iso = false;
-    if (iso) rp = pold[c];
-  }
-  rhs_p[c] = rp;
+  bool iso = (fl & F_ALPHA_U) != 0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q)
+    if ((q >> 1) < P.dim && !is_bnd(N, q) && !(fn[q] & F_ALPHA_U)) iso = false;
+  rhs_p[c] = iso ? po : rp;
 }
 
 // Pressure of an identity row (a forced cell whose face neighbours are all
@@ -620,31 +655,45 @@ __global__ void k_flux_correct(Params P, const double* rAU, const double* psol, 
   tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
+  const Nbr N = make_nbr(P, i, j, k, c);
   double* ph[3] = {phx, phy, phz};
-  bool solid = flags[c] & F_SOLID;
+  // loads first (clamped neighbours), stores last
+  const uint8_t fl = flags[c];
+  const double rc = rAU[c], psc = psol[c], po = pold[c];
+  double rhi[3], phi_hi[3], phi_lo[3], pshi[3];
+  long long f[3], fo[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    f[d] = fidx(P, d, i, j, k);
+    fo[d] = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
+    rhi[d] = rAU[N.n[2 * d + 1]];
+    pshi[d] = psol[N.n[2 * d + 1]];
+    phi_hi[d] = ph[d][f[d] + fo[d]];
+    phi_lo[d] = ph[d][f[d]];
+  }
+  const bool solid = fl & F_SOLID;
+  const double cbv = solid ? 0.0 : rc;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     if (d >= P.dim) continue;
-    long long f = fidx(P, d, i, j, k);
-    long long fo = d == 0 ? 1LL : (d == 1 ? (long long)P.nx : (long long)P.nx * P.ny);
-    if (!on_bnd(P, d, +1, i, j, k)) {
-      long long n = c + stride(P, d);
-      double cf = 0.5 * (rAU[c] + rAU[n]) * P.AoD[d];
-      ph[d][f + fo] = ph[d][f + fo] - cf * (psol[n] - psol[c]);
-    }
-    for (int s = -1; s <= 1; s += 2) {
-      if (!on_bnd(P, d, s, i, j, k) || face_kind(P, d, s) != HFDIB_BC_OUTLET) continue;
-      double cb = solid ? 0.0 : rAU[c] * P.Ab[d];
-      long long ff = s > 0 ? f + fo : f;
-      ph[d][ff] = ph[d][ff] + (double)s * cb * psol[c];
-    }
+    const bool lo = is_bnd(N, 2 * d), hi = is_bnd(N, 2 * d + 1);
+    const bool out_lo = lo && face_kind(P, d, -1) == HFDIB_BC_OUTLET;
+    const bool out_hi = hi && face_kind(P, d, +1) == HFDIB_BC_OUTLET;
+    const double cb = cbv * P.Ab[d];
+    const double cf = 0.5 * (rc + rhi[d]) * P.AoD[d];
+    const double v_in = phi_hi[d] - cf * (pshi[d] - psc);
+    const double v_out = phi_hi[d] + cb * psc;
+    const double vh = sel(hi, sel(out_hi, v_out, phi_hi[d]), v_in);
+    const double vl = sel(out_lo, phi_lo[d] + (-1.0) * cb * psc, phi_lo[d]);
+    if (!hi || out_hi) ph[d][f[d] + fo[d]] = vh;
+    if (out_lo) ph[d][f[d]] = vl;
     if (m32.f[0]) {
-      m32.f[d][f + fo] = (float)ph[d][f + fo];
-      if (on_bnd(P, d, -1, i, j, k)) m32.f[d][f] = (float)ph[d][f];
+      m32.f[d][f[d] + fo[d]] = (float)vh;
+      if (lo) m32.f[d][f[d]] = (float)vl;
     }
   }
-  double ps = (flags[c] & F_ALPHA_U) ? decoupled_pressure(P, flags, psol, i, j, k, c) : psol[c];
-  pnew[c] = pold[c] + P.urf_p * (ps - pold[c]);
+  double ps = (fl & F_ALPHA_U) ? decoupled_pressure(P, flags, psol, i, j, k, c) : psc;
+  pnew[c] = po + P.urf_p * (ps - po);
 }
 
 // u = HbyA - rAU grad p (relaxed p), optional re-imposition of u_ib, copy p
@@ -655,18 +704,27 @@ __global__ void k_vel_update(Params P, const double* h0, const double* h1, const
   tile_ijk(P, i, j, k);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, k);
-  uint8_t fl = flags[c];
-  const double* hv[3] = {h0, h1, h2};
-  const double* ub[3] = {ub0, ub1, ub2};
-  double* uu[3] = {u0, u1, u2};
-  double a = aPr[rb_split(P, i, j, k)];
-  bool alpha = (fl & F_ALPHA_U) && P.recorrect;
-  bool forced = fl & F_ALPHA_U;
-  for (int cc = 0; cc < P.dim; ++cc) {
-    double v = forced ? hv[cc][c] : hv[cc][c] - gradp_V(P, pnew, fl, cc, i, j, k, c) / a;
-    if (alpha) v = v + 1.0 * (ub[cc][c] - v);
-    uu[cc][c] = v;
+  const Nbr N = make_nbr(P, i, j, k, c);
+  // loads first, stores last
+  const uint8_t fl = flags[c];
+  const double a = aPr[rb_split(P, i, j, k)], pP = pnew[c];
+  const double h[3] = {h0[c], h1[c], h2[c]};
+  const double ub[3] = {ub0[c], ub1[c], ub2[c]};
+  double pn[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) pn[q] = pnew[N.n[q]];
+  const bool alpha = (fl & F_ALPHA_U) && P.recorrect;
+  const bool forced = fl & F_ALPHA_U;
+  const bool solid = fl & F_SOLID;
+  double v[3];
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc) {
+    double w = sel(forced, h[cc], h[cc] - gradp_V_nb(P, solid, cc, N, pP, pn) / a);
+    v[cc] = sel(alpha, w + 1.0 * (ub[cc] - w), w);
   }
+  u0[c] = v[0];
+  u1[c] = v[1];
+  if (P.dim == 3) u2[c] = v[2];
 }
 
 __global__ void k_copy(long long n, const double* src, double* dst) {
