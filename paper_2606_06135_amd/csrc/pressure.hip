@@ -421,21 +421,33 @@ __device__ __forceinline__ bool level_pair(const LevelDevT<T>& L, int color, int
 // sum_nb c_nb f(nb) at (i,j,k) of a stored level (f gives the neighbour value)
 template <typename T, typename F>
 __device__ __forceinline__ T level_nbsum_f(const LevelDevT<T>& L, int i, int j, int k, F f) {
-  long long c = lidx(L, i, j, k);
-  T s = (T)0;
-  if (i > 0) s += L.cx[(long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * f(c - 1, -1, 0, 0);
-  if (i < L.nx - 1)
-    s += L.cx[(long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k)] * f(c + 1, 1, 0, 0);
-  if (j > 0) s += L.cy[(long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k)] * f(c - L.nx, 0, -1, 0);
-  if (j < L.ny - 1)
-    s += L.cy[(long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k)] * f(c + L.nx, 0, 1, 0);
-  if (L.dim == 3) {
-    long long sz = (long long)L.nx * L.ny;
-    if (k > 0) s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k)] * f(c - sz, 0, 0, -1);
-    if (k < L.nz - 1)
-      s += L.cz[(long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))] * f(c + sz, 0, 0, 1);
+  // all six terms from clamped loads (a face on the domain boundary takes the
+  // cell itself and offset 0, and its term is dropped by a select): the loads of
+  // the stencil are in flight together
+  const long long c = lidx(L, i, j, k);
+  const long long sz = (long long)L.nx * L.ny;
+  const bool in[6] = {i > 0, i < L.nx - 1, j > 0, j < L.ny - 1, L.dim == 3 && k > 0, L.dim == 3 && k < L.nz - 1};
+  const long long cf[6] = {
+      (long long)i + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k),
+      (long long)(i + 1) + (long long)(L.nx + 1) * ((long long)j + (long long)L.ny * k),
+      (long long)i + (long long)L.nx * ((long long)j + (long long)(L.ny + 1) * k),
+      (long long)i + (long long)L.nx * ((long long)(j + 1) + (long long)(L.ny + 1) * k),
+      (long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * k),
+      (long long)i + (long long)L.nx * ((long long)j + (long long)L.ny * (k + 1))};
+  const T* coef[6] = {L.cx, L.cx, L.cy, L.cy, L.cz, L.cz};
+  const long long st[6] = {-1, 1, -(long long)L.nx, (long long)L.nx, -sz, sz};
+  T a[6], v[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    const int s = (q & 1) ? 1 : -1, d = q >> 1;
+    const bool use = in[q];
+    a[q] = coef[q][cf[q]];  // (the z-face arrays have nz + 1 planes in 2-D as well)
+    v[q] = f(use ? c + st[q] : c, (d == 0 && use) ? s : 0, (d == 1 && use) ? s : 0, (d == 2 && use) ? s : 0);
   }
-  return s;
+  T sum = (T)0;
+#pragma unroll
+  for (int q = 0; q < 6; ++q) sum = sel(in[q], sum + a[q] * v[q], sum);
+  return sum;
 }
 
 template <typename T>
