@@ -674,16 +674,26 @@ __device__ __forceinline__ LdsLev<T> lds_lev(const TailLevelsT<T>& TL, int t, T*
 }
 template <typename T>
 __device__ __forceinline__ T lds_nbsum(const LdsLev<T>& L, const T* z, int i, int j, int k) {
-  int c = i + L.nx * (j + L.ny * k);
+  // the x and y terms from clamped LDS reads issued together, dropped by selects
+  // on the domain boundary (a 2-D level stages no z coefficients: its z block
+  // is skipped as a whole)
+  const int c = i + L.nx * (j + L.ny * k);
+  const bool xm = i > 0, xp = i < L.nx - 1, ym = j > 0, yp = j < L.ny - 1;
+  const T axm = L.cx[i + (L.nx + 1) * (j + L.ny * k)], axp = L.cx[i + 1 + (L.nx + 1) * (j + L.ny * k)];
+  const T aym = L.cy[i + L.nx * (j + (L.ny + 1) * k)], ayp = L.cy[i + L.nx * (j + 1 + (L.ny + 1) * k)];
+  const T zxm = z[xm ? c - 1 : c], zxp = z[xp ? c + 1 : c], zym = z[ym ? c - L.nx : c], zyp = z[yp ? c + L.nx : c];
   T s = (T)0;
-  if (i > 0) s += L.cx[i + (L.nx + 1) * (j + L.ny * k)] * z[c - 1];
-  if (i < L.nx - 1) s += L.cx[i + 1 + (L.nx + 1) * (j + L.ny * k)] * z[c + 1];
-  if (j > 0) s += L.cy[i + L.nx * (j + (L.ny + 1) * k)] * z[c - L.nx];
-  if (j < L.ny - 1) s += L.cy[i + L.nx * (j + 1 + (L.ny + 1) * k)] * z[c + L.nx];
+  s = sel(xm, s + axm * zxm, s);
+  s = sel(xp, s + axp * zxp, s);
+  s = sel(ym, s + aym * zym, s);
+  s = sel(yp, s + ayp * zyp, s);
   if (L.dim == 3) {
-    int sz = L.nx * L.ny;
-    if (k > 0) s += L.cz[i + L.nx * (j + L.ny * k)] * z[c - sz];
-    if (k < L.nz - 1) s += L.cz[i + L.nx * (j + L.ny * (k + 1))] * z[c + sz];
+    const int sz = L.nx * L.ny;
+    const bool zm = k > 0, zp = k < L.nz - 1;
+    const T azm = L.cz[i + L.nx * (j + L.ny * k)], azp = L.cz[i + L.nx * (j + L.ny * (k + 1))];
+    const T zzm = z[zm ? c - sz : c], zzp = z[zp ? c + sz : c];
+    s = sel(zm, s + azm * zzm, s);
+    s = sel(zp, s + azp * zzp, s);
   }
   return s;
 }
