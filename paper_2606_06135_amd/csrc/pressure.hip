@@ -32,14 +32,13 @@ using FineOp = FineOpT<double>;
 template <typename T>
 __device__ __forceinline__ T fine_coef(const Params& P, const FineOpT<T>& O, long long c, int d, int s, int i, int j,
                                        int k, long long* nb) {
-  if (on_bnd(P, d, s, i, j, k)) {
-    *nb = -1;
-    if (face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID)) return O.rAU[c] * (T)P.Ab[d];
-    return (T)0;
-  }
-  long long n = c + s * stride(P, d);
-  *nb = n;
-  return (T)0.5 * (O.rAU[c] + O.rAU[n]) * (T)P.AoD[d];
+  // both values from clamped loads, chosen with selects
+  const bool b = on_bnd(P, d, s, i, j, k);
+  const long long n = b ? c : c + s * stride(P, d);
+  *nb = b ? -1 : n;
+  const T rc = O.rAU[c], rn = O.rAU[n];
+  const bool outl = face_kind(P, d, s) == HFDIB_BC_OUTLET && !(O.flags[c] & F_SOLID);
+  return sel(b, sel(outl, rc * (T)P.Ab[d], (T)0), (T)0.5 * (rc + rn) * (T)P.AoD[d]);
 }
 
 // The six face coefficients of a fine-level row from clamped loads (no branch
@@ -288,45 +287,39 @@ __device__ __forceinline__ long long lidx(const LevelDevT<T>& L, int i, int j, i
 template <typename T>
 __device__ __forceinline__ T cface_fine(const Params& P, const FineOp& O, const LevelDevT<T>& L, int d, int I, int J,
                                         int K) {
-  const int nzs = L.dim == 3 ? 2 : 1;
-  double s = 0.0;
+  // the fine faces under coarse face (d; I, J, K): the low faces of the first
+  // fine layer of the coarse cell, or on the high domain boundary the high faces
+  // of the last fine layer; all four read (in 2-D the second layer along z
+  // repeats the first and is not added)
+  const bool d3 = L.dim == 3;
+  double v[4];
   long long n;
-  if (d == 0) {
-    for (int b = 0; b < 2; ++b)
-      for (int e = 0; e < nzs; ++e) {
-        int j = 2 * J + b, k = L.dim == 3 ? 2 * K + e : 0;
-        if (I < L.nx) {
-          int i = 2 * I;
-          s += fine_coef(P, O, cidx(P, i, j, k), 0, -1, i, j, k, &n);
-        } else {
-          int i = 2 * I - 1;
-          s += fine_coef(P, O, cidx(P, i, j, k), 0, +1, i, j, k, &n);
-        }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      int i, j, k, sg;
+      if (d == 0) {
+        const bool low = I < L.nx;
+        i = low ? 2 * I : 2 * I - 1, j = 2 * J + a, k = d3 ? 2 * K + b : 0, sg = low ? -1 : 1;
+      } else if (d == 1) {
+        const bool low = J < L.ny;
+        i = 2 * I + a, j = low ? 2 * J : 2 * J - 1, k = d3 ? 2 * K + b : 0, sg = low ? -1 : 1;
+      } else {
+        const bool low = K < L.nz;
+        i = 2 * I + a, j = 2 * J + b, k = low ? 2 * K : 2 * K - 1, sg = low ? -1 : 1;
       }
-  } else if (d == 1) {
-    for (int a = 0; a < 2; ++a)
-      for (int e = 0; e < nzs; ++e) {
-        int i = 2 * I + a, k = L.dim == 3 ? 2 * K + e : 0;
-        if (J < L.ny) {
-          int j = 2 * J;
-          s += fine_coef(P, O, cidx(P, i, j, k), 1, -1, i, j, k, &n);
-        } else {
-          int j = 2 * J - 1;
-          s += fine_coef(P, O, cidx(P, i, j, k), 1, +1, i, j, k, &n);
-        }
-      }
+      v[2 * a + b] = fine_coef(P, O, cidx(P, i, j, k), d, sg, i, j, k, &n);
+    }
+  // summed in the order of the loops over the two tangential directions
+  double s = 0.0;
+  if (d == 2) {
+    s = v[0] + v[1] + v[2] + v[3];
   } else {
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
-        int i = 2 * I + a, j = 2 * J + b;
-        if (K < L.nz) {
-          int k = 2 * K;
-          s += fine_coef(P, O, cidx(P, i, j, k), 2, -1, i, j, k, &n);
-        } else {
-          int k = 2 * K - 1;
-          s += fine_coef(P, O, cidx(P, i, j, k), 2, +1, i, j, k, &n);
-        }
-      }
+    s = s + v[0];
+    s = sel(d3, s + v[1], s);
+    s = s + v[2];
+    s = sel(d3, s + v[3], s);
   }
   return (T)(0.5 * s);
 }

@@ -709,7 +709,6 @@ __global__ void k_vel_update(Params P, const double* h0, const double* h1, const
   const uint8_t fl = flags[c];
   const double a = aPr[rb_split(P, i, j, k)], pP = pnew[c];
   const double h[3] = {h0[c], h1[c], h2[c]};
-  const double ub[3] = {ub0[c], ub1[c], ub2[c]};
   double pn[6];
 #pragma unroll
   for (int q = 0; q < 6; ++q) pn[q] = pnew[N.n[q]];
@@ -718,9 +717,12 @@ __global__ void k_vel_update(Params P, const double* h0, const double* h1, const
   const bool solid = fl & F_SOLID;
   double v[3];
 #pragma unroll
-  for (int cc = 0; cc < 3; ++cc) {
-    double w = sel(forced, h[cc], h[cc] - gradp_V_nb(P, solid, cc, N, pP, pn) / a);
-    v[cc] = sel(alpha, w + 1.0 * (ub[cc] - w), w);
+  for (int cc = 0; cc < 3; ++cc) v[cc] = sel(forced, h[cc], h[cc] - gradp_V_nb(P, solid, cc, N, pP, pn) / a);
+  if (alpha) {
+    // (forced cells only: their u_ib is read there)
+    const double ub[3] = {ub0[c], ub1[c], ub2[c]};
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) v[cc] = v[cc] + 1.0 * (ub[cc] - v[cc]);
   }
   u0[c] = v[0];
   u1[c] = v[1];

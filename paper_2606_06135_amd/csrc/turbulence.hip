@@ -100,20 +100,30 @@ k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv
   tile_ijk(P, i, j, k);
   if (i < P.nx && j < P.ny) {
     const long long c = cidx(P, i, j, k);
+    const Nbr N = make_nbr(P, i, j, k, c);
+    // loads first (clamped neighbours along all three axes; the terms beyond dim
+    // are dropped by selects)
     const uint8_t fl = flags[c];
+    const double kk = kv[c], ww = wv[c];
     if (P.model == HFDIB_KOMEGA_SST) {
-      const Nbr N = make_nbr(P, i, j, k, c);
+      double kn[6], wn[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        kn[q] = kv[N.n[q]];
+        wn[q] = wv[N.n[q]];
+      }
+      const double dwc = dw[c];
       const bool solid = fl & F_SOLID;
-      const double kk = kv[c], ww = wv[c];
-      double gk[3] = {0, 0, 0}, gw[3] = {0, 0, 0};
+      double kw = 0.0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        if (d >= P.dim) continue;
-        gk[d] = ggrad_bf(P, kv, N, c, d, sc_bface(P, d, +1, solid, kk, P.k_in), sc_bface(P, d, -1, solid, kk, P.k_in));
-        gw[d] = ggrad_bf(P, wv, N, c, d, sc_bface(P, d, +1, solid, ww, P.w_in), sc_bface(P, d, -1, solid, ww, P.w_in));
+        const double kp = sel(is_bnd(N, 2 * d + 1), sc_bface(P, d, +1, solid, kk, P.k_in), 0.5 * (kk + kn[2 * d + 1]));
+        const double km = sel(is_bnd(N, 2 * d), sc_bface(P, d, -1, solid, kk, P.k_in), 0.5 * (kn[2 * d] + kk));
+        const double wp = sel(is_bnd(N, 2 * d + 1), sc_bface(P, d, +1, solid, ww, P.w_in), 0.5 * (ww + wn[2 * d + 1]));
+        const double wm = sel(is_bnd(N, 2 * d), sc_bface(P, d, -1, solid, ww, P.w_in), 0.5 * (wn[2 * d] + ww));
+        const double gk = (kp - km) * P.idelta[d], gw = (wp - wm) * P.idelta[d];
+        kw = sel(d < P.dim, kw + gk * gw, kw);
       }
-      const double kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2];
-      const double dwc = dw[c];
       double cd = 2.0 * P.sigma_w2 / ww * kw;
       cd = cd > P.cd_floor ? cd : P.cd_floor;
       const double a = sqrt(kk) / (P.Cmu * ww * dwc);
@@ -125,7 +135,7 @@ k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv
       F1[c] = tanh(a2 * a2);
       kwo[c] = kw;
     }
-    if (!(fl & F_IC)) wmx = wv[c];
+    wmx = (fl & F_IC) ? 0.0 : ww;
   }
   __shared__ double lmax[4];
   const double m = wave_max(wmx);
@@ -478,13 +488,13 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, G
   tile_ijk(P, i, j, kz);
   if (i >= P.nx || j >= P.ny) return;
   long long c = cidx(P, i, j, kz);
-  uint8_t fl = flags[c];
+  // loads first, stores last
+  const uint8_t fl = flags[c];
   double kk = k[c];
+  const double ww = w[c], dwc = dw[c], S2c = S2[c];
   if (fl & F_ALPHA_U) kk = kk + 1.0 * (kib[c] - kk);
   double kmin = P.bound_frac * P.k_in;
   kk = kk > kmin ? kk : kmin;
-  k[c] = kk;
-  double ww = w[c];
   double nt;
   if (P.model == HFDIB_KEPS) {
     nt = P.Cmu * kk * kk / ww;
@@ -494,16 +504,17 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, G
     RkeInv I = rke_invariants(P, Gs, c);
     nt = rke_cmu(P, I, kk, ww) * kk * kk / ww;
   } else {
-    double d = dw[c];
+    double d = dwc;
     double bs = P.Cmu;
     double a = 2.0 * sqrt(kk) / (bs * ww * d);
     double bb = 500.0 * P.nu / (d * d * ww);
     double arg2 = a > bb ? a : bb;
     double F2 = tanh(arg2 * arg2);
-    double den1 = P.a1 * ww, den2 = sqrt(S2[c]) * F2;
+    double den1 = P.a1 * ww, den2 = sqrt(S2c) * F2;
     nt = P.a1 * kk / (den1 > den2 ? den1 : den2);
   }
   if (fl & F_IC) nt = 0.0;
+  k[c] = kk;
   nut[c] = nt;
   if (nut32) nut32[c] = (float)nt;
 }
