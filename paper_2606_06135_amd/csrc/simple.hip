@@ -456,39 +456,52 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
   if (i >= P.nx) return;
   long long c = cidx(P, i, j, k);
   const long long sidx = rb_split(P, i, j, k);  // defects and diagonal are colour-split
-  float a = a32[sidx];
+  // loads first (clamped neighbours, selects), stores last
+  const float a = a32[sidx], b0 = r0[sidx], b1 = r1[sidx], b2 = r2[sidx];
   float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
   if (!init) {
-    Nbr N = make_nbr(P, i, j, k, c);
+    const Nbr N = make_nbr(P, i, j, k, c);
     const float nu = (float)P.nu;
-    float nuP = nu + M.nut[c];
+    const float nuP = nu + M.nut[c];
+    float nun[6], fo[6], z0[6], z1[6], z2[6];
 #pragma unroll
-    for (int d = 0; d < 3; ++d)
+    for (int q = 0; q < 6; ++q) {
+      const int d = q >> 1, s = (q & 1) ? 1 : -1;
+      const long long n = N.n[q];
+      const long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
+      nun[q] = M.nut[n];
+      fo[q] = M.phi[d][f];
+      z0[q] = d0[n];
+      z1[q] = d1[n];
+      z2[q] = d2[n];
+    }
 #pragma unroll
-      for (int sh = 0; sh < 2; ++sh) {
-        const int s = sh ? 1 : -1, q = 2 * d + sh;
-        if (d >= P.dim) continue;
-        long long n = N.n[q];
-        long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
-        float mf = s > 0 ? -M.phi[d][f] : M.phi[d][f];
-        float an = 0.5f * (nuP + (nu + M.nut[n])) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
-        an = is_bnd(N, q) ? 0.0f : an;
-        n0 += an * d0[n];
-        n1 += an * d1[n];
-        if (three) n2 += an * d2[n];
-      }
+    for (int q = 0; q < 6; ++q) {
+      const int d = q >> 1;
+      const float mf = (q & 1) ? -fo[q] : fo[q];
+      float an = 0.5f * (nuP + (nu + nun[q])) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
+      an = sel(d < P.dim && !is_bnd(N, q), an, 0.0f);
+      n0 += an * z0[q];
+      n1 += an * z1[q];
+      n2 += an * z2[q];
+    }
   }
-  float e0 = (r0[sidx] + n0) / a, e1 = (r1[sidx] + n1) / a;
+  const float e0 = (b0 + n0) / a, e1 = (b1 + n1) / a, e2 = (b2 + n2) / a;
+  double uo[3] = {0.0, 0.0, 0.0};
+  if (fin) {
+    uo[0] = u0[c];
+    uo[1] = u1[c];
+    if (three) uo[2] = u2[c];
+  }
   d0[c] = e0;
   d1[c] = e1;
   if (fin) {
-    u0[c] = u0[c] + (double)e0;
-    u1[c] = u1[c] + (double)e1;
+    u0[c] = uo[0] + (double)e0;
+    u1[c] = uo[1] + (double)e1;
   }
   if (three) {
-    float e2 = (r2[sidx] + n2) / a;
     d2[c] = e2;
-    if (fin) u2[c] = u2[c] + (double)e2;
+    if (fin) u2[c] = uo[2] + (double)e2;
   }
 }
 

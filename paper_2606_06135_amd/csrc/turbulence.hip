@@ -428,32 +428,39 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, const
   }
   if (i >= P.nx) return;
   long long c = cidx(P, i, j, k);
-  bool fixed = flags[c] & fixmask;
+  const long long sidx = rb_split(P, i, j, k);
+  // loads first (clamped neighbours, selects), stores last
+  const bool fixed = flags[c] & fixmask;
+  const float rs = r[sidx], as = a32[sidx];
+  float nb = 0.0f;
+  if (!init) {
+    const float gP = gamc[c];
+    const Nbr N = make_nbr(P, i, j, k, c);
+    float gn[6], fo[6], zn[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int d = q >> 1, s = (q & 1) ? 1 : -1;
+      const long long n = N.n[q];
+      gn[q] = gamc[n];
+      fo[q] = S.phi[d][fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0)];
+      zn[q] = dv[n];
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const int d = q >> 1;
+      const float mf = (q & 1) ? -fo[q] : fo[q];
+      const float a = 0.5f * (gP + gn[q]) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
+      nb = sel(d < P.dim && !is_bnd(N, q), nb + a * zn[q], nb);
+    }
+  }
   if (fixed) {
     if (init) dv[c] = 0.0f;
     return;
   }
-  float nb = 0.0f;
-  if (!init) {
-    float gP = gamc[c];
-    Nbr N = make_nbr(P, i, j, k, c);
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int sh = 0; sh < 2; ++sh) {
-        const int s = sh ? 1 : -1, q = 2 * d + sh;
-        if (d >= P.dim) continue;
-        long long n = N.n[q];
-        long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
-        float mf = s > 0 ? -S.phi[d][f] : S.phi[d][f];
-        float a = 0.5f * (gP + gamc[n]) * (float)P.AoD[d] + (mf > 0.0f ? mf : 0.0f);
-        nb += is_bnd(N, q) ? 0.0f : a * dv[n];
-      }
-  }
-  const long long sidx = rb_split(P, i, j, k);
-  float e = (r[sidx] + nb) / a32[sidx];
+  const float e = (rs + nb) / as;
+  const double xo = fin ? x[c] : 0.0;
   dv[c] = e;
-  if (fin) x[c] = x[c] + (double)e;
+  if (fin) x[c] = xo + (double)e;
 }
 
 // k_ib on boundary cells: quadratic along n_P with the wall-function surface
