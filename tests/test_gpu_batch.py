@@ -113,6 +113,26 @@ def test_invalid_tile_depth_rejected(gpu):
     assert np.isfinite(s.get_field("ux").cpu().numpy()).all()
 
 
+def test_sampled_kernel_timing(gpu):
+    # recording every 3rd of 7 iterations times iterations 0, 3 and 6 only: one
+    # momentum assembly and one iteration span each; the timed launches leave
+    # the results as they are
+    spec = synth.case_small_body3d(model="sst", nu=1e-4)
+    a = _solver(spec, gpu, p_rtol=1e-2, p_maxit=100)
+    b = _solver(spec, gpu, p_rtol=1e-2, p_maxit=100)
+    a.timing(True, 3)
+    a.iterate(7)
+    for name in ("mom_assemble", "iteration", "p_solve"):
+        ms, cnt = a.timing_query(name)
+        assert cnt == 3 and ms > 0.0, (name, cnt, ms)
+    ms, cnt = a.timing_query("mom_sweep")
+    assert cnt == 3 * 2 * spec.n_sweeps
+    a.timing(False)
+    b.iterate(7)
+    for k in ("ux", "p", "k", "w"):
+        np.testing.assert_array_equal(a.get_field(k).cpu().numpy(), b.get_field(k).cpu().numpy())
+
+
 def test_autotune_leaves_the_state_alone(gpu):
     spec = synth.case_small_body3d(model="sst", nu=1e-4)
     s = _solver(spec, gpu)

@@ -109,4 +109,7 @@ def test_init_validation_and_call_order(hiplib):
     counts = (C.c_int * 3)()
     assert L.hfdib_get_counts(ctx, counts) == -5
     assert L.hfdib_status_string(-4) == b"diverged"
+    # kernel timing: a recording period >= 1, or 0 (off); host-side state only
+    assert L.hfdib_timing_enable(ctx, -1) == -1
+    assert L.hfdib_timing_enable(ctx, 3) == 0 and L.hfdib_timing_enable(ctx, 0) == 0
     L.hfdib_destroy(ctx)
