@@ -183,6 +183,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->pr = B.take<double>(N);
   c->pz = B.take<double>(N);
   c->pd = B.take<double>(N);
+  c->pd2 = B.take<double>(N);
   c->pq = B.take<double>(N);
   c->invD = B.take<double>(N);
   c->flags = B.take<uint8_t>(N);

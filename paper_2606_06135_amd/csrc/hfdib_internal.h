@@ -110,6 +110,7 @@ struct hfdib_ctx {
   double *G[9], *S2;
   int grad_ok;
   double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
+  double* pd2;  // second PCG search-direction buffer (the direction update writes the other one)
   double* invD;  // inverse diagonal of the fine pressure operator (FP64 policy)
   uint8_t* flags;
   // --- face arrays

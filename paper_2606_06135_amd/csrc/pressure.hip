@@ -12,6 +12,8 @@
 // coarse operator; the preconditioner output is read back by the FP64 CG).
 #include "device_common.h"
 
+#include <utility>
+
 #include <cmath>
 #include <vector>
 
@@ -97,6 +99,39 @@ __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, dou
     if (dg == 0.0) acc = xc;  // uncoupled row: identity
     y[c] = acc;
     v[0] = xc * acc;
+  }
+  block_sums_store<1>(v, part, pstride, block_linear());
+}
+
+// the direction update d = z + beta d_old fused with y = A d (and partial sums
+// of d.y): each cell forms d at itself and its neighbours as the update would
+// (the same operations, so the same values), writes its own d to d_new and y
+template <typename TZ>
+__global__ void k_fine_apply_dir(Params P, FineOp O, const TZ* z, const double* d_old, double* d_new, double* y,
+                                 const double* scal, double* part, long long pstride) {
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  double v[1] = {0.0};
+  if (i < P.nx && j < P.ny) {
+    long long c = cidx(P, i, j, k);
+    Nbr N = make_nbr(P, i, j, k, c);
+    double cf[6];
+    fine_row(P, O, N, c, cf);
+    const double beta = scal[S_BETA];
+    const double dc = (double)z[c] + beta * d_old[c];
+    double dn[6];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) dn[q] = (double)z[N.n[q]] + beta * d_old[N.n[q]];
+    double acc = 0.0, dg = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      acc = sel(is_bnd(N, q), acc + cf[q] * dc, acc + cf[q] * (dc - dn[q]));
+      dg += cf[q];
+    }
+    if (dg == 0.0) acc = dc;  // uncoupled row: identity
+    d_new[c] = dc;
+    y[c] = acc;
+    v[0] = dc * acc;
   }
   block_sums_store<1>(v, part, pstride, block_linear());
 }
@@ -816,12 +851,6 @@ __global__ void k_axpy2(long long n, const double* scal, double* x, const double
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
-template <typename TZ>
-__global__ void k_xpby(long long n, const double* scal, const TZ* z, double* d) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  if (c < n) d[c] = (double)z[c] + scal[S_BETA] * d[c];
-}
-
 
 // first stage of a large reduction: workgroup (b, v) reduces entries
 // [b chunk, (b+1) chunk) of partial row v (sum, or max when is_max) into
@@ -1080,28 +1109,34 @@ static void pcg_start(hfdib_ctx* c, const PcgSet<T>& A, const double* rhs, doubl
 
 // one CG step: q = A d, alpha, x += alpha d, r -= alpha q, r.r (the reduction of
 // r.r also copies the PCG scalars to the pinned host mirror hmir when given)
+// (dir: the direction update d = z + beta d is fused into the operator apply,
+// which writes the new d to the other direction buffer; the buffers then swap)
 template <typename T>
-static void pcg_step(hfdib_ctx* c, const PcgSet<T>& A, double* x, double* hmir) {
+static void pcg_step(hfdib_ctx* c, const PcgSet<T>& A, double* x, double* hmir, bool dir = false) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3(P);
   const int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
-  LaunchEv ev = timer_launch(c, T_PAPPLY, true, true);
-  launch_ev(k_fine_apply, g, b, c->stream, ev, P, A.O, (const double*)c->pd, c->pq, c->partials, c->pstride);
+  if (dir) {
+    hipLaunchKernelGGL(k_fine_apply_dir<T>, g, b, 0, c->stream, P, A.O, (const T*)A.z_m, (const double*)c->pd, c->pd2,
+                       c->pq, (const double*)S, c->partials, c->pstride);
+    std::swap(c->pd, c->pd2);
+  } else {
+    // (the timed class of the operator apply is this plain launch)
+    LaunchEv ev = timer_launch(c, T_PAPPLY, true, true);
+    launch_ev(k_fine_apply, g, b, c->stream, ev, P, A.O, (const double*)c->pd, c->pq, c->partials, c->pstride);
+  }
   launch_finalize(c, (int)((long long)g.x * g.y * g.z), 1, S_DQ, 1);
   hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const double*)S, x, (const double*)c->pd,
                      c->pr, A.r32, (const double*)c->pq, c->partials, c->pstride);
   launch_finalize(c, nb1, 1, S_RR, 0, 1.0, 0, hmir, hmir ? (double)++c->mir_seq : 0.0);
 }
 
-// z = M^-1 r, beta = r.z / rho, d = z + beta d
+// z = M^-1 r, beta = r.z / rho (the direction update d = z + beta d is done by
+// the next CG step's operator apply)
 template <typename T>
 static void pcg_direction(hfdib_ctx* c, const PcgSet<T>& A, bool presmoothed = false) {
-  const Params& P = c->P;
-  double* S = c->scal + SCAL_PCG;
   launch_finalize(c, vcycle<T>(c, A.OM, A.invD, A.r_m, A.z_m, c->pr, nullptr, presmoothed), 1, S_RZ, 2);
-  hipLaunchKernelGGL(k_xpby<T>, dim3(nblocks1(P.N)), dim3(NTHREADS), 0, c->stream, P.N, (const double*)S,
-                     (const T*)A.z_m, c->pd);
 }
 
 // The adaptive solve in the pieces between which the host reads the
@@ -1127,7 +1162,7 @@ template <typename T>
 static void pcg_continue_t(hfdib_ctx* c, const double* rAU, double* x, bool presmoothed) {
   PcgSet<T> A = pcg_set<T>(c, rAU);
   pcg_direction<T>(c, A, presmoothed);
-  pcg_step<T>(c, A, x, c->hmir_dev);
+  pcg_step<T>(c, A, x, c->hmir_dev, true);
 }
 static void pcg_begin(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, const double* xmean_dev) {
   if (c->P.precision == HFDIB_MIXED)
@@ -1176,7 +1211,7 @@ static void pcg_fixed(hfdib_ctx* c, const double* rAU, const double* rhs, double
   pcg_operators<T>(c, A);
   pcg_start<T>(c, A, rhs, x, xmean_dev);
   for (int it = 1; it <= nit; ++it) {
-    pcg_step<T>(c, A, x, nullptr);
+    pcg_step<T>(c, A, x, nullptr, it > 1);
     if (it == nit) break;
     pcg_direction<T>(c, A);
   }
