@@ -166,33 +166,6 @@ __device__ __forceinline__ T sel(bool b, T x, T y) {
   return b ? x : y;
 }
 
-// (psi_+ - psi_-)/delta_d with linear face interpolation (Gauss gradient)
-// (loads from clamped indices: no branch around them)
-__device__ __forceinline__ double ggrad(const Params& P, const double* a, long long c, int d, int i, int j, int k,
-                                       double fb_p, double fb_m) {
-  long long st = stride(P, d);
-  const bool hi = on_bnd(P, d, +1, i, j, k), lo = on_bnd(P, d, -1, i, j, k);
-  double aP = a[c], ap = a[hi ? c : c + st], am = a[lo ? c : c - st];
-  double fp = sel(hi, fb_p, 0.5 * (aP + ap));
-  double fm = sel(lo, fb_m, 0.5 * (am + aP));
-  return (fp - fm) * P.idelta[d];
-}
-// d u_jj / d x_ii at cell (i,j,k) (index c, lambda > 0 flag `solid`)
-__device__ __forceinline__ double gradu(const Params& P, const double* const* u, bool solid, int ii, int jj, int i,
-                                        int j, int k, long long c) {
-  const double* a = u[jj];
-  double uP = a[c];
-  return ggrad(P, a, c, ii, i, j, k, u_bface(P, jj, ii, +1, solid, uP), u_bface(P, jj, ii, -1, solid, uP));
-}
-// full velocity gradient G[ii][jj] = d u_jj / d x_ii at a cell (zero outside dim)
-__device__ __forceinline__ void gradu_all(const Params& P, const double* const* u, bool solid, int i, int j, int k,
-                                          long long c, double (&G)[3][3]) {
-#pragma unroll
-  for (int jj = 0; jj < 3; ++jj)
-#pragma unroll
-    for (int ii = 0; ii < 3; ++ii)
-      G[ii][jj] = sel(ii < P.dim && jj < P.dim, gradu(P, u, solid, ii, jj, i, j, k, c), 0.0);
-}
 // 2 S:S with S the symmetric part of G (summed over all nine entries)
 __device__ __forceinline__ double strain2(const double (&G)[3][3]) {
   double S2 = 0.0;
@@ -245,14 +218,6 @@ __device__ __forceinline__ double gradu_bf(const Params& P, const double* uj, in
   double fp = sel(hi, u_bface(P, jc, a, +1, solid, uP), 0.5 * (uP + up));
   double fm = sel(lo, u_bface(P, jc, a, -1, solid, uP), 0.5 * (um + uP));
   return (fp - fm) * P.idelta[a];
-}
-// (psi_+ - psi_-)/delta_d of a scalar from clamped loads (boundary face values given)
-__device__ __forceinline__ double ggrad_bf(const Params& P, const double* a, const Nbr& N, long long c, int d,
-                                           double fb_p, double fb_m) {
-  double aP = a[c], ap = a[N.n[2 * d + 1]], am = a[N.n[2 * d]];
-  double fp = sel(is_bnd(N, 2 * d + 1), fb_p, 0.5 * (aP + ap));
-  double fm = sel(is_bnd(N, 2 * d), fb_m, 0.5 * (am + aP));
-  return (fp - fm) * P.idelta[d];
 }
 // full velocity gradient G[a][jc] = d u_jc / d x_a at a cell (zero outside dim)
 __device__ __forceinline__ void gradu_all_bf(const Params& P, const double* const* u, bool solid, const Nbr& N,

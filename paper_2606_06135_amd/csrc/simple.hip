@@ -47,20 +47,8 @@ __device__ __forceinline__ double p_bface(const Params& P, int d, int s, bool so
   return (outl && !solid) ? 0.0 : pP;
 }
 
-// V (grad p)_c at cell (i,j,k), Gauss with linear interpolation
-__device__ __forceinline__ double gradp_V(const Params& P, const double* p, uint8_t fl, int cc, int i, int j,
-                                          int k, long long c) {
-  long long st = stride(P, cc);
-  bool solid = fl & F_SOLID;
-  const bool hi = on_bnd(P, cc, +1, i, j, k), lo = on_bnd(P, cc, -1, i, j, k);
-  double pP = p[c], pp = p[hi ? c : c + st], pm = p[lo ? c : c - st];
-  double fp = hi ? p_bface(P, cc, +1, solid, pP) : 0.5 * (pP + pp);
-  double fm = lo ? p_bface(P, cc, -1, solid, pP) : 0.5 * (pm + pP);
-  return P.V * ((fp - fm) * P.idelta[cc]);
-}
-
-// the same from preloaded values: pP = p_c, pn[q] = p at the (clamped) face
-// neighbour q of N
+// V (grad p)_c, Gauss with linear interpolation, from preloaded values: pP = p_c,
+// pn[q] = p at the (clamped) face neighbour q of N
 __device__ __forceinline__ double gradp_V_nb(const Params& P, bool solid, int cc, const Nbr& N, double pP,
                                              const double (&pn)[6]) {
   const double fp = sel(is_bnd(N, 2 * cc + 1), p_bface(P, cc, +1, solid, pP), 0.5 * (pP + pn[2 * cc + 1]));
@@ -208,13 +196,6 @@ __device__ __forceinline__ void mom_anb(const Params& P, const Mom& M, double nu
       const double a = anb_coef(P, nuP, P.nu + M.nut[N.n[q]], d, outward_flux(P, M.phi, d, s, i, j, k));
       anb[q] = sel(d < P.dim && !is_bnd(N, q), a, 0.0);
     }
-}
-// sum over the faces of anb * x_nb (domain faces carry anb = 0), order W..T
-__device__ __forceinline__ double nb_sum(const double (&anb)[6], const Nbr& N, const double* x) {
-  double nb = 0.0;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) nb += anb[q] * x[N.n[q]];
-  return nb;
 }
 
 // Assembly of the relaxed momentum rows with the explicit IB source

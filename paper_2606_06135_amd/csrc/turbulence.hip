@@ -573,10 +573,6 @@ __global__ void k_wall_bc(Params P, int nbc, const int* bc_cells, const double* 
 // ====================================================================== host
 namespace hfdib {
 
-__global__ void k_set1(double* a, double v) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *a = v;
-}
-
 int turbulence_stage(hfdib_ctx* c) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3(P);
