@@ -212,10 +212,15 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->wall_utau = B.take<double>(cap);
   c->ipts = B.take<double>(3LL * cap);
   // partial rows hold one entry per block of the largest tile-shape candidate
+  // (every width, and the momentum assembly's 32 x 2 x 4 tiles)
   long long nblk3 = 0;
-  for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX; ++lx) {
+  for (int lx = TILE_LOG2_MIN; lx <= TILE_LOG2_MAX + 1; ++lx) {
     Params Q = P;
-    Q.tx_log2 = lx;
+    Q.tx_log2 = lx <= TILE_LOG2_MAX ? lx : 5;
+    if (lx > TILE_LOG2_MAX) {
+      if (P.dim != 3 || P.nz % 4 != 0) continue;
+      Q.tz_log2 = 2;
+    }
     dim3 g = grid3(Q);
     long long nb = (long long)g.x * g.y * g.z;
     nblk3 = nb > nblk3 ? nb : nblk3;

@@ -833,6 +833,21 @@ __global__ void k_grad(Params P, const double* u0, const double* u1, const doubl
 // the momentum assembly instance of the configured convection scheme
 using MomAssembleFn = void (*)(Params, Mom, MixOut, double*, double*, double*, double*, const double*, double*,
                                long long);
+// Launch shape of the momentum assembly: 32 x 2 x 4 tiles in z-first order
+// wherever the grid allows (3-D, nz a multiple of 4): its stencil reads about
+// fifteen arrays at the z-neighbours, and tiles spanning four planes re-read
+// fewer of them (7 % faster at 2.36 M cells; the other kernels are fastest with
+// the configured tiles).  Elsewhere the configured tiles.
+static Params mom_assemble_params(const Params& P) {
+  Params A = P;
+  if (P.dim == 3 && P.nz % 4 == 0) {
+    A.tx_log2 = 5;
+    A.tz_log2 = 2;
+    A.tile_zfirst = 1;
+  }
+  return A;
+}
+
 static MomAssembleFn mom_assemble_kernel(const Params& P) {
   if (P.dim == 2) {
     if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1, 2>;
@@ -864,7 +879,8 @@ int tile_bench_round(hfdib_ctx* c) {
   if (st != HFDIB_OK) return st;
   Mom M = make_mom(c);
   MixOut X{{nullptr, nullptr, nullptr}, nullptr};
-  hipLaunchKernelGGL(mom_assemble_kernel(P), grid3(P), block3(P), 0, c->stream, P, M, X, c->rhs[0], c->rhs[1],
+  const Params PA = mom_assemble_params(P);
+  hipLaunchKernelGGL(mom_assemble_kernel(P), grid3(PA), block3(PA), 0, c->stream, PA, M, X, c->rhs[0], c->rhs[1],
                      c->rhs[2], c->aPr, c->scal + SCAL_PCG + SC_MEANS, c->partials, c->pstride);
   pressure_apply_bench(c);
   HFDIB_CHECK_LAUNCH(c, "tile bench");
@@ -922,9 +938,11 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   MixOut X{{nullptr, nullptr, nullptr}, nullptr};
   if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32};
   ev = timer_launch(c, T_MOMASM, true, true);
-  launch_ev(mom_assemble_kernel(P), g, b, c->stream, ev, P, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, S + SC_MEANS,
-            c->partials, c->pstride);
-  launch_finalize(c, (int)nblk3, 9, SC_RESSUM, 0);
+  const Params PA = mom_assemble_params(P);
+  const dim3 ga = grid3(PA);
+  launch_ev(mom_assemble_kernel(P), ga, block3(PA), c->stream, ev, PA, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
+            S + SC_MEANS, c->partials, c->pstride);
+  launch_finalize(c, (int)((long long)ga.x * ga.y * ga.z), 9, SC_RESSUM, 0);
   Mir32 M32{{c->phi32[0], c->phi32[1], c->phi32[2]}, c->nut32};
   // (one timing span over the 2 n_s consecutive launches)
   for (int s = 0; s < P.n_sweeps; ++s)
