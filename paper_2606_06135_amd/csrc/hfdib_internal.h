@@ -181,6 +181,9 @@ inline int nblocks1(long long n) {
   long long b = (n + NTHREADS - 1) / NTHREADS;
   return (int)(b < 1 ? 1 : b);
 }
+// blocks of the streaming sums (each thread adds SUM_PER cells)
+constexpr int SUM_PER = 8;
+inline int nblocks_sum(long long n) { return nblocks1((n + SUM_PER - 1) / SUM_PER); }
 
 // error plumbing
 int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);

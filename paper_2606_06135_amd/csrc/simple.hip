@@ -116,16 +116,22 @@ __global__ void k_interp_flux(Params P, const double* v0, const double* v1, cons
 }
 
 // sums of u, v, w, p, k over all cells (means for the residual normalisation)
+// (each thread adds SUM_PER cells, a block's cells being SUM_PER consecutive
+// runs of NTHREADS, before the block reduction)
 __global__ void k_sums5(Params P, const double* a0, const double* a1, const double* a2, const double* a3,
                         const double* a4, double* part, long long pstride) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
+  const long long c0 = (long long)blockIdx.x * NTHREADS * SUM_PER + threadIdx.x;
   double v[5] = {0, 0, 0, 0, 0};
-  if (c < P.N) {
-    v[0] = a0[c];
-    v[1] = a1[c];
-    v[2] = a2[c];
-    v[3] = a3[c];
-    v[4] = a4[c];
+#pragma unroll
+  for (int r = 0; r < SUM_PER; ++r) {
+    const long long c = c0 + (long long)r * NTHREADS;
+    if (c < P.N) {
+      v[0] += a0[c];
+      v[1] += a1[c];
+      v[2] += a2[c];
+      v[3] += a3[c];
+      v[4] += a4[c];
+    }
   }
   block_sums_store<5>(v, part, pstride, blockIdx.x);
 }
@@ -912,16 +918,15 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   (void)it;
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3(P);
-  long long nblk3 = (long long)g.x * g.y * g.z;
-  int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   int st;
   // means of the previous iterate (residual normalisation); opens the timing
   // span of the iteration
   LaunchEv ev = timer_launch(c, T_ITER, true, false);
-  launch_ev(k_sums5, dim3(nb1), dim3(NTHREADS), c->stream, ev, P, c->u[0], c->u[1], c->u[2], c->p, c->k, c->partials,
+  const int nbs = nblocks_sum(P.N);
+  launch_ev(k_sums5, dim3(nbs), dim3(NTHREADS), c->stream, ev, P, c->u[0], c->u[1], c->u[2], c->p, c->k, c->partials,
             c->pstride);
-  launch_finalize(c, nb1, 5, SC_MEANS, 0, (double)P.N);
+  launch_finalize(c, nbs, 5, SC_MEANS, 0, (double)P.N);
   // 1. IB-pre
   if (c->n_bc + c->n_wall > 0)
     hipLaunchKernelGGL(k_ib_pre, dim3(nblocks1(c->n_bc + c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_bc,

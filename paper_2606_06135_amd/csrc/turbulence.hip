@@ -185,9 +185,15 @@ __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, cons
 }
 
 
+// (each thread adds SUM_PER cells, as in the sums of the iteration means)
 __global__ void k_sum1(long long n, const double* a, double* part, long long pstride) {
-  long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
-  double v[1] = {c < n ? a[c] : 0.0};
+  const long long c0 = (long long)blockIdx.x * NTHREADS * SUM_PER + threadIdx.x;
+  double v[1] = {0.0};
+#pragma unroll
+  for (int r = 0; r < SUM_PER; ++r) {
+    const long long c = c0 + (long long)r * NTHREADS;
+    if (c < n) v[0] += a[c];
+  }
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
@@ -577,7 +583,6 @@ int turbulence_stage(hfdib_ctx* c) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3(P);
   long long nblk3 = (long long)g.x * g.y * g.z;
-  int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   double* wmax = S + SC_WMAX;
   G9 Gs;
@@ -596,8 +601,9 @@ int turbulence_stage(hfdib_ctx* c) {
       hipLaunchKernelGGL(k_turb_imposed, dim3(nblocks1(ntot)), dim3(NTHREADS), 0, c->stream, P, L0, L1, c->n_ic,
                          c->ic_cells, wmax, Gs, c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
   }
-  hipLaunchKernelGGL(k_sum1, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, c->w, c->partials, c->pstride);
-  launch_finalize(c, nb1, 1, SC_MEANS + 5, 0, (double)P.N);
+  const int nbs = nblocks_sum(P.N);
+  hipLaunchKernelGGL(k_sum1, dim3(nbs), dim3(NTHREADS), 0, c->stream, P.N, c->w, c->partials, c->pstride);
+  launch_finalize(c, nbs, 1, SC_MEANS + 5, 0, (double)P.N);
   Scal Sc;
   for (int q = 0; q < 3; ++q) {
     Sc.phi[q] = c->phi[q];
