@@ -122,16 +122,24 @@ __global__ void k_sums5(Params P, const double* a0, const double* a1, const doub
                         const double* a4, double* part, long long pstride) {
   const long long c0 = (long long)blockIdx.x * NTHREADS * SUM_PER + threadIdx.x;
   double v[5] = {0, 0, 0, 0, 0};
+  // (indices past the end read the last cell and add 0: no branch around the
+  // loads, all of a thread's loads in flight together)
+  double e[SUM_PER][5];
 #pragma unroll
   for (int r = 0; r < SUM_PER; ++r) {
     const long long c = c0 + (long long)r * NTHREADS;
-    if (c < P.N) {
-      v[0] += a0[c];
-      v[1] += a1[c];
-      v[2] += a2[c];
-      v[3] += a3[c];
-      v[4] += a4[c];
-    }
+    const long long ci = c < P.N ? c : P.N - 1;
+    e[r][0] = a0[ci];
+    e[r][1] = a1[ci];
+    e[r][2] = a2[ci];
+    e[r][3] = a3[ci];
+    e[r][4] = a4[ci];
+  }
+#pragma unroll
+  for (int r = 0; r < SUM_PER; ++r) {
+    const bool in = c0 + (long long)r * NTHREADS < P.N;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) v[q] = sel(in, v[q] + e[r][q], v[q]);
   }
   block_sums_store<5>(v, part, pstride, blockIdx.x);
 }

@@ -189,11 +189,14 @@ __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, cons
 __global__ void k_sum1(long long n, const double* a, double* part, long long pstride) {
   const long long c0 = (long long)blockIdx.x * NTHREADS * SUM_PER + threadIdx.x;
   double v[1] = {0.0};
+  double e[SUM_PER];
 #pragma unroll
   for (int r = 0; r < SUM_PER; ++r) {
     const long long c = c0 + (long long)r * NTHREADS;
-    if (c < n) v[0] += a[c];
+    e[r] = a[c < n ? c : n - 1];
   }
+#pragma unroll
+  for (int r = 0; r < SUM_PER; ++r) v[0] = sel(c0 + (long long)r * NTHREADS < n, v[0] + e[r], v[0]);
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
