@@ -281,10 +281,14 @@ int hfdib_get_ib_array(hfdib_ctx* ctx, int array_id, void* dst_dev);
  * V-cycle; stops at |r| <= rtol |b| or after maxit iterations, where |b| is taken
  * over the coupled rows (an uncoupled row, all of whose coefficients are zero,
  * is the identity p = rhs and its right-hand side does not enter |b|).
- * *iters and *relres (host, nullable) report the outcome.  Synchronises the
- * host once per PCG iteration: the device writes the convergence scalars to a
- * 200-byte pinned host buffer that the context allocates on its first solve
- * (EDEVICE if that fails) and frees in hfdib_destroy. */
+ * *iters and *relres (host, nullable) report the outcome.  Waits on the host
+ * once per PCG iteration: the device writes the convergence scalars and then a
+ * sequence number to a 208-byte pinned, host-coherent buffer that the context
+ * allocates on its first solve (EDEVICE if that fails) and frees in
+ * hfdib_destroy; the host polls the sequence number (and the stream, for
+ * errors).  Returns after the last iteration's scalars have arrived; the
+ * solution is complete in stream order (the standalone call also synchronises
+ * the stream before returning). */
 int hfdib_pressure_solve(hfdib_ctx* ctx, const double* rAU_dev, const double* rhs_dev,
                          double* p_dev, double rtol, int maxit, int* iters, double* relres);
 
