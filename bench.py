@@ -275,6 +275,8 @@ def main():
         "config": {"workload": spec.name + "_" + spec.model, "cells": N, "model": "k-omega SST" if spec.model == "sst"
                    else spec.model, "precision": args.precision, "p_rtol": args.p_rtol, "n_sweeps": spec.n_sweeps,
                    "boundary_cells": counts["bc"], "insolid_cells": counts["ic"], "tile": tile,
+                   # the momentum assembly's own launch shape (3-D, nz a multiple of 4)
+                   "assembly_tile": ("32x2x4 z-first" if spec.dim == 3 and spec.nz % 4 == 0 else "as tile"),
                    "pcg_iters_per_step": round(stats[0] / max(done, 1), 2), "finite": bool(finite),
                    "final_residuals": [float(x) for x in res]},
         "roofline": roof,
