@@ -847,21 +847,6 @@ __global__ void k_grad(Params P, const double* u0, const double* u1, const doubl
 // the momentum assembly instance of the configured convection scheme
 using MomAssembleFn = void (*)(Params, Mom, MixOut, double*, double*, double*, double*, const double*, double*,
                                long long);
-// Launch shape of the momentum assembly: 32 x 2 x 4 tiles in z-first order
-// wherever the grid allows (3-D, nz a multiple of 4): its stencil reads about
-// fifteen arrays at the z-neighbours, and tiles spanning four planes re-read
-// fewer of them (7 % faster at 2.36 M cells; the other kernels are fastest with
-// the configured tiles).  Elsewhere the configured tiles.
-static Params mom_assemble_params(const Params& P) {
-  Params A = P;
-  if (P.dim == 3 && P.nz % 4 == 0) {
-    A.tx_log2 = 5;
-    A.tz_log2 = 2;
-    A.tile_zfirst = 1;
-  }
-  return A;
-}
-
 static MomAssembleFn mom_assemble_kernel(const Params& P) {
   if (P.dim == 2) {
     if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1, 2>;
@@ -877,7 +862,8 @@ int velocity_gradient(hfdib_ctx* c) {
   const Params& P = c->P;
   GradOut O;
   for (int q = 0; q < 9; ++q) O.G[q] = c->G[q];
-  hipLaunchKernelGGL(k_grad, grid3(P), block3(P), 0, c->stream, P, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
+  const Params PG = deep_tile_params(P);
+  hipLaunchKernelGGL(k_grad, grid3(PG), block3(PG), 0, c->stream, PG, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
   HFDIB_CHECK_LAUNCH(c, "velocity gradient");
   c->grad_ok = 1;
   return HFDIB_OK;
@@ -893,7 +879,7 @@ int tile_bench_round(hfdib_ctx* c) {
   if (st != HFDIB_OK) return st;
   Mom M = make_mom(c);
   MixOut X{{nullptr, nullptr, nullptr}, nullptr};
-  const Params PA = mom_assemble_params(P);
+  const Params PA = deep_tile_params(P);
   hipLaunchKernelGGL(mom_assemble_kernel(P), grid3(PA), block3(PA), 0, c->stream, PA, M, X, c->rhs[0], c->rhs[1],
                      c->rhs[2], c->aPr, c->scal + SCAL_PCG + SC_MEANS, c->partials, c->pstride);
   pressure_apply_bench(c);
@@ -951,7 +937,7 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   MixOut X{{nullptr, nullptr, nullptr}, nullptr};
   if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32};
   ev = timer_launch(c, T_MOMASM, true, true);
-  const Params PA = mom_assemble_params(P);
+  const Params PA = deep_tile_params(P);
   const dim3 ga = grid3(PA);
   launch_ev(mom_assemble_kernel(P), ga, block3(PA), c->stream, ev, PA, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
             S + SC_MEANS, c->partials, c->pstride);
@@ -976,8 +962,11 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                        c->bc_cells, c->n_ic, c->ic_cells, c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1],
                        c->u[2]);
   // 4. pressure corrector
-  hipLaunchKernelGGL(k_hbya, g, b, 0, c->stream, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->hbya[0],
-                     c->hbya[1], c->hbya[2], c->rAU);
+  {
+    const Params PH = deep_tile_params(P);
+    hipLaunchKernelGGL(k_hbya, grid3(PH), block3(PH), 0, c->stream, PH, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
+                       c->hbya[0], c->hbya[1], c->hbya[2], c->rAU);
+  }
   hipLaunchKernelGGL(k_flux_rhs, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->lam, c->flags,
                      c->p, c->phi[0], c->phi[1], c->phi[2], c->rhs_p, c->px);
   HFDIB_CHECK_LAUNCH(c, "momentum stage");
