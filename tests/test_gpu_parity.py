@@ -294,3 +294,23 @@ def test_full_size_pressure_solve_satisfies_oracle_matrix(gpu, scale, precision)
     assert rr <= 1e-12
     assert res <= 1e-9
     assert it < 300
+
+
+def test_full_size_first_iteration_residuals(gpu):
+    # the normalised residuals of the first iteration on the benchmark grid
+    # (256 x 96 x 96, SST, the benchmark's tile shape), both sides from the same
+    # initial state: sums over all 2.36 M rows of |b - A u| of the assembled momentum
+    # rows (with the IB source, skipping the forced rows) and of the pressure rows,
+    # taken before the pressure solve, so the oracle's pressure tolerance does not
+    # enter; Uy, Uz and p start from zero fields, where the ratio is exactly 1
+    spec = synth.case_ahmed(scale=1)
+    _say("full-size first-iteration residuals", spec.ncells)
+    sim = Simple(spec, geo=precompute(spec), p_solver="cg", p_rtol=0.5)
+    r = sim.step()
+    s = _solver(spec, gpu, p_rtol=1e-2, p_maxit=200)
+    done, res = s.iterate(1)
+    assert done == 1
+    _say("  oracle", {k: r[k] for k in ("Ux", "Uy", "Uz", "p")}, "gpu", res[:4])
+    assert 1e-3 < r["Ux"] < 0.5
+    for q, nm in enumerate(("Ux", "Uy", "Uz", "p")):
+        assert abs(res[q] - r[nm]) <= 1e-9 * r[nm], (nm, res[q], r[nm])
