@@ -665,7 +665,10 @@ class Simple:
         else:
             dw = geo.dw
             bs = C["Cmu"]
-            arg2 = np.maximum(2.0 * np.sqrt(k) / (bs * w * dw), 500.0 * nu / (dw * dw * w))
+            # dw = 0 in the in-solid group: arg2 = +inf there, F2 = 1 (its limit at
+            # a wall); those cells get nu_t = 0 below
+            with np.errstate(divide="ignore"):
+                arg2 = np.maximum(2.0 * np.sqrt(k) / (bs * w * dw), 500.0 * nu / (dw * dw * w))
             F2 = np.tanh(arg2 * arg2)
             nut = C["a1"] * k / np.maximum(C["a1"] * w, np.sqrt(S2) * F2)
         nf = nut.ravel().copy()
