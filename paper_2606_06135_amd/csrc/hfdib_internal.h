@@ -181,9 +181,13 @@ inline dim3 grid3_rb(const Params& P) {
 // since tiles over four planes re-read fewer planes (the momentum assembly:
 // 157 -> 146 us at 2.36 M cells); elsewhere, and for every other kernel, the
 // configured tiles
-inline Params deep_tile_params(const Params& P) {
+// plane_limited: only on planes of at most 32768 cells (HbyA and the velocity
+// gradient run faster on these tiles with 256 x 96 planes and slower with
+// 512 x 192 planes; our reading: the z-first runs of tiles come back to their y-halo rows
+// after these have left the L2)
+inline Params deep_tile_params(const Params& P, bool plane_limited = false) {
   Params A = P;
-  if (P.dim == 3 && P.nz % 4 == 0) {
+  if (P.dim == 3 && P.nz % 4 == 0 && (!plane_limited || (long long)P.nx * P.ny <= 32768)) {
     A.tx_log2 = 5;
     A.tz_log2 = 2;
     A.tile_zfirst = 1;

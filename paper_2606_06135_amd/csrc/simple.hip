@@ -862,7 +862,7 @@ int velocity_gradient(hfdib_ctx* c) {
   const Params& P = c->P;
   GradOut O;
   for (int q = 0; q < 9; ++q) O.G[q] = c->G[q];
-  const Params PG = deep_tile_params(P);
+  const Params PG = deep_tile_params(P, true);
   hipLaunchKernelGGL(k_grad, grid3(PG), block3(PG), 0, c->stream, PG, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
   HFDIB_CHECK_LAUNCH(c, "velocity gradient");
   c->grad_ok = 1;
@@ -963,7 +963,7 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                        c->u[2]);
   // 4. pressure corrector
   {
-    const Params PH = deep_tile_params(P);
+    const Params PH = deep_tile_params(P, true);
     hipLaunchKernelGGL(k_hbya, grid3(PH), block3(PH), 0, c->stream, PH, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
                        c->hbya[0], c->hbya[1], c->hbya[2], c->rAU);
   }
