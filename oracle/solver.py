@@ -35,13 +35,14 @@ from .grid import Grid
 from .geometry import precompute, IC, BC
 from . import wallfn as wf
 from . import realizable
+from . import closure
 
 DIRS = None  # filled per grid: list of (d, s)
 
 
 class Simple:
     def __init__(self, spec, geo=None, solid_vel=None, p_solver="direct", p_rtol=1e-12, recorrect=True,
-                 continuity="literal"):
+                 continuity="literal", identity_mean=True):
         self.spec = spec
         self.g = Grid(spec)
         self.C = dict(spec.constants)
@@ -54,10 +55,14 @@ class Simple:
         self.p_rtol = p_rtol
         self.recorrect = recorrect
         self.continuity = continuity
+        # identity pressure rows take the mean solved pressure of their coupled
+        # face neighbours after each solve (off: they keep their value)
+        self.identity_mean = identity_mean
         self.ic = self.geo.tag == IC
         self.bcm = self.geo.tag == BC
         self.bc_cells = self.geo.bc_cells
         self.ic_cells = self.geo.ic_cells
+        self.k_in, self.eps_in, self.omega_in = wf.inlet_from_spec(spec, self.C)
         self.it = 0
         self.last = {}
         self.initial_conditions()
@@ -107,13 +112,13 @@ class Simple:
             self.u[2] = np.zeros(g.shape)
         self.p = np.zeros(g.shape)
         if sp_.model in ("keps", "rkeps"):
-            self.k = np.full(g.shape, sp_.k_in)
-            self.w = np.full(g.shape, sp_.eps_in)
-            self.nut = np.full(g.shape, self.C["Cmu"] * sp_.k_in ** 2 / sp_.eps_in)
+            self.k = np.full(g.shape, self.k_in)
+            self.w = np.full(g.shape, self.eps_in)
+            self.nut = np.full(g.shape, self.C["Cmu"] * self.k_in ** 2 / self.eps_in)
         elif sp_.model in ("sst", "komega"):
-            self.k = np.full(g.shape, sp_.k_in)
-            self.w = np.full(g.shape, sp_.omega_in)
-            self.nut = np.full(g.shape, sp_.k_in / sp_.omega_in)
+            self.k = np.full(g.shape, self.k_in)
+            self.w = np.full(g.shape, self.omega_in)
+            self.nut = np.full(g.shape, self.k_in / self.omega_in)
         else:
             self.k = np.zeros(g.shape)
             self.w = np.zeros(g.shape)
@@ -269,6 +274,47 @@ class Simple:
                 out[c] = out[c] - np.where(has, F * (uf - uC), 0.0)
         return out
 
+    def ib_wall_coupling(self, cells, normal, y, yp, nuEff):
+        """Change of the momentum diagonal of boundary cells on the logarithmic
+        branch (the reading of the paper's high-Reynolds-number treatment, where
+        the boundary velocity follows from the turbulent viscosity instead of the
+        interpolation): each face shared with an in-solid neighbour couples the
+        cell to the solid through D_w = (nu + nu_w) |n . e_f| A_f / y, the
+        wall-function viscosity nu_w = nu (kappa y+ / ln(E y+) - 1) over the wall
+        distance y with the projected face area, instead of the face-mean
+        diffusivity over the centre distance, D_f = mean(nu_eff) A_f / d_f.
+        Returns sum_f (D_w - D_f) per listed cell; the solid velocity of the cell
+        goes to the right-hand side with the same coefficient, so that the face
+        coupling is exact once the in-solid neighbour holds u_s.  Under the log law
+        the momentum flux to the wall is then u_tau^2 per unit wall area."""
+        g, C, nu = self.g, self.C, self.spec.nu
+        nuw = nu + wf.nut_wall(yp, nu, C)
+        ic = self.ic.ravel()
+        ne = nuEff.ravel()
+        idx = [np.asarray(a).ravel()[cells] for a in g.idx3]
+        n_ = (g.nx, g.ny, g.nz)
+        dD = np.zeros(len(cells))
+        for (d, s) in self.dirs:
+            q = idx[d] + s
+            inside = (q >= 0) & (q < n_[d])
+            nb = cells + s * (1 if d == 0 else (g.nx if d == 1 else g.nx * g.ny))
+            nb = np.where(inside, nb, cells)
+            wall = inside & ic[nb]
+            Df = 0.5 * (ne[cells] + ne[nb]) * g.area[d] / g.delta[d]
+            Dw = nuw * g.area[d] * np.abs(normal[:, d]) / y
+            dD = dD + np.where(wall, Dw - Df, 0.0)
+        return dD
+
+    def wall_shear_rate_sq(self, u, cells, normal, y, us=None):
+        """(|u_t,P - u_s,t| / y)^2 on the listed cells: the tangential part (to the
+        unit normal) of the velocity relative to the wall velocity (0 for domain
+        walls), over the wall distance y"""
+        ur = np.stack([u[c].ravel()[cells] - (0.0 if us is None else us[c].ravel()[cells]) for c in range(3)],
+                      axis=1)
+        un = (ur * normal).sum(axis=1)
+        tang = ur - un[:, None] * normal
+        return (tang * tang).sum(axis=1) / (y * y)
+
     def pressure_gradient_V(self, p):
         """V (grad p)_P (Gauss; outlet faces p = 0, other faces zero gradient)"""
         gp = self.g.gauss_grad(p, self.p_face_value)
@@ -390,6 +436,19 @@ class Simple:
             for c in g.axes:
                 ub = sp_.u_in[c] if kind == "inlet" else 0.0
                 bsrc[c][g.bnd(d, s)] += a * ub
+        # boundary cells on the logarithmic branch (not forced): their faces to
+        # in-solid neighbours carry the wall shear of the wall function
+        lg_cells = bcc[~alpha_bc]
+        if turb and len(lg_cells):
+            dD = self.ib_wall_coupling(lg_cells, geo.normal[~alpha_bc], geo.yeff[~alpha_bc], yp[~alpha_bc], nuEff)
+            af_ = aP.ravel()
+            af_[lg_cells] += dD
+            aP = af_.reshape(g.shape)
+            for c in g.axes:
+                bf_ = bsrc[c].ravel()
+                bf_[lg_cells] += dD * self.us[c].ravel()[lg_cells]
+                bsrc[c] = bf_.reshape(g.shape)
+        self.last["wall_dD"] = np.zeros(0) if not (turb and len(lg_cells)) else dD
         Gu = self.grad_u(u_old)
         T = self.transpose_term(nuEff, Gu)
         scheme = getattr(sp_, "conv_scheme", "upwind")
@@ -460,7 +519,8 @@ class Simple:
             has = g.has_neighbor(d, s) & g.neighbor(~iso, d, s, fill=False)
             acc += np.where(has, g.neighbor(p_sol, d, s, fill=0.0), 0.0)
             cnt += has
-        p_sol = np.where(iso & (cnt > 0), acc / np.maximum(cnt, 1), p_sol)
+        if self.identity_mean:
+            p_sol = np.where(iso & (cnt > 0), acc / np.maximum(cnt, 1), p_sol)
         cint, cout = self.pressure_coeffs(rAU)
         phi = [a.copy() for a in phis]
         for d in g.axes:
@@ -509,34 +569,27 @@ class Simple:
         sst = sp_.model == "sst"
         urf = sp_.urf_t
         Gu = self.grad_u(u)
-        S2 = np.zeros(g.shape)  # 2 S:S
-        for i in range(3):
-            for j in range(3):
-                sij = 0.5 * (Gu[i][j] + Gu[j][i])
-                S2 = S2 + 2.0 * sij * sij
-        G = nut_old * S2
+        S2 = closure.strain_rate_sq(Gu)  # 2 S:S
+        G = closure.production(nut_old, S2)
         wc = geo.wall_cells
         alpha_w = (self.ic | self.bcm).ravel()
         alpha_w[wc] = True
         alpha_w = alpha_w.reshape(g.shape)
-        kin = sp_.k_in
-        win = sp_.eps_in if keps else sp_.omega_in
+        kin = self.k_in
+        win = self.eps_in if keps else self.omega_in
         if sst:
+            # Menter's SST from the previous iterate: F1 (d_w = 0 in the in-solid
+            # group gives F1 = 1 there, see oracle.closure), blended coefficients,
+            # production limiter
             gk = g.gauss_grad(k_old, self.scalar_face_value(kin))
             gw = g.gauss_grad(w_old, self.scalar_face_value(win))
-            kw = gk[0] * gw[0] + gk[1] * gw[1] + gk[2] * gw[2]
-            dw = geo.dw
-            bs = C["Cmu"]
-            CDkw = np.maximum(2.0 * C["sigma_w2"] / w_old * kw, C["cd_floor"])
-            arg1 = np.minimum(np.maximum(np.sqrt(k_old) / (bs * w_old * dw), 500.0 * nu / (dw * dw * w_old)),
-                              4.0 * C["sigma_w2"] * k_old / (CDkw * dw * dw))
-            F1 = np.tanh(arg1 ** 4)
-
-            def blend(a, b):
-                return F1 * C[a] + (1.0 - F1) * C[b]
-            sig_k, sig_w = blend("sigma_k1", "sigma_k2"), blend("sigma_w1", "sigma_w2")
-            beta, gamma = blend("beta_1", "beta_2"), blend("gamma_1", "gamma_2")
-            Pk = np.minimum(G, C["c_lim"] * bs * k_old * w_old)
+            CDkw, kw = closure.sst_cross_diffusion(gk, gw, w_old, C)
+            F1 = closure.sst_f1(k_old, w_old, geo.dw, CDkw, nu, C)
+            sig_k = closure.sst_blend(F1, C, "sigma_k1", "sigma_k2")
+            sig_w = closure.sst_blend(F1, C, "sigma_w1", "sigma_w2")
+            beta = closure.sst_blend(F1, C, "beta_1", "beta_2")
+            gamma = closure.sst_blend(F1, C, "gamma_1", "gamma_2")
+            Pk = closure.sst_production_limit(G, k_old, w_old, C)
         else:
             Pk = G.copy()
 
@@ -549,21 +602,17 @@ class Simple:
             w_bc = om_bc
         nonic = ~self.ic
         w_ic = w_old[nonic].max() if nonic.any() else win  # max over boundary and free-stream cells
-        nrm = geo.normal
-        ngu = np.zeros((len(bcc), 3))
-        for j in range(3):
-            for i in range(3):
-                ngu[:, j] += nrm[:, i] * Gu[i][j].ravel()[bcc]
-        ngu2 = (ngu * ngu).sum(axis=1)
-        P_bc = wf.production_ib(yp, Pk.ravel()[bcc], ngu2, nu, C)
+        # |n . grad u| of the logarithmic-branch production: the wall-normal
+        # difference of the tangential velocity relative to the solid over the
+        # wall distance, |u_t,P - u_s,t| / y (the wall-face normal gradient of the
+        # wall-function form the paper adopts; it makes P_ib the equilibrium
+        # production u_tau^3 / (kappa y) under the log law)
+        P_bc = wf.production_ib(yp, Pk.ravel()[bcc],
+                                self.wall_shear_rate_sq(u, bcc, geo.normal, yeff, self.us), nu, C)
         # first cells at no-slip domain walls: the same wall functions with y = d/2
         om_w = wf.omega_ib(yp_w, geo.wall_y, utau_w, nu, C)
         w_w = C["Cmu"] * k_old.ravel()[wc] * om_w if keps else om_w
-        ngw = np.zeros((len(wc), 3))
-        for j in range(3):
-            for i in range(3):
-                ngw[:, j] += geo.wall_n[:, i] * Gu[i][j].ravel()[wc]
-        P_w = wf.production_ib(yp_w, Pk.ravel()[wc], (ngw * ngw).sum(axis=1), nu, C)
+        P_w = wf.production_ib(yp_w, Pk.ravel()[wc], self.wall_shear_rate_sq(u, wc, geo.wall_n, geo.wall_y), nu, C)
         wib = np.zeros(g.N)
         wib[icc] = w_ic
         wib[bcc] = w_bc
@@ -605,7 +654,7 @@ class Simple:
         else:
             aP = aP + beta * w_old * V
             b0 = b0 + gamma * (w_old / k_old) * Pk * V
-            CD = (1.0 - F1) * 2.0 * C["sigma_w2"] * kw / w_old
+            CD = closure.sst_cd_term(F1, kw, w_old, C)
             b0 = b0 + np.where(CD > 0.0, CD * V, 0.0)
             aP = aP + np.where(CD < 0.0, -CD / w_old * V, 0.0)
         aPr = aP / urf
@@ -663,14 +712,10 @@ class Simple:
         elif not sst:
             nut = k / w
         else:
-            dw = geo.dw
-            bs = C["Cmu"]
-            # dw = 0 in the in-solid group: arg2 = +inf there, F2 = 1 (its limit at
-            # a wall); those cells get nu_t = 0 below
-            with np.errstate(divide="ignore"):
-                arg2 = np.maximum(2.0 * np.sqrt(k) / (bs * w * dw), 500.0 * nu / (dw * dw * w))
-            F2 = np.tanh(arg2 * arg2)
-            nut = C["a1"] * k / np.maximum(C["a1"] * w, np.sqrt(S2) * F2)
+            # (d_w = 0 in the in-solid group gives F2 = 1 there; those cells get
+            # nu_t = 0 below)
+            F2 = closure.sst_f2(k, w, geo.dw, nu, C)
+            nut = closure.sst_nut(k, w, S2, F2, C)
         nf = nut.ravel().copy()
         lg = yp > C["ylam"]
         nf[bcc] = np.where(lg, wf.nut_wall(yp, nu, C), nf[bcc])

@@ -77,8 +77,25 @@ def loglaw_utau(ut_mag, yeff, nu, utau0, C, maxit=20, tol=1e-14):
 
 
 def inlet_values(U, I, lt, C):
-    """inlet k, epsilon, omega from intensity and length scale"""
+    """inlet k, epsilon, omega from intensity and length scale (the paper's
+    inlet condition of the pipe-flow section: k = 3/2 U^2 I^2,
+    eps = C_nu k^(3/2) / l_t, omega = eps / (C_nu k))"""
     k = 1.5 * U ** 2 * I ** 2
     eps = C["Cmu"] * k ** 1.5 / lt
     om = eps / (C["Cmu"] * k)
     return k, eps, om
+
+
+def inlet_from_spec(spec, C):
+    """(k_in, eps_in, omega_in) of a case: as given, or from its intensity
+    (inlet_I > 0) with the length scale inlet_l; without a length scale the given
+    omega_in is kept and eps_in = C_nu k_in omega_in"""
+    I = getattr(spec, "inlet_I", 0.0) or 0.0
+    if not I > 0.0:
+        return spec.k_in, spec.eps_in, spec.omega_in
+    U = float(np.sqrt(sum(float(v) ** 2 for v in spec.u_in)))
+    lt = getattr(spec, "inlet_l", 0.0) or 0.0
+    if lt > 0.0:
+        return inlet_values(U, I, lt, C)
+    k = 1.5 * U ** 2 * I ** 2
+    return k, C["Cmu"] * k * spec.omega_in, spec.omega_in
