@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define HFDIB_ABI_VERSION 3
+#define HFDIB_ABI_VERSION 4
 
 typedef enum {
   HFDIB_OK = 0,
@@ -100,7 +100,15 @@ typedef enum { HFDIB_CONV_UPWIND = 0, HFDIB_CONV_LINEAR_UPWIND = 1, HFDIB_CONV_V
 typedef enum { HFDIB_FP64 = 0, HFDIB_MIXED = 1 } hfdib_precision;
 
 /* Grid and boundary data.  dim = 2 requires nz = 1 and EMPTY z faces.
- * bc[] order: xmin, xmax, ymin, ymax, zmin, zmax. */
+ * bc[] order: xmin, xmax, ymin, ymax, zmin, zmax.
+ * Inlet turbulence: with turb_intensity = I > 0 the library derives the inlet
+ * values from the intensity as in the paper's inlet condition (boundary-condition
+ * paragraph of the pipe-flow section, eq. bcspkoein): k_in = 3/2 |u_in|^2 I^2 and,
+ * with turb_length = l_t > 0, eps_in = C_nu k_in^(3/2) / l_t and
+ * omega_in = eps_in / (C_nu k_in) (C_nu = hfdib_config.Cmu); with turb_length <= 0
+ * omega_in is taken as given and eps_in = C_nu k_in omega_in.  The k_in, eps_in
+ * (and, with l_t > 0, omega_in) fields are then ignored.  With turb_intensity <= 0
+ * k_in, eps_in and omega_in are used as given. */
 typedef struct {
   int dim;
   int nx, ny, nz;
@@ -109,6 +117,7 @@ typedef struct {
   int bc[6];
   double u_in[3];
   double k_in, eps_in, omega_in;
+  double turb_intensity, turb_length;
 } hfdib_grid_desc;
 
 /* Solver configuration.  hfdib_default_config() fills every field. */

@@ -14,7 +14,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhfdib.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 BC = {"inlet": 0, "outlet": 1, "noslip": 2, "slip": 3, "empty": 4}
 MODEL = {"laminar": 0, "keps": 1, "sst": 2, "komega": 3, "rkeps": 4}
@@ -36,7 +36,8 @@ class GridDesc(C.Structure):
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
                 ("bc", C.c_int * 6), ("u_in", C.c_double * 3),
-                ("k_in", C.c_double), ("eps_in", C.c_double), ("omega_in", C.c_double)]
+                ("k_in", C.c_double), ("eps_in", C.c_double), ("omega_in", C.c_double),
+                ("turb_intensity", C.c_double), ("turb_length", C.c_double)]
 
 
 _CONST_NAMES = ["Cmu", "kappa", "E", "beta1_wf", "Ceps2_wf", "C_wf", "ylam",
@@ -146,7 +147,9 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
         d.bc[f] = BC[spec.bc[f]]
     for q in range(3):
         d.u_in[q] = spec.u_in[q]
-    d.k_in, d.eps_in, d.omega_in = spec.k_in, spec.eps_in, spec.omega_in
+    d.k_in, d.eps_in, d.omega_in = (0.0 if v is None else v for v in (spec.k_in, spec.eps_in, spec.omega_in))
+    d.turb_intensity = getattr(spec, "inlet_I", 0.0) or 0.0
+    d.turb_length = getattr(spec, "inlet_l", 0.0) or 0.0
     c = default_config()
     c.model = MODEL[spec.model]
     c.n_sweeps = spec.n_sweeps

@@ -176,6 +176,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->t0 = B.take<double>(nsplit);
   c->t1 = B.take<double>(nsplit);
   c->t2 = B.take<double>(N);
+  c->wallD = B.take<double>(N);
   for (int q = 0; q < 9; ++q) c->G[q] = B.take<double>(N);
   c->S2 = B.take<double>(N);
   c->rhs_p = B.take<double>(N);
@@ -277,6 +278,25 @@ static size_t layout(hfdib_ctx* c, char* base) {
   return B.off + 256;
 }
 
+// Inlet turbulence values: given, or (turb_intensity > 0) derived from the
+// intensity and length scale by the paper's inlet condition (eq. bcspkoein):
+// k = 3/2 |u_in|^2 I^2, eps = C_nu k^(3/2) / l_t, omega = eps / (C_nu k); without a
+// length scale omega is given and eps = C_nu k omega.
+static void inlet_values(const hfdib_grid_desc& d, const hfdib_config& c, double* k, double* eps, double* om) {
+  *k = d.k_in;
+  *eps = d.eps_in;
+  *om = d.omega_in;
+  if (!(d.turb_intensity > 0.0)) return;
+  const double U2 = d.u_in[0] * d.u_in[0] + d.u_in[1] * d.u_in[1] + d.u_in[2] * d.u_in[2];
+  *k = 1.5 * U2 * d.turb_intensity * d.turb_intensity;
+  if (d.turb_length > 0.0) {
+    *eps = c.Cmu * std::pow(*k, 1.5) / d.turb_length;
+    *om = *eps / (c.Cmu * *k);
+  } else {
+    *eps = c.Cmu * *k * *om;
+  }
+}
+
 static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::string* why) {
   if (!d || !c) {
     *why = "null descriptor";
@@ -351,8 +371,10 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     return HFDIB_EINVAL;
   }
   if (c->model != HFDIB_LAMINAR) {
-    double win = (c->model == HFDIB_KEPS || c->model == HFDIB_RKEPS) ? d->eps_in : d->omega_in;
-    if (!(d->k_in > 0.0 && win > 0.0)) {
+    double kin, ein, oin;
+    inlet_values(*d, *c, &kin, &ein, &oin);
+    double win = (c->model == HFDIB_KEPS || c->model == HFDIB_RKEPS) ? ein : oin;
+    if (!(kin > 0.0 && win > 0.0 && std::isfinite(kin) && std::isfinite(win))) {
       *why = "turbulent models need positive inlet k and eps/omega";
       return HFDIB_EINVAL;
     }
@@ -388,10 +410,12 @@ static void fill_params(hfdib_ctx* c) {
   P.h = d.dim == 2 ? std::sqrt(d.dx * d.dy) : std::pow(P.V, 1.0 / 3.0);
   for (int f = 0; f < 6; ++f) P.bc[f] = d.bc[f];
   for (int q = 0; q < 3; ++q) P.u_in[q] = d.u_in[q];
-  P.k_in = d.k_in;
+  double kin, ein, oin;
+  inlet_values(d, g, &kin, &ein, &oin);
+  P.k_in = kin;
   P.w_in = (g.model == HFDIB_KEPS || g.model == HFDIB_RKEPS)
-               ? d.eps_in
-               : ((g.model == HFDIB_KOMEGA_SST || g.model == HFDIB_KOMEGA) ? d.omega_in : 0.0);
+               ? ein
+               : ((g.model == HFDIB_KOMEGA_SST || g.model == HFDIB_KOMEGA) ? oin : 0.0);
   P.model = g.model;
   P.n_sweeps = g.n_sweeps;
   P.nu = g.nu;

@@ -13,7 +13,6 @@ from .cases import (  # noqa: F401
     case_bfs,
     case_ahmed,
     case_ahmed_small,
-    inlet_turbulence,
     case_channel_ib,
     case_channel_bodyfitted,
     case_cavity_block,

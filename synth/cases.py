@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import dataclasses
 import hashlib
-from typing import Dict, Tuple
+from typing import Dict, Optional, Tuple
 
 import numpy as np
 
@@ -61,9 +61,12 @@ class CaseSpec:
     dz: float
     bc: Tuple[str, str, str, str, str, str]  # kinds of xmin,xmax,ymin,ymax,zmin,zmax
     u_in: Tuple[float, float, float]
-    k_in: float
-    eps_in: float
-    omega_in: float
+    # inlet turbulence, either given directly (k_in, eps_in, omega_in) or, when
+    # inlet_I > 0, as a turbulence intensity with a length scale inlet_l (or, with
+    # inlet_l = 0, with omega_in given); each solver converts them itself
+    k_in: Optional[float]
+    eps_in: Optional[float]
+    omega_in: Optional[float]
     nu: float
     model: str
     urf_u: float = 0.7
@@ -80,6 +83,8 @@ class CaseSpec:
     constants: Dict[str, float] = dataclasses.field(default_factory=lambda: dict(DEFAULT_CONSTANTS))
     lam: np.ndarray = None
     seed: int = 0
+    inlet_I: float = 0.0
+    inlet_l: float = 0.0
 
     @property
     def shape(self):
@@ -105,16 +110,6 @@ class CaseSpec:
         return self
 
 
-def inlet_turbulence(U, intensity, length_scale, Cmu=0.09):
-    """Inlet turbulence from intensity and length scale, as prescribed in the
-    paper's boundary-condition paragraph (k = 3/2 U^2 I^2, eps = Cmu k^1.5 / l,
-    omega = eps / (Cmu k))."""
-    k = 1.5 * (U * intensity) ** 2
-    eps = Cmu * k ** 1.5 / length_scale
-    omega = eps / (Cmu * k)
-    return k, eps, omega
-
-
 def _spec(**kw):
     return CaseSpec(**kw)
 
@@ -129,12 +124,11 @@ def case_bfs(nx=160, ny=40, h=1.0, model="keps"):
     mixing length 0.07 h.  The block lies on cell faces, so lambda is 0/1."""
     dx = 20.0 * h / nx
     dy = 5.0 * h / ny
-    k, eps, om = inlet_turbulence(1.0, 0.05, 0.07 * h)
     s = _spec(name=f"bfs_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
               x0=0.0, y0=0.0, z0=0.0, dx=dx, dy=dy, dz=1.0,
               bc=("inlet", "outlet", "noslip", "slip", "empty", "empty"),
-              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
-              nu=2e-4, model=model)
+              u_in=(1.0, 0.0, 0.0), k_in=None, eps_in=None, omega_in=None,
+              nu=2e-4, model=model, inlet_I=0.05, inlet_l=0.07 * h)
     s.lam = G.lambda_from_sdf(G.sdf_box((-np.inf, -np.inf, -np.inf), (3.0 * h, 1.0 * h, np.inf)), s)
     return s.validate()
 
@@ -147,12 +141,11 @@ def case_ahmed(scale=1, model="sst"):
     inlet I = 2 %, length scale a tenth of the body height."""
     d = 0.03 / scale
     nx, ny, nz = 256 * scale, 96 * scale, 96 * scale
-    k, eps, om = inlet_turbulence(1.0, 0.02, 0.1 * 0.288)
     s = _spec(name=f"ahmed_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
               x0=-2.0, y0=-1.44, z0=0.0, dx=d, dy=d, dz=d,
               bc=("inlet", "outlet", "slip", "slip", "noslip", "slip"),
-              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
-              nu=1.044 / 7.7e5, model=model)
+              u_in=(1.0, 0.0, 0.0), k_in=None, eps_in=None, omega_in=None,
+              nu=1.044 / 7.7e5, model=model, inlet_I=0.02, inlet_l=0.1 * 0.288)
     s.lam = G.lambda_from_sdf(G.sdf_ahmed_like(), s)
     return s.validate()
 
@@ -160,12 +153,11 @@ def case_ahmed(scale=1, model="sst"):
 def case_ahmed_small(model="sst", nx=48, ny=16, nz=16, d=0.06):
     """Reduced Ahmed-like case for oracle-speed parity tests: the same body in a
     tighter box x in [-0.5, -0.5 + nx d], y centred, z from the ground."""
-    k, eps, om = inlet_turbulence(1.0, 0.02, 0.1 * 0.288)
     s = _spec(name=f"ahmed_small_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
               x0=-0.5, y0=-0.5 * ny * d, z0=0.0, dx=d, dy=d, dz=d,
               bc=("inlet", "outlet", "slip", "slip", "noslip", "slip"),
-              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
-              nu=1.044 / 7.7e5, model=model)
+              u_in=(1.0, 0.0, 0.0), k_in=None, eps_in=None, omega_in=None,
+              nu=1.044 / 7.7e5, model=model, inlet_I=0.02, inlet_l=0.1 * 0.288)
     s.lam = G.lambda_from_sdf(G.sdf_ahmed_like(), s)
     return s.validate()
 
@@ -218,12 +210,11 @@ def case_cavity_block(nx=24, ny=12, model="laminar"):
 def case_small_body3d(nx=24, ny=12, nz=12, model="laminar", shape="sphere", nu=1e-2):
     """Small 3D duct with a sphere (cut cells) or a grid-aligned box."""
     d = 1.0 / ny
-    k, eps, om = inlet_turbulence(1.0, 0.05, 0.07)
     s = _spec(name=f"{shape}3d_{nx}x{ny}x{nz}", dim=3, nx=nx, ny=ny, nz=nz,
               x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=d,
               bc=("inlet", "outlet", "slip", "slip", "noslip", "slip"),
-              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
-              nu=nu, model=model)
+              u_in=(1.0, 0.0, 0.0), k_in=None, eps_in=None, omega_in=None,
+              nu=nu, model=model, inlet_I=0.05, inlet_l=0.07)
     if shape == "sphere":
         f = G.sdf_sphere((0.6, 0.5, 0.5), 0.2)
     else:
@@ -239,7 +230,7 @@ def case_uniform_duct(nx=64, ny=4, model="keps", U=1.0, L=1.0):
     s = _spec(name=f"duct_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
               x0=0.0, y0=0.0, z0=0.0, dx=d, dy=d, dz=1.0,
               bc=("inlet", "outlet", "slip", "slip", "empty", "empty"),
-              u_in=(U, 0.0, 0.0), k_in=1e-2, eps_in=1e-2, omega_in=1e-2 / (0.09 * 1e-2),
+              u_in=(U, 0.0, 0.0), k_in=1e-2, eps_in=1e-2, omega_in=100.0 / 9.0,
               nu=1e-5, model=model)
     s.lam = np.zeros(s.shape)
     return s.validate()
@@ -250,21 +241,18 @@ def case_naca(gamma_deg=4.0, nx=256, ny=128, model="sst", intensity=0.03):
     angle of attack gamma about the quarter chord, in x in [-2, 6],
     y in [-2, 2] (square cells: 256 x 128, 512 x 256 or 1024 x 512).
     Re = 1e6 on the chord (nu = 1e-6, U = 1 along +x), inlet turbulence
-    intensity I (k = 1.5 I^2; default 3 %), omega_in = 5 U / c; inlet at
+    intensity I (default 3 %) with omega_in = 5 U / c; inlet at
     x = -2, outlet at x = 6, slip far-field top and bottom.  Lift is along +y,
     drag along +x.  (With I = 0.1 % every near-wall cell starts on the viscous
     branch and the iteration diverges on the two finer grids; the paper takes
     its inlet values from a reference that is not available here.)"""
     dx = 8.0 / nx
     dy = 4.0 / ny
-    k = 1.5 * intensity ** 2
-    om = 5.0
-    eps = 0.09 * k * om
     s = _spec(name=f"naca0012_a{gamma_deg:+.2f}_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
               x0=-2.0, y0=-2.0, z0=0.0, dx=dx, dy=dy, dz=1.0,
               bc=("inlet", "outlet", "slip", "slip", "empty", "empty"),
-              u_in=(1.0, 0.0, 0.0), k_in=k, eps_in=eps, omega_in=om,
-              nu=1e-6, model=model)
+              u_in=(1.0, 0.0, 0.0), k_in=None, eps_in=None, omega_in=5.0,
+              nu=1e-6, model=model, inlet_I=intensity)
     s.lam = G.lambda_from_sdf(G.sdf_naca_symmetric(0.12, 1.0, gamma_deg), s)
     return s.validate()
 

@@ -29,9 +29,9 @@ def test_every_declared_symbol_is_exported(hiplib):
 
 
 def test_abi_version_and_defaults(hiplib):
-    assert hiplib.hfdib_abi_version() == 3
+    assert hiplib.hfdib_abi_version() == 4
     c = B.default_config()
-    assert c.abi_version == 3 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
+    assert c.abi_version == 4 and c.n_sweeps == 2 and c.recorrect == 1 and c.continuity == 0
     assert c.yplus_dist == 0 and c.conv_scheme == 0
     # the library's defaults are the constants the oracle receives
     for n in B._CONST_NAMES:
