@@ -156,6 +156,14 @@ typedef struct {
   double A0_rke, C2_rke, sigma_k_rke, sigma_eps_rke;
   /* safeguards */
   double bound_frac, yperp_min_frac, cd_floor;
+  /* 1: hfdib_set_indicator keeps the current state (velocity, pressure, fluxes,
+     k, eps/omega, nu_t) instead of resetting it to the initial conditions, e.g. to
+     restart from a converged state after a small change of lambda */
+  int keep_state;
+  /* residual blow-up guard of hfdib_simple_iterate: HFDIB_EDIVERGED when the sum of
+     the absolute momentum residuals sum |b - A u| at a residual check exceeds
+     div_factor times its value at the first check of the call (<= 0: off) */
+  double div_factor;
 } hfdib_config;
 
 typedef struct hfdib_ctx hfdib_ctx;
@@ -169,6 +177,14 @@ enum {
   HFDIB_FIELD_CLASS,    /* get only: 0 free-stream, 1 boundary, 2 in-solid */
   HFDIB_FIELD_ALPHA_U,  /* get only: alpha_u of the last iteration */
   HFDIB_FIELD_WALLDIST, /* get only: SST wall distance */
+  /* get only, values of the last iteration (eq. of the imposed fields, eqs. for
+     k_vis, omega_ib and P_ib): the imposed velocity on forced cells (in-solid cells
+     and boundary cells with alpha_u = 1; other cells undefined), the imposed k on
+     the same cells, the imposed eps/omega on in-solid, boundary and domain-wall
+     cells (alpha_omega = 1; other cells undefined), the production of k with P_ib
+     on those cells, and y+ (boundary and domain-wall cells, 0 elsewhere) */
+  HFDIB_FIELD_UIB_X, HFDIB_FIELD_UIB_Y, HFDIB_FIELD_UIB_Z, HFDIB_FIELD_KIB, HFDIB_FIELD_WIB,
+  HFDIB_FIELD_PK, HFDIB_FIELD_YPLUS,
   HFDIB_FIELD_COUNT
 };
 
@@ -189,6 +205,9 @@ enum {
   HFDIB_IB_YPLUS,        /* double[n_bc]: y+ of the last iteration */
   HFDIB_IB_UTAU_LOGLAW,  /* double[n_bc]: log-law u_tau of the last iteration (0 off branch) */
   HFDIB_IB_WALL_Y,       /* double[n_wall] */
+  HFDIB_IB_UTAU,         /* double[n_bc]: u_tau = C_mu^(1/4) sqrt(k) of the last iteration */
+  HFDIB_IB_WALL_YPLUS,   /* double[n_wall]: y+ of the last iteration */
+  HFDIB_IB_WALL_UTAU,    /* double[n_wall]: u_tau of the last iteration */
   HFDIB_IB_COUNT
 };
 
@@ -196,7 +215,8 @@ enum {
 int hfdib_abi_version(void);
 
 /* Fills *cfg with the defaults (standard model constants, URF 0.7/0.3/0.85,
- * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1, continuity 0). */
+ * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1, continuity 0, keep_state 0,
+ * div_factor 1e6). */
 void hfdib_default_config(hfdib_config* cfg);
 
 /* Bytes of device workspace a context needs for this grid and configuration. */
@@ -213,7 +233,8 @@ int hfdib_init_grid(const hfdib_grid_desc* d, const hfdib_config* c, void* works
 /* Sets the indicator field (Sec. "Mask fields construction") and runs the
  * per-lambda precompute: cell groups, normals, sigma, y_perp, y_eff,
  * interpolation stencils, wall-function cells and (SST) the wall distance; then
- * resets the state to the initial conditions.  lambda_dev: N doubles in [0,1]
+ * resets the state to the initial conditions (unless cfg.keep_state).
+ * lambda_dev: N doubles in [0,1]
  * (device).  solid_vel_dev: 3*N doubles (ux block, uy block, uz block) with the
  * solid velocity, or NULL for a resting solid.  Both are copied.  Synchronises
  * the stream once (to validate lambda and read list sizes).
@@ -227,7 +248,8 @@ int hfdib_set_indicator(hfdib_ctx* ctx, const double* lambda_dev, const double* 
  * synchronises once per PCG iteration (see hfdib_pressure_solve).
  * *iters_done (nullable) receives the count; res_out (nullable, host, 6 doubles)
  * the residuals of Ux, Uy, Uz, p, k, eps/omega of the last iteration.  Returns
- * EDIVERGED on NaN/Inf. */
+ * EDIVERGED on a NaN/Inf residual or on a residual blow-up (see
+ * hfdib_config.div_factor), with the state left as of the failing iteration. */
 int hfdib_simple_iterate(hfdib_ctx* ctx, int max_iters, double tol, int check_every,
                          int* iters_done, double* res_out);
 

@@ -21,10 +21,11 @@ MODEL = {"laminar": 0, "keps": 1, "sst": 2, "komega": 3, "rkeps": 4}
 YPLUS_DIST = {"eff": 0, "perp": 1}
 CONV_SCHEME = {"upwind": 0, "linear_upwind": 1, "vanleer": 2}
 FIELD = {"ux": 0, "uy": 1, "uz": 2, "p": 3, "k": 4, "w": 5, "nut": 6,
-         "phix": 7, "phiy": 8, "phiz": 9, "lambda": 10, "class": 11, "alpha_u": 12, "walldist": 13}
+         "phix": 7, "phiy": 8, "phiz": 9, "lambda": 10, "class": 11, "alpha_u": 12, "walldist": 13,
+         "uib_x": 14, "uib_y": 15, "uib_z": 16, "kib": 17, "wib": 18, "pk": 19, "yplus": 20}
 IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "yeff": 5, "mode": 6,
       "lagrange": 7, "st1_idx": 8, "st1_w": 9, "st2_idx": 10, "st2_w": 11, "yplus": 12,
-      "utau_loglaw": 13, "wall_y": 14}
+      "utau_loglaw": 13, "wall_y": 14, "utau": 15, "wall_yplus": 16, "wall_utau": 17}
 TIMER = {"p_apply": 0, "mom_sweep": 1, "mom_assemble": 2, "p_solve": 3, "iteration": 4, "scalar_sweep": 5,
          "scalar_assemble": 6}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
@@ -53,7 +54,8 @@ class Config(C.Structure):
                 ("nu", C.c_double), ("urf_u", C.c_double), ("urf_p", C.c_double), ("urf_t", C.c_double),
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("recorrect", C.c_int),
                 ("bc_capacity", C.c_int), ("continuity", C.c_int), ("yplus_dist", C.c_int),
-                ("conv_scheme", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES]
+                ("conv_scheme", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES] + [
+                    ("keep_state", C.c_int), ("div_factor", C.c_double)]
 
 
 class HfdibError(RuntimeError):
@@ -136,7 +138,7 @@ def default_config():
 
 
 def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0, continuity="literal",
-                     precision="fp64"):
+                     precision="fp64", keep_state=False, div_factor=None):
     """Grid descriptor and configuration from a case description (any object with
     the attributes of synth.CaseSpec)."""
     d = GridDesc()
@@ -163,6 +165,9 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
     c.yplus_dist = YPLUS_DIST[getattr(spec, "yplus_dist", "eff")]
     c.conv_scheme = CONV_SCHEME[getattr(spec, "conv_scheme", "upwind")]
     c.precision = {"fp64": 0, "mixed": 1}[precision]
+    c.keep_state = 1 if keep_state else 0
+    if div_factor is not None:
+        c.div_factor = float(div_factor)
     for n in _CONST_NAMES:
         if n in spec.constants:
             setattr(c, n, float(spec.constants[n]))
@@ -293,7 +298,8 @@ class Solver:
                  "st1_idx": (8 * n["bc"], t.int32), "st1_w": (8 * n["bc"], t.float64),
                  "st2_idx": (8 * n["bc"], t.int32), "st2_w": (8 * n["bc"], t.float64),
                  "yplus": (n["bc"], t.float64), "utau_loglaw": (n["bc"], t.float64),
-                 "wall_y": (n["wall"], t.float64)}
+                 "wall_y": (n["wall"], t.float64), "utau": (n["bc"], t.float64),
+                 "wall_yplus": (n["wall"], t.float64), "wall_utau": (n["wall"], t.float64)}
         cnt, dt = sizes[name]
         out = t.empty(max(cnt, 1), dtype=dt, device=self.device)
         self._sync_in()

@@ -501,6 +501,11 @@ __global__ void k_flag_field(long long n, const uint8_t* flags, int which, doubl
   if (which == 0) out[c] = (f & F_IC) ? 2.0 : ((f & F_BC) ? 1.0 : 0.0);
   else out[c] = (f & F_ALPHA_U) ? 1.0 : 0.0;
 }
+__global__ void k_scatter_list(int n, const int* cells, const double* v, double* dst) {
+  int b = blockIdx.x * NTHREADS + threadIdx.x;
+  if (b < n) dst[cells[b]] = v[b];
+}
+
 __global__ void k_fill0(long long n, double* a) {
   long long c = (long long)blockIdx.x * NTHREADS + threadIdx.x;
   if (c < n) a[c] = 0.0;
@@ -561,6 +566,8 @@ void hfdib_default_config(hfdib_config* c) {
   c->bound_frac = 1e-10;
   c->yperp_min_frac = 1e-6;
   c->cd_floor = 1e-10;
+  c->keep_state = 0;
+  c->div_factor = 1e6;
 }
 
 int hfdib_workspace_bytes(const hfdib_grid_desc* d, const hfdib_config* c, size_t* bytes) {
@@ -624,10 +631,18 @@ int hfdib_set_indicator(hfdib_ctx* c, const double* lambda_dev, const double* so
   }
   hipLaunchKernelGGL(k_fill0, dim3(n1), dim3(NTHREADS), 0, c->stream, P.N, c->dw);
   HFDIB_CHECK_LAUNCH(c, "set_indicator");
+  // (keep_state needs a state: a context whose indicator was set before)
+  const bool keep = c->cfg.keep_state && c->ready;
   c->ready = 0;
   int st = geometry_precompute(c);
   if (st != HFDIB_OK) return st;
-  st = init_state(c);
+  if (keep) {
+    // the state stays; the velocity gradient and the FP32 mirrors are refreshed
+    c->grad_ok = 0;
+    st = refresh_mirrors(c);
+  } else {
+    st = init_state(c);
+  }
   if (st != HFDIB_OK) return st;
   c->ready = 1;
   return HFDIB_OK;
@@ -642,7 +657,10 @@ int hfdib_simple_iterate(hfdib_ctx* c, int max_iters, double tol, int check_ever
   }
   if (max_iters < 0) return HFDIB_EINVAL;
   memset(c->stats, 0, sizeof(c->stats));
-  double res[6] = {0, 0, 0, 0, 0, 0};
+  // residuals of the checks: the six normalised ones, then the sum of the
+  // absolute momentum residuals (the blow-up guard)
+  double res[7] = {0, 0, 0, 0, 0, 0, 0};
+  double abs0 = -1.0;
   int done = 0;
   int status = HFDIB_OK;
   for (int it = 0; it < max_iters; ++it) {
@@ -662,8 +680,14 @@ int hfdib_simple_iterate(hfdib_ctx* c, int max_iters, double tol, int check_ever
         if (!std::isfinite(res[q])) finite = false;
         mx = res[q] > mx ? res[q] : mx;
       }
-      if (!finite) {
+      if (!finite || !std::isfinite(res[6])) {
         c->err = "non-finite residual";
+        status = HFDIB_EDIVERGED;
+        break;
+      }
+      if (abs0 < 0.0) abs0 = res[6];
+      if (c->cfg.div_factor > 0.0 && res[6] > c->cfg.div_factor * abs0) {
+        c->err = "momentum residual grew by more than div_factor since the first check";
         status = HFDIB_EDIVERGED;
         break;
       }
@@ -672,7 +696,7 @@ int hfdib_simple_iterate(hfdib_ctx* c, int max_iters, double tol, int check_ever
   }
   c->stats[1] = done;
   if (iters_done) *iters_done = done;
-  if (res_out) memcpy(res_out, res, sizeof(res));
+  if (res_out) memcpy(res_out, res, 6 * sizeof(double));
   return status;
 }
 
@@ -692,6 +716,12 @@ static double* field_ptr(hfdib_ctx* c, int id, size_t* n) {
     case HFDIB_FIELD_PHI_Z: *n = (size_t)P.nx * P.ny * (P.nz + 1); return c->phi[2];
     case HFDIB_FIELD_LAMBDA: return c->lam;
     case HFDIB_FIELD_WALLDIST: return c->dw;
+    case HFDIB_FIELD_UIB_X: return c->uib[0];
+    case HFDIB_FIELD_UIB_Y: return c->uib[1];
+    case HFDIB_FIELD_UIB_Z: return c->uib[2];
+    case HFDIB_FIELD_KIB: return c->kib;
+    case HFDIB_FIELD_WIB: return c->wib;
+    case HFDIB_FIELD_PK: return c->Pk;
     default: return nullptr;
   }
 }
@@ -701,6 +731,18 @@ int hfdib_get_field(hfdib_ctx* c, int id, double* dst) {
   if (id == HFDIB_FIELD_CLASS || id == HFDIB_FIELD_ALPHA_U) {
     hipLaunchKernelGGL(k_flag_field, dim3(nblocks1(c->P.N)), dim3(NTHREADS), 0, c->stream, c->P.N, c->flags,
                        id == HFDIB_FIELD_CLASS ? 0 : 1, dst);
+    HFDIB_CHECK_LAUNCH(c, "get_field");
+    return HFDIB_OK;
+  }
+  if (id == HFDIB_FIELD_YPLUS) {
+    // y+ of the boundary and domain-wall cells, 0 elsewhere
+    hipLaunchKernelGGL(k_fill0, dim3(nblocks1(c->P.N)), dim3(NTHREADS), 0, c->stream, c->P.N, dst);
+    if (c->n_bc > 0)
+      hipLaunchKernelGGL(k_scatter_list, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, c->n_bc,
+                         (const int*)c->bc_cells, (const double*)c->bc_yplus, dst);
+    if (c->n_wall > 0)
+      hipLaunchKernelGGL(k_scatter_list, dim3(nblocks1(c->n_wall)), dim3(NTHREADS), 0, c->stream, c->n_wall,
+                         (const int*)c->wall_cells, (const double*)c->wall_yplus, dst);
     HFDIB_CHECK_LAUNCH(c, "get_field");
     return HFDIB_OK;
   }
@@ -837,6 +879,9 @@ int hfdib_get_ib_array(hfdib_ctx* c, int id, void* dst) {
     case HFDIB_IB_YPLUS: src = c->bc_yplus; bytes = nb * 8; break;
     case HFDIB_IB_UTAU_LOGLAW: src = c->bc_utauU; bytes = nb * 8; break;
     case HFDIB_IB_WALL_Y: src = c->wall_y; bytes = nw * 8; break;
+    case HFDIB_IB_UTAU: src = c->bc_utau; bytes = nb * 8; break;
+    case HFDIB_IB_WALL_YPLUS: src = c->wall_yplus; bytes = nw * 8; break;
+    case HFDIB_IB_WALL_UTAU: src = c->wall_utau; bytes = nw * 8; break;
     default: return HFDIB_EINVAL;
   }
   if (bytes == 0) return HFDIB_OK;

@@ -104,6 +104,7 @@ struct hfdib_ctx {
   double *rhs[3], *aPr, *hbya[3], *rAU, *F1;
   double *uib[3], *kib, *wib, *Pk, *us[3];
   double *t0, *t1, *t2;  // scratch (turbulence rhs / diagonal)
+  double* wallD;  // immersed-wall coupling of boundary cells on the logarithmic branch
   // velocity gradient of the current u: G[3 a + jc] = d u_jc / d x_a, and 2 S:S
   // (computed once per iteration after the velocity update; grad_ok = 0 when
   // u changed otherwise)

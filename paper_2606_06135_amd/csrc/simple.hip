@@ -14,6 +14,8 @@ struct Mom {
   const uint8_t* flags;
   const double* uib[3];
   const double* G[9];  // stored velocity gradient of u (G[3 a + jc] = d u_jc / d x_a)
+  const double* us[3];   // solid velocity
+  const double* wallD;   // immersed-wall coupling of boundary cells on the logarithmic branch (k_ib_pre)
 };
 
 // FP32 outputs of the momentum assembly under the mixed policy (all null under
@@ -148,12 +150,22 @@ __global__ void k_sums5(Params P, const double* a0, const double* a1, const doub
 // boundary cells: u_tau = Cmu^(1/4) sqrt(k_P), y+ = y_eff u_tau / nu (eq. for
 // y+ and u_tau), alpha_u = alpha_k = [y+ <= y+_lam] (eq. for alpha_u), and the
 // imposed velocity from the quadratic along n_P through (0,u_s), P1, P2.
+// Boundary cells on the logarithmic branch (not forced) get instead, in wallD,
+// the change of their momentum diagonal that makes each face shared with an
+// in-solid neighbour couple the cell to the solid through the wall function:
+// sum over those faces of D_w - D_f, D_w = (nu + nu_w) |n . e_f| A_f / y (nu_w the
+// log-law wall viscosity at the cell's y+, y its wall distance), D_f = the
+// face-mean diffusivity over the centre distance that the row already holds.
+// The momentum assembly adds it to a_P and, times the solid velocity, to the
+// right-hand side (the paper's high-Reynolds-number treatment, in which the
+// boundary velocity follows from the turbulent viscosity: under the log law the
+// momentum flux to the wall is u_tau^2 per unit wall area).
 __global__ void k_ib_pre(Params P, int nbc, const int* bc_cells, const double* bc_yeff, const double* bc_L,
                          const int* st1, const double* w1, const int* st2, const double* w2, const double* kold,
                          const double* u0, const double* u1, const double* u2, const double* us0, const double* us1,
                          const double* us2, uint8_t* flags, double* ub0, double* ub1, double* ub2, double* bc_utau,
                          double* bc_yplus, int nw, const int* wall_cells, const double* wall_y, double* wall_utau,
-                         double* wall_yplus) {
+                         double* wall_yplus, const double* bc_n, const double* nut, double* wallD) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= nbc + nw) return;
   if (b >= nbc) {
@@ -181,7 +193,28 @@ __global__ void k_ib_pre(Params P, int nbc, const int* bc_cells, const double* b
   bool a = yp <= P.ylam;
   uint8_t f = flags[c];
   flags[c] = a ? (uint8_t)(f | F_ALPHA_U) : (uint8_t)(f & ~F_ALPHA_U);
-  if (!a) return;
+  if (!a) {
+    // (only the in-solid bit of the neighbours' flags is read: it never changes)
+    const int i = (int)(c % P.nx), j = (int)((c / P.nx) % P.ny), kz = (int)(c / ((long long)P.nx * P.ny));
+    const int ii[3] = {i, j, kz}, nn[3] = {P.nx, P.ny, P.nz};
+    const long long st[3] = {1, P.nx, (long long)P.nx * P.ny};
+    const double y = bc_yeff[b];
+    const double nuw = P.nu + nut_wall(P, yp);
+    const double nuP = P.nu + nut[c];
+    double dD = 0.0;
+    for (int d = 0; d < P.dim; ++d)
+      for (int s = -1; s <= 1; s += 2) {
+        const int q = ii[d] + s;
+        if (q < 0 || q >= nn[d]) continue;
+        const long long n = c + s * st[d];
+        if (!(flags[n] & F_IC)) continue;
+        const double Df = 0.5 * (nuP + (P.nu + nut[n])) * P.area[d] / P.delta[d];
+        const double Dw = nuw * P.area[d] * fabs(bc_n[3 * b + d]) / y;
+        dD += Dw - Df;
+      }
+    wallD[c] = dD;
+    return;
+  }
   const double* uu[3] = {u0, u1, u2};
   const double* us[3] = {us0, us1, us2};
   double* ub[3] = {ub0, ub1, ub2};
@@ -289,9 +322,16 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
           bsrc[cc] += a * ubv;
         }
       }
+    const bool alpha = fl & F_ALPHA_U;
+    if ((fl & F_BC) && !alpha && P.model != HFDIB_LAMINAR) {
+      // boundary cell on the logarithmic branch: immersed-wall coupling (k_ib_pre)
+      const double dD = M.wallD[c];
+      aP += dD;
+#pragma unroll
+      for (int cc = 0; cc < DIM; ++cc) bsrc[cc] += dD * M.us[cc][c];
+    }
     const double urf = P.urf_u;
     const double aPr = aP / urf;
-    const bool alpha = fl & F_ALPHA_U;
     double rh[DIM], Ax[DIM];
 #pragma unroll
     for (int cc = 0; cc < DIM; ++cc) {
@@ -756,10 +796,12 @@ static Mom make_mom(hfdib_ctx* c) {
     M.uib[q] = c->uib[q];
   }
   for (int q = 0; q < 9; ++q) M.G[q] = c->G[q];
+  for (int q = 0; q < 3; ++q) M.us[q] = c->us[q];
   M.p = c->p;
   M.nut = c->nut;
   M.k = c->k;
   M.flags = c->flags;
+  M.wallD = c->wallD;
   return M;
 }
 
@@ -821,6 +863,8 @@ __global__ void k_residuals(const double* S, int dim, int turb, double* out) {
     out[4] = 0.0;
     out[5] = 0.0;
   }
+  // sum of the absolute momentum residuals (blow-up guard of the iteration)
+  out[6] = S[SC_RESSUM] + (dim > 1 ? S[SC_RESSUM + 3] : 0.0) + (dim > 2 ? S[SC_RESSUM + 6] : 0.0);
 }
 
 // velocity gradient (Gauss, linear face interpolation) and 2 S:S of the current u
@@ -926,7 +970,8 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
     hipLaunchKernelGGL(k_ib_pre, dim3(nblocks1(c->n_bc + c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_bc,
                        c->bc_cells, c->bc_yeff, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->k, c->u[0],
                        c->u[1], c->u[2], c->us[0], c->us[1], c->us[2], c->flags, c->uib[0], c->uib[1], c->uib[2],
-                       c->bc_utau, c->bc_yplus, c->n_wall, c->wall_cells, c->wall_y, c->wall_utau, c->wall_yplus);
+                       c->bc_utau, c->bc_yplus, c->n_wall, c->wall_cells, c->wall_y, c->wall_utau, c->wall_yplus,
+                       c->bc_n, c->nut, c->wallD);
   // 2. momentum predictor (needs the gradient of the current u)
   if (!c->grad_ok) {
     st = velocity_gradient(c);
@@ -1001,7 +1046,7 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   launch_ev(k_residuals, dim3(1), dim3(64), c->stream, ev, S, P.dim, P.model != HFDIB_LAMINAR ? 1 : 0, S + SC_RES);
   HFDIB_CHECK_LAUNCH(c, "residuals");
   if (res_host) {
-    HFDIB_CHECK(c, hipMemcpyAsync(res_host, S + SC_RES, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+    HFDIB_CHECK(c, hipMemcpyAsync(res_host, S + SC_RES, 7 * sizeof(double), hipMemcpyDeviceToHost, c->stream),
                 "residual copy");
     HFDIB_CHECK(c, hipStreamSynchronize(c->stream), "residual sync");
   }

@@ -148,8 +148,18 @@ k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv
 // imposed omega/eps and production on the boundary cells and the domain-wall
 // cells (one thread per list entry), and on the in-solid cells (omega/eps = the
 // maximum over the other cells, no production), in one launch
+// The logarithmic-branch production takes |n . grad u| as the wall-normal
+// difference of the tangential velocity relative to the solid (0 at domain
+// walls) over the wall distance y: (|u_t,P - u_s,t| / y)^2 (the wall-face normal
+// gradient of the wall-function form of eq. omegaws; under the log law it makes
+// P_ib the equilibrium production u_tau^3 / (kappa y)).
+struct Vel3 {
+  const double* u[3];
+  const double* us[3];
+};
+
 __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, const int* ic_cells, const double* wmax,
-                               G9 Gs, const double* S2, const double* kold, const double* nut, double* Pk,
+                               Vel3 V, const double* S2, const double* kold, const double* nut, double* Pk,
                                double* wib, double* w) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= L0.n + L1.n + nic) return;
@@ -165,19 +175,23 @@ __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, cons
   const WallList& L = first ? L0 : L1;
   if (!first) b -= L0.n;
   int c = L.cells[b];
-  double G[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int jc = 0; jc < 3; ++jc) G[a][jc] = (a < P.dim && jc < P.dim) ? Gs.g[3 * a + jc][c] : 0.0;
   double yp = L.ypl[b], ut = L.utl[b], y = L.y[b];
   double om = omega_ib(P, yp, y, ut);
   double kk = kold[c];
   double val = (P.model == HFDIB_KEPS || P.model == HFDIB_RKEPS) ? P.Cmu * kk * om : om;
-  double ng[3] = {0.0, 0.0, 0.0};
-  for (int jj = 0; jj < 3; ++jj)
-    for (int ii = 0; ii < 3; ++ii) ng[jj] += L.nv[3 * b + ii] * G[ii][jj];
-  double ng2 = ng[0] * ng[0] + ng[1] * ng[1] + ng[2] * ng[2];
+  double ur[3], un = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    ur[q] = V.u[q][c] - (first ? V.us[q][c] : 0.0);
+    un += ur[q] * L.nv[3 * b + q];
+  }
+  double t2 = 0.0;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const double tq = ur[q] - un * L.nv[3 * b + q];
+    t2 += tq * tq;
+  }
+  double ng2 = t2 / (y * y);
   double Pm = model_production(P, S2[c], nut[c], kk, w[c]);
   Pk[c] = prod_ib(P, yp, Pm, ng2);
   wib[c] = val;
@@ -602,7 +616,8 @@ int turbulence_stage(hfdib_ctx* c) {
     int ntot = c->n_bc + c->n_wall + c->n_ic;
     if (ntot > 0)
       hipLaunchKernelGGL(k_turb_imposed, dim3(nblocks1(ntot)), dim3(NTHREADS), 0, c->stream, P, L0, L1, c->n_ic,
-                         c->ic_cells, wmax, Gs, c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
+                         c->ic_cells, wmax, Vel3{{c->u[0], c->u[1], c->u[2]}, {c->us[0], c->us[1], c->us[2]}},
+                         c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
   }
   const int nbs = nblocks_sum(P.N);
   hipLaunchKernelGGL(k_sum1, dim3(nbs), dim3(NTHREADS), 0, c->stream, P.N, c->w, c->partials, c->pstride);

@@ -1,0 +1,195 @@
+"""Parity of the HIP library with the CPU oracle beyond whole-field norms after a
+fixed iteration count:
+
+* the per-boundary-cell records of the immersed-boundary steps (eqs. for y+,
+  u_tau, the imposed fields, k_vis, omega_ib and P_ib), cell by cell;
+* the converged state (the fixed point of the iteration) in FP64 and under the
+  mixed policy, against the oracle converged on the CPU;
+* the full-size Ahmed-like workload (256 x 96 x 96, SST) after ten iterations,
+  against a stored oracle fixture sampled at every boundary and in-solid cell
+  and at a seeded sample of the others (tests/golden/make_ahmed_fixture.py);
+* boundary details: the y+ field, keep_state, and the divergence guard.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.solver import Simple
+from parity_util import rel_l2
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _solver(spec, gpu, **kw):
+    import torch
+    from paper_2606_06135_amd import Solver
+    kw.setdefault("p_rtol", 1e-13)
+    kw.setdefault("p_maxit", 300)
+    s = Solver.from_spec(spec, device=gpu, **kw)
+    s.set_indicator(torch.from_numpy(spec.lam.ravel()))
+    return s
+
+
+def _maxrel(a, b):
+    a, b = np.asarray(a, float).ravel(), np.asarray(b, float).ravel()
+    if b.size == 0:
+        return 0.0
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+RECORD_CASES = {
+    "sphere3d_keps": (lambda: synth.case_small_body3d(model="keps", nu=1e-4), 20),
+    "sphere3d_sst": (lambda: synth.case_small_body3d(model="sst", nu=1e-4), 20),
+    "bfs_keps_160x40": (lambda: synth.case_bfs(), 30),
+    "ahmed_small_sst": (lambda: synth.case_ahmed_small(), 15),
+    "naca_128x64_sst": (lambda: synth.case_naca(4.0, 128, 64), 20),
+}
+
+
+@pytest.mark.parametrize("name", list(RECORD_CASES))
+def test_immersed_boundary_records_match_oracle(gpu, name):
+    mk, iters = RECORD_CASES[name]
+    spec = mk()
+    _say("IB records", name, spec.ncells, "iterations", iters)
+    sim = Simple(spec)
+    for _ in range(iters):
+        sim.step()
+    s = _solver(spec, gpu)
+    s.iterate(iters)
+    L = sim.last
+    bc = sim.bc_cells
+    fa = L["alpha"].ravel()
+    forced_bc = fa[bc]
+    out = {}
+    out["yplus"] = _maxrel(s.ib_array("yplus").cpu().numpy(), L["yp"])
+    out["utau"] = _maxrel(s.ib_array("utau").cpu().numpy(), L["utau"])
+    out["utau_loglaw"] = _maxrel(s.ib_array("utau_loglaw").cpu().numpy(), L["utau_U"])
+    # the y+ field: boundary and domain-wall cells, 0 elsewhere
+    ypf = s.get_field("yplus").cpu().numpy()
+    ref = np.zeros(spec.ncells)
+    ref[bc] = L["yp"]
+    wc = sim.geo.wall_cells
+    if len(wc):
+        ref[wc] = s.ib_array("wall_yplus").cpu().numpy()
+    out["yplus_field"] = _maxrel(ypf, ref)
+    # imposed velocity and k on the forced cells (in-solid, boundary with alpha_u = 1)
+    forced = np.concatenate([sim.ic_cells, bc[forced_bc]])
+    for q, nm in enumerate(("uib_x", "uib_y", "uib_z")[:spec.dim]):
+        g = s.get_field(nm).cpu().numpy()
+        out[nm] = _maxrel(g[forced], L["uib"][q].ravel()[forced])
+    out["kib"] = _maxrel(s.get_field("kib").cpu().numpy()[forced], L["kib"].ravel()[forced])
+    # imposed eps/omega and the production on the alpha_omega cells, and P_k everywhere
+    aw = L["alpha_w"].ravel()
+    out["wib"] = _maxrel(s.get_field("wib").cpu().numpy()[aw], L["wib"].ravel()[aw])
+    pk = s.get_field("pk").cpu().numpy()
+    out["P_ib"] = _maxrel(pk[aw], L["Pk"].ravel()[aw])
+    out["P_k"] = _maxrel(pk, L["Pk"].ravel())
+    _say("  max relative deviation", {k: f"{v:.1e}" for k, v in out.items()},
+         "forced boundary cells", int(forced_bc.sum()), "of", len(bc))
+    for k, v in out.items():
+        assert v <= 1e-9, (name, k, v)
+
+
+CONVERGING = {
+    "channel_ib_laminar": lambda: synth.case_channel_ib(nx=32, n_fluid=8),
+    "block2d_laminar": lambda: synth.case_cavity_block(),
+    "box3d_sst": lambda: synth.case_small_body3d(model="sst", shape="box", nu=1e-5),
+    "ahmed_small_sst": lambda: synth.case_ahmed_small(),
+}
+FIELDS = ("ux", "uy", "uz", "p", "k", "w", "nut")
+
+
+@pytest.mark.parametrize("name", list(CONVERGING))
+def test_fixed_point_matches_converged_oracle(gpu, name):
+    # the oracle converged on the CPU (pressure by CG to 1e-13, normalised
+    # residuals <= 1e-9) against the GPU converged in FP64 and under the mixed
+    # policy (each to <= 1e-9): relative L2 <= 1e-6 per field
+    spec = CONVERGING[name]()
+    _say("fixed point", name, spec.ncells)
+    sim = Simple(spec, p_solver="cg", p_rtol=1e-13)
+    for it in range(3000):
+        r = sim.step()
+        if max(r.values()) <= 1e-9:
+            break
+    assert max(r.values()) <= 1e-9
+    of = {k: np.asarray(v).ravel() for k, v in sim.fields().items()}
+    _say(f"  oracle: {it + 1} iterations")
+    for prec in ("fp64", "mixed"):
+        s = _solver(spec, gpu, precision=prec, p_rtol=1e-2, p_maxit=200)
+        done, res = s.iterate(3000, 1e-9, 10)
+        assert max(res) <= 1e-9, (prec, done, res)
+        errs = {}
+        for k in FIELDS:
+            if spec.model == "laminar" and k in ("k", "w", "nut"):
+                continue
+            if spec.dim == 2 and k == "uz":
+                continue
+            a = s.get_field(k).cpu().numpy()
+            errs[k] = rel_l2(a, of[k])
+        _say(f"  {prec}: {done} iterations; relative L2 vs oracle", {k: f"{v:.1e}" for k, v in errs.items()})
+        for k, v in errs.items():
+            assert v <= 1e-6, (name, prec, k, v)
+
+
+def test_full_size_iterated_state_matches_oracle_fixture(gpu):
+    path = os.path.join(HERE, "golden", "ahmed_256x96x96_sst_it10.npz")
+    fx = np.load(path)
+    spec = synth.case_ahmed(scale=1)
+    assert str(fx["lambda_sha256"]) == spec.lambda_sha256()
+    n_it = int(fx["iterations"])
+    _say("full-size fixture", spec.ncells, "iterations", n_it)
+    s = _solver(spec, gpu, p_rtol=float(fx["p_rtol"]), p_maxit=400)
+    done, res = s.iterate(n_it)
+    assert done == n_it
+    cells = fx["cells"]
+    errs = {}
+    for k in ("ux", "uy", "uz", "p", "k", "w", "nut"):
+        errs[k] = rel_l2(s.get_field(k).cpu().numpy()[cells], fx[k])
+    _say("  sampled cells", len(cells), "relative L2", {k: f"{v:.1e}" for k, v in errs.items()})
+    for k, v in errs.items():
+        assert v <= 1e-9, (k, v)
+    # the normalised residuals of the last iteration (FP64 on both sides)
+    last = fx["residuals"][-1]
+    for q in range(6):
+        assert abs(res[q] - last[q]) <= 1e-6 * max(1.0, abs(last[q])), (q, res[q], last[q])
+
+
+def test_keep_state_restarts_from_the_current_state(gpu):
+    import torch
+    spec = synth.case_small_body3d(model="keps", nu=1e-4)
+    s = _solver(spec, gpu, p_rtol=1e-2, keep_state=True)
+    s.iterate(5)
+    before = {k: s.get_field(k).cpu().numpy() for k in ("ux", "p", "k", "w", "nut")}
+    s.set_indicator(torch.from_numpy(spec.lam.ravel()))
+    for k, v in before.items():
+        np.testing.assert_array_equal(s.get_field(k).cpu().numpy(), v)
+    # without the flag the state returns to the initial conditions
+    t = _solver(spec, gpu, p_rtol=1e-2)
+    t0 = t.get_field("ux").cpu().numpy()
+    t.iterate(5)
+    t.set_indicator(torch.from_numpy(spec.lam.ravel()))
+    np.testing.assert_array_equal(t.get_field("ux").cpu().numpy(), t0)
+
+
+def test_divergence_guard_returns_ediverged(gpu):
+    # the blow-up guard, forced from the host: with div_factor below 1 the first
+    # check already counts as growth; 0 switches the guard off
+    from paper_2606_06135_amd import HfdibError
+    spec = synth.case_cavity_block()
+    s = _solver(spec, gpu, p_rtol=1e-2, div_factor=0.5)
+    with pytest.raises(HfdibError) as e:
+        s.iterate(3, 1e-30, 1)
+    assert e.value.status == -4
+    assert s.stats()[1] == 1  # stopped at the failing iteration
+    ok = _solver(spec, gpu, p_rtol=1e-2, div_factor=0.0)
+    done, res = ok.iterate(5, 1e-30, 1)
+    assert done == 5
