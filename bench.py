@@ -107,6 +107,8 @@ def main():
                          "iterations take the same time for every shape within 1 %")
     ap.add_argument("--case", default="ahmed", choices=["ahmed", "bfs", "ahmed2"])
     ap.add_argument("--p-rtol", type=float, default=1e-2)
+    ap.add_argument("--p-sweeps", type=int, default=2,
+                    help="red-black sweeps before and after the coarse correction in the pressure V-cycle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
     ap.add_argument("--timing-every", type=int, default=4,
@@ -144,7 +146,8 @@ def main():
     N = spec.ncells
     log(f"lambda ready in {time.time() - t0:.1f}s; cells {N}")
     dev = torch.device("cuda:0")
-    solver = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=100, precision=args.precision)
+    solver = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=100, precision=args.precision,
+                              p_sweeps=args.p_sweeps)
     lam = torch.from_numpy(spec.lam.ravel()).to(dev)
     t0 = time.time()
     solver.set_indicator(lam)

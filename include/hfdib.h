@@ -164,6 +164,10 @@ typedef struct {
      the absolute momentum residuals sum |b - A u| at a residual check exceeds
      div_factor times its value at the first check of the call (<= 0: off) */
   double div_factor;
+  /* red-black Gauss-Seidel sweeps before and after the coarse correction on every
+     level of the pressure preconditioner's V-cycle (1..4; the V-cycle stays
+     symmetric: red-black sweeps before, black-red after) */
+  int p_sweeps;
 } hfdib_config;
 
 typedef struct hfdib_ctx hfdib_ctx;
@@ -216,7 +220,7 @@ int hfdib_abi_version(void);
 
 /* Fills *cfg with the defaults (standard model constants, URF 0.7/0.3/0.85,
  * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1, continuity 0, keep_state 0,
- * div_factor 1e6). */
+ * div_factor 1e6, p_sweeps 2). */
 void hfdib_default_config(hfdib_config* cfg);
 
 /* Bytes of device workspace a context needs for this grid and configuration. */

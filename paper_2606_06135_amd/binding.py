@@ -55,7 +55,7 @@ class Config(C.Structure):
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("recorrect", C.c_int),
                 ("bc_capacity", C.c_int), ("continuity", C.c_int), ("yplus_dist", C.c_int),
                 ("conv_scheme", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES] + [
-                    ("keep_state", C.c_int), ("div_factor", C.c_double)]
+                    ("keep_state", C.c_int), ("div_factor", C.c_double), ("p_sweeps", C.c_int)]
 
 
 class HfdibError(RuntimeError):
@@ -138,7 +138,7 @@ def default_config():
 
 
 def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0, continuity="literal",
-                     precision="fp64", keep_state=False, div_factor=None):
+                     precision="fp64", keep_state=False, div_factor=None, p_sweeps=None):
     """Grid descriptor and configuration from a case description (any object with
     the attributes of synth.CaseSpec)."""
     d = GridDesc()
@@ -168,6 +168,8 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
     c.keep_state = 1 if keep_state else 0
     if div_factor is not None:
         c.div_factor = float(div_factor)
+    if p_sweeps is not None:
+        c.p_sweeps = int(p_sweeps)
     for n in _CONST_NAMES:
         if n in spec.constants:
             setattr(c, n, float(spec.constants[n]))

@@ -68,6 +68,7 @@ struct Params {
   int tx_log2;    // tile width of the full-grid kernels: 2^tx_log2 cells (5..8), 256 threads per tile
   int tz_log2;    // tile depth: 2^tz_log2 planes (0..2; 2^tz_log2 divides nz, tx_log2 + tz_log2 <= 8)
   int tile_zfirst;  // 1: tiles ordered z fastest within each XCD's run (else x, then y, then z)
+  int p_nu;         // red-black sweeps before and after the coarse correction in the pressure V-cycle
 };
 
 // Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).

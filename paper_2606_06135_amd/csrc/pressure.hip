@@ -541,6 +541,53 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T>
   C.r[lidx(C, I, J, K)] = s;
 }
 
+// Restriction after further pre-smoothing sweeps (the V-cycle's nu > 1): the
+// last half sweep was black, so black rows are satisfied and only the red
+// children contribute, each by its full residual r - A z.
+template <typename T>
+__global__ void k_restrict_fine_res(Params P, FineOpT<T> O, const T* r, const T* z, LevelDevT<T> C) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int J = blockIdx.y * blockDim.y + threadIdx.y;
+  int K = blockIdx.z;
+  if (I >= C.nx || J >= C.ny) return;
+  const int nzs = C.dim == 3 ? 2 : 1;
+  T s = (T)0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < nzs; ++e) {
+        if ((a + b + e) & 1) continue;  // black child
+        int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
+        long long c = cidx(P, i, j, k);
+        Nbr N = make_nbr(P, i, j, k, c);
+        T cf[6], dg, bs;
+        fine_row(P, O, N, c, cf);
+        T Az = fine_Ax(cf, N, z, c, dg, bs);
+        Az = sel(dg == (T)0, z[c], Az);  // uncoupled row: identity
+        s += r[c] - Az;
+      }
+  C.r[lidx(C, I, J, K)] = s;
+}
+
+template <typename T>
+__global__ void k_restrict_level_res(LevelDevT<T> F, LevelDevT<T> C) {
+  int I = blockIdx.x * blockDim.x + threadIdx.x;
+  int J = blockIdx.y * blockDim.y + threadIdx.y;
+  int K = blockIdx.z;
+  if (I >= C.nx || J >= C.ny) return;
+  int nzs = C.dim == 3 ? 2 : 1;
+  T s = (T)0;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int e = 0; e < nzs; ++e) {
+        if ((a + b + e) & 1) continue;
+        int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
+        const long long c = lidx(F, i, j, k);
+        const T nb = level_nbsum_f(F, i, j, k, [&](long long n, int, int, int) { return F.z[n]; });
+        s += F.r[c] - (F.diag[c] * F.z[c] - nb);
+      }
+  C.r[lidx(C, I, J, K)] = s;
+}
+
 // restriction after the pre-smoothing sweep of a stored level: the residual of
 // a red row is sum_nb c z_nb (black rows are satisfied), summed over the red
 // children of each coarse cell
@@ -599,13 +646,17 @@ __device__ __forceinline__ void tail_smooth(const LevelDevT<T>& L, int color, in
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle_global(TailLevelsT<T> TL, int m) {
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle_global(TailLevelsT<T> TL, int m, int nu) {
   int n = TL.n;
   for (int t = 0; t < n - 1; ++t) {
     const LevelDevT<T>& F = TL.L[t];
     const LevelDevT<T>& C = TL.L[t + 1];
     tail_smooth(F, 0, 1);
     tail_smooth(F, 1, 0);
+    for (int s = 1; s < nu; ++s) {
+      tail_smooth(F, 0, 0);
+      tail_smooth(F, 1, 0);
+    }
     int nzs = C.dim == 3 ? 2 : 1;
     for (long long q = threadIdx.x; q < C.N; q += TAIL_THREADS) {
       int I = (int)(q % C.nx), J = (int)((q / C.nx) % C.ny), K = (int)(q / ((long long)C.nx * C.ny));
@@ -657,8 +708,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle_global(TailLevelsT
       F.z[c] += C.z[lidx(C, i / 2, j / 2, F.dim == 3 ? k / 2 : 0)];
     }
     __syncthreads();
-    tail_smooth(F, 1, 0);
-    tail_smooth(F, 0, 0);
+    for (int s = 0; s < nu; ++s) {
+      tail_smooth(F, 1, 0);
+      tail_smooth(F, 0, 0);
+    }
   }
 }
 
@@ -747,7 +800,7 @@ __device__ __forceinline__ void lds_copy(T* dst, const T* src, int n) {
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL, int m) {
+__global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL, int m, int nu) {
   extern __shared__ unsigned char tail_lds_raw[];
   T* base = reinterpret_cast<T*>(tail_lds_raw);
   const int n = TL.n;
@@ -793,6 +846,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
     LdsLev<T> F = lds_lev(TL, t, base), C = lds_lev(TL, t + 1, base);
     lds_smooth(F, 0, 1);
     lds_smooth(F, 1, 0);
+    for (int s = 1; s < nu; ++s) {
+      lds_smooth(F, 0, 0);
+      lds_smooth(F, 1, 0);
+    }
     int nzs = C.dim == 3 ? 2 : 1;
     for (int q = threadIdx.x; q < C.N; q += TAIL_THREADS) {
       int I, J, K;
@@ -825,8 +882,10 @@ __global__ void __launch_bounds__(TAIL_THREADS) k_tail_vcycle(TailLevelsT<T> TL,
       F.z[c] += C.z[(i / 2) + C.nx * ((j / 2) + C.ny * (F.dim == 3 ? k / 2 : 0))];
     }
     __syncthreads();
-    lds_smooth(F, 1, 0);
-    lds_smooth(F, 0, 0);
+    for (int s = 0; s < nu; ++s) {
+      lds_smooth(F, 1, 0);
+      lds_smooth(F, 0, 0);
+    }
   }
   LdsLev<T> L0 = lds_lev(TL, 0, base);
   for (int c = threadIdx.x; c < L0.N; c += TAIL_THREADS) TL.L[0].z[c] = L0.z[c];
@@ -988,20 +1047,37 @@ template <typename T>
 static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, const double* rdot,
                   double* dcopy = nullptr, bool presmoothed = false) {
   const Params& P = c->P;
+  const int nu = P.p_nu;
   dim3 g = grid3_rb(P), bf = block3(P), b = block_lv();
   if (!presmoothed) vcycle_presmooth<T>(c, O, invD, r, z);
+  // further pre-smoothing sweeps (red, then black)
+  for (int s = 1; s < nu; ++s)
+    for (int color = 0; color < 2; ++color)
+      hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, color, (const T*)nullptr, 0, 0,
+                         (const double*)nullptr, (double*)nullptr, 0LL, (double*)nullptr);
   const T* zc = nullptr;
   int cnx = 0, cny = 0;
   if (c->nlev > 1) {
     LevelDevT<T> L1 = levdev<T>(c, 1);
-    hipLaunchKernelGGL(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, (const T*)z, L1);
+    if (nu == 1)
+      hipLaunchKernelGGL(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, (const T*)z, L1);
+    else
+      hipLaunchKernelGGL(k_restrict_fine_res<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, (const T*)z,
+                         L1);
     // large coarse levels: one kernel per pass
     int l = 1;
     while (l < c->nlev - 1 && c->lev[l].N > TAIL_MAX) {
       LevelDevT<T> L = levdev<T>(c, l);
-      hipLaunchKernelGGL(k_level_presmooth<T>, lgrid_rb(L.nx, L.ny, L.nz), b, 0, c->stream, L);
+      dim3 gr = lgrid_rb(L.nx, L.ny, L.nz);
+      hipLaunchKernelGGL(k_level_presmooth<T>, gr, b, 0, c->stream, L);
+      for (int s = 1; s < nu; ++s)
+        for (int color = 0; color < 2; ++color)
+          hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, color, L, 0);
       LevelDevT<T> C = levdev<T>(c, l + 1);
-      hipLaunchKernelGGL(k_restrict_level<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
+      if (nu == 1)
+        hipLaunchKernelGGL(k_restrict_level<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
+      else
+        hipLaunchKernelGGL(k_restrict_level_res<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
       ++l;
     }
     // small levels l..nlev-1 (and the coarsest solve) in one workgroup, staged
@@ -1018,25 +1094,32 @@ static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, 
     }
     size_t lds = (size_t)elems * sizeof(T);
     if (lds <= (size_t)TAIL_LDS_BYTES)
-      hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), lds, c->stream, TL, 6);
+      hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), lds, c->stream, TL, 6, nu);
     else
-      hipLaunchKernelGGL(k_tail_vcycle_global<T>, dim3(1), dim3(TAIL_THREADS), 0, c->stream, TL, 6);
+      hipLaunchKernelGGL(k_tail_vcycle_global<T>, dim3(1), dim3(TAIL_THREADS), 0, c->stream, TL, 6, nu);
     for (int q = l - 1; q >= 1; --q) {
       LevelDevT<T> L = levdev<T>(c, q);
       LevelDevT<T> C = levdev<T>(c, q + 1);
       dim3 gr = lgrid_rb(L.nx, L.ny, L.nz);
-      hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 1, C, 1);
-      hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 0, C, 0);
+      for (int s = 0; s < nu; ++s) {
+        hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 1, C, s == 0 ? 1 : 0);
+        hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 0, C, 0);
+      }
     }
     zc = L1.z;
     cnx = L1.nx;
     cny = L1.ny;
   }
-  // post-smoothing, black first (with the prolongation on the fly), then red
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, zc, cnx, cny, (const double*)nullptr,
-                     (double*)nullptr, 0LL, (double*)nullptr);
-  hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0, rdot,
-                     c->partials, c->pstride, dcopy);
+  // post-smoothing sweeps, black first (the first one with the prolongation on
+  // the fly), then red; the last red half sweep also forms the r . z partials
+  for (int s = 0; s < nu; ++s) {
+    const bool last = s == nu - 1;
+    hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, s == 0 ? zc : (const T*)nullptr,
+                       cnx, cny, (const double*)nullptr, (double*)nullptr, 0LL, (double*)nullptr);
+    hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0,
+                       last ? rdot : (const double*)nullptr, last ? c->partials : (double*)nullptr,
+                       last ? c->pstride : 0LL, last ? dcopy : (double*)nullptr);
+  }
   return (int)g.x;
 }
 
