@@ -278,6 +278,19 @@ int hfdib_get_counts(hfdib_ctx* ctx, int* counts);
  * Synchronises the stream.  HFDIB_ESTATE before hfdib_set_indicator. */
 int hfdib_forces(hfdib_ctx* ctx, double* out8);
 
+/* For callers that cannot allocate or wait on the host (code under HIP graph
+ * capture, tight serving loops): the same eight values as hfdib_forces, written
+ * to out8_dev (8 doubles of caller device memory) in stream order, with no host
+ * synchronisation and no allocation of any kind.  The block partial sums live in
+ * a fixed 4 MiB device array of the library (one per GPU, kept until the process
+ * ends), which limits the grid to about 33 M cells (4 doubles per 256-cell tile
+ * plus 4 per 256 boundary cells); larger grids get HFDIB_EINVAL with the sizes in
+ * hfdib_last_error.  Every call on a GPU shares that array: calls that overlap on
+ * one GPU (different streams or contexts) race and must be ordered by the caller.
+ * The sums may differ from hfdib_forces in the last bits (another summation
+ * order of the partials).  HFDIB_ESTATE before hfdib_set_indicator. */
+int hfdib_forces_noalloc(hfdib_ctx* ctx, double* out8_dev);
+
 /* Tile shape of the full-grid kernels: 256-thread tiles of width 32, 64 (the
  * default), 128 or 256 cells along x.  hfdib_autotune_tiles times, for each
  * width, reps rounds of the gradient pass, the momentum assembly and the

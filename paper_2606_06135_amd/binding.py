@@ -98,6 +98,7 @@ def lib():
     L.hfdib_last_error.argtypes = [vp]
     L.hfdib_last_error.restype = C.c_char_p
     L.hfdib_forces.argtypes = [vp, C.POINTER(d)]
+    L.hfdib_forces_noalloc.argtypes = [vp, vp]
     L.hfdib_autotune_tiles.argtypes = [vp, i, C.POINTER(i), C.POINTER(d)]
     L.hfdib_set_tile_width.argtypes = [vp, i]
     L.hfdib_set_tile_depth.argtypes = [vp, i]
@@ -112,7 +113,7 @@ def lib():
     for fn in ("hfdib_workspace_bytes", "hfdib_init_grid", "hfdib_set_indicator", "hfdib_simple_iterate",
                "hfdib_get_field", "hfdib_set_field", "hfdib_get_counts", "hfdib_get_ib_array",
                "hfdib_pressure_solve", "hfdib_last_stats", "hfdib_timing_enable", "hfdib_timing_query",
-               "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
+               "hfdib_forces", "hfdib_forces_noalloc", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
                "hfdib_autotune_tiles", "hfdib_set_tile_width", "hfdib_set_tile_depth",
                "hfdib_set_tile_order"):
         getattr(L, fn).restype = i
@@ -126,7 +127,7 @@ EXPORTED = ["hfdib_abi_version", "hfdib_default_config", "hfdib_workspace_bytes"
             "hfdib_set_indicator", "hfdib_simple_iterate", "hfdib_get_field", "hfdib_set_field",
             "hfdib_get_counts", "hfdib_get_ib_array", "hfdib_pressure_solve", "hfdib_last_stats",
             "hfdib_timing_enable", "hfdib_timing_query", "hfdib_destroy", "hfdib_status_string",
-            "hfdib_last_error", "hfdib_forces", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
+            "hfdib_last_error", "hfdib_forces", "hfdib_forces_noalloc", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
             "hfdib_batch_last_error", "hfdib_batch_destroy", "hfdib_autotune_tiles", "hfdib_set_tile_width",
             "hfdib_set_tile_depth", "hfdib_set_tile_order"]
 
@@ -346,6 +347,15 @@ class Solver:
         a = (C.c_double * 8)()
         _check("hfdib_forces", lib().hfdib_forces(self.ctx, a), self.ctx)
         return {"pressure": [a[0], a[1], a[2]], "viscous": [a[3], a[4], a[5]], "area": a[6], "bc_area": a[7]}
+
+    def forces_noalloc(self, out=None):
+        """hfdib_forces_noalloc into a device tensor of 8 doubles (no host wait)."""
+        if out is None:
+            out = self.torch.empty(8, dtype=self.torch.float64, device=self.device)
+        self._sync_in()
+        _check("hfdib_forces_noalloc", lib().hfdib_forces_noalloc(self.ctx, C.c_void_p(out.data_ptr())), self.ctx)
+        self._sync_out(out)
+        return out
 
     def coefficients(self, ref_area, u_ref=1.0, drag_dir=(1.0, 0.0, 0.0), lift_dir=(0.0, 1.0, 0.0)):
         """Drag and lift coefficients C = 2 F.v / (|u|^2 A_ref) of the current state."""

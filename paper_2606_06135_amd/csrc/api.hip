@@ -779,6 +779,15 @@ int hfdib_forces(hfdib_ctx* c, double* out8) {
   return hfdib::body_forces(c, out8);
 }
 
+int hfdib_forces_noalloc(hfdib_ctx* c, double* out8_dev) {
+  if (!c || !out8_dev) return HFDIB_EINVAL;
+  if (!c->ready) {
+    c->err = "hfdib_forces_noalloc before hfdib_set_indicator";
+    return HFDIB_ESTATE;
+  }
+  return hfdib::body_forces_noalloc(c, out8_dev);
+}
+
 int hfdib_autotune_tiles(hfdib_ctx* c, int reps, int* best_width, double* ms_out) {
   if (!c || reps < 1) return HFDIB_EINVAL;
   if (!c->ready) {

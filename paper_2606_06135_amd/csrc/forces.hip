@@ -10,6 +10,8 @@
 // the tangential velocity relative to the solid at a boundary cell and tau_w
 // the wall shear stress: u_tau^2 from the log-law Newton solve on cells of the
 // logarithmic branch, nu |u_t| / y_eff on cells of the viscous branch.
+#include <mutex>
+
 #include "device_common.h"
 
 namespace hfdib {
@@ -84,6 +86,102 @@ int body_forces(hfdib_ctx* c, double* out8) {
   for (int d = 0; d < 3; ++d) out8[3 + d] = bc_area > 0.0 ? area * h[4 + d] / bc_area : 0.0;
   out8[6] = area;
   out8[7] = bc_area;
+  return HFDIB_OK;
+}
+
+// ---------------------------------------------------------------- no allocation
+// The variant of body_forces for callers that cannot allocate or synchronise:
+// the block partial sums live in a file-scope device array (one copy per GPU,
+// shared by every context on it) instead of the context's workspace, and the
+// eight results go to a caller device buffer without a host read.  Every
+// partial slot the final kernel reads is written by the partial kernels of the
+// same call, so nothing has to be cleared; calls that overlap on one GPU race
+// on the array.
+constexpr size_t FORCE_SCRATCH_DOUBLES = (4u << 20) / sizeof(double);  // 4 MiB
+static __device__ __align__(256) double scratch[FORCE_SCRATCH_DOUBLES];
+
+constexpr int MAX_DEVICES = 64;
+static double* g_scratch_dev[MAX_DEVICES];  // device address of scratch, per device
+static std::mutex g_scratch_mu;
+
+// device address of this device's copy of scratch (looked up once per device)
+static int scratch_address(hfdib_ctx* c, double** out) {
+  int dev = -1;
+  HFDIB_CHECK(c, hipGetDevice(&dev), "forces_noalloc: current device");
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    c->err = "forces_noalloc: device ordinal out of range";
+    return HFDIB_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    HFDIB_CHECK(c, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "forces_noalloc: scratch address");
+    g_scratch_dev[dev] = (double*)ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return HFDIB_OK;
+}
+
+// sums the 4 cell rows and (nbb > 0) the 4 boundary-cell rows of partials and
+// writes the force record (the same composition as body_forces) to out8
+__global__ void __launch_bounds__(256) k_force_finish(const double* pc, long long nbc3, const double* pb, int nbb,
+                                                      double* out8) {
+  __shared__ double lds[4][8];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (long long b = tid; b < nbc3; b += 256)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] += pc[(long long)q * nbc3 + b];
+  for (int b = tid; b < nbb; b += 256)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[4 + q] += pb[(long long)q * nbb + b];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double sq = wave_sum(acc[q]);
+    if (lane == 0) lds[wid][q] = sq;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double h[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) h[q] = lds[0][q] + lds[1][q] + lds[2][q] + lds[3][q];
+    const double area = h[3], bc_area = h[7];
+    out8[0] = h[0];
+    out8[1] = h[1];
+    out8[2] = h[2];
+    for (int d = 0; d < 3; ++d) out8[3 + d] = bc_area > 0.0 ? area * h[4 + d] / bc_area : 0.0;
+    out8[6] = area;
+    out8[7] = bc_area;
+  }
+}
+
+int body_forces_noalloc(hfdib_ctx* c, double* out8_dev) {
+  const Params& P = c->P;
+  dim3 g = grid3(P), b = block3(P);
+  const long long nblk3 = (long long)g.x * g.y * g.z;
+  const int nbb = c->n_bc > 0 ? nblocks1(c->n_bc) : 0;
+  const long long need = 4 * nblk3 + 4LL * nbb;
+  if (need > (long long)FORCE_SCRATCH_DOUBLES) {
+    c->err = "hfdib_forces_noalloc: the grid needs " + std::to_string(need * 8) +
+             " bytes of partial sums, more than the fixed scratch of " +
+             std::to_string(FORCE_SCRATCH_DOUBLES * 8) + " bytes (about 33 M cells)";
+    return HFDIB_EINVAL;
+  }
+  double* sc = nullptr;
+  int st = scratch_address(c, &sc);
+  if (st != HFDIB_OK) return st;
+  double* pc = sc;                 // 4 rows of nblk3 cell partials
+  double* pb = sc + 4 * nblk3;     // 4 rows of nbb boundary-cell partials
+  hipLaunchKernelGGL(k_force_cells, g, b, 0, c->stream, P, c->p, c->lam, pc, nblk3);
+  if (nbb > 0)
+    hipLaunchKernelGGL(k_force_bc, dim3(nbb), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells, c->bc_n,
+                       c->bc_yeff, c->bc_yplus, c->bc_utauU, c->lam, c->u[0], c->u[1], c->u[2], c->us[0], c->us[1],
+                       c->us[2], pb, (long long)nbb);
+  hipLaunchKernelGGL(k_force_finish, dim3(1), dim3(256), 0, c->stream, (const double*)pc, nblk3,
+                     (const double*)pb, nbb, out8_dev);
+  HFDIB_CHECK_LAUNCH(c, "forces_noalloc");
   return HFDIB_OK;
 }
 

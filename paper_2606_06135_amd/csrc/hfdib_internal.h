@@ -265,6 +265,7 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
 int turbulence_stage(hfdib_ctx* c);
 int velocity_gradient(hfdib_ctx* c);
 int body_forces(hfdib_ctx* c, double* out8);
+int body_forces_noalloc(hfdib_ctx* c, double* out8_dev);
 int tile_bench_round(hfdib_ctx* c);
 void pressure_apply_bench(hfdib_ctx* c);
 // offsets (relative to SCAL_PCG) of device scalars
