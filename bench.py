@@ -42,24 +42,40 @@ sys.path.insert(0, HERE)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 
-# Algorithmic bytes per cell and launch of the timed kernel classes (minimal
-# fused design: every FP64 array streamed once per pass, neighbours reused on
-# chip; per-pass figures of the byte model of one SIMPLE iteration):
+# Algorithmic bytes per cell and launch of the timed kernel classes (every FP64
+# array streamed once per pass at the granularity the pass needs, neighbours
+# reused on chip; per-pass figures of the byte model of one SIMPLE iteration):
 #   k / omega sweeps: 2 x 144 B/cell for n_s = 2 -> 36 per one-colour launch
 #   momentum sweeps: 224 B/cell for n_s = 2 -> 56 per one-colour launch
 #   momentum assembly: u,v,w,p,phi(3),nu_t (+flags) in, b(3), a_P out: 97
 #   omega and k assembly: 2 x 80 -> 80 per launch
-#   fine pressure-operator apply (SpMV): x, rAU in, y out: 24
+#   pressure operator apply: x, rAU (+flags) in, y out: 25
+#   V-cycle half sweep (one colour): r and D^-1 of that colour (8), rAU (8),
+#     flags (1), z of the other colour in and of this colour out (8): 25
+#   V-cycle pre-smoothing pass from zero: r, D^-1, rAU (+flags) in, z out: 33
+#   restriction of the red rows' residuals: r of the red cells (4), z, rAU
+#     (+flags) in, the coarse residual (1/8 of a cell) out: 22
+#   apply with the direction update: z, d_old, rAU (+flags) in, d_new, q out: 41
+#   CG vector update: x, d, r, q in, x, r out: 48
+# (reduction finalize launches and the coarse levels of the V-cycle are bound by
+# launch latency, not by bytes: they are timed but have no byte model)
 ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 97.0, "scalar_assemble": 80.0,
-              "p_apply": 24.0}
+              "p_apply": 25.0, "p_smooth": 25.0, "p_presmooth": 33.0, "p_restrict": 22.0, "p_apply_dir": 41.0,
+              "p_axpy": 48.0}
 KERNEL = {"scalar_sweep": "k_scalar_sweep", "mom_sweep": "k_mom_sweep", "mom_assemble": "k_mom_assemble",
-          "scalar_assemble": "k_scalar_assemble", "p_apply": "k_fine_apply"}
-# the mixed policy's sweeps are one-colour launches of their own kernels
-ALGO_BYTES_MIXED = dict(ALGO_BYTES)
+          "scalar_assemble": "k_scalar_assemble", "p_apply": "k_fine_apply", "p_smooth": "k_fine_smooth",
+          "p_presmooth": "k_fine_presmooth", "p_restrict": "k_restrict_fine_res", "p_apply_dir": "k_fine_apply_dir",
+          "p_axpy": "k_axpy2"}
+PRESSURE_CLASSES = ("p_apply", "p_smooth", "p_presmooth", "p_restrict", "p_apply_dir", "p_axpy")
+# the mixed policy's sweeps are one-colour launches of their own kernels; its
+# V-cycle moves FP32 arrays
+ALGO_BYTES_MIXED = dict(ALGO_BYTES, p_smooth=13.0, p_presmooth=17.0, p_restrict=12.0, p_apply_dir=37.0, p_axpy=52.0)
 KERNEL_MIXED = dict(KERNEL, scalar_sweep="k_scalar_sweep32", mom_sweep="k_mom_sweep32")
 KERNEL_SOURCES = {"k_scalar_sweep": "turbulence.hip", "k_scalar_sweep32": "turbulence.hip",
                   "k_scalar_assemble": "turbulence.hip", "k_mom_sweep": "simple.hip",
-                  "k_mom_sweep32": "simple.hip", "k_mom_assemble": "simple.hip", "k_fine_apply": "pressure.hip"}
+                  "k_mom_sweep32": "simple.hip", "k_mom_assemble": "simple.hip"}
+for _k in ("k_fine_apply", "k_fine_smooth", "k_fine_presmooth", "k_restrict_fine_res", "k_fine_apply_dir", "k_axpy2"):
+    KERNEL_SOURCES[_k] = "pressure.hip"
 
 
 def kernel_source_hash(kernel):
@@ -108,7 +124,9 @@ def main():
     ap.add_argument("--case", default="ahmed", choices=["ahmed", "bfs", "ahmed2"])
     ap.add_argument("--p-rtol", type=float, default=1e-2)
     ap.add_argument("--p-sweeps", type=int, default=2,
-                    help="red-black sweeps before and after the coarse correction in the pressure V-cycle")
+                    help="red-black sweeps before and after the coarse correction on the fine pressure level")
+    ap.add_argument("--p-sweeps-coarse", type=int, default=2,
+                    help="the same on the coarse levels of the pressure V-cycle")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
     ap.add_argument("--timing-every", type=int, default=4,
@@ -147,7 +165,7 @@ def main():
     log(f"lambda ready in {time.time() - t0:.1f}s; cells {N}")
     dev = torch.device("cuda:0")
     solver = Solver.from_spec(spec, device=dev, p_rtol=args.p_rtol, p_maxit=100, precision=args.precision,
-                              p_sweeps=args.p_sweeps)
+                              p_sweeps=args.p_sweeps, p_sweeps_coarse=args.p_sweeps_coarse)
     lam = torch.from_numpy(spec.lam.ravel()).to(dev)
     t0 = time.time()
     solver.set_indicator(lam)
@@ -206,17 +224,19 @@ def main():
     roof = None
     roof_all = []
     kern = {}
+    psolve_hbm = None
     if not args.no_timing:
         for name in ("p_apply", "mom_sweep", "mom_assemble", "scalar_sweep", "scalar_assemble", "p_solve",
-                     "iteration"):
+                     "iteration", "p_smooth", "p_presmooth", "p_restrict", "p_apply_dir", "p_axpy", "p_coarse",
+                     "finalize"):
             ms, cnt = solver.timing_query(name)
             kern[name] = (ms, cnt)
         solver.timing(False)
         log("kernel timing (ms total, launches): " + ", ".join(f"{k}={v[0]:.2f}/{v[1]}" for k, v in kern.items()))
-        # dominant single kernel among the timed classes with a byte model
         algo, knames = (ALGO_BYTES, KERNEL) if args.precision == "fp64" else (ALGO_BYTES_MIXED, KERNEL_MIXED)
         cand = {k: kern[k] for k in algo if kern[k][1] > 0}
         workload = spec.name + "_" + spec.model + "_" + args.precision
+        it_ms = max(kern["iteration"][0], 1e-12)
 
         def roofline_of(cls):
             ms, cnt = cand[cls]
@@ -229,13 +249,32 @@ def main():
                     "traffic": None if traffic is None else round(traffic),
                     "kernel": kname, "avg_launch_us": round(avg_s * 1e6, 2),
                     "algorithmic_bytes_per_cell": algo[cls], "timed_every_nth_iteration": args.timing_every,
-                    "share_of_iteration": round(ms / max(kern["iteration"][0], 1e-12), 4)}
+                    "share_of_iteration": round(ms / it_ms, 4)}
         if cand:
-            # the dominant kernel (largest share of the iteration) ...
+            # the dominant kernel: the largest total time in the timed iterations
             dom = max(cand, key=lambda k: cand[k][0])
             roof = roofline_of(dom)
-            # ... and every timed kernel class, by share (the two largest are close)
             roof_all = [roofline_of(k) for k in sorted(cand, key=lambda k: -cand[k][0])]
+        # the pressure solve as a whole: algorithmic bytes of the fine-level
+        # kernels it ran (coarse levels and reductions not counted) over its time,
+        # and the per-CG-iteration byte model of the minimal design (190 B/cell)
+        ps_ms, ps_cnt = kern["p_solve"]
+        if ps_cnt > 0:
+            nbytes = sum(algo[k] * N * kern[k][1] for k in PRESSURE_CLASSES if k in algo)
+            ach = nbytes / (ps_ms / 1e3) / 1e9
+            n_cg_timed = kern["p_apply_dir"][1] + kern["p_apply"][1]
+            ach190 = 190.0 * N * n_cg_timed / (ps_ms / 1e3) / 1e9
+            share = {k: round(kern[k][0] / ps_ms, 4) for k in
+                     ("p_smooth", "p_presmooth", "p_restrict", "p_apply", "p_apply_dir", "p_axpy", "p_coarse")}
+            psolve_hbm = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                          "frac": round(ach / PEAK_HBM_GBS, 4),
+                          "bytes_per_cell_per_cg_iteration": round(nbytes / max(n_cg_timed, 1) / N, 1),
+                          "achieved_at_190_B_per_cell_per_cg_iteration": round(ach190, 1),
+                          "frac_at_190": round(ach190 / PEAK_HBM_GBS, 4),
+                          "ms_per_solve": round(ps_ms / ps_cnt, 4), "cg_iterations_timed": n_cg_timed,
+                          "share_of_solve": share,
+                          "finalize_ms_per_iteration": round(kern["finalize"][0] / max(kern["iteration"][1], 1), 4),
+                          "p_sweeps": [args.p_sweeps, args.p_sweeps_coarse]}
 
     # whole-iteration %HBM peak with the per-iteration byte model of the minimal
     # fused design (3-D SST, FP64): 1178 B/cell for everything but the pressure
@@ -258,6 +297,7 @@ def main():
     sweep = None
     if args.sweep_iters > 0:
         sweep = naca_sweep(args)
+    hbm_ref = hbm_reference()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(spec, args.p_rtol)
@@ -284,6 +324,8 @@ def main():
                    "final_residuals": [float(x) for x in res]},
         "roofline": roof,
         "roofline_kernels": roof_all,
+        "pressure_solve_hbm": psolve_hbm,
+        "hbm_reference": hbm_ref,
         "iteration_hbm": iteration_hbm,
         "cpu_baseline": cpu,
         "mixed_vs_fp64": mixed,
@@ -425,26 +467,82 @@ def naca_sweep(args):
             "diverged": st["diverged"], "per_instance": inst}
 
 
+def hbm_reference():
+    """Achievable HBM bandwidth on this GPU for the same element type: a copy
+    (b = a) and a STREAM triad (a = b + s c) of FP64 arrays of 18.9 M elements
+    (151 MB each, beyond the last-level cache), with torch's element-wise
+    kernels, best of 10 timed repetitions.  A reference for the kernels'
+    achieved bandwidth beside the nominal 8 TB/s."""
+    import torch
+    n = 18874368
+    dev = torch.device("cuda:0")
+    a = torch.rand(n, dtype=torch.float64, device=dev)
+    b = torch.rand(n, dtype=torch.float64, device=dev)
+    c = torch.rand(n, dtype=torch.float64, device=dev)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 16 * n),
+                             ("triad", lambda: torch.add(b, c, alpha=1.5, out=a), 24 * n)):
+        for _ in range(3):
+            fn()
+        best = None
+        for _ in range(10):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name + "_GBs"] = round(nbytes / (best / 1e3) / 1e9, 1)
+    del a, b, c
+    torch.cuda.empty_cache()
+    out["elements"] = n
+    return out
+
+
 def cpu_baseline(spec, p_rtol):
-    """The oracle (plain NumPy, FP64) on the host: one SIMPLE iteration of the
-    same workload after its precompute; rate in cell-iters/s."""
+    """The oracle (plain NumPy, FP64) on the host: two SIMPLE iterations of the
+    same workload after its precompute, once limited to one thread and once with
+    every host thread allowed; rate in cell-iters/s, with the core count and the
+    CPU model."""
     import warnings
     warnings.simplefilter("ignore")
     from oracle.solver import Simple
     log("cpu baseline: oracle precompute ...")
     t0 = time.time()
     sim = Simple(spec, p_solver="cg", p_rtol=p_rtol)
-    log(f"cpu baseline: precompute {time.time() - t0:.1f}s; timing one iteration")
-    n_it = 2
+    log(f"cpu baseline: precompute {time.time() - t0:.1f}s; timing {2} iterations on one thread, then on all")
+    import copy
+    import platform
     from threadpoolctl import threadpool_limits
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for _ in range(n_it):
-            sim.step()
-        dt = time.perf_counter() - t0
-    return {"value": spec.ncells * n_it / dt, "unit": "cell-iters/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_it} SIMPLE iteration(s) of the same {spec.ncells}-cell workload from the initial "
-                      f"conditions, pressure by SciPy CG (rtol {p_rtol}), {dt:.1f}s wall"}
+    nproc = os.cpu_count()
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    n_it = 2
+    rates = {}
+    for label, limit in (("one", 1), ("all", None)):
+        s = copy.deepcopy(sim)
+        with threadpool_limits(limits=limit):
+            t0 = time.perf_counter()
+            for _ in range(n_it):
+                s.step()
+            dt = time.perf_counter() - t0
+        rates[label] = (spec.ncells * n_it / dt, dt)
+        del s
+    return {"value": rates["one"][0], "unit": "cell-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_it} SIMPLE iterations of the same {spec.ncells}-cell workload from the initial "
+                      f"conditions, pressure by SciPy CG (rtol {p_rtol}), {rates['one'][1]:.1f}s wall on one thread",
+            "all_cores": {"value": rates["all"][0], "threads_available": nproc, "seconds": round(rates["all"][1], 2),
+                          "note": "the NumPy/SciPy oracle is element-wise and sparse code: it uses one core "
+                                  "whatever the thread limit (only dense BLAS calls would use more)"},
+            "nproc": nproc, "cpu_model": model}
 
 
 if __name__ == "__main__":

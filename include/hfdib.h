@@ -164,10 +164,11 @@ typedef struct {
      the absolute momentum residuals sum |b - A u| at a residual check exceeds
      div_factor times its value at the first check of the call (<= 0: off) */
   double div_factor;
-  /* red-black Gauss-Seidel sweeps before and after the coarse correction on every
-     level of the pressure preconditioner's V-cycle (1..4; the V-cycle stays
-     symmetric: red-black sweeps before, black-red after) */
-  int p_sweeps;
+  /* red-black Gauss-Seidel sweeps before and after the coarse correction in the
+     pressure preconditioner's V-cycle, on the fine level (p_sweeps) and on every
+     coarse level (p_sweeps_coarse), each 1..4; the V-cycle stays symmetric
+     (red-black sweeps before, black-red after) */
+  int p_sweeps, p_sweeps_coarse;
 } hfdib_config;
 
 typedef struct hfdib_ctx hfdib_ctx;
@@ -220,7 +221,7 @@ int hfdib_abi_version(void);
 
 /* Fills *cfg with the defaults (standard model constants, URF 0.7/0.3/0.85,
  * n_sweeps 2, p_rtol 1e-2, p_maxit 200, recorrect 1, continuity 0, keep_state 0,
- * div_factor 1e6, p_sweeps 2). */
+ * div_factor 1e6, p_sweeps 2, p_sweeps_coarse 2). */
 void hfdib_default_config(hfdib_config* cfg);
 
 /* Bytes of device workspace a context needs for this grid and configuration. */
@@ -356,7 +357,12 @@ int hfdib_last_stats(hfdib_ctx* ctx, double* out8);
 int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
 /* kernel_class: 0 pressure operator apply (fine level), 1 momentum sweep,
  * 2 momentum assembly, 3 whole pressure solve, 4 whole SIMPLE iteration,
- * 5 k / eps-omega sweep (one colour), 6 turbulence scalar assembly.
+ * 5 k / eps-omega sweep (one colour), 6 turbulence scalar assembly,
+ * 7 fine-level V-cycle half sweep (one colour), 8 fine-level pre-smoothing pass
+ * from zero, 9 restriction of the fine residual, 10 operator apply with the
+ * direction update, 11 CG vector update (x, r), 12 coarse levels of one V-cycle
+ * (one span from the first coarse-level launch to the last, counted as one),
+ * 13 reduction finalize launches (every reduction of the iteration).
  * Returns accumulated milliseconds and the launch count (host pointers).
  * Synchronises the stream. */
 int hfdib_timing_query(hfdib_ctx* ctx, int kernel_class, double* total_ms, long long* count);

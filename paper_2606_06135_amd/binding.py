@@ -27,7 +27,8 @@ IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "y
       "lagrange": 7, "st1_idx": 8, "st1_w": 9, "st2_idx": 10, "st2_w": 11, "yplus": 12,
       "utau_loglaw": 13, "wall_y": 14, "utau": 15, "wall_yplus": 16, "wall_utau": 17}
 TIMER = {"p_apply": 0, "mom_sweep": 1, "mom_assemble": 2, "p_solve": 3, "iteration": 4, "scalar_sweep": 5,
-         "scalar_assemble": 6}
+         "scalar_assemble": 6, "p_smooth": 7, "p_presmooth": 8, "p_restrict": 9, "p_apply_dir": 10, "p_axpy": 11,
+         "p_coarse": 12, "finalize": 13}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
           -4: "diverged", -5: "call out of order"}
 
@@ -55,7 +56,7 @@ class Config(C.Structure):
                 ("p_rtol", C.c_double), ("p_maxit", C.c_int), ("recorrect", C.c_int),
                 ("bc_capacity", C.c_int), ("continuity", C.c_int), ("yplus_dist", C.c_int),
                 ("conv_scheme", C.c_int)] + [(n, C.c_double) for n in _CONST_NAMES] + [
-                    ("keep_state", C.c_int), ("div_factor", C.c_double), ("p_sweeps", C.c_int)]
+                    ("keep_state", C.c_int), ("div_factor", C.c_double), ("p_sweeps", C.c_int), ("p_sweeps_coarse", C.c_int)]
 
 
 class HfdibError(RuntimeError):
@@ -139,7 +140,7 @@ def default_config():
 
 
 def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity=0, continuity="literal",
-                     precision="fp64", keep_state=False, div_factor=None, p_sweeps=None):
+                     precision="fp64", keep_state=False, div_factor=None, p_sweeps=None, p_sweeps_coarse=None):
     """Grid descriptor and configuration from a case description (any object with
     the attributes of synth.CaseSpec)."""
     d = GridDesc()
@@ -171,6 +172,8 @@ def make_desc_config(spec, p_rtol=1e-2, p_maxit=200, recorrect=True, bc_capacity
         c.div_factor = float(div_factor)
     if p_sweeps is not None:
         c.p_sweeps = int(p_sweeps)
+    if p_sweeps_coarse is not None:
+        c.p_sweeps_coarse = int(p_sweeps_coarse)
     for n in _CONST_NAMES:
         if n in spec.constants:
             setattr(c, n, float(spec.constants[n]))

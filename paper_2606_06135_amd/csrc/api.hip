@@ -350,8 +350,8 @@ static int check_inputs(const hfdib_grid_desc* d, const hfdib_config* c, std::st
     *why = "n_sweeps >= 1, p_maxit >= 1 and p_rtol > 0 are required";
     return HFDIB_EINVAL;
   }
-  if (c->p_sweeps < 1 || c->p_sweeps > 4) {
-    *why = "p_sweeps must lie in 1..4";
+  if (c->p_sweeps < 1 || c->p_sweeps > 4 || c->p_sweeps_coarse < 1 || c->p_sweeps_coarse > 4) {
+    *why = "p_sweeps and p_sweeps_coarse must lie in 1..4";
     return HFDIB_EINVAL;
   }
   if (c->model < HFDIB_LAMINAR || c->model > HFDIB_RKEPS) {
@@ -489,6 +489,7 @@ static void fill_params(hfdib_ctx* c) {
   P.continuity = g.continuity;
   P.precision = g.precision;
   P.p_nu = g.p_sweeps;
+  P.p_nu_c = g.p_sweeps_coarse;
   P.tx_log2 = 6;
 }
 
@@ -574,6 +575,7 @@ void hfdib_default_config(hfdib_config* c) {
   c->keep_state = 0;
   c->div_factor = 1e6;
   c->p_sweeps = 2;
+  c->p_sweeps_coarse = 2;
 }
 
 int hfdib_workspace_bytes(const hfdib_grid_desc* d, const hfdib_config* c, size_t* bytes) {

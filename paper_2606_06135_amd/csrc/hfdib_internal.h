@@ -68,7 +68,8 @@ struct Params {
   int tx_log2;    // tile width of the full-grid kernels: 2^tx_log2 cells (5..8), 256 threads per tile
   int tz_log2;    // tile depth: 2^tz_log2 planes (0..2; 2^tz_log2 divides nz, tx_log2 + tz_log2 <= 8)
   int tile_zfirst;  // 1: tiles ordered z fastest within each XCD's run (else x, then y, then z)
-  int p_nu;         // red-black sweeps before and after the coarse correction in the pressure V-cycle
+  int p_nu;         // red-black sweeps before and after the coarse correction on the fine pressure level
+  int p_nu_c;       // the same on the coarse levels
 };
 
 // Coarse multigrid level (level 0 is the fine grid, matrix free from rAU).
@@ -221,7 +222,8 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);
 
 // timing classes
 enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_SCALSWEEP = 5, T_SCALASM = 6,
-       T_NCLASS = 7 };
+       T_PSMOOTH = 7, T_PPRESMOOTH = 8, T_PRESTRICT = 9, T_PAPPLYDIR = 10, T_PAXPY = 11, T_PCOARSE = 12,
+       T_FINALIZE = 13, T_NCLASS = 14 };
 void timer_begin(hfdib_ctx* c, int cls);
 // brackets one SIMPLE iteration (begin = true at its start, false at its end):
 // with a recording period n > 1 only every n-th iteration is recorded

@@ -1021,14 +1021,17 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
   if (nblk > 32 * FIN_THREADS) {
     int chunk = (nblk + FIN2_CHUNKS - 1) / FIN2_CHUNKS;
     int nchunks = (nblk + chunk - 1) / chunk;
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), 0, c->stream, part, c->pstride, nblk,
-                       chunk, op == 4 ? 1 : 0, c->partials2);
-    hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, (const double*)c->partials2,
-                       (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor, hmir, seq);
+    LaunchEv e0 = timer_launch(c, T_FINALIZE, true, false, 2);
+    launch_ev(k_reduce_chunks, dim3(nchunks, nval), dim3(RED_THREADS), c->stream, e0, part, c->pstride, nblk, chunk,
+              op == 4 ? 1 : 0, c->partials2);
+    LaunchEv e1 = timer_launch(c, T_FINALIZE, false, true, 2);
+    launch_ev(k_finalize, dim3(nval), dim3(FIN_THREADS), c->stream, e1, (const double*)c->partials2,
+              (long long)FIN2_STRIDE, nchunks, c->scal + SCAL_PCG, out, op, divisor, hmir, seq);
     return;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(nval), dim3(FIN_THREADS), 0, c->stream, part, c->pstride, nblk,
-                     c->scal + SCAL_PCG, out, op, divisor, hmir, seq);
+  LaunchEv ev = timer_launch(c, T_FINALIZE, true, true);
+  launch_ev(k_finalize, dim3(nval), dim3(FIN_THREADS), c->stream, ev, part, c->pstride, nblk, c->scal + SCAL_PCG, out,
+            op, divisor, hmir, seq);
 }
 
 // the first pass of a V-cycle: fine-level pre-smoothing of z from zero (it
@@ -1036,7 +1039,18 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
 template <typename T>
 static void vcycle_presmooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z) {
   const Params& P = c->P;
-  hipLaunchKernelGGL(k_fine_presmooth<T>, grid3_rb(P), block3(P), 0, c->stream, P, O, invD, r, z);
+  LaunchEv ev = timer_launch(c, T_PPRESMOOTH, true, true);
+  launch_ev(k_fine_presmooth<T>, grid3_rb(P), block3(P), c->stream, ev, P, O, invD, r, z);
+}
+
+// one fine-level half sweep of the V-cycle (timed as its own class)
+template <typename T>
+static void fine_smooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, int color, const T* zc,
+                        int cnx, int cny, const double* rdot, double* part, long long pstride, double* dcopy) {
+  const Params& P = c->P;
+  LaunchEv ev = timer_launch(c, T_PSMOOTH, true, true);
+  launch_ev(k_fine_smooth<T>, grid3_rb(P), block3(P), c->stream, ev, P, O, invD, r, z, color, zc, cnx, cny, rdot,
+            part, pstride, dcopy);
 }
 
 // one V-cycle z = M^-1 r in storage type T; the last sweep also leaves the
@@ -1047,34 +1061,42 @@ template <typename T>
 static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, const double* rdot,
                   double* dcopy = nullptr, bool presmoothed = false) {
   const Params& P = c->P;
-  const int nu = P.p_nu;
-  dim3 g = grid3_rb(P), bf = block3(P), b = block_lv();
+  const int nu = P.p_nu, nuc = P.p_nu_c;  // sweeps per side on the fine level and on the coarse levels
+  dim3 g = grid3_rb(P), b = block_lv();
   if (!presmoothed) vcycle_presmooth<T>(c, O, invD, r, z);
   // further pre-smoothing sweeps (red, then black)
   for (int s = 1; s < nu; ++s)
     for (int color = 0; color < 2; ++color)
-      hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, color, (const T*)nullptr, 0, 0,
-                         (const double*)nullptr, (double*)nullptr, 0LL, (double*)nullptr);
+      fine_smooth<T>(c, O, invD, r, z, color, (const T*)nullptr, 0, 0, (const double*)nullptr, (double*)nullptr, 0LL,
+                     (double*)nullptr);
   const T* zc = nullptr;
   int cnx = 0, cny = 0;
   if (c->nlev > 1) {
     LevelDevT<T> L1 = levdev<T>(c, 1);
+    LaunchEv er = timer_launch(c, T_PRESTRICT, true, true);
     if (nu == 1)
-      hipLaunchKernelGGL(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, (const T*)z, L1);
+      launch_ev(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, c->stream, er, P, O, (const T*)z, L1);
     else
-      hipLaunchKernelGGL(k_restrict_fine_res<T>, lgrid(L1.nx, L1.ny, L1.nz), b, 0, c->stream, P, O, r, (const T*)z,
-                         L1);
+      launch_ev(k_restrict_fine_res<T>, lgrid(L1.nx, L1.ny, L1.nz), b, c->stream, er, P, O, r, (const T*)z, L1);
+    // the coarse levels are timed as one span: opened by their first launch,
+    // closed by the last
+    bool opened = false;
+    auto cev = [&](bool last) {
+      LaunchEv e = timer_launch(c, T_PCOARSE, !opened, last);
+      opened = true;
+      return e;
+    };
     // large coarse levels: one kernel per pass
     int l = 1;
     while (l < c->nlev - 1 && c->lev[l].N > TAIL_MAX) {
       LevelDevT<T> L = levdev<T>(c, l);
       dim3 gr = lgrid_rb(L.nx, L.ny, L.nz);
-      hipLaunchKernelGGL(k_level_presmooth<T>, gr, b, 0, c->stream, L);
-      for (int s = 1; s < nu; ++s)
+      launch_ev(k_level_presmooth<T>, gr, b, c->stream, cev(false), L);
+      for (int s = 1; s < nuc; ++s)
         for (int color = 0; color < 2; ++color)
           hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, color, L, 0);
       LevelDevT<T> C = levdev<T>(c, l + 1);
-      if (nu == 1)
+      if (nuc == 1)
         hipLaunchKernelGGL(k_restrict_level<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
       else
         hipLaunchKernelGGL(k_restrict_level_res<T>, lgrid(C.nx, C.ny, C.nz), b, 0, c->stream, L, C);
@@ -1093,17 +1115,26 @@ static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, 
                (L.dim == 3 ? (long long)L.nx * L.ny * (L.nz + 1) : 0);
     }
     size_t lds = (size_t)elems * sizeof(T);
-    if (lds <= (size_t)TAIL_LDS_BYTES)
-      hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), lds, c->stream, TL, 6, nu);
-    else
-      hipLaunchKernelGGL(k_tail_vcycle_global<T>, dim3(1), dim3(TAIL_THREADS), 0, c->stream, TL, 6, nu);
+    {
+      const bool tail_last = l == 1;
+      LaunchEv et = cev(tail_last);
+      if (lds <= (size_t)TAIL_LDS_BYTES) {
+        if (et.start || et.stop)
+          hipExtLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), lds, c->stream, et.start, et.stop, 0,
+                                TL, 6, nuc);
+        else
+          hipLaunchKernelGGL(k_tail_vcycle<T>, dim3(1), dim3(TAIL_THREADS), lds, c->stream, TL, 6, nuc);
+      } else {
+        launch_ev(k_tail_vcycle_global<T>, dim3(1), dim3(TAIL_THREADS), c->stream, et, TL, 6, nuc);
+      }
+    }
     for (int q = l - 1; q >= 1; --q) {
       LevelDevT<T> L = levdev<T>(c, q);
       LevelDevT<T> C = levdev<T>(c, q + 1);
       dim3 gr = lgrid_rb(L.nx, L.ny, L.nz);
-      for (int s = 0; s < nu; ++s) {
+      for (int s = 0; s < nuc; ++s) {
         hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 1, C, s == 0 ? 1 : 0);
-        hipLaunchKernelGGL(k_level_smooth<T>, gr, b, 0, c->stream, L, 0, C, 0);
+        launch_ev(k_level_smooth<T>, gr, b, c->stream, cev(q == 1 && s == nuc - 1), L, 0, C, 0);
       }
     }
     zc = L1.z;
@@ -1114,11 +1145,10 @@ static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, 
   // the fly), then red; the last red half sweep also forms the r . z partials
   for (int s = 0; s < nu; ++s) {
     const bool last = s == nu - 1;
-    hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 1, s == 0 ? zc : (const T*)nullptr,
-                       cnx, cny, (const double*)nullptr, (double*)nullptr, 0LL, (double*)nullptr);
-    hipLaunchKernelGGL(k_fine_smooth<T>, g, bf, 0, c->stream, P, O, invD, r, z, 0, (const T*)nullptr, 0, 0,
-                       last ? rdot : (const double*)nullptr, last ? c->partials : (double*)nullptr,
-                       last ? c->pstride : 0LL, last ? dcopy : (double*)nullptr);
+    fine_smooth<T>(c, O, invD, r, z, 1, s == 0 ? zc : (const T*)nullptr, cnx, cny, (const double*)nullptr,
+                   (double*)nullptr, 0LL, (double*)nullptr);
+    fine_smooth<T>(c, O, invD, r, z, 0, (const T*)nullptr, 0, 0, last ? rdot : (const double*)nullptr,
+                   last ? c->partials : (double*)nullptr, last ? c->pstride : 0LL, last ? dcopy : (double*)nullptr);
   }
   return (int)g.x;
 }
@@ -1201,8 +1231,9 @@ static void pcg_step(hfdib_ctx* c, const PcgSet<T>& A, double* x, double* hmir, 
   const int nb1 = nblocks1(P.N);
   double* S = c->scal + SCAL_PCG;
   if (dir) {
-    hipLaunchKernelGGL(k_fine_apply_dir<T>, g, b, 0, c->stream, P, A.O, (const T*)A.z_m, (const double*)c->pd, c->pd2,
-                       c->pq, (const double*)S, c->partials, c->pstride);
+    LaunchEv ed = timer_launch(c, T_PAPPLYDIR, true, true);
+    launch_ev(k_fine_apply_dir<T>, g, b, c->stream, ed, P, A.O, (const T*)A.z_m, (const double*)c->pd, c->pd2, c->pq,
+              (const double*)S, c->partials, c->pstride);
     std::swap(c->pd, c->pd2);
   } else {
     // (the timed class of the operator apply is this plain launch)
@@ -1210,8 +1241,9 @@ static void pcg_step(hfdib_ctx* c, const PcgSet<T>& A, double* x, double* hmir, 
     launch_ev(k_fine_apply, g, b, c->stream, ev, P, A.O, (const double*)c->pd, c->pq, c->partials, c->pstride);
   }
   launch_finalize(c, (int)((long long)g.x * g.y * g.z), 1, S_DQ, 1);
-  hipLaunchKernelGGL(k_axpy2, dim3(nb1), dim3(NTHREADS), 0, c->stream, P.N, (const double*)S, x, (const double*)c->pd,
-                     c->pr, A.r32, (const double*)c->pq, c->partials, c->pstride);
+  LaunchEv ea = timer_launch(c, T_PAXPY, true, true);
+  launch_ev(k_axpy2, dim3(nb1), dim3(NTHREADS), c->stream, ea, P.N, (const double*)S, x, (const double*)c->pd, c->pr,
+            A.r32, (const double*)c->pq, c->partials, c->pstride);
   launch_finalize(c, nb1, 1, S_RR, 0, 1.0, 0, hmir, hmir ? (double)++c->mir_seq : 0.0);
 }
 
