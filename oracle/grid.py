@@ -101,10 +101,11 @@ class Grid:
         ``bvalue(d, s, psiP)`` returns the boundary-face values on face (d, s)
         given the owner values psiP.  Returns a list of 3 arrays (z = 0 in 2D).
         """
-        g = [np.zeros(self.shape) for _ in range(3)]
+        dt = np.result_type(psi.dtype, np.float64)  # (complex states of the adjoint's complex steps)
+        g = [np.zeros(self.shape, dtype=dt) for _ in range(3)]
         for d in self.axes:
-            fp = np.empty(self.shape)
-            fm = np.empty(self.shape)
+            fp = np.empty(self.shape, dtype=dt)
+            fm = np.empty(self.shape, dtype=dt)
             fp[self.interior_lo(d)] = 0.5 * (psi[self.interior_lo(d)] + psi[self.interior_hi(d)])
             fm[self.interior_hi(d)] = fp[self.interior_lo(d)]
             fp[self.bnd(d, +1)] = bvalue(d, +1, psi[self.bnd(d, +1)])

@@ -58,6 +58,7 @@ class Simple:
         # identity pressure rows take the mean solved pressure of their coupled
         # face neighbours after each solve (off: they keep their value)
         self.identity_mean = identity_mean
+        self.frozen_turbulence = False
         self.ic = self.geo.tag == IC
         self.bcm = self.geo.tag == BC
         self.bc_cells = self.geo.bc_cells
@@ -542,7 +543,10 @@ class Simple:
                               HbyA=HbyA, phistar=phis, rhs_p=bp, p_sol=p_sol, RHS=RHS))
 
         # ---- 3.5 turbulence -------------------------------------------------
-        if turb:
+        # (frozen_turbulence: k, eps/omega and nu_t are held, so y+ and the masks
+        # stay as well: the momentum-continuity system of the frozen-turbulence
+        # adjoint)
+        if turb and not self.frozen_turbulence:
             self.turbulence(u, phi, k_old, w_old, nut_old, alpha, alpha_bc, utau, yp, utau_w, yp_w, res)
             # velocity-based friction velocity from the log law (diagnostic)
             lg = yp > C["ylam"]

@@ -20,6 +20,7 @@ from .cases import (  # noqa: F401
     case_uniform_duct,
     case_naca,
     naca_sweep_specs,
+    case_bend2d,
 )
 from .geometry import (  # noqa: F401
     lambda_from_sdf,
@@ -28,5 +29,6 @@ from .geometry import (  # noqa: F401
     sdf_halfspace,
     sdf_sphere,
     sdf_naca_symmetric,
+    sdf_lbend,
     naca4_half_thickness,
 )

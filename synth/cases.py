@@ -266,3 +266,47 @@ def naca_sweep_specs(n=64, gamma_min=-10.0, gamma_max=20.0, sizes=((256, 128), (
         nx, ny = sizes[j % len(sizes)]
         out.append(case_naca(g, nx, ny))
     return out
+
+
+def case_bend2d(nx=384, ny=192, seed=12345, model="keps", design=True):
+    """The adjoint workload: a 2D 90-degree bend duct of width 0.25 in
+    [0, 2] x [0, 1] (square cells; 384 x 192 by default), inlet at x = 0 for
+    0.65 < y < 0.9, outlet at y = 0 for 1.6 < x < 1.85; Re = 2000 on the width
+    (U = 1, nu = 1.25e-4), k-epsilon, inlet I = 5 % with length scale 0.07 of the
+    width.  Lambda: the duct's projection, and inside the design box
+    [1.35, 1.85] x [0.4, 0.9] the larger of it and clip((g - 1)/0.5, 0, 1) with g
+    white noise of the given seed, Gaussian-smoothed over 3 cells and scaled to
+    unit standard deviation; the seed is advanced until the cells with
+    lambda < 0.5 connect the inlet to the outlet."""
+    from scipy import ndimage
+    d = 2.0 / nx
+    s = _spec(name=f"bend2d_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,
+              x0=0.0, y0=0.0, z0=0.0, dx=d, dy=1.0 / ny, dz=1.0,
+              bc=("inlet", "slip", "outlet", "slip", "empty", "empty"),
+              u_in=(1.0, 0.0, 0.0), k_in=None, eps_in=None, omega_in=None,
+              nu=1.25e-4, model=model, inlet_I=0.05, inlet_l=0.07 * 0.25)
+    geom = G.lambda_from_sdf(G.sdf_lbend(), s)
+    if not design:
+        s.lam = geom
+        return s.validate()
+    xc = (np.arange(nx) + 0.5) * d
+    yc = (np.arange(ny) + 0.5) / ny
+    X, Y = np.meshgrid(xc, yc)
+    box = (X > 1.35) & (X < 1.85) & (Y > 0.4) & (Y < 0.9)
+    inlet = (X < d) & (Y > 0.65) & (Y < 0.9)
+    outlet = (Y < 1.0 / ny) & (X > 1.6) & (X < 1.85)
+    sd = seed
+    while True:
+        g = ndimage.gaussian_filter(np.random.default_rng(sd).standard_normal((ny, nx)), 3.0)
+        g = g / g.std()
+        lam = geom[0].copy()
+        lam[box] = np.maximum(lam[box], np.clip((g[box] - 1.0) / 0.5, 0.0, 1.0))
+        lab, _ = ndimage.label(lam < 0.5)
+        ins = set(np.unique(lab[inlet & (lab > 0)]))
+        outs = set(np.unique(lab[outlet & (lab > 0)]))
+        if ins & outs:
+            break
+        sd += 1
+    s.lam = lam[None]
+    s.seed = sd
+    return s.validate()

@@ -211,3 +211,16 @@ def sdf_naca_symmetric(t=0.12, chord=1.0, gamma_deg=0.0, pivot=(0.25, 0.0), npts
         inside = (xc > 0.0) & (xc < 1.0) & (np.abs(yr) < chord * naca4_half_thickness(np.clip(xc, 0.0, 1.0), t))
         return np.where(inside, -dist, dist).reshape(shape)
     return f
+
+
+def sdf_lbend(y_in=(0.65, 0.9), x_end=1.85, x_leg=(1.6, 1.85)):
+    """Fluid inside an L-shaped duct: a horizontal leg x < x_end, y_in[0] < y <
+    y_in[1] joined to a vertical leg x_leg[0] < x < x_leg[1], y < y_in[1] (the
+    solid is everything else).  Union of two rectangles: the signed distance is
+    the larger of the two inside distances (positive in the fluid)."""
+    h = sdf_box((-np.inf, y_in[0], -np.inf), (x_end, y_in[1], np.inf))
+    v = sdf_box((x_leg[0], -np.inf, -np.inf), (x_leg[1], y_in[1], np.inf))
+
+    def f(x, y, z):
+        return np.maximum(-h(x, y, z), -v(x, y, z))
+    return f
