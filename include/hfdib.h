@@ -279,6 +279,16 @@ int hfdib_get_counts(hfdib_ctx* ctx, int* counts);
  * Synchronises the stream.  HFDIB_ESTATE before hfdib_set_indicator. */
 int hfdib_forces(hfdib_ctx* ctx, double* out8);
 
+/* Drag and lift coefficients of the current state (the drag-coefficient equation
+ * of the cylinder section and the lift-coefficient equation of the airfoil
+ * section): C = 2 F.e / (u_ref^2 A_ref) for the total force F of hfdib_forces
+ * (pressure plus viscous part) along the unit directions drag_dir and lift_dir
+ * (host, 3 doubles each).  out2 (host): [0] C_d, [1] C_l.  Synchronises the
+ * stream.  HFDIB_EINVAL for ref_area <= 0 or u_ref = 0, HFDIB_ESTATE before
+ * hfdib_set_indicator. */
+int hfdib_force_coefficients(hfdib_ctx* ctx, double ref_area, double u_ref, const double* drag_dir,
+                             const double* lift_dir, double* out2);
+
 /* For callers that cannot allocate or wait on the host (code under HIP graph
  * capture, tight serving loops): the same eight values as hfdib_forces, written
  * to out8_dev (8 doubles of caller device memory) in stream order, with no host

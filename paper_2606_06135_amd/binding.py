@@ -100,6 +100,7 @@ def lib():
     L.hfdib_last_error.restype = C.c_char_p
     L.hfdib_forces.argtypes = [vp, C.POINTER(d)]
     L.hfdib_forces_noalloc.argtypes = [vp, vp]
+    L.hfdib_force_coefficients.argtypes = [vp, d, d, C.POINTER(d), C.POINTER(d), C.POINTER(d)]
     L.hfdib_autotune_tiles.argtypes = [vp, i, C.POINTER(i), C.POINTER(d)]
     L.hfdib_set_tile_width.argtypes = [vp, i]
     L.hfdib_set_tile_depth.argtypes = [vp, i]
@@ -114,7 +115,8 @@ def lib():
     for fn in ("hfdib_workspace_bytes", "hfdib_init_grid", "hfdib_set_indicator", "hfdib_simple_iterate",
                "hfdib_get_field", "hfdib_set_field", "hfdib_get_counts", "hfdib_get_ib_array",
                "hfdib_pressure_solve", "hfdib_last_stats", "hfdib_timing_enable", "hfdib_timing_query",
-               "hfdib_forces", "hfdib_forces_noalloc", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
+               "hfdib_forces", "hfdib_forces_noalloc", "hfdib_force_coefficients", "hfdib_batch_create",
+               "hfdib_batch_run", "hfdib_batch_status",
                "hfdib_autotune_tiles", "hfdib_set_tile_width", "hfdib_set_tile_depth",
                "hfdib_set_tile_order"):
         getattr(L, fn).restype = i
@@ -128,7 +130,8 @@ EXPORTED = ["hfdib_abi_version", "hfdib_default_config", "hfdib_workspace_bytes"
             "hfdib_set_indicator", "hfdib_simple_iterate", "hfdib_get_field", "hfdib_set_field",
             "hfdib_get_counts", "hfdib_get_ib_array", "hfdib_pressure_solve", "hfdib_last_stats",
             "hfdib_timing_enable", "hfdib_timing_query", "hfdib_destroy", "hfdib_status_string",
-            "hfdib_last_error", "hfdib_forces", "hfdib_forces_noalloc", "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
+            "hfdib_last_error", "hfdib_forces", "hfdib_forces_noalloc", "hfdib_force_coefficients",
+            "hfdib_batch_create", "hfdib_batch_run", "hfdib_batch_status",
             "hfdib_batch_last_error", "hfdib_batch_destroy", "hfdib_autotune_tiles", "hfdib_set_tile_width",
             "hfdib_set_tile_depth", "hfdib_set_tile_order"]
 
@@ -361,13 +364,13 @@ class Solver:
         return out
 
     def coefficients(self, ref_area, u_ref=1.0, drag_dir=(1.0, 0.0, 0.0), lift_dir=(0.0, 1.0, 0.0)):
-        """Drag and lift coefficients C = 2 F.v / (|u|^2 A_ref) of the current state."""
-        f = self.forces()
-        tot = [f["pressure"][q] + f["viscous"][q] for q in range(3)]
-        q = 0.5 * u_ref * u_ref * ref_area
-        cd = sum(tot[i] * drag_dir[i] for i in range(3)) / q
-        cl = sum(tot[i] * lift_dir[i] for i in range(3)) / q
-        return cd, cl
+        """Drag and lift coefficients of the current state (hfdib_force_coefficients)."""
+        out = (C.c_double * 2)()
+        dd = (C.c_double * 3)(*drag_dir)
+        ld = (C.c_double * 3)(*lift_dir)
+        _check("hfdib_force_coefficients",
+               lib().hfdib_force_coefficients(self.ctx, float(ref_area), float(u_ref), dd, ld, out), self.ctx)
+        return out[0], out[1]
 
     def stats(self):
         a = (C.c_double * 8)()

@@ -781,6 +781,27 @@ int hfdib_forces(hfdib_ctx* c, double* out8) {
   return hfdib::body_forces(c, out8);
 }
 
+int hfdib_force_coefficients(hfdib_ctx* c, double ref_area, double u_ref, const double* drag_dir,
+                             const double* lift_dir, double* out2) {
+  if (!c || !drag_dir || !lift_dir || !out2 || !(ref_area > 0.0) || u_ref == 0.0) return HFDIB_EINVAL;
+  if (!c->ready) {
+    c->err = "hfdib_force_coefficients before hfdib_set_indicator";
+    return HFDIB_ESTATE;
+  }
+  double f[8];
+  int st = hfdib::body_forces(c, f);
+  if (st != HFDIB_OK) return st;
+  const double q = 0.5 * u_ref * u_ref * ref_area;
+  double cd = 0.0, cl = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    cd += (f[d] + f[3 + d]) * drag_dir[d];
+    cl += (f[d] + f[3 + d]) * lift_dir[d];
+  }
+  out2[0] = cd / q;
+  out2[1] = cl / q;
+  return HFDIB_OK;
+}
+
 int hfdib_forces_noalloc(hfdib_ctx* c, double* out8_dev) {
   if (!c || !out8_dev) return HFDIB_EINVAL;
   if (!c->ready) {

@@ -236,16 +236,14 @@ def case_uniform_duct(nx=64, ny=4, model="keps", U=1.0, L=1.0):
     return s.validate()
 
 
-def case_naca(gamma_deg=4.0, nx=256, ny=128, model="sst", intensity=0.03):
+def case_naca(gamma_deg=4.0, nx=256, ny=128, model="sst", intensity=0.001):
     """2D NACA 0012 section (chord 1, leading edge at the origin) pitched to the
     angle of attack gamma about the quarter chord, in x in [-2, 6],
     y in [-2, 2] (square cells: 256 x 128, 512 x 256 or 1024 x 512).
     Re = 1e6 on the chord (nu = 1e-6, U = 1 along +x), inlet turbulence
-    intensity I (default 3 %) with omega_in = 5 U / c; inlet at
+    intensity I (default 0.1 %) with omega_in = 5 U / c; inlet at
     x = -2, outlet at x = 6, slip far-field top and bottom.  Lift is along +y,
-    drag along +x.  (With I = 0.1 % every near-wall cell starts on the viscous
-    branch and the iteration diverges on the two finer grids; the paper takes
-    its inlet values from a reference that is not available here.)"""
+    drag along +x."""
     dx = 8.0 / nx
     dy = 4.0 / ny
     s = _spec(name=f"naca0012_a{gamma_deg:+.2f}_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1,

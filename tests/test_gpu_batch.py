@@ -63,6 +63,35 @@ def test_forces_match_oracle(gpu, name):
     assert abs(F["bc_area"] - G["bc_area"]) <= 1e-12 * max(F["bc_area"], 1e-300)
 
 
+def test_naca_sweep_forces_match_oracle_fixture(gpu):
+    # one instance of the batched sweep on each of its grids (256 x 128, 512 x 256,
+    # 1024 x 512) at its own inlet turbulence: drag, lift and the force components
+    # after 10 iterations against the stored oracle values
+    # (tests/golden/make_naca_forces.py)
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "naca_sweep_forces_it10.json")
+    with open(path) as fh:
+        fx = json.load(fh)
+    specs = synth.naca_sweep_specs(64)
+    for rec in fx["instances"]:
+        sp = specs[rec["index"]]
+        assert sp.lambda_sha256() == rec["lambda_sha256"]
+        s = _solver(sp, gpu, p_maxit=400)
+        s.iterate(fx["iterations"])
+        G = s.forces()
+        cd, cl = s.coefficients(ref_area=1.0)
+        scale = max(np.abs(rec["pressure"]).max(), np.abs(rec["viscous"]).max())
+        dev = max(np.abs(np.array(G["pressure"]) - rec["pressure"]).max(),
+                  np.abs(np.array(G["viscous"]) - rec["viscous"]).max()) / scale
+        _say(f"  {sp.name}: cd {cd:.6e} (oracle {rec['cd']:.6e}), cl {cl:.6e} (oracle {rec['cl']:.6e}), "
+             f"force deviation {dev:.1e}")
+        assert dev <= 1e-9, (sp.name, dev)
+        assert abs(cd - rec["cd"]) <= 1e-9 * max(abs(rec["cd"]), abs(rec["cl"]))
+        assert abs(cl - rec["cl"]) <= 1e-9 * max(abs(rec["cd"]), abs(rec["cl"]))
+        assert abs(G["area"] - rec["area"]) <= 1e-12 * rec["area"]
+
+
 @pytest.mark.parametrize("width", [32, 64, 128, 256])
 def test_tile_widths_keep_parity(gpu, width):
     # odd extents: partial tiles in x and y for every width
