@@ -460,6 +460,10 @@ def naca_sweep(args):
                      "max_residual": max(st["residuals"][j])})
     log(f"naca sweep: {iters} iterations of {len(specs)} instances in {dt:.2f}s")
     return {"workload": "naca0012_sweep_64", "instances": len(specs), "cells": cells, "iterations": iters,
+            "inlet_turbulence_intensity": specs[0].inlet_I,
+            "launch_design": "one HIP graph holding every instance (a branch per context), two SIMPLE iterations "
+                             "per graph launch with a fixed PCG iteration count, relaunched ceil(iterations / 2) "
+                             "times with no host synchronisation between launches; not a persistent kernel",
             "warmup_iterations_each": args.sweep_warmup, "pcg_iters": args.sweep_pcg, "seconds": round(dt, 3),
             "instance_iterations_per_s": round(len(specs) * iters / dt, 1),
             "instances_per_s": round(len(specs) / dt, 4), "cell_iters_per_s": cells * iters / dt,
