@@ -17,9 +17,10 @@ sigma equation), so
   boundary cell; its |grad lambda| V-weighted mean over the boundary cells
   times the interface area sum_cells |grad lambda| V gives F_v.
 
-Parity unpinned beyond the checks of tests/test_oracle_forces.py (the discrete
-Archimedes identity, closed bodies in uniform pressure, the shear of a
-grid-aligned channel, thin-airfoil lift on the GPU side).
+Pinned by tests/test_oracle_forces.py (the discrete Archimedes identity,
+closed bodies in uniform pressure, the shear of a grid-aligned channel).  The
+thin-airfoil lift 2 pi gamma is not a pin: the immersed NACA section's flow
+gives 0.3-0.8 of it at small angles (the flow, not the force sum, falls short).
 """
 
 import numpy as np
