@@ -47,6 +47,9 @@ CASES = {
     "naca_64x32_sst_linear_upwind": (lambda: _conv(synth.case_naca(4.0, 64, 32), "linear_upwind"), 30),
     "sphere3d_sst_1sweep": (lambda: _sweeps(synth.case_small_body3d(nx=37, ny=13, nz=11, model="sst", nu=1e-4), 1), 20),
     "bfs_keps_3sweeps": (lambda: _sweeps(synth.case_bfs(), 3), 30),
+    # a seeded random design field: cut cells of every lambda in (0, 1)
+    "bend2d_64x32_keps": (lambda: synth.case_bend2d(64, 32, seed=12356), 40),
+    "bend2d_96x48_keps": (lambda: synth.case_bend2d(96, 48), 30),
 }
 
 
