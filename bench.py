@@ -52,7 +52,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 #   pressure operator apply: x, rAU (+flags) in, y out: 25
 #   V-cycle half sweep (one colour): r and D^-1 of that colour (8), rAU (8),
 #     flags (1), z of the other colour in and of this colour out (8): 25
-#   V-cycle pre-smoothing pass from zero: r, D^-1, rAU (+flags) in, z out: 33
+#   V-cycle pre-smoothing pass from zero: r, D^-1, rAU (+flags) in, z and the
+#     colour-split copy of r out: 41
 #   restriction of the red rows' residuals: r of the red cells (4), z, rAU
 #     (+flags) in, the coarse residual (1/8 of a cell) out: 22
 #   apply with the direction update: z, d_old, rAU (+flags) in, d_new, q out: 41
@@ -60,7 +61,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # (reduction finalize launches and the coarse levels of the V-cycle are bound by
 # launch latency, not by bytes: they are timed but have no byte model)
 ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 97.0, "scalar_assemble": 80.0,
-              "p_apply": 25.0, "p_smooth": 25.0, "p_presmooth": 33.0, "p_restrict": 22.0, "p_apply_dir": 41.0,
+              "p_apply": 25.0, "p_smooth": 25.0, "p_presmooth": 41.0, "p_restrict": 22.0, "p_apply_dir": 41.0,
               "p_axpy": 48.0}
 KERNEL = {"scalar_sweep": "k_scalar_sweep", "mom_sweep": "k_mom_sweep", "mom_assemble": "k_mom_assemble",
           "scalar_assemble": "k_scalar_assemble", "p_apply": "k_fine_apply", "p_smooth": "k_fine_smooth",
@@ -69,7 +70,7 @@ KERNEL = {"scalar_sweep": "k_scalar_sweep", "mom_sweep": "k_mom_sweep", "mom_ass
 PRESSURE_CLASSES = ("p_apply", "p_smooth", "p_presmooth", "p_restrict", "p_apply_dir", "p_axpy")
 # the mixed policy's sweeps are one-colour launches of their own kernels; its
 # V-cycle moves FP32 arrays
-ALGO_BYTES_MIXED = dict(ALGO_BYTES, p_smooth=13.0, p_presmooth=17.0, p_restrict=12.0, p_apply_dir=37.0, p_axpy=52.0)
+ALGO_BYTES_MIXED = dict(ALGO_BYTES, p_smooth=13.0, p_presmooth=21.0, p_restrict=12.0, p_apply_dir=37.0, p_axpy=52.0)
 KERNEL_MIXED = dict(KERNEL, scalar_sweep="k_scalar_sweep32", mom_sweep="k_mom_sweep32")
 KERNEL_SOURCES = {"k_scalar_sweep": "turbulence.hip", "k_scalar_sweep32": "turbulence.hip",
                   "k_scalar_assemble": "turbulence.hip", "k_mom_sweep": "simple.hip",

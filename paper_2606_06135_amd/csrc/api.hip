@@ -186,7 +186,14 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->pd = B.take<double>(N);
   c->pd2 = B.take<double>(N);
   c->pq = B.take<double>(N);
-  c->invD = B.take<double>(N);
+  {
+    // the V-cycle's colour-split fine-level vectors (FP64 policy; FP32 below)
+    const long long ns = 2 * P.nrb > N ? 2 * P.nrb : N;
+    c->invD = B.take<double>(ns);
+    const bool fp64 = P.precision != HFDIB_MIXED;
+    c->pzs = fp64 ? B.take<double>(ns) : nullptr;
+    c->prs = fp64 ? B.take<double>(ns) : nullptr;
+  }
   c->flags = B.take<uint8_t>(N);
   c->phi[0] = B.take<double>((long long)(P.nx + 1) * P.ny * P.nz);
   c->phi[1] = B.take<double>((long long)P.nx * (P.ny + 1) * P.nz);
@@ -259,6 +266,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
   // FP32 arrays of the mixed policy
   for (int q = 0; q < 3; ++q) c->r32[q] = c->d32[q] = c->phi32[q] = nullptr;
   c->a32 = c->nut32 = c->rAU32 = c->pr32 = c->pz32 = c->invD32 = c->gam32 = nullptr;
+  c->pzs32 = c->prs32 = nullptr;
   if (mixed) {
     // FP32 defects and relaxed diagonals, colour-split like their FP64 counterparts
     const long long n32 = 2 * P.nrb > N ? 2 * P.nrb : N;
@@ -273,7 +281,9 @@ static size_t layout(hfdib_ctx* c, char* base) {
     c->rAU32 = B.take<float>(N);
     c->pr32 = B.take<float>(N);
     c->pz32 = B.take<float>(N);
-    c->invD32 = B.take<float>(N);
+    c->invD32 = B.take<float>(n32);
+    c->pzs32 = B.take<float>(n32);
+    c->prs32 = B.take<float>(n32);
   }
   return B.off + 256;
 }

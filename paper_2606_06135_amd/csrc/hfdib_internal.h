@@ -114,7 +114,8 @@ struct hfdib_ctx {
   int grad_ok;
   double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
   double* pd2;  // second PCG search-direction buffer (the direction update writes the other one)
-  double* invD;  // inverse diagonal of the fine pressure operator (FP64 policy)
+  double* invD;  // inverse diagonal of the fine pressure operator (FP64 policy), colour-split
+  double *pzs, *prs;  // colour-split z and r of the V-cycle's fine level (FP64 policy)
   uint8_t* flags;
   // --- face arrays
   double* phi[3];
@@ -124,6 +125,7 @@ struct hfdib_ctx {
   // inputs (rAU) and the preconditioner residual / output
   float *r32[3], *d32[3], *a32, *phi32[3], *nut32;
   float *rAU32, *pr32, *pz32, *invD32;
+  float *pzs32, *prs32;  // colour-split z and r of the V-cycle's fine level (mixed policy)
   float* gam32;  // FP32 diffusivity of the scalar being solved (mixed policy)
   // --- lists
   int cap;  // capacity of each list

@@ -84,6 +84,19 @@ __device__ __forceinline__ T fine_Ax(const T (&cf)[6], const Nbr& N, const T* x,
   return acc;
 }
 
+// Inside the V-cycle the fine-level vectors of the smoother (z, the residual r
+// and the inverse diagonal) are stored colour-split (rb_split: all cells of one
+// colour, then the other, each row's cells of a colour contiguous), so that a
+// one-colour half sweep reads and writes only the halves it needs; the
+// V-cycle's input r and output z are in the natural order.
+// Split index of the face neighbour q of cell (i, j, k) (the cell itself across
+// a domain face, like the clamped natural indices of Nbr).
+__device__ __forceinline__ long long nb_split(const Params& P, const Nbr& N, int i, int j, int k, int q) {
+  const int d = q >> 1, sg = (q & 1) ? 1 : -1;
+  const int o = is_bnd(N, q) ? 0 : sg;
+  return rb_split(P, i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
+}
+
 // y = A x (and partial sums of x.y)
 __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, double* part, long long pstride) {
   int i, j, k;
@@ -178,7 +191,7 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
 // correction; the inverse diagonal D^-1 of the fine operator (1 for uncoupled
 // rows) is computed once per pressure solve.
 //
-// Inverse diagonal (and, under the mixed policy, the FP32 mirror of rAU).
+// Inverse diagonal, colour-split (and, under the mixed policy, the FP32 mirror of rAU).
 template <typename T>
 __global__ void k_fine_invdiag(Params P, FineOp O, T* invD, float* rAU32) {
   int i, j, k;
@@ -191,22 +204,26 @@ __global__ void k_fine_invdiag(Params P, FineOp O, T* invD, float* rAU32) {
   double dg = 0.0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) dg += cf[q];
-  invD[c] = (T)(dg == 0.0 ? 1.0 : 1.0 / dg);
+  invD[rb_split(P, i, j, k)] = (T)(dg == 0.0 ? 1.0 : 1.0 / dg);  // colour-split
   if (rAU32) rAU32[c] = (float)O.rAU[c];
 }
 
 // Pre-smoothing sweep in one pass: the red value of a cell is r D^-1 (its
 // neighbours are 0 before the sweep), so each thread takes one red/black pair
 // of a row, writes the red value and the black value
-// (r + sum_f c_f r_nb D^-1_nb) D^-1 from recomputed red neighbour values.
+// (r + sum_f c_f r_nb D^-1_nb) D^-1 from recomputed red neighbour values.  It
+// reads r in the natural order and leaves z and r colour-split (zs, rs) for
+// the rest of the V-cycle.
 template <typename T>
-__global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* z) {
+__global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* zs, T* rs) {
   int i, j, k;
   tile_ijk_rb(P, 0, i, j, k);  // i: the red cell of the pair
   if (j >= P.ny) return;
   if (i < P.nx) {
-    long long c = cidx(P, i, j, k);
-    z[c] = r[c] * invD[c];
+    const long long c = cidx(P, i, j, k), sp = rb_split(P, i, j, k);
+    const T rc = r[c];
+    zs[sp] = rc * invD[sp];
+    rs[sp] = rc;
   }
   int ib = i ^ 1;  // the black cell of the pair
   if (ib >= P.nx) return;
@@ -218,23 +235,28 @@ __global__ void k_fine_presmooth(Params P, FineOpT<T> O, const T* invD, const T*
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     rn[q] = r[N.n[q]];
-    dn[q] = invD[N.n[q]];
+    dn[q] = invD[nb_split(P, N, ib, j, k, q)];
   }
   T nb = (T)0;
 #pragma unroll
   for (int q = 0; q < 6; ++q) nb = sel(is_bnd(N, q), nb, nb + cf[q] * (rn[q] * dn[q]));
-  z[c] = (r[c] + nb) * invD[c];
+  const long long sp = rb_split(P, ib, j, k);
+  const T rc = r[c];
+  zs[sp] = (rc + nb) * invD[sp];
+  rs[sp] = rc;
 }
 
 // One colour of a red-black half sweep (all neighbours are of the other
-// colour): z = (r + sum_f c_f z_nb) D^-1.  When zc is given (first sweep after
-// the coarse correction, black), the neighbour values are taken as
-// z_nb + zc(parent of nb): the prolongation is applied on the fly (the
-// prolonged values of this colour are overwritten, those of the other colour
-// are only read here and overwritten by the next sweep).
+// colour): z = (r + sum_f c_f z_nb) D^-1, on the colour-split z, r and D^-1.
+// When zc is given (first sweep after the coarse correction, black), the
+// neighbour values are taken as z_nb + zc(parent of nb): the prolongation is
+// applied on the fly (the prolonged values of this colour are overwritten,
+// those of the other colour are only read here and overwritten by the next
+// sweep).
 template <typename T>
 __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r, T* z, int color, const T* zc,
-                              int cnx, int cny, const double* rdot, double* part, long long pstride, double* dcopy) {
+                              int cnx, int cny, const double* rdot, double* part, long long pstride, double* dcopy,
+                              T* zout) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
   const bool own = i < P.nx && j < P.ny;
@@ -248,7 +270,7 @@ __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r,
     T nb = (T)0;
     T zn[6];
 #pragma unroll
-    for (int q = 0; q < 6; ++q) zn[q] = z[N.n[q]];
+    for (int q = 0; q < 6; ++q) zn[q] = z[nb_split(P, N, i, j, k, q)];
     if (zc) {
       const int i2 = i >> 1, j2 = j >> 1, k2 = P.dim == 3 ? k >> 1 : 0;
       T zp[6];
@@ -268,24 +290,28 @@ __global__ void k_fine_smooth(Params P, FineOpT<T> O, const T* invD, const T* r,
 #pragma unroll
       for (int q = 0; q < 6; ++q) nb = sel(is_bnd(N, q), nb, nb + cf[q] * zn[q]);
     }
-    znew = (r[c] + nb) * invD[c];
-    z[c] = znew;
+    const long long sp = rb_split(P, i, j, k);
+    znew = (r[sp] + nb) * invD[sp];
+    z[sp] = znew;
   }
-  // the last sweep of a V-cycle also forms the partial sums of r . z (FP64 r):
-  // its own cell, then the other cell of its pair, whose z is already final;
-  // optionally it copies both cells' z to the FP64 search direction (dcopy)
+  // the last sweep of a V-cycle writes z in the natural order (zout: both cells
+  // of its pair, the other one's z being already final) and forms the partial
+  // sums of r . z (FP64 r); optionally it copies both cells' z to the FP64
+  // search direction (dcopy)
   if (rdot) {
     double v[1] = {0.0};
     if (j < P.ny) {
       if (own) {
         v[0] = rdot[c] * (double)znew;
+        zout[c] = znew;
         if (dcopy) dcopy[c] = (double)znew;
       }
       const int io = i ^ 1;
       if (io < P.nx) {
         const long long co = cidx(P, io, j, k);
-        const T zo = z[co];
+        const T zo = z[rb_split(P, io, j, k)];
         v[0] += rdot[co] * (double)zo;
+        zout[co] = zo;
         if (dcopy) dcopy[co] = (double)zo;
       }
     }
@@ -516,6 +542,7 @@ __global__ void k_level_smooth(LevelDevT<T> L, int color, LevelDevT<T> C, int pr
 // the pre-smoothing sweep: black rows are satisfied exactly, and a red row's
 // residual is r - D r D^-1 + sum_f c_f z_nb = sum_f c_f z_nb (its neighbours
 // are black), so only the red children contribute, each by that sum.
+// (z colour-split)
 template <typename T>
 __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T> C) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -534,7 +561,7 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T>
         T cf[6], zn[6];
         fine_row(P, O, N, c, cf);
 #pragma unroll
-        for (int q = 0; q < 6; ++q) zn[q] = z[N.n[q]];
+        for (int q = 0; q < 6; ++q) zn[q] = z[nb_split(P, N, i, j, k, q)];
 #pragma unroll
         for (int q = 0; q < 6; ++q) s = sel(is_bnd(N, q), s, s + cf[q] * zn[q]);
       }
@@ -543,7 +570,8 @@ __global__ void k_restrict_fine(Params P, FineOpT<T> O, const T* z, LevelDevT<T>
 
 // Restriction after further pre-smoothing sweeps (the V-cycle's nu > 1): the
 // last half sweep was black, so black rows are satisfied and only the red
-// children contribute, each by its full residual r - A z.
+// children contribute, each by its full residual r - A z (r, z colour-split;
+// the operator and its order of terms as fine_Ax).
 template <typename T>
 __global__ void k_restrict_fine_res(Params P, FineOpT<T> O, const T* r, const T* z, LevelDevT<T> C) {
   int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -559,11 +587,22 @@ __global__ void k_restrict_fine_res(Params P, FineOpT<T> O, const T* r, const T*
         int i = 2 * I + a, j = 2 * J + b, k = C.dim == 3 ? 2 * K + e : 0;
         long long c = cidx(P, i, j, k);
         Nbr N = make_nbr(P, i, j, k, c);
-        T cf[6], dg, bs;
+        T cf[6];
         fine_row(P, O, N, c, cf);
-        T Az = fine_Ax(cf, N, z, c, dg, bs);
-        Az = sel(dg == (T)0, z[c], Az);  // uncoupled row: identity
-        s += r[c] - Az;
+        const long long sp = rb_split(P, i, j, k);
+        const T xc = z[sp];
+        T xn[6];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) xn[q] = z[nb_split(P, N, i, j, k, q)];
+        T Az = (T)0, dg = (T)0;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          const bool b = is_bnd(N, q);
+          Az = sel(b, Az + cf[q] * xc, Az + cf[q] * (xc - xn[q]));
+          dg += cf[q];
+        }
+        Az = sel(dg == (T)0, xc, Az);  // uncoupled row: identity
+        s += r[sp] - Az;
       }
   C.r[lidx(C, I, J, K)] = s;
 }
@@ -1034,23 +1073,44 @@ void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double d
             op, divisor, hmir, seq);
 }
 
-// the first pass of a V-cycle: fine-level pre-smoothing of z from zero (it
-// writes z alone)
+// the colour-split work vectors of the V-cycle's fine level (z and r) in
+// storage type T
 template <typename T>
-static void vcycle_presmooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z) {
-  const Params& P = c->P;
-  LaunchEv ev = timer_launch(c, T_PPRESMOOTH, true, true);
-  launch_ev(k_fine_presmooth<T>, grid3_rb(P), block3(P), c->stream, ev, P, O, invD, r, z);
+struct SplitBuf {
+  T* z;
+  T* r;
+};
+template <typename T>
+static SplitBuf<T> split_buf(hfdib_ctx* c);
+template <>
+SplitBuf<double> split_buf<double>(hfdib_ctx* c) {
+  return SplitBuf<double>{c->pzs, c->prs};
+}
+template <>
+SplitBuf<float> split_buf<float>(hfdib_ctx* c) {
+  return SplitBuf<float>{c->pzs32, c->prs32};
 }
 
-// one fine-level half sweep of the V-cycle (timed as its own class)
+// the first pass of a V-cycle: fine-level pre-smoothing of z from zero (it
+// writes only the colour-split z and r of the V-cycle)
 template <typename T>
-static void fine_smooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, T* z, int color, const T* zc,
-                        int cnx, int cny, const double* rdot, double* part, long long pstride, double* dcopy) {
+static void vcycle_presmooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r) {
   const Params& P = c->P;
+  const SplitBuf<T> S = split_buf<T>(c);
+  LaunchEv ev = timer_launch(c, T_PPRESMOOTH, true, true);
+  launch_ev(k_fine_presmooth<T>, grid3_rb(P), block3(P), c->stream, ev, P, O, invD, r, S.z, S.r);
+}
+
+// one fine-level half sweep of the V-cycle (timed as its own class), on the
+// colour-split vectors; with rdot (the last one) it also writes z to zout
+template <typename T>
+static void fine_smooth(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, int color, const T* zc, int cnx, int cny,
+                        const double* rdot, double* part, long long pstride, double* dcopy, T* zout) {
+  const Params& P = c->P;
+  const SplitBuf<T> S = split_buf<T>(c);
   LaunchEv ev = timer_launch(c, T_PSMOOTH, true, true);
-  launch_ev(k_fine_smooth<T>, grid3_rb(P), block3(P), c->stream, ev, P, O, invD, r, z, color, zc, cnx, cny, rdot,
-            part, pstride, dcopy);
+  launch_ev(k_fine_smooth<T>, grid3_rb(P), block3(P), c->stream, ev, P, O, invD, (const T*)S.r, S.z, color, zc, cnx,
+            cny, rdot, part, pstride, dcopy, zout);
 }
 
 // one V-cycle z = M^-1 r in storage type T; the last sweep also leaves the
@@ -1063,21 +1123,23 @@ static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, 
   const Params& P = c->P;
   const int nu = P.p_nu, nuc = P.p_nu_c;  // sweeps per side on the fine level and on the coarse levels
   dim3 g = grid3_rb(P), b = block_lv();
-  if (!presmoothed) vcycle_presmooth<T>(c, O, invD, r, z);
+  const SplitBuf<T> S = split_buf<T>(c);
+  if (!presmoothed) vcycle_presmooth<T>(c, O, invD, r);
   // further pre-smoothing sweeps (red, then black)
   for (int s = 1; s < nu; ++s)
     for (int color = 0; color < 2; ++color)
-      fine_smooth<T>(c, O, invD, r, z, color, (const T*)nullptr, 0, 0, (const double*)nullptr, (double*)nullptr, 0LL,
-                     (double*)nullptr);
+      fine_smooth<T>(c, O, invD, color, (const T*)nullptr, 0, 0, (const double*)nullptr, (double*)nullptr, 0LL,
+                     (double*)nullptr, (T*)nullptr);
   const T* zc = nullptr;
   int cnx = 0, cny = 0;
   if (c->nlev > 1) {
     LevelDevT<T> L1 = levdev<T>(c, 1);
     LaunchEv er = timer_launch(c, T_PRESTRICT, true, true);
     if (nu == 1)
-      launch_ev(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, c->stream, er, P, O, (const T*)z, L1);
+      launch_ev(k_restrict_fine<T>, lgrid(L1.nx, L1.ny, L1.nz), b, c->stream, er, P, O, (const T*)S.z, L1);
     else
-      launch_ev(k_restrict_fine_res<T>, lgrid(L1.nx, L1.ny, L1.nz), b, c->stream, er, P, O, r, (const T*)z, L1);
+      launch_ev(k_restrict_fine_res<T>, lgrid(L1.nx, L1.ny, L1.nz), b, c->stream, er, P, O, (const T*)S.r,
+                (const T*)S.z, L1);
     // the coarse levels are timed as one span: opened by their first launch,
     // closed by the last
     bool opened = false;
@@ -1145,10 +1207,11 @@ static int vcycle(hfdib_ctx* c, const FineOpT<T>& O, const T* invD, const T* r, 
   // the fly), then red; the last red half sweep also forms the r . z partials
   for (int s = 0; s < nu; ++s) {
     const bool last = s == nu - 1;
-    fine_smooth<T>(c, O, invD, r, z, 1, s == 0 ? zc : (const T*)nullptr, cnx, cny, (const double*)nullptr,
-                   (double*)nullptr, 0LL, (double*)nullptr);
-    fine_smooth<T>(c, O, invD, r, z, 0, (const T*)nullptr, 0, 0, last ? rdot : (const double*)nullptr,
-                   last ? c->partials : (double*)nullptr, last ? c->pstride : 0LL, last ? dcopy : (double*)nullptr);
+    fine_smooth<T>(c, O, invD, 1, s == 0 ? zc : (const T*)nullptr, cnx, cny, (const double*)nullptr,
+                   (double*)nullptr, 0LL, (double*)nullptr, (T*)nullptr);
+    fine_smooth<T>(c, O, invD, 0, (const T*)nullptr, 0, 0, last ? rdot : (const double*)nullptr,
+                   last ? c->partials : (double*)nullptr, last ? c->pstride : 0LL, last ? dcopy : (double*)nullptr,
+                   z);
   }
   return (int)g.x;
 }
@@ -1271,7 +1334,7 @@ static void pcg_begin_t(hfdib_ctx* c, const double* rAU, const double* rhs, doub
 template <typename T>
 static void pcg_ahead_t(hfdib_ctx* c, const double* rAU) {
   PcgSet<T> A = pcg_set<T>(c, rAU);
-  vcycle_presmooth<T>(c, A.OM, A.invD, A.r_m, A.z_m);
+  vcycle_presmooth<T>(c, A.OM, A.invD, A.r_m);
 }
 template <typename T>
 static void pcg_continue_t(hfdib_ctx* c, const double* rAU, double* x, bool presmoothed) {

@@ -30,10 +30,10 @@ def test_byte_models_are_the_per_pass_figures():
     assert bench.ALGO_BYTES["p_apply"] == 25
     # the fine-level pressure passes of one CG iteration with two sweeps per side
     # (pre-smoothing pass, one more red-black sweep, restriction, four post half
-    # sweeps, apply with direction update, vector update): 294 B/cell
+    # sweeps, apply with direction update, vector update): 302 B/cell
     b = bench.ALGO_BYTES
     assert b["p_presmooth"] + 2 * b["p_smooth"] + b["p_restrict"] + 4 * b["p_smooth"] + b["p_apply_dir"] + \
-        b["p_axpy"] == 294
+        b["p_axpy"] == 302
     for cls in bench.ALGO_BYTES:
         assert bench.KERNEL[cls].startswith("k_") and bench.KERNEL[cls] in bench.KERNEL_SOURCES
         assert bench.KERNEL_MIXED[cls] in bench.KERNEL_SOURCES
