@@ -193,6 +193,9 @@ static size_t layout(hfdib_ctx* c, char* base) {
     const bool fp64 = P.precision != HFDIB_MIXED;
     c->pzs = fp64 ? B.take<double>(ns) : nullptr;
     c->prs = fp64 ? B.take<double>(ns) : nullptr;
+    // the sweeps' colour-split copies of the state (FP64 policy)
+    for (int q = 0; q < 3; ++q) c->usp[q] = fp64 ? B.take<double>(ns) : nullptr;
+    c->xsp = fp64 ? B.take<double>(ns) : nullptr;
   }
   c->flags = B.take<uint8_t>(N);
   c->phi[0] = B.take<double>((long long)(P.nx + 1) * P.ny * P.nz);

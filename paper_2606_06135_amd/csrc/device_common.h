@@ -206,6 +206,14 @@ __device__ __forceinline__ Nbr make_nbr(const Params& P, int i, int j, int k, lo
   return N;
 }
 __device__ __forceinline__ bool is_bnd(const Nbr& N, int q) { return (N.bnd >> q) & 1u; }
+// index in a colour-split array (rb_split) of the face neighbour q of cell
+// (i, j, k): the cell itself across a domain face, like the clamped natural
+// indices of Nbr
+__device__ __forceinline__ long long nb_split(const Params& P, const Nbr& N, int i, int j, int k, int q) {
+  const int d = q >> 1, sg = (q & 1) ? 1 : -1;
+  const int o = is_bnd(N, q) ? 0 : sg;
+  return rb_split(P, i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
+}
 
 // d u_jc / d x_a at cell x (Gauss, linear face interpolation) from clamped
 // loads; lo / hi: x lies on the low / high domain face along a; solid: lambda > 0

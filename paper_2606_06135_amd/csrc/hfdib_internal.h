@@ -116,6 +116,8 @@ struct hfdib_ctx {
   double* pd2;  // second PCG search-direction buffer (the direction update writes the other one)
   double* invD;  // inverse diagonal of the fine pressure operator (FP64 policy), colour-split
   double *pzs, *prs;  // colour-split z and r of the V-cycle's fine level (FP64 policy)
+  double* usp[3];     // colour-split copy of u for the momentum sweeps (FP64 policy)
+  double* xsp;        // colour-split copy of k or eps/omega for the scalar sweeps (FP64 policy)
   uint8_t* flags;
   // --- face arrays
   double* phi[3];

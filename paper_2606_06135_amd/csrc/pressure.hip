@@ -88,14 +88,8 @@ __device__ __forceinline__ T fine_Ax(const T (&cf)[6], const Nbr& N, const T* x,
 // and the inverse diagonal) are stored colour-split (rb_split: all cells of one
 // colour, then the other, each row's cells of a colour contiguous), so that a
 // one-colour half sweep reads and writes only the halves it needs; the
-// V-cycle's input r and output z are in the natural order.
-// Split index of the face neighbour q of cell (i, j, k) (the cell itself across
-// a domain face, like the clamped natural indices of Nbr).
-__device__ __forceinline__ long long nb_split(const Params& P, const Nbr& N, int i, int j, int k, int q) {
-  const int d = q >> 1, sg = (q & 1) ? 1 : -1;
-  const int o = is_bnd(N, q) ? 0 : sg;
-  return rb_split(P, i + (d == 0 ? o : 0), j + (d == 1 ? o : 0), k + (d == 2 ? o : 0));
-}
+// V-cycle's input r and output z are in the natural order (nb_split gives the
+// split index of a face neighbour).
 
 // y = A x (and partial sums of x.y)
 __global__ void k_fine_apply(Params P, FineOp O, const double* x, double* y, double* part, long long pstride) {

@@ -24,6 +24,7 @@ struct Mom {
 struct MixOut {
   float* r[3];
   float* a;
+  double* us[3];  // FP64 policy: the colour-split copy of u the sweeps work on (else null)
 };
 
 // FP32 coefficient mirrors read by the FP32 sweeps
@@ -431,27 +432,49 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
 #pragma unroll
       for (int cc = 0; cc < DIM; ++cc) X.r[cc][sidx] = (float)(rh[cc] - Ax[cc]);
     }
+    if (X.us[0]) {
+#pragma unroll
+      for (int cc = 0; cc < DIM; ++cc) X.us[cc][sidx] = uc[cc];
+    }
   }
   block_sums_store<9>(red, part, pstride, block_linear());
 }
 
-// one colour of a red-black Gauss-Seidel sweep over the three components
+// one colour of a red-black Gauss-Seidel sweep over the three components, on
+// the colour-split copy s of u that the assembly wrote (a one-colour pass reads
+// only the other colour's half and writes only its own).  fin: the last half
+// sweep (black), which also writes u in the natural order for both cells of its
+// pair (the red partner is a face neighbour, its final value already loaded).
 __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
-                            const double* aPr, double* u0, double* u1, double* u2, int color) {
+                            const double* aPr, double* s0, double* s1, double* s2, double* u0, double* u1, double* u2,
+                            int color, int fin) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
+  if (j >= P.ny) return;
+  double* uo[3] = {u0, u1, u2};
+  if (i >= P.nx) {
+    // only the partner of this pair lies in the grid (odd nx)
+    const int io = i ^ 1;
+    if (fin && io < P.nx) {
+      const long long co = cidx(P, io, j, k), so = rb_split(P, io, j, k);
+      const double* sv[3] = {s0, s1, s2};
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        if (cc < P.dim) uo[cc][co] = sv[cc][so];
+    }
+    return;
+  }
   long long c = cidx(P, i, j, k);
   Nbr N = make_nbr(P, i, j, k, c);
   const long long sidx = rb_split(P, i, j, k);
   // every load of the three rows before the first store (the stores could
   // alias later loads otherwise, which would serialise the components)
   double un[3][6];
-  const double* u[3] = {u0, u1, u2};
+  double* s[3] = {s0, s1, s2};
 #pragma unroll
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
-    for (int q = 0; q < 6; ++q) un[cc][q] = u[cc][N.n[q]];
+    for (int q = 0; q < 6; ++q) un[cc][q] = s[cc][nb_split(P, N, i, j, k, q)];
   const double b0 = rhs0[sidx], b1 = rhs1[sidx], b2 = rhs2[sidx], a = aPr[sidx];
   double anb[6];
   mom_anb(P, M, P.nu + M.nut[c], N, i, j, k, anb);
@@ -460,9 +483,22 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
   for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
     for (int q = 0; q < 6; ++q) nb[cc] += anb[q] * un[cc][q];
-  u0[c] = (b0 + nb[0]) / a;
-  u1[c] = (b1 + nb[1]) / a;
-  if (P.dim == 3) u2[c] = (b2 + nb[2]) / a;
+  const double v[3] = {(b0 + nb[0]) / a, (b1 + nb[1]) / a, (b2 + nb[2]) / a};
+#pragma unroll
+  for (int cc = 0; cc < 3; ++cc)
+    if (cc < P.dim) s[cc][sidx] = v[cc];
+  if (fin) {
+    // the partner (i ^ 1) is the west (i odd) or east (i even) neighbour
+    const int io = i ^ 1;
+    const bool partner = io < P.nx, west = i & 1;
+    const long long co = cidx(P, io < P.nx ? io : i, j, k);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      if (cc >= P.dim) continue;
+      uo[cc][c] = v[cc];
+      if (partner) uo[cc][co] = sel(west, un[cc][0], un[cc][1]);
+    }
+  }
 }
 
 // Mixed policy: one colour of a red-black Gauss-Seidel sweep of the FP32
@@ -979,8 +1015,8 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   }
   Mom M = make_mom(c);
   bool mixed = P.precision == HFDIB_MIXED;
-  MixOut X{{nullptr, nullptr, nullptr}, nullptr};
-  if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32};
+  MixOut X{{nullptr, nullptr, nullptr}, nullptr, {c->usp[0], c->usp[1], c->usp[2]}};
+  if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32, {nullptr, nullptr, nullptr}};
   ev = timer_launch(c, T_MOMASM, true, true);
   const Params PA = deep_tile_params(P);
   const dim3 ga = grid3(PA);
@@ -998,8 +1034,8 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                   c->d32[0], c->d32[1], c->d32[2], c->u[0], c->u[1], c->u[2], color, first ? 1 : 0,
                   s == P.n_sweeps - 1 ? 1 : 0);
       else
-        launch_ev(k_mom_sweep, grid3_rb(P), b, c->stream, ev, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr, c->u[0],
-                  c->u[1], c->u[2], color);
+        launch_ev(k_mom_sweep, grid3_rb(P), b, c->stream, ev, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
+                  c->usp[0], c->usp[1], c->usp[2], c->u[0], c->u[1], c->u[2], color, last ? 1 : 0);
     }
   // 3. u <- u + alpha_u (u_ib - u)
   if (c->n_bc + c->n_ic > 0)

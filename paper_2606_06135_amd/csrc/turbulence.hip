@@ -262,7 +262,7 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
 template <bool RKE>
 __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, float* r32, float* a32,
                                   double* gam_out, float* gam_out32, const double* xmean, double* part,
-                                  long long pstride) {
+                                  long long pstride, double* xs_out) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   double red[3] = {0, 0, 0};
@@ -365,6 +365,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     const long long sidx = rb_split(P, i, j, k);
     rhs_out[sidx] = rhs;
     aPr_out[sidx] = aPr;
+    if (xs_out) xs_out[sidx] = x;  // FP64 policy: the colour-split copy the sweeps work on
     // rows the sweeps update: all k rows; omega/eps rows outside alpha_omega
     bool swept = eq == 1 || !(fl & F_ALPHA_W);
     if (!skip || (a32 && swept)) {
@@ -398,11 +399,21 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 // (FP64) the diffusivity of each cell comes from the array the assembly wrote
 // (the same value gam() gives), rhs and a'_P from the colour-split arrays, so a
 // one-colour launch streams only its own half of them
-__global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const double* rhs, const double* aPr, double* x,
-                               int color, uint8_t fixmask) {
+// The sweeps work on the colour-split copy xs of x that the assembly wrote (a
+// one-colour pass reads only the other colour's half and writes only its
+// own); fin: the last half sweep (black), which also writes x in the natural
+// order for both cells of its pair (the red partner is a face neighbour).
+__global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const double* rhs, const double* aPr, double* xs,
+                               double* x, int color, uint8_t fixmask, int fin) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
+  if (j >= P.ny) return;
+  if (i >= P.nx) {
+    // only the partner of this pair lies in the grid (odd nx)
+    const int io = i ^ 1;
+    if (fin && io < P.nx) x[cidx(P, io, j, k)] = xs[rb_split(P, io, j, k)];
+    return;
+  }
   long long c = cidx(P, i, j, k);
   const Nbr N = make_nbr(P, i, j, k, c);
   const long long sidx = rb_split(P, i, j, k);
@@ -414,7 +425,7 @@ __global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const doubl
 #pragma unroll
   for (int q = 0; q < 6; ++q) {
     gn[q] = gamc[N.n[q]];
-    xn[q] = x[N.n[q]];
+    xn[q] = xs[nb_split(P, N, i, j, k, q)];
     fo[q] = outward_flux(P, S.phi, q >> 1, (q & 1) ? 1 : -1, i, j, k);
   }
   double nb = 0.0;
@@ -426,7 +437,15 @@ __global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const doubl
     a = sel(d < P.dim && !is_bnd(N, q), a, 0.0);
     nb += a * xn[q];
   }
-  if (!(fl & fixmask)) x[c] = (b + nb) / ap;
+  const bool upd = !(fl & fixmask);
+  const double v = (b + nb) / ap;
+  if (upd) xs[sidx] = v;
+  if (fin) {
+    // the partner (i ^ 1) is the west (i odd) or east (i even) neighbour
+    const int io = i ^ 1;
+    if (upd) x[c] = v;
+    if (io < P.nx) x[cidx(P, io, j, k)] = sel((i & 1) != 0, xn[0], xn[1]);
+  }
 }
 
 // Mixed policy: red-black sweep of the FP32 correction d of a scalar equation
@@ -655,14 +674,15 @@ int turbulence_stage(hfdib_ctx* c) {
           launch_ev(k_scalar_sweep32, grid3_rb(P), b, c->stream, ev, P, S32, c->flags, c->gam32, r32, a32, c->d32[0], x,
                     color, fixmask, first ? 1 : 0, s == P.n_sweeps - 1 ? 1 : 0);
         else
-          launch_ev(k_scalar_sweep, grid3_rb(P), b, c->stream, ev, P, Sc, gam_c, c->t0, c->t1, x, color, fixmask);
+          launch_ev(k_scalar_sweep, grid3_rb(P), b, c->stream, ev, P, Sc, gam_c, c->t0, c->t1, c->xsp, x, color,
+                    fixmask, last ? 1 : 0);
       }
   };
   // omega / eps equation, alpha_omega rows fixed
   auto assemble = P.model == HFDIB_RKEPS ? k_scalar_assemble<true> : k_scalar_assemble<false>;
   LaunchEv ev = timer_launch(c, T_SCALASM, true, true);
   launch_ev(assemble, g, b, c->stream, ev, P, Sc, 0, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
-            mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride);
+            mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride, c->xsp);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
   sweeps(0, c->w, (uint8_t)F_ALPHA_W);
   // k_ib, then the k equation with S_ib (bounds omega/eps on the way)
@@ -672,7 +692,7 @@ int turbulence_stage(hfdib_ctx* c) {
                        c->kib);
   ev = timer_launch(c, T_SCALASM, true, true);
   launch_ev(assemble, g, b, c->stream, ev, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
-            mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride);
+            mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride, c->xsp);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
   hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, Gs, c->kib, c->k, c->w,
