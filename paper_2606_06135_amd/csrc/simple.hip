@@ -432,7 +432,9 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
 #pragma unroll
       for (int cc = 0; cc < DIM; ++cc) X.r[cc][sidx] = (float)(rh[cc] - Ax[cc]);
     }
-    if (X.us[0]) {
+    if (X.us[0] && ((i + j + k) & 1)) {
+      // (only the black half: the first half sweep, red, reads the black
+      // neighbours and writes the red half itself)
 #pragma unroll
       for (int cc = 0; cc < DIM; ++cc) X.us[cc][sidx] = uc[cc];
     }
@@ -443,8 +445,9 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
 // one colour of a red-black Gauss-Seidel sweep over the three components, on
 // the colour-split copy s of u that the assembly wrote (a one-colour pass reads
 // only the other colour's half and writes only its own).  fin: the last half
-// sweep (black), which also writes u in the natural order for both cells of its
-// pair (the red partner is a face neighbour, its final value already loaded).
+// sweep (black), which writes u in the natural order instead, for both cells of
+// its pair (the red partner is a face neighbour, its final value already
+// loaded); the split copy is dead after it.
 __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
                             const double* aPr, double* s0, double* s1, double* s2, double* u0, double* u1, double* u2,
                             int color, int fin) {
@@ -484,10 +487,11 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
 #pragma unroll
     for (int q = 0; q < 6; ++q) nb[cc] += anb[q] * un[cc][q];
   const double v[3] = {(b0 + nb[0]) / a, (b1 + nb[1]) / a, (b2 + nb[2]) / a};
+  if (!fin) {
 #pragma unroll
-  for (int cc = 0; cc < 3; ++cc)
-    if (cc < P.dim) s[cc][sidx] = v[cc];
-  if (fin) {
+    for (int cc = 0; cc < 3; ++cc)
+      if (cc < P.dim) s[cc][sidx] = v[cc];
+  } else {
     // the partner (i ^ 1) is the west (i odd) or east (i even) neighbour
     const int io = i ^ 1;
     const bool partner = io < P.nx, west = i & 1;

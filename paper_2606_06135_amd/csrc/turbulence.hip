@@ -365,7 +365,10 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     const long long sidx = rb_split(P, i, j, k);
     rhs_out[sidx] = rhs;
     aPr_out[sidx] = aPr;
-    if (xs_out) xs_out[sidx] = x;  // FP64 policy: the colour-split copy the sweeps work on
+    // FP64 policy: the colour-split copy the sweeps work on (the black half, and
+    // the fixed rows, which no sweep writes: the first half sweep, red, reads the
+    // black neighbours and writes the other red cells itself)
+    if (xs_out && (((i + j + k) & 1) || (eq == 0 && (fl & F_ALPHA_W)))) xs_out[sidx] = x;
     // rows the sweeps update: all k rows; omega/eps rows outside alpha_omega
     bool swept = eq == 1 || !(fl & F_ALPHA_W);
     if (!skip || (a32 && swept)) {
@@ -401,8 +404,9 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 // one-colour launch streams only its own half of them
 // The sweeps work on the colour-split copy xs of x that the assembly wrote (a
 // one-colour pass reads only the other colour's half and writes only its
-// own); fin: the last half sweep (black), which also writes x in the natural
-// order for both cells of its pair (the red partner is a face neighbour).
+// own); fin: the last half sweep (black), which writes x in the natural order
+// instead, for both cells of its pair (the red partner is a face neighbour);
+// the split copy is dead after it.
 __global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const double* rhs, const double* aPr, double* xs,
                                double* x, int color, uint8_t fixmask, int fin) {
   int i, j, k;
@@ -439,7 +443,7 @@ __global__ void k_scalar_sweep(Params P, Scal S, const double* gamc, const doubl
   }
   const bool upd = !(fl & fixmask);
   const double v = (b + nb) / ap;
-  if (upd) xs[sidx] = v;
+  if (upd && !fin) xs[sidx] = v;
   if (fin) {
     // the partner (i ^ 1) is the west (i odd) or east (i even) neighbour
     const int io = i ^ 1;
