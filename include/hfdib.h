@@ -304,8 +304,8 @@ int hfdib_forces_noalloc(hfdib_ctx* ctx, double* out8_dev);
 
 /* Tile shape of the full-grid kernels: 256-thread tiles of width 32, 64 (the
  * default), 128 or 256 cells along x.  hfdib_autotune_tiles times, for each
- * width, reps rounds of the gradient pass, the momentum assembly and the
- * pressure operator on the current state (none of them changes the state),
+ * width, reps rounds of the momentum assembly and the pressure operator on
+ * the current state (neither changes the state),
  * keeps the fastest width and returns it in *best_width (nullable) with the
  * average milliseconds per round of widths 32, 64, 128, 256 in ms4 (host,
  * nullable).  The width changes only the order of partial sums in reductions.

@@ -177,8 +177,8 @@ static size_t layout(hfdib_ctx* c, char* base) {
   c->t1 = B.take<double>(nsplit);
   c->t2 = B.take<double>(N);
   c->wallD = B.take<double>(N);
-  for (int q = 0; q < 9; ++q) c->G[q] = B.take<double>(N);
   c->S2 = B.take<double>(N);
+  for (int q = 0; q < 3; ++q) c->ex[q] = B.take<double>(N);
   c->rhs_p = B.take<double>(N);
   c->px = B.take<double>(N);
   c->pr = B.take<double>(N);
@@ -631,6 +631,13 @@ int hfdib_init_grid(const hfdib_grid_desc* d, const hfdib_config* c, void* works
   layout(ctx, ctx->ws);
   ctx->stream = (hipStream_t)hip_stream;
   ctx->ready = 0;
+  {
+    int dev = 0, n = 0;
+    ctx->ncu = (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0)
+                   ? n
+                   : 256;
+  }
   ctx->timers = new (std::nothrow) Timers();
   memset(ctx->stats, 0, sizeof(ctx->stats));
   *out = ctx;
@@ -658,8 +665,7 @@ int hfdib_set_indicator(hfdib_ctx* c, const double* lambda_dev, const double* so
   int st = geometry_precompute(c);
   if (st != HFDIB_OK) return st;
   if (keep) {
-    // the state stays; the velocity gradient and the FP32 mirrors are refreshed
-    c->grad_ok = 0;
+    // the state stays; the FP32 mirrors are refreshed
     st = refresh_mirrors(c);
   } else {
     st = init_state(c);
@@ -781,7 +787,6 @@ int hfdib_set_field(hfdib_ctx* c, int id, const double* src) {
   double* dst = field_ptr(c, id, &n);
   if (!dst) return HFDIB_EINVAL;
   HFDIB_CHECK(c, hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "set_field");
-  c->grad_ok = 0;
   return hfdib::refresh_mirrors(c);
 }
 

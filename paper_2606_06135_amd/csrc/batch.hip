@@ -106,14 +106,9 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
       delete b;
       return HFDIB_EDEVICE;
     }
-  // eager set-up outside the capture: the gradient of the current state, the
-  // convergence records, everything finished before capturing
+  // eager set-up outside the capture: the convergence records, everything
+  // finished before capturing
   for (hfdib_ctx* c : b->ctx) {
-    if (!c->grad_ok && velocity_gradient(c) != HFDIB_OK) {
-      b->err = c->err;
-      hfdib_batch_destroy(b);
-      return HFDIB_EDEVICE;
-    }
     hipLaunchKernelGGL(k_conv_reset, dim3(1), dim3(64), 0, c->stream, c->scal + SCAL_PCG);
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) {
       int st = batch_fail(b, "batch set-up", e);
@@ -185,13 +180,8 @@ int hfdib_batch_create(hfdib_ctx* const* ctxs, int n, int pcg_iters, double tol,
 int hfdib_batch_run(hfdib_batch* b, int iters) {
   if (!b || iters < 0) return HFDIB_EINVAL;
   hipError_t e;
-  // work queued on the contexts' own streams must finish first; a state changed
-  // from outside (set_field) needs its gradient again
+  // work queued on the contexts' own streams must finish first
   for (hfdib_ctx* c : b->ctx) {
-    if (!c->grad_ok && velocity_gradient(c) != HFDIB_OK) {
-      b->err = c->err;
-      return HFDIB_EDEVICE;
-    }
     if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return batch_fail(b, "batch run", e);
   }
   for (int l = 0; l < (iters + 1) / 2; ++l)

@@ -227,6 +227,22 @@ __device__ __forceinline__ double gradu_bf(const Params& P, const double* uj, in
   double fm = sel(lo, u_bface(P, jc, a, -1, solid, uP), 0.5 * (um + uP));
   return (fp - fm) * P.idelta[a];
 }
+// d u_jc / d x_b at the (clamped) face neighbour q of cell (i, j, k), the value
+// the cell gradient above takes at that cell: across the axis of q the
+// neighbour has the cell's domain faces, along it its own position decides;
+// sn: the neighbour has lambda > 0.  (Across a domain face the neighbour index
+// is the cell itself and the value is to be discarded.)
+__device__ __forceinline__ double gradu_nb(const Params& P, const double* uj, int jc, int b, const Nbr& N, int q, int i,
+                                           int j, int k, bool sn) {
+  const int a = q >> 1;
+  bool lo = is_bnd(N, 2 * b), hi = is_bnd(N, 2 * b + 1);
+  if (a == b) {
+    const int x = comp(a, i, j, k) + (is_bnd(N, q) ? 0 : ((q & 1) ? 1 : -1));
+    lo = x == 0;
+    hi = x == ncell(P, a) - 1;
+  }
+  return gradu_bf(P, uj, jc, b, N.n[q], lo, hi, sn);
+}
 // full velocity gradient G[a][jc] = d u_jc / d x_a at a cell (zero outside dim)
 __device__ __forceinline__ void gradu_all_bf(const Params& P, const double* const* u, bool solid, const Nbr& N,
                                              long long c, double (&G)[3][3]) {

@@ -99,6 +99,7 @@ struct hfdib_ctx {
   char* ws;
   size_t ws_bytes;
   int ready;  // set_indicator done
+  int ncu;    // compute units of the device (launch shapes)
   std::string err;
 
   // --- cell arrays (N)
@@ -107,11 +108,12 @@ struct hfdib_ctx {
   double *uib[3], *kib, *wib, *Pk, *us[3];
   double *t0, *t1, *t2;  // scratch (turbulence rhs / diagonal)
   double* wallD;  // immersed-wall coupling of boundary cells on the logarithmic branch
-  // velocity gradient of the current u: G[3 a + jc] = d u_jc / d x_a, and 2 S:S
-  // (computed once per iteration after the velocity update; grad_ok = 0 when
-  // u changed otherwise)
-  double *G[9], *S2;
-  int grad_ok;
+  // 2 S:S of the current velocity (written by the first turbulence pass of an
+  // iteration, read by the production terms)
+  double* S2;
+  // explicit momentum terms of the previous iterate (transpose viscous term and
+  // deferred convection correction), written before each assembly
+  double* ex[3];
   double *rhs_p, *px, *pr, *pz, *pd, *pq, *pnew;
   double* pd2;  // second PCG search-direction buffer (the direction update writes the other one)
   double* invD;  // inverse diagonal of the fine pressure operator (FP64 policy), colour-split
@@ -269,7 +271,6 @@ int refresh_mirrors(hfdib_ctx* c);
 void launch_finalize(hfdib_ctx* c, int nblk, int nval, int out, int op, double divisor = 1.0, int row0 = 0,
                      double* hmir = nullptr, double seq = 0.0);
 int turbulence_stage(hfdib_ctx* c);
-int velocity_gradient(hfdib_ctx* c);
 int body_forces(hfdib_ctx* c, double* out8);
 int body_forces_noalloc(hfdib_ctx* c, double* out8_dev);
 int tile_bench_round(hfdib_ctx* c);

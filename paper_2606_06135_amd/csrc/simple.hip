@@ -13,9 +13,9 @@ struct Mom {
   const double* k;  // (wall functions of no-slip domain faces)
   const uint8_t* flags;
   const double* uib[3];
-  const double* G[9];  // stored velocity gradient of u (G[3 a + jc] = d u_jc / d x_a)
   const double* us[3];   // solid velocity
   const double* wallD;   // immersed-wall coupling of boundary cells on the logarithmic branch (k_ib_pre)
+  const double* ex[3];   // explicit terms of the previous iterate (k_mom_explicit)
 };
 
 // FP32 outputs of the momentum assembly under the mixed policy (all null under
@@ -246,18 +246,332 @@ __device__ __forceinline__ void mom_anb(const Params& P, const Mom& M, double nu
     }
 }
 
-// Assembly of the relaxed momentum rows with the explicit IB source
-// (discrete f_ib = alpha [M(u~) + grad p]), plus the normalised-residual sums
-// of the rows that are solved (alpha_u = 0).
-// CONV: momentum convection 0 upwind, 1 linear upwind, 2 van Leer; the
-// higher-order schemes enter as a deferred correction of the upwind rows,
-// -sum_f F_out (u_f - u_C) from the previous iterate, with C the upwind cell of
-// the face, D the downwind one, and the face value
+// Explicit terms of the momentum rows that depend on the previous iterate
+// alone, one pass before the assembly: the transpose part of the viscous term,
+// div(nuEff (grad u)^T) with face value nuEff_f (d u_d / d x_cc)_f, the face
+// gradient being the mean of the two cell gradients; and under the
+// higher-order convection schemes (CONV: 0 upwind, 1 linear upwind, 2 van Leer)
+// their deferred correction of the upwind rows, -sum_f F_out (u_f - u_C), with C
+// the upwind cell of the face, D the downwind one, and the face value
 //   linear upwind  u_f = u_C + (x_f - x_C) . grad u_C
 //   van Leer       u_f = u_C + psi(r) (u_D - u_C) / 2, psi(r) = (r + |r|) / (1 + |r|),
 //                  r = 2 (x_D - x_C) . grad u_C / (u_D - u_C) - 1 (0 where u_D = u_C)
-// (interior faces; grad u_C the stored Gauss gradient)
+// (interior faces).  The cell gradients (Gauss, linear face interpolation, at
+// the cell and at its face neighbours) are taken from u here, not stored: the
+// extra u values (edge and second neighbours) come from cache lines the stencil
+// already holds.  Out: ex[cc] = the sum of both terms of component cc.
 template <int CONV, int DIM>
+__global__ void __launch_bounds__(256)
+k_mom_explicit(Params P, Mom M, double* ex0, double* ex1, double* ex2) {
+  int i, j, k;
+  tile_ijk(P, i, j, k);
+  if (i >= P.nx || j >= P.ny) return;
+  const long long c = cidx(P, i, j, k);
+  const Nbr N = make_nbr(P, i, j, k, c);
+  const bool solid = M.flags[c] & F_SOLID;
+  const double nuP = P.nu + M.nut[c];
+  double nuN[6], fo[6];
+  bool sn[6];  // neighbours with lambda > 0 (domain-face values of their gradients)
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    nuN[q] = P.nu + M.nut[N.n[q]];
+    fo[q] = CONV != 0 ? outward_flux(P, M.phi, q >> 1, (q & 1) ? 1 : -1, i, j, k) : 0.0;
+    sn[q] = M.flags[N.n[q]] & F_SOLID;
+  }
+  double ex[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int cc = 0; cc < DIM; ++cc) {
+    double T = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      // d u_d / d x_cc at the cell and at its two neighbours along d
+      const double GP = gradu_bf(P, M.u[d], d, cc, c, is_bnd(N, 2 * cc), is_bnd(N, 2 * cc + 1), solid);
+#pragma unroll
+      for (int sh = 0; sh < 2; ++sh) {
+        const int s = sh ? 1 : -1, q = 2 * d + sh;
+        const bool fb = is_bnd(N, q);
+        const double GN = gradu_nb(P, M.u[d], d, cc, N, q, i, j, k, sn[q]);
+        const double nuf = sel(fb, nuP, 0.5 * (nuP + nuN[q]));
+        const double gf = sel(fb, GP, 0.5 * (GP + GN));
+        T += (double)s * P.area[d] * nuf * gf;
+      }
+    }
+    if (CONV != 0) {
+      const double uP = M.u[cc][c];
+      double Cc = 0.0;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) {
+        // d u_cc / d x_d at the cell and at its two neighbours along d
+        const double gP = gradu_bf(P, M.u[cc], cc, d, c, is_bnd(N, 2 * d), is_bnd(N, 2 * d + 1), solid);
+#pragma unroll
+        for (int sh = 0; sh < 2; ++sh) {
+          const int s = sh ? 1 : -1, q = 2 * d + sh;
+          const double gN = gradu_nb(P, M.u[cc], cc, d, N, q, i, j, k, sn[q]);
+          const double uN = M.u[cc][N.n[q]];
+          const double F = fo[q];
+          const bool up = F > 0.0;
+          const double uC = sel(up, uP, uN), uD = sel(up, uN, uP);
+          const double gC = sel(up, gP, gN);
+          const double dxC = (double)s * 0.5 * P.delta[d] * sel(up, 1.0, -1.0);
+          double uf;
+          if (CONV == 1) {
+            uf = uC + dxC * gC;
+          } else {
+            const double dCD = uD - uC;
+            const double r = sel(dCD != 0.0, 2.0 * (2.0 * dxC * gC) / dCD - 1.0, 0.0);
+            const double psi = (r + fabs(r)) / (1.0 + fabs(r));
+            uf = uC + 0.5 * psi * dCD;
+          }
+          Cc = sel(is_bnd(N, q), Cc, Cc - F * (uf - uC));
+        }
+      }
+      T = T + Cc;
+    }
+    ex[cc] = T;
+  }
+  ex0[c] = ex[0];
+  ex1[c] = ex[1];
+  if (DIM == 3) ex2[c] = ex[2];
+}
+
+// The same explicit terms on 3-D grids, with the stencil staged through LDS.
+// Computed in place from u, the cell gradients of a cell and its face
+// neighbours touch about 60 values of u per cell (edge and second neighbours
+// included).  Here a workgroup owns a 32 x 8 column of cells over exz
+// consecutive planes and marches along z: a ring of three planes (k - 1, k,
+// k + 1) of u, v, w and nu_t, each with a halo of two cells in x and y, sits in
+// LDS, so each value is fetched from global memory about twice (halo and the
+// plane re-reads at the column ends) and the stencil reads are LDS reads at
+// fixed offsets; the values two planes away (d/dz of the z-neighbours'
+// gradients) are loaded per cell.  The host chooses exz so that the workgroups
+// fill the chip in few rounds.
+// Domain faces cost no branches or selects in the gradients: a position one
+// cell beyond a domain face (and inside the domain along the other axes) is
+// staged as the ghost value 2 u_f - u_X of the face value u_f that the Gauss
+// gradient of the cell X inside takes on that face, so the interior formula
+// 0.5 (u_X + ghost) gives u_f (up to rounding).  Every other position outside
+// the domain holds the nearest cell's value and enters only terms the selects
+// on domain faces drop (face values of nu_t and of the gradient on a domain
+// face are the cell's own, as in the global-memory form).
+constexpr int EXTX = 32, EXTY = 8, EXW = EXTX + 4, EXH = EXTY + 4;
+inline long long blocks_explicit_z(const Params& P, int exz) {
+  return (long long)((P.nx + EXTX - 1) / EXTX) * ((P.ny + EXTY - 1) / EXTY) * ((P.nz + exz - 1) / exz);
+}
+// u_q at global position (gi, gj, gk) as staged: the value itself inside the
+// domain; one cell beyond exactly one domain face the ghost 2 u_f - u of its
+// inner neighbour (face value u_bface, the inner cell's in-solid bit); any
+// other outside position the nearest cell's value
+struct Staged {
+  double u[3], nu;
+};
+// the ghost 2 u_f - u of component q beyond face f (2 d + high side) of a cell
+// with value u (u_f the face value of u_bface; the owner's value on faces of
+// in-solid cells)
+__device__ __forceinline__ double ghost_value(const Params& P, int f, int q, bool solid, double u) {
+  double A = 1.0, Bc = 0.0;
+#pragma unroll
+  for (int ff = 0; ff < 6; ++ff) {
+    A = sel(f == ff, P.ubA[ff][q], A);
+    Bc = sel(f == ff, P.ubB[ff][q], Bc);
+  }
+  const double uf = solid ? u : A * u + Bc;
+  return 2.0 * uf - u;
+}
+// ghost face of an outside position (offsets ox, oy, oz beyond the domain):
+// the face index when exactly one offset is nonzero and it is +-1, else -1
+__device__ __forceinline__ int ghost_face(int ox, int oy, int oz) {
+  const int nout = (ox != 0) + (oy != 0) + (oz != 0);
+  if (nout != 1 || ox < -1 || ox > 1 || oy < -1 || oy > 1 || oz < -1 || oz > 1) return -1;
+  return ox != 0 ? (ox > 0 ? 1 : 0) : (oy != 0 ? (oy > 0 ? 3 : 2) : (oz > 0 ? 5 : 4));
+}
+__device__ __forceinline__ Staged staged_value(const Params& P, const Mom& M, int gi, int gj, int gk) {
+  const int ci = gi < 0 ? 0 : (gi >= P.nx ? P.nx - 1 : gi);
+  const int cj = gj < 0 ? 0 : (gj >= P.ny ? P.ny - 1 : gj);
+  const int ck = gk < 0 ? 0 : (gk >= P.nz ? P.nz - 1 : gk);
+  const long long g = cidx(P, ci, cj, ck);
+  Staged v;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) v.u[q] = M.u[q][g];
+  v.nu = M.nut[g];
+  const int f = ghost_face(gi - ci, gj - cj, gk - ck);
+  if (f >= 0) {  // (positions outside the domain only)
+    const bool solid = M.flags[g] & F_SOLID;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) v.u[q] = ghost_value(P, f, q, solid, v.u[q]);
+  }
+  return v;
+}
+// component q alone at (i, j, gk), as staged
+__device__ __forceinline__ double staged_u(const Params& P, const Mom& M, int q, int i, int j, int gk) {
+  const int ck = gk < 0 ? 0 : (gk >= P.nz ? P.nz - 1 : gk);
+  const long long g = cidx(P, i, j, ck);
+  double u = M.u[q][g];
+  const int f = ghost_face(0, 0, gk - ck);
+  if (f >= 0) u = ghost_value(P, f, q, M.flags[g] & F_SOLID, u);
+  return u;
+}
+template <int CONV>
+__global__ void __launch_bounds__(256)
+k_mom_explicit_z(Params P, Mom M, double* ex0, double* ex1, double* ex2, int exz) {
+  __shared__ double su[3][3][EXH][EXW];        // component, ring slot, y, x
+  __shared__ double snu[3][EXH - 2][EXW - 2];  // (face neighbours only: halo of one)
+  // workgroup -> (x, y, z-segment), the z-segments of a column contiguous on
+  // one XCD (their shared planes stay in that XCD's L2)
+  const unsigned nb = gridDim.x, b = blockIdx.x;
+  const unsigned qq = nb >> 3, rr = nb & 7u, xc = b & 7u, id = b >> 3;
+  const unsigned L = xc < rr ? xc * (qq + 1) + id : rr * (qq + 1) + (xc - rr) * qq + id;
+  const int bxn = (P.nx + EXTX - 1) / EXTX, bzn = (P.nz + exz - 1) / exz;
+  const int tz = (int)(L % (unsigned)bzn), rest = (int)(L / (unsigned)bzn);
+  const int i0 = (rest % bxn) * EXTX, j0 = (rest / bxn) * EXTY, k0 = tz * exz;
+  const int k1 = k0 + exz < P.nz ? k0 + exz : P.nz;
+  const int lx = threadIdx.x, ly = threadIdx.y, tid = lx + EXTX * ly;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool act = i < P.nx && j < P.ny;
+  // a plane is staged in two steps: fetch (global loads into registers, for the
+  // thread's two positions of the 36 x 12 plane) and commit (registers to the
+  // plane's ring slot); the fetch of plane k + 2 is in flight while plane k is
+  // computed
+  static_assert(EXW * EXH <= 512 && EXW * EXH > 256, "two staging positions per thread");
+  const bool two = tid + 256 < EXW * EXH;
+  Staged pf[2];
+  auto fetch = [&](int kp) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = r == 0 ? tid : (two ? tid + 256 : tid);
+      const int hx = e % EXW, hy = e / EXW;
+      pf[r] = staged_value(P, M, i0 + hx - 2, j0 + hy - 2, kp);
+    }
+  };
+  auto commit = [&](int kp) {
+    const int sl = (kp + 3) % 3;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (r == 1 && !two) continue;
+      const int e = tid + 256 * r;
+      const int hx = e % EXW, hy = e / EXW;
+      su[0][sl][hy][hx] = pf[r].u[0];
+      su[1][sl][hy][hx] = pf[r].u[1];
+      su[2][sl][hy][hx] = pf[r].u[2];
+      if (hx >= 1 && hx <= EXW - 2 && hy >= 1 && hy <= EXH - 2) snu[sl][hy - 1][hx - 1] = pf[r].nu;
+    }
+  };
+  fetch(k0 - 1);
+  commit(k0 - 1);
+  fetch(k0);
+  commit(k0);
+  fetch(k0 + 1);
+  for (int k = k0; k < k1; ++k) {
+    commit(k + 1);
+    __syncthreads();
+    const int sm = (k + 2) % 3, s0 = k % 3, sp = (k + 1) % 3;
+    // values two planes away at this column (the staged form: ghosts one plane
+    // beyond a z face), issued before the next plane's fetch, which stays in
+    // flight while this plane is computed
+    double far[3][2] = {{0.0, 0.0}, {0.0, 0.0}, {0.0, 0.0}};
+    if (act) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (CONV == 0 && q != 2) continue;  // (upwind: d/dz of w only)
+        far[q][0] = staged_u(P, M, q, i, j, k - 2);
+        far[q][1] = staged_u(P, M, q, i, j, k + 2);
+      }
+    }
+    fetch(k + 2);
+    if (act) {
+      const long long c = cidx(P, i, j, k);
+      const Nbr N = make_nbr(P, i, j, k, c);
+      // u_q at offset (ox, oy, oz) from the cell (|ox|, |oy| <= 2, |oz| <= 1,
+      // or oz = +-2 with ox = oy = 0)
+      auto V = [&](int q, int ox, int oy, int oz) -> double {
+        if (oz == -2) return far[q][0];
+        if (oz == 2) return far[q][1];
+        const int sl = oz < 0 ? sm : (oz > 0 ? sp : s0);
+        return su[q][sl][ly + 2 + oy][lx + 2 + ox];
+      };
+      // d u_jc / d x_b at offset o (Gauss gradient, linear face interpolation;
+      // domain faces through the ghosts)
+      auto grad = [&](int jc, int b, int ox, int oy, int oz) -> double {
+        const int ex = b == 0, ey = b == 1, ez = b == 2;
+        const double uP = V(jc, ox, oy, oz);
+        const double fp = 0.5 * (uP + V(jc, ox + ex, oy + ey, oz + ez));
+        const double fm = 0.5 * (V(jc, ox - ex, oy - ey, oz - ez) + uP);
+        return (fp - fm) * P.idelta[b];
+      };
+      const double nuP = P.nu + snu[s0][ly + 1][lx + 1];
+      double nuN[6], fo[6];
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        const int a = q >> 1, s = (q & 1) ? 1 : -1;
+        const int ox = a == 0 ? s : 0, oy = a == 1 ? s : 0, oz = a == 2 ? s : 0;
+        const int sl = oz < 0 ? sm : (oz > 0 ? sp : s0);
+        nuN[q] = P.nu + snu[sl][ly + 1 + oy][lx + 1 + ox];
+        fo[q] = CONV != 0 ? outward_flux(P, M.phi, a, s, i, j, k) : 0.0;
+      }
+      double ex[3];
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) {
+        double T = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          // d u_d / d x_cc at the cell and at its two neighbours along d
+          const double GP = grad(d, cc, 0, 0, 0);
+#pragma unroll
+          for (int sh = 0; sh < 2; ++sh) {
+            const int s = sh ? 1 : -1, q = 2 * d + sh;
+            const bool fb = is_bnd(N, q);
+            const double GN = grad(d, cc, d == 0 ? s : 0, d == 1 ? s : 0, d == 2 ? s : 0);
+            const double nuf = sel(fb, nuP, 0.5 * (nuP + nuN[q]));
+            const double gf = sel(fb, GP, 0.5 * (GP + GN));
+            T += (double)s * P.area[d] * nuf * gf;
+          }
+        }
+        if (CONV != 0) {
+          const double uP = V(cc, 0, 0, 0);
+          double Cc = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; ++d) {
+            // d u_cc / d x_d at the cell and at its two neighbours along d
+            const double gP = grad(cc, d, 0, 0, 0);
+#pragma unroll
+            for (int sh = 0; sh < 2; ++sh) {
+              const int s = sh ? 1 : -1, q = 2 * d + sh;
+              const int ox = d == 0 ? s : 0, oy = d == 1 ? s : 0, oz = d == 2 ? s : 0;
+              const double gN = grad(cc, d, ox, oy, oz);
+              const double uN = V(cc, ox, oy, oz);
+              const double F = fo[q];
+              const bool up = F > 0.0;
+              const double uC = sel(up, uP, uN), uD = sel(up, uN, uP);
+              const double gC = sel(up, gP, gN);
+              const double dxC = (double)s * 0.5 * P.delta[d] * sel(up, 1.0, -1.0);
+              double uf;
+              if (CONV == 1) {
+                uf = uC + dxC * gC;
+              } else {
+                const double dCD = uD - uC;
+                const double r = sel(dCD != 0.0, 2.0 * (2.0 * dxC * gC) / dCD - 1.0, 0.0);
+                const double psi = (r + fabs(r)) / (1.0 + fabs(r));
+                uf = uC + 0.5 * psi * dCD;
+              }
+              Cc = sel(is_bnd(N, q), Cc, Cc - F * (uf - uC));
+            }
+          }
+          T = T + Cc;
+        }
+        ex[cc] = T;
+      }
+      ex0[c] = ex[0];
+      ex1[c] = ex[1];
+      ex2[c] = ex[2];
+    }
+    __syncthreads();
+  }
+}
+
+// Assembly of the relaxed momentum rows with the explicit IB source
+// (discrete f_ib = alpha [M(u~) + grad p]), plus the normalised-residual sums
+// of the rows that are solved (alpha_u = 0); the explicit terms of the previous
+// iterate come from k_mom_explicit (M.ex).
+template <int DIM>
 __global__ void __launch_bounds__(256)
 k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rhs2, double* aPr_out,
                const double* means, double* part, long long pstride) {
@@ -336,53 +650,7 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
     double rh[DIM], Ax[DIM];
 #pragma unroll
     for (int cc = 0; cc < DIM; ++cc) {
-      // explicit div(nuEff (grad u)^T): face value nuEff_f (d u_d / d x_cc)_f, the
-      // face gradient being the mean of the two cell (Gauss) gradients
-      double T = 0.0;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) {
-        const double* Gd = M.G[3 * cc + d];
-        const double GP = Gd[c];
-#pragma unroll
-        for (int sh = 0; sh < 2; ++sh) {
-          const int s = sh ? 1 : -1, q = 2 * d + sh;
-          const bool fb = is_bnd(N, q);
-          const double GN = Gd[N.n[q]];
-          const double nuf = sel(fb, nuP, 0.5 * (nuP + nuN[q]));
-          const double gf = sel(fb, GP, 0.5 * (GP + GN));
-          T += (double)s * P.area[d] * nuf * gf;
-        }
-      }
-      if (CONV != 0) {
-        double Cc = 0.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-          const double* Gc = M.G[3 * d + cc];  // d u_cc / d x_d
-          const double gP = Gc[c];
-#pragma unroll
-          for (int sh = 0; sh < 2; ++sh) {
-            const int s = sh ? 1 : -1, q = 2 * d + sh;
-            const double gN = Gc[N.n[q]];
-            const double F = fo[q];
-            const bool up = F > 0.0;
-            const double uC = sel(up, uc[cc], un[cc][q]), uD = sel(up, un[cc][q], uc[cc]);
-            const double gC = sel(up, gP, gN);
-            const double dxC = (double)s * 0.5 * P.delta[d] * sel(up, 1.0, -1.0);
-            double uf;
-            if (CONV == 1) {
-              uf = uC + dxC * gC;
-            } else {
-              const double dCD = uD - uC;
-              const double r = sel(dCD != 0.0, 2.0 * (2.0 * dxC * gC) / dCD - 1.0, 0.0);
-              const double psi = (r + fabs(r)) / (1.0 + fabs(r));
-              uf = uC + 0.5 * psi * dCD;
-            }
-            Cc = sel(is_bnd(N, q), Cc, Cc - F * (uf - uC));
-          }
-        }
-        T = T + Cc;
-      }
-      const double b0 = T + bsrc[cc];
+      const double b0 = M.ex[cc][c] + bsrc[cc];
       // V (grad p)_c, Gauss with linear interpolation
       const double pP = M.p[c], pp = M.p[N.n[2 * cc + 1]], pm = M.p[N.n[2 * cc]];
       const double fp = sel(is_bnd(N, 2 * cc + 1), p_bface(P, cc, +1, solid, pP), 0.5 * (pP + pp));
@@ -835,8 +1103,8 @@ static Mom make_mom(hfdib_ctx* c) {
     M.phi[q] = c->phi[q];
     M.uib[q] = c->uib[q];
   }
-  for (int q = 0; q < 9; ++q) M.G[q] = c->G[q];
   for (int q = 0; q < 3; ++q) M.us[q] = c->us[q];
+  for (int q = 0; q < 3; ++q) M.ex[q] = c->ex[q];
   M.p = c->p;
   M.nut = c->nut;
   M.k = c->k;
@@ -882,7 +1150,6 @@ int init_state(hfdib_ctx* c) {
   // memory-counter calibration
   hipLaunchKernelGGL(k_copy, dim3(nb), dim3(NTHREADS), 0, c->stream, P.N, (const double*)c->p, c->px);
   HFDIB_CHECK_LAUNCH(c, "init state");
-  c->grad_ok = 0;
   return refresh_mirrors(c);
 }
 
@@ -907,61 +1174,59 @@ __global__ void k_residuals(const double* S, int dim, int turb, double* out) {
   out[6] = S[SC_RESSUM] + (dim > 1 ? S[SC_RESSUM + 3] : 0.0) + (dim > 2 ? S[SC_RESSUM + 6] : 0.0);
 }
 
-// velocity gradient (Gauss, linear face interpolation) and 2 S:S of the current u
-struct GradOut {
-  double* G[9];
-};
-__global__ void k_grad(Params P, const double* u0, const double* u1, const double* u2, const uint8_t* flags, GradOut O,
-                       double* S2) {
-  int i, j, k;
-  tile_ijk(P, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
-  long long c = cidx(P, i, j, k);
-  const double* u[3] = {u0, u1, u2};
-  double G[3][3];
-  gradu_all_bf(P, u, flags[c] & F_SOLID, make_nbr(P, i, j, k, c), c, G);
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int jc = 0; jc < 3; ++jc)
-      if (a < P.dim && jc < P.dim) O.G[3 * a + jc][c] = G[a][jc];
-  S2[c] = strain2(G);
-}
-
 // the momentum assembly instance of the configured convection scheme
 using MomAssembleFn = void (*)(Params, Mom, MixOut, double*, double*, double*, double*, const double*, double*,
                                long long);
 static MomAssembleFn mom_assemble_kernel(const Params& P) {
+  return P.dim == 2 ? k_mom_assemble<2> : k_mom_assemble<3>;
+}
+// the explicit-term pass of the configured convection scheme
+using MomExplicitFn = void (*)(Params, Mom, double*, double*, double*);
+static MomExplicitFn mom_explicit_kernel(const Params& P) {
   if (P.dim == 2) {
-    if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1, 2>;
-    if (P.conv == HFDIB_CONV_VANLEER) return k_mom_assemble<2, 2>;
-    return k_mom_assemble<0, 2>;
+    if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_explicit<1, 2>;
+    if (P.conv == HFDIB_CONV_VANLEER) return k_mom_explicit<2, 2>;
+    return k_mom_explicit<0, 2>;
   }
-  if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_assemble<1, 3>;
-  if (P.conv == HFDIB_CONV_VANLEER) return k_mom_assemble<2, 3>;
-  return k_mom_assemble<0, 3>;
+  if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_explicit<1, 3>;
+  if (P.conv == HFDIB_CONV_VANLEER) return k_mom_explicit<2, 3>;
+  return k_mom_explicit<0, 3>;
 }
-
-int velocity_gradient(hfdib_ctx* c) {
+static void launch_mom_explicit(hfdib_ctx* c, const Mom& M) {
   const Params& P = c->P;
-  GradOut O;
-  for (int q = 0; q < 9; ++q) O.G[q] = c->G[q];
-  const Params PG = deep_tile_params(P, true);
-  hipLaunchKernelGGL(k_grad, grid3(PG), block3(PG), 0, c->stream, PG, c->u[0], c->u[1], c->u[2], c->flags, O, c->S2);
-  HFDIB_CHECK_LAUNCH(c, "velocity gradient");
-  c->grad_ok = 1;
-  return HFDIB_OK;
+  if (P.dim == 3) {
+    auto kern = P.conv == HFDIB_CONV_LINEAR_UPWIND ? k_mom_explicit_z<1>
+                : (P.conv == HFDIB_CONV_VANLEER ? k_mom_explicit_z<2> : k_mom_explicit_z<0>);
+    // planes per workgroup: fewest rounds of resident workgroups (4 per CU for
+    // the upwind instance, LDS-bound; 2 for the others, register-bound) times
+    // the planes each one stages
+    const long long slots = (long long)(P.conv == HFDIB_CONV_UPWIND ? 4 : 2) * c->ncu;
+    int best = 8;
+    long long bcost = -1;
+    for (int z = 4; z <= 16; ++z) {
+      const long long cost = (blocks_explicit_z(P, z) + slots - 1) / slots * (z + 2);
+      if (bcost < 0 || cost < bcost) {
+        bcost = cost;
+        best = z;
+      }
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks_explicit_z(P, best)), dim3(EXTX, EXTY, 1), 0, c->stream, P, M,
+                       c->ex[0], c->ex[1], c->ex[2], best);
+    return;
+  }
+  const Params PA = deep_tile_params(P);
+  hipLaunchKernelGGL(mom_explicit_kernel(PA), grid3(PA), block3(PA), 0, c->stream, PA, M, c->ex[0], c->ex[1],
+                     c->ex[2]);
 }
 
-// One round of the kernels the tile autotuner times: the gradient pass, the
-// momentum assembly and the pressure operator.  None of them changes the state
-// (the gradient and the assembly outputs are recomputed from the same state by
-// the next iteration; the operator writes a PCG scratch vector).
+// One round of the kernels the tile autotuner times: the explicit-term pass,
+// the momentum assembly and the pressure operator.  None of them changes the
+// state (the pass and assembly outputs are recomputed from the same state by the
+// next iteration; the operator writes a PCG scratch vector).
 int tile_bench_round(hfdib_ctx* c) {
   const Params& P = c->P;
-  int st = velocity_gradient(c);
-  if (st != HFDIB_OK) return st;
   Mom M = make_mom(c);
+  launch_mom_explicit(c, M);
   MixOut X{{nullptr, nullptr, nullptr}, nullptr};
   const Params PA = deep_tile_params(P);
   hipLaunchKernelGGL(mom_assemble_kernel(P), grid3(PA), block3(PA), 0, c->stream, PA, M, X, c->rhs[0], c->rhs[1],
@@ -1012,12 +1277,9 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                        c->u[1], c->u[2], c->us[0], c->us[1], c->us[2], c->flags, c->uib[0], c->uib[1], c->uib[2],
                        c->bc_utau, c->bc_yplus, c->n_wall, c->wall_cells, c->wall_y, c->wall_utau, c->wall_yplus,
                        c->bc_n, c->nut, c->wallD);
-  // 2. momentum predictor (needs the gradient of the current u)
-  if (!c->grad_ok) {
-    st = velocity_gradient(c);
-    if (st != HFDIB_OK) return st;
-  }
+  // 2. momentum predictor
   Mom M = make_mom(c);
+  launch_mom_explicit(c, M);
   bool mixed = P.precision == HFDIB_MIXED;
   MixOut X{{nullptr, nullptr, nullptr}, nullptr, {c->usp[0], c->usp[1], c->usp[2]}};
   if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32, {nullptr, nullptr, nullptr}};
@@ -1073,10 +1335,6 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   c->p = c->pnew;
   c->pnew = tmp;
   HFDIB_CHECK_LAUNCH(c, "velocity update");
-  // gradient of the updated u: used by the turbulence stage and by the next
-  // momentum assembly (u does not change in between)
-  st = velocity_gradient(c);
-  if (st != HFDIB_OK) return st;
   // 6. turbulence
   if (P.model != HFDIB_LAMINAR) {
     st = turbulence_stage(c);

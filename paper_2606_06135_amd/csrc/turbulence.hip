@@ -29,23 +29,22 @@ __device__ __forceinline__ double prod_ib(const Params& P, double yp, double Gk,
 
 // boundary cells (mode 0) and domain-wall cells (mode 1): imposed omega/eps and
 // production; the omega field takes its fixed value on these rows
-struct G9 {
-  const double* g[9];
+struct Vel {
+  const double* u[3];
 };
 
 // Realizable k-epsilon (Shih et al. 1995): invariants S:S, Omega:Omega and
 // S_ij S_jk S_ki of the deviatoric strain rate S and the rotation rate Omega of
-// the stored velocity gradient G[a][b] = d u_b / d x_a (entries beyond dim are 0;
-// the transposed tensor has the same invariants)
+// the velocity gradient G[a][b] = d u_b / d x_a of cell c with neighbours N
+// (Gauss, from u; entries beyond dim are 0; the transposed tensor has the same
+// invariants)
 struct RkeInv {
   double SS, OO, S3;
 };
-__device__ __forceinline__ RkeInv rke_invariants(const Params& P, const G9& Gs, long long c) {
+__device__ __forceinline__ RkeInv rke_invariants(const Params& P, const Vel& U, bool solid, const Nbr& N,
+                                                 long long c) {
   double G[3][3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) G[a][b] = (a < P.dim && b < P.dim) ? Gs.g[3 * a + b][c] : 0.0;
+  gradu_all_bf(P, U.u, solid, N, c, G);
   const double tr = G[0][0] + G[1][1] + G[2][2];
   double S[3][3];
   RkeInv I{0.0, 0.0, 0.0};
@@ -89,12 +88,13 @@ struct WallList {
 };
 
 // Turbulence inputs of the previous iterate, taken before this stage changes
-// any k or omega/eps value: the SST blending F1 and grad k . grad omega (the
+// any k or omega/eps value: 2 S:S of the current velocity (Gauss gradient, the
+// production term), the SST blending F1 and grad k . grad omega (the
 // cross-diffusion term), and per block the maximum of omega/eps over the cells
 // outside the in-solid group (the value imposed on in-solid cells)
 __global__ void __launch_bounds__(256)
-k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv, const double* dw, double* F1,
-              double* kwo, double* part) {
+k_turb_inputs(Params P, const uint8_t* flags, Vel U, const double* kv, const double* wv, const double* dw, double* S2,
+              double* F1, double* kwo, double* part) {
   double wmx = 0.0;
   int i, j, k;
   tile_ijk(P, i, j, k);
@@ -105,6 +105,12 @@ k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv
     // are dropped by selects)
     const uint8_t fl = flags[c];
     const double kk = kv[c], ww = wv[c];
+    double s2;
+    {
+      double G[3][3];
+      gradu_all_bf(P, U.u, fl & F_SOLID, N, c, G);
+      s2 = strain2(G);
+    }
     if (P.model == HFDIB_KOMEGA_SST) {
       double kn[6], wn[6];
 #pragma unroll
@@ -135,6 +141,7 @@ k_turb_inputs(Params P, const uint8_t* flags, const double* kv, const double* wv
       F1[c] = tanh(a2 * a2);
       kwo[c] = kw;
     }
+    S2[c] = s2;
     wmx = (fl & F_IC) ? 0.0 : ww;
   }
   __shared__ double lmax[4];
@@ -236,7 +243,7 @@ struct Scal {
   double* w;        // omega/eps (fixed values already in place)
   const double* wib;
   const double* kib;
-  G9 G;  // velocity gradient (realizable k-epsilon)
+  Vel U;  // velocity (realizable k-epsilon: its gradient)
 };
 
 // neighbour coefficients of a scalar row (faces W, E, S, N, B, T; 0 on domain
@@ -313,7 +320,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
         b0 = b0 + P.C1 * Pc * wo / kold * V;
       } else if (RKE) {
         // C1 |S| eps explicit, C2 eps^2 / (k + sqrt(nu eps)) linearised in eps
-        RkeInv I = rke_invariants(P, S.G, c);
+        RkeInv I = rke_invariants(P, S.U, solid, N, c);
         double Sm = sqrt(2.0 * I.SS);
         double eta = Sm * kold / wo;
         double C1 = fmax(0.43, eta / (eta + 5.0));
@@ -535,7 +542,7 @@ __global__ void k_kib(Params P, int nbc, const int* bc_cells, const uint8_t* fla
 
 // k <- k + alpha_k (k_ib - k), bounding, turbulent viscosity of the model
 // (in-solid cells 0); eps/omega is already bounded
-__global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, G9 Gs, const double* kib, double* k,
+__global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, Vel U, const double* kib, double* k,
                              const double* w, const double* dw, double* nut, float* nut32) {
   int i, j, kz;
   tile_ijk(P, i, j, kz);
@@ -554,7 +561,7 @@ __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, G
   } else if (P.model == HFDIB_KOMEGA) {
     nt = kk / ww;
   } else if (P.model == HFDIB_RKEPS) {
-    RkeInv I = rke_invariants(P, Gs, c);
+    RkeInv I = rke_invariants(P, U, fl & F_SOLID, make_nbr(P, i, j, kz, c), c);
     nt = rke_cmu(P, I, kk, ww) * kk * kk / ww;
   } else {
     double d = dwc;
@@ -625,12 +632,11 @@ int turbulence_stage(hfdib_ctx* c) {
   long long nblk3 = (long long)g.x * g.y * g.z;
   double* S = c->scal + SCAL_PCG;
   double* wmax = S + SC_WMAX;
-  G9 Gs;
-  for (int q = 0; q < 9; ++q) Gs.g[q] = c->G[q];
+  const Vel U{{c->u[0], c->u[1], c->u[2]}};
   // SST blending and cross diffusion of the previous iterate, maximum of
   // omega/eps over cells outside the in-solid group
-  hipLaunchKernelGGL(k_turb_inputs, g, b, 0, c->stream, P, (const uint8_t*)c->flags, (const double*)c->k,
-                     (const double*)c->w, (const double*)c->dw, c->F1, c->t2, c->partials);
+  hipLaunchKernelGGL(k_turb_inputs, g, b, 0, c->stream, P, (const uint8_t*)c->flags, U, (const double*)c->k,
+                     (const double*)c->w, (const double*)c->dw, c->S2, c->F1, c->t2, c->partials);
   launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4);
   // imposed omega/eps and production on boundary, wall and in-solid cells
   {
@@ -659,7 +665,7 @@ int turbulence_stage(hfdib_ctx* c) {
   Sc.w = c->w;
   Sc.wib = c->wib;
   Sc.kib = c->kib;
-  Sc.G = Gs;
+  Sc.U = U;
   bool mixed = P.precision == HFDIB_MIXED;
   float* r32 = mixed ? c->r32[0] : nullptr;
   float* a32 = mixed ? c->a32 : nullptr;
@@ -699,7 +705,7 @@ int turbulence_stage(hfdib_ctx* c) {
             mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride, c->xsp);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
   sweeps(1, c->k, (uint8_t)0);
-  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, Gs, c->kib, c->k, c->w,
+  hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, U, c->kib, c->k, c->w,
                      c->dw, c->nut, mixed ? c->nut32 : nullptr);
   if (c->n_bc > 0) {
     hipLaunchKernelGGL(k_wall_bc, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
