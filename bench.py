@@ -47,7 +47,10 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # reused on chip; per-pass figures of the byte model of one SIMPLE iteration):
 #   k / omega sweeps: 2 x 144 B/cell for n_s = 2 -> 36 per one-colour launch
 #   momentum sweeps: 224 B/cell for n_s = 2 -> 56 per one-colour launch
-#   momentum assembly: u,v,w,p,phi(3),nu_t (+flags) in, b(3), a_P out: 97
+#   momentum assembly: u,v,w,p,phi(3),nu_t, the explicit terms (3) (+flags) in,
+#     b(3), a_P out: 121
+#   explicit momentum terms (transpose viscous term; deferred convection
+#     correction under the higher-order schemes): u,v,w,nu_t in, 3 terms out: 56
 #   omega and k assembly: 2 x 80 -> 80 per launch
 #   pressure operator apply: x, rAU (+flags) in, y out: 25
 #   V-cycle half sweep (one colour): r and D^-1 of that colour (8), rAU (8),
@@ -60,10 +63,12 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 #   CG vector update: x, d, r, q in, x, r out: 48
 # (reduction finalize launches and the coarse levels of the V-cycle are bound by
 # launch latency, not by bytes: they are timed but have no byte model)
-ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 97.0, "scalar_assemble": 80.0,
+ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 121.0, "mom_explicit": 56.0,
+              "scalar_assemble": 80.0,
               "p_apply": 25.0, "p_smooth": 25.0, "p_presmooth": 41.0, "p_restrict": 22.0, "p_apply_dir": 41.0,
               "p_axpy": 48.0}
 KERNEL = {"scalar_sweep": "k_scalar_sweep", "mom_sweep": "k_mom_sweep", "mom_assemble": "k_mom_assemble",
+          "mom_explicit": "k_mom_explicit_z",
           "scalar_assemble": "k_scalar_assemble", "p_apply": "k_fine_apply", "p_smooth": "k_fine_smooth",
           "p_presmooth": "k_fine_presmooth", "p_restrict": "k_restrict_fine_res", "p_apply_dir": "k_fine_apply_dir",
           "p_axpy": "k_axpy2"}
@@ -74,7 +79,7 @@ ALGO_BYTES_MIXED = dict(ALGO_BYTES, p_smooth=13.0, p_presmooth=21.0, p_restrict=
 KERNEL_MIXED = dict(KERNEL, scalar_sweep="k_scalar_sweep32", mom_sweep="k_mom_sweep32")
 KERNEL_SOURCES = {"k_scalar_sweep": "turbulence.hip", "k_scalar_sweep32": "turbulence.hip",
                   "k_scalar_assemble": "turbulence.hip", "k_mom_sweep": "simple.hip",
-                  "k_mom_sweep32": "simple.hip", "k_mom_assemble": "simple.hip"}
+                  "k_mom_sweep32": "simple.hip", "k_mom_assemble": "simple.hip", "k_mom_explicit_z": "simple.hip"}
 for _k in ("k_fine_apply", "k_fine_smooth", "k_fine_presmooth", "k_restrict_fine_res", "k_fine_apply_dir", "k_axpy2"):
     KERNEL_SOURCES[_k] = "pressure.hip"
 
@@ -230,8 +235,9 @@ def main():
     kern = {}
     psolve_hbm = None
     if not args.no_timing:
-        for name in ("p_apply", "mom_sweep", "mom_assemble", "scalar_sweep", "scalar_assemble", "p_solve",
-                     "iteration", "p_smooth", "p_presmooth", "p_restrict", "p_apply_dir", "p_axpy", "p_coarse",
+        for name in ("p_apply", "mom_sweep", "mom_assemble", "mom_explicit", "scalar_sweep", "scalar_assemble",
+                     "p_solve", "iteration", "p_smooth", "p_presmooth", "p_restrict", "p_apply_dir", "p_axpy",
+                     "p_coarse",
                      "finalize"):
             ms, cnt = solver.timing_query(name)
             kern[name] = (ms, cnt)

@@ -372,7 +372,9 @@ int hfdib_timing_enable(hfdib_ctx* ctx, int enable);
  * from zero, 9 restriction of the fine residual, 10 operator apply with the
  * direction update, 11 CG vector update (x, r), 12 coarse levels of one V-cycle
  * (one span from the first coarse-level launch to the last, counted as one),
- * 13 reduction finalize launches (every reduction of the iteration).
+ * 13 reduction finalize launches (every reduction of the iteration),
+ * 14 momentum explicit-term pass (transpose viscous term, deferred convection
+ * correction).
  * Returns accumulated milliseconds and the launch count (host pointers).
  * Synchronises the stream. */
 int hfdib_timing_query(hfdib_ctx* ctx, int kernel_class, double* total_ms, long long* count);

@@ -28,7 +28,7 @@ IB = {"bc_cells": 0, "ic_cells": 1, "wall_cells": 2, "normal": 3, "yperp": 4, "y
       "utau_loglaw": 13, "wall_y": 14, "utau": 15, "wall_yplus": 16, "wall_utau": 17}
 TIMER = {"p_apply": 0, "mom_sweep": 1, "mom_assemble": 2, "p_solve": 3, "iteration": 4, "scalar_sweep": 5,
          "scalar_assemble": 6, "p_smooth": 7, "p_presmooth": 8, "p_restrict": 9, "p_apply_dir": 10, "p_axpy": 11,
-         "p_coarse": 12, "finalize": 13}
+         "p_coarse": 12, "finalize": 13, "mom_explicit": 14}
 STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP runtime error",
           -4: "diverged", -5: "call out of order"}
 

@@ -229,7 +229,7 @@ int set_hip_error(hfdib_ctx* c, hipError_t e, const char* where);
 // timing classes
 enum { T_PAPPLY = 0, T_MOMSWEEP = 1, T_MOMASM = 2, T_PSOLVE = 3, T_ITER = 4, T_SCALSWEEP = 5, T_SCALASM = 6,
        T_PSMOOTH = 7, T_PPRESMOOTH = 8, T_PRESTRICT = 9, T_PAPPLYDIR = 10, T_PAXPY = 11, T_PCOARSE = 12,
-       T_FINALIZE = 13, T_NCLASS = 14 };
+       T_FINALIZE = 13, T_MOMEXPL = 14, T_NCLASS = 15 };
 void timer_begin(hfdib_ctx* c, int cls);
 // brackets one SIMPLE iteration (begin = true at its start, false at its end):
 // with a recording period n > 1 only every n-th iteration is recorded

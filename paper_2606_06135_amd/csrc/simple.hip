@@ -1210,13 +1210,14 @@ static void launch_mom_explicit(hfdib_ctx* c, const Mom& M) {
         best = z;
       }
     }
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks_explicit_z(P, best)), dim3(EXTX, EXTY, 1), 0, c->stream, P, M,
-                       c->ex[0], c->ex[1], c->ex[2], best);
+    LaunchEv ev = timer_launch(c, T_MOMEXPL, true, true);
+    launch_ev(kern, dim3((unsigned)blocks_explicit_z(P, best)), dim3(EXTX, EXTY, 1), c->stream, ev, P, M, c->ex[0],
+              c->ex[1], c->ex[2], best);
     return;
   }
   const Params PA = deep_tile_params(P);
-  hipLaunchKernelGGL(mom_explicit_kernel(PA), grid3(PA), block3(PA), 0, c->stream, PA, M, c->ex[0], c->ex[1],
-                     c->ex[2]);
+  LaunchEv ev = timer_launch(c, T_MOMEXPL, true, true);
+  launch_ev(mom_explicit_kernel(PA), grid3(PA), block3(PA), c->stream, ev, PA, M, c->ex[0], c->ex[1], c->ex[2]);
 }
 
 // One round of the kernels the tile autotuner times: the explicit-term pass,

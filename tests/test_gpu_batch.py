@@ -151,7 +151,7 @@ def test_sampled_kernel_timing(gpu):
     b = _solver(spec, gpu, p_rtol=1e-2, p_maxit=100)
     a.timing(True, 3)
     a.iterate(7)
-    for name in ("mom_assemble", "iteration", "p_solve"):
+    for name in ("mom_assemble", "mom_explicit", "iteration", "p_solve"):
         ms, cnt = a.timing_query(name)
         assert cnt == 3 and ms > 0.0, (name, cnt, ms)
     ms, cnt = a.timing_query("mom_sweep")
