@@ -50,7 +50,8 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 #   momentum assembly: u,v,w,p,phi(3),nu_t, the explicit terms (3) (+flags) in,
 #     b(3), a_P out: 121
 #   explicit momentum terms (transpose viscous term; deferred convection
-#     correction under the higher-order schemes): u,v,w,nu_t in, 3 terms out: 56
+#     correction under the higher-order schemes) and the iteration means:
+#     u,v,w,nu_t,p,k in, 3 terms out: 72
 #   omega and k assembly: 2 x 80 -> 80 per launch
 #   pressure operator apply: x, rAU (+flags) in, y out: 25
 #   V-cycle half sweep (one colour): r and D^-1 of that colour (8), rAU (8),
@@ -63,7 +64,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 #   CG vector update: x, d, r, q in, x, r out: 48
 # (reduction finalize launches and the coarse levels of the V-cycle are bound by
 # launch latency, not by bytes: they are timed but have no byte model)
-ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 121.0, "mom_explicit": 56.0,
+ALGO_BYTES = {"scalar_sweep": 36.0, "mom_sweep": 56.0, "mom_assemble": 121.0, "mom_explicit": 72.0,
               "scalar_assemble": 80.0,
               "p_apply": 25.0, "p_smooth": 25.0, "p_presmooth": 41.0, "p_restrict": 22.0, "p_apply_dir": 41.0,
               "p_axpy": 48.0}

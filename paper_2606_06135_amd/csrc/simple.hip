@@ -118,35 +118,6 @@ __global__ void k_interp_flux(Params P, const double* v0, const double* v1, cons
   }
 }
 
-// sums of u, v, w, p, k over all cells (means for the residual normalisation)
-// (each thread adds SUM_PER cells, a block's cells being SUM_PER consecutive
-// runs of NTHREADS, before the block reduction)
-__global__ void k_sums5(Params P, const double* a0, const double* a1, const double* a2, const double* a3,
-                        const double* a4, double* part, long long pstride) {
-  const long long c0 = (long long)blockIdx.x * NTHREADS * SUM_PER + threadIdx.x;
-  double v[5] = {0, 0, 0, 0, 0};
-  // (indices past the end read the last cell and add 0: no branch around the
-  // loads, all of a thread's loads in flight together)
-  double e[SUM_PER][5];
-#pragma unroll
-  for (int r = 0; r < SUM_PER; ++r) {
-    const long long c = c0 + (long long)r * NTHREADS;
-    const long long ci = c < P.N ? c : P.N - 1;
-    e[r][0] = a0[ci];
-    e[r][1] = a1[ci];
-    e[r][2] = a2[ci];
-    e[r][3] = a3[ci];
-    e[r][4] = a4[ci];
-  }
-#pragma unroll
-  for (int r = 0; r < SUM_PER; ++r) {
-    const bool in = c0 + (long long)r * NTHREADS < P.N;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) v[q] = sel(in, v[q] + e[r][q], v[q]);
-  }
-  block_sums_store<5>(v, part, pstride, blockIdx.x);
-}
-
 // ---------------------------------------------------------------- IB-pre
 // boundary cells: u_tau = Cmu^(1/4) sqrt(k_P), y+ = y_eff u_tau / nu (eq. for
 // y+ and u_tau), alpha_u = alpha_k = [y+ <= y+_lam] (eq. for alpha_u), and the
@@ -259,13 +230,15 @@ __device__ __forceinline__ void mom_anb(const Params& P, const Mom& M, double nu
 // (interior faces).  The cell gradients (Gauss, linear face interpolation, at
 // the cell and at its face neighbours) are taken from u here, not stored: the
 // extra u values (edge and second neighbours) come from cache lines the stencil
-// already holds.  Out: ex[cc] = the sum of both terms of component cc.
+// already holds.  Out: ex[cc] = the sum of both terms of component cc, and per
+// workgroup the sums of u, v, w, p, k over its cells (the iteration means).
 template <int CONV, int DIM>
 __global__ void __launch_bounds__(256)
-k_mom_explicit(Params P, Mom M, double* ex0, double* ex1, double* ex2) {
+k_mom_explicit(Params P, Mom M, double* ex0, double* ex1, double* ex2, double* part, long long pstride) {
   int i, j, k;
   tile_ijk(P, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
+  double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (i < P.nx && j < P.ny) {
   const long long c = cidx(P, i, j, k);
   const Nbr N = make_nbr(P, i, j, k, c);
   const bool solid = M.flags[c] & F_SOLID;
@@ -332,6 +305,13 @@ k_mom_explicit(Params P, Mom M, double* ex0, double* ex1, double* ex2) {
   ex0[c] = ex[0];
   ex1[c] = ex[1];
   if (DIM == 3) ex2[c] = ex[2];
+  sums[0] = M.u[0][c];
+  sums[1] = M.u[1][c];
+  sums[2] = M.u[2][c];
+  sums[3] = M.p[c];
+  sums[4] = M.k[c];
+  }
+  block_sums_store<5>(sums, part, pstride, block_linear());
 }
 
 // The same explicit terms on 3-D grids, with the stencil staged through LDS.
@@ -412,7 +392,7 @@ __device__ __forceinline__ double staged_u(const Params& P, const Mom& M, int q,
 }
 template <int CONV>
 __global__ void __launch_bounds__(256)
-k_mom_explicit_z(Params P, Mom M, double* ex0, double* ex1, double* ex2, int exz) {
+k_mom_explicit_z(Params P, Mom M, double* ex0, double* ex1, double* ex2, int exz, double* part, long long pstride) {
   __shared__ double su[3][3][EXH][EXW];        // component, ring slot, y, x
   __shared__ double snu[3][EXH - 2][EXW - 2];  // (face neighbours only: halo of one)
   // workgroup -> (x, y, z-segment), the z-segments of a column contiguous on
@@ -455,6 +435,7 @@ k_mom_explicit_z(Params P, Mom M, double* ex0, double* ex1, double* ex2, int exz
       if (hx >= 1 && hx <= EXW - 2 && hy >= 1 && hy <= EXH - 2) snu[sl][hy - 1][hx - 1] = pf[r].nu;
     }
   };
+  double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // u, v, w, p, k over the workgroup's cells
   fetch(k0 - 1);
   commit(k0 - 1);
   fetch(k0);
@@ -562,9 +543,14 @@ k_mom_explicit_z(Params P, Mom M, double* ex0, double* ex1, double* ex2, int exz
       ex0[c] = ex[0];
       ex1[c] = ex[1];
       ex2[c] = ex[2];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) sums[q] += V(q, 0, 0, 0);
+      sums[3] += M.p[c];
+      sums[4] += M.k[c];
     }
     __syncthreads();
   }
+  block_sums_store<5>(sums, part, pstride, blockIdx.x);
 }
 
 // Assembly of the relaxed momentum rows with the explicit IB source
@@ -1181,7 +1167,7 @@ static MomAssembleFn mom_assemble_kernel(const Params& P) {
   return P.dim == 2 ? k_mom_assemble<2> : k_mom_assemble<3>;
 }
 // the explicit-term pass of the configured convection scheme
-using MomExplicitFn = void (*)(Params, Mom, double*, double*, double*);
+using MomExplicitFn = void (*)(Params, Mom, double*, double*, double*, double*, long long);
 static MomExplicitFn mom_explicit_kernel(const Params& P) {
   if (P.dim == 2) {
     if (P.conv == HFDIB_CONV_LINEAR_UPWIND) return k_mom_explicit<1, 2>;
@@ -1192,7 +1178,9 @@ static MomExplicitFn mom_explicit_kernel(const Params& P) {
   if (P.conv == HFDIB_CONV_VANLEER) return k_mom_explicit<2, 3>;
   return k_mom_explicit<0, 3>;
 }
-static void launch_mom_explicit(hfdib_ctx* c, const Mom& M) {
+// (returns the number of workgroups, whose partial sums of u, v, w, p, k are in
+// c->partials)
+static int launch_mom_explicit(hfdib_ctx* c, const Mom& M) {
   const Params& P = c->P;
   if (P.dim == 3) {
     auto kern = P.conv == HFDIB_CONV_LINEAR_UPWIND ? k_mom_explicit_z<1>
@@ -1204,20 +1192,27 @@ static void launch_mom_explicit(hfdib_ctx* c, const Mom& M) {
     int best = 8;
     long long bcost = -1;
     for (int z = 4; z <= 16; ++z) {
+      // (a partial-sum row holds one entry per workgroup; it is sized for the
+      // finest tile grid, which has at least as many tiles as any z here)
+      if (blocks_explicit_z(P, z) > c->pstride) continue;
       const long long cost = (blocks_explicit_z(P, z) + slots - 1) / slots * (z + 2);
       if (bcost < 0 || cost < bcost) {
         bcost = cost;
         best = z;
       }
     }
+    const int nb = (int)blocks_explicit_z(P, best);
     LaunchEv ev = timer_launch(c, T_MOMEXPL, true, true);
-    launch_ev(kern, dim3((unsigned)blocks_explicit_z(P, best)), dim3(EXTX, EXTY, 1), c->stream, ev, P, M, c->ex[0],
-              c->ex[1], c->ex[2], best);
-    return;
+    launch_ev(kern, dim3((unsigned)nb), dim3(EXTX, EXTY, 1), c->stream, ev, P, M, c->ex[0], c->ex[1], c->ex[2], best,
+              c->partials, c->pstride);
+    return nb;
   }
   const Params PA = deep_tile_params(P);
+  const dim3 g = grid3(PA);
   LaunchEv ev = timer_launch(c, T_MOMEXPL, true, true);
-  launch_ev(mom_explicit_kernel(PA), grid3(PA), block3(PA), c->stream, ev, PA, M, c->ex[0], c->ex[1], c->ex[2]);
+  launch_ev(mom_explicit_kernel(PA), g, block3(PA), c->stream, ev, PA, M, c->ex[0], c->ex[1], c->ex[2], c->partials,
+            c->pstride);
+  return (int)((long long)g.x * g.y * g.z);
 }
 
 // One round of the kernels the tile autotuner times: the explicit-term pass,
@@ -1264,13 +1259,13 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   dim3 g = grid3(P), b = block3(P);
   double* S = c->scal + SCAL_PCG;
   int st;
-  // means of the previous iterate (residual normalisation); opens the timing
-  // span of the iteration
-  LaunchEv ev = timer_launch(c, T_ITER, true, false);
-  const int nbs = nblocks_sum(P.N);
-  launch_ev(k_sums5, dim3(nbs), dim3(NTHREADS), c->stream, ev, P, c->u[0], c->u[1], c->u[2], c->p, c->k, c->partials,
-            c->pstride);
-  launch_finalize(c, nbs, 5, SC_MEANS, 0, (double)P.N);
+  // the explicit momentum terms of the previous iterate, and its means (the
+  // residual normalisation) from the same pass; opens the timing span of the
+  // iteration
+  timer_begin(c, T_ITER);
+  Mom M = make_mom(c);
+  const int nbx = launch_mom_explicit(c, M);
+  launch_finalize(c, nbx, 5, SC_MEANS, 0, (double)P.N);
   // 1. IB-pre
   if (c->n_bc + c->n_wall > 0)
     hipLaunchKernelGGL(k_ib_pre, dim3(nblocks1(c->n_bc + c->n_wall)), dim3(NTHREADS), 0, c->stream, P, c->n_bc,
@@ -1279,12 +1274,10 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
                        c->bc_utau, c->bc_yplus, c->n_wall, c->wall_cells, c->wall_y, c->wall_utau, c->wall_yplus,
                        c->bc_n, c->nut, c->wallD);
   // 2. momentum predictor
-  Mom M = make_mom(c);
-  launch_mom_explicit(c, M);
   bool mixed = P.precision == HFDIB_MIXED;
   MixOut X{{nullptr, nullptr, nullptr}, nullptr, {c->usp[0], c->usp[1], c->usp[2]}};
   if (mixed) X = MixOut{{c->r32[0], c->r32[1], c->r32[2]}, c->a32, {nullptr, nullptr, nullptr}};
-  ev = timer_launch(c, T_MOMASM, true, true);
+  LaunchEv ev = timer_launch(c, T_MOMASM, true, true);
   const Params PA = deep_tile_params(P);
   const dim3 ga = grid3(PA);
   launch_ev(mom_assemble_kernel(P), ga, block3(PA), c->stream, ev, PA, M, X, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,

@@ -206,7 +206,7 @@ __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, cons
 }
 
 
-// (each thread adds SUM_PER cells, as in the sums of the iteration means)
+// (each thread adds SUM_PER cells)
 __global__ void k_sum1(long long n, const double* a, double* part, long long pstride) {
   const long long c0 = (long long)blockIdx.x * NTHREADS * SUM_PER + threadIdx.x;
   double v[1] = {0.0};
