@@ -46,11 +46,26 @@ CASES = {
     "block2d_laminar_vanleer": (lambda: _conv(synth.case_cavity_block(), "vanleer"), 30),
     "naca_64x32_sst_linear_upwind": (lambda: _conv(synth.case_naca(4.0, 64, 32), "linear_upwind"), 30),
     "sphere3d_sst_1sweep": (lambda: _sweeps(synth.case_small_body3d(nx=37, ny=13, nz=11, model="sst", nu=1e-4), 1), 20),
+    # ragged 3-D grid (no dimension a multiple of the explicit-term pass's
+    # 32 x 8 tiles or of its plane chunks) with a solid block on the no-slip floor
+    # and the slip side wall: in-solid cells on domain faces
+    "floorbox3d_sst_ragged": (lambda: _floorbox(synth.case_small_body3d(nx=35, ny=11, nz=7, model="sst", nu=1e-4)),
+                              20),
+    "floorbox3d_sst_linear_upwind": (lambda: _conv(_floorbox(synth.case_small_body3d(nx=35, ny=11, nz=7, model="sst",
+                                                                                        nu=1e-4)), "linear_upwind"),
+                                     20),
     "bfs_keps_3sweeps": (lambda: _sweeps(synth.case_bfs(), 3), 30),
     # a seeded random design field: cut cells of every lambda in (0, 1)
     "bend2d_64x32_keps": (lambda: synth.case_bend2d(64, 32, seed=12356), 40),
     "bend2d_96x48_keps": (lambda: synth.case_bend2d(96, 48), 30),
 }
+
+
+def _floorbox(spec):
+    # a grid-aligned block from the floor (z = 0) and the y = 0 side wall
+    spec.lam = synth.geometry.lambda_from_sdf(synth.geometry.sdf_box((0.4, -0.5, -0.5), (0.7, 0.3, 0.25)), spec)
+    spec.name += "_floorbox"
+    return spec.validate()
 
 
 def _sweeps(spec, n):
