@@ -54,6 +54,12 @@ CASES = {
     "floorbox3d_sst_linear_upwind": (lambda: _conv(_floorbox(synth.case_small_body3d(nx=35, ny=11, nz=7, model="sst",
                                                                                         nu=1e-4)), "linear_upwind"),
                                      20),
+    # four planes (the library's least; one chunk of the pass, ghost planes at
+    # both ends; the block spans the height, so in-solid cells sit on both z
+    # faces), van Leer
+    "floorbox3d_nz4_keps_vanleer": (lambda: _conv(_floorbox(synth.case_small_body3d(nx=35, ny=11, nz=4, model="keps",
+                                                                                       nu=1e-4), ztop=0.5), "vanleer"),
+                                    20),
     "bfs_keps_3sweeps": (lambda: _sweeps(synth.case_bfs(), 3), 30),
     # a seeded random design field: cut cells of every lambda in (0, 1)
     "bend2d_64x32_keps": (lambda: synth.case_bend2d(64, 32, seed=12356), 40),
@@ -61,9 +67,9 @@ CASES = {
 }
 
 
-def _floorbox(spec):
+def _floorbox(spec, ztop=0.25):
     # a grid-aligned block from the floor (z = 0) and the y = 0 side wall
-    spec.lam = synth.geometry.lambda_from_sdf(synth.geometry.sdf_box((0.4, -0.5, -0.5), (0.7, 0.3, 0.25)), spec)
+    spec.lam = synth.geometry.lambda_from_sdf(synth.geometry.sdf_box((0.4, -0.5, -0.5), (0.7, 0.3, ztop)), spec)
     spec.name += "_floorbox"
     return spec.validate()
 
