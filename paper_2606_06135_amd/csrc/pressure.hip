@@ -146,8 +146,12 @@ __global__ void k_fine_apply_dir(Params P, FineOp O, const TZ* z, const double* 
 // r = b - A x (and its FP32 copy when r32 is given); partial sums of r.r, b.b
 // and (for the SIMPLE residual) |r|, |Ax - A xbar|, |b - A xbar| with
 // xbar = *xmean (nullable)
+// (also the inverse diagonal of the fine smoother, colour-split, in FP64
+// (invD64) or FP32 (invD32, with the FP32 mirror of rAU): the row sum the
+// residual forms anyway)
 __global__ void k_fine_residual(Params P, FineOp O, const double* b, const double* x, double* r, float* r32,
-                                const double* xmean, double* part, long long pstride) {
+                                const double* xmean, double* part, long long pstride, double* invD64,
+                                float* invD32, float* rAU32) {
   int i, j, k;
   tile_ijk(P, i, j, k);
   double v[5] = {0, 0, 0, 0, 0};
@@ -164,6 +168,12 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
     double rc = bc - acc;
     r[c] = rc;
     if (r32) r32[c] = (float)rc;
+    const double idg = ident ? 1.0 : 1.0 / dg;
+    if (invD64) invD64[rb_split(P, i, j, k)] = idg;
+    if (invD32) {
+      invD32[rb_split(P, i, j, k)] = (float)idg;
+      rAU32[c] = (float)O.rAU[c];
+    }
     v[0] = rc * rc;
     // |b| of the relative tolerance and the normalised residual: coupled rows only
     // (an identity row's right-hand side is a pressure value, not a source)
@@ -183,24 +193,7 @@ __global__ void k_fine_residual(Params P, FineOp O, const double* b, const doubl
 // Fine-level smoothing.  The V-cycle uses one red-black Gauss-Seidel sweep
 // before (red first, from z = 0) and one after (black first) the coarse
 // correction; the inverse diagonal D^-1 of the fine operator (1 for uncoupled
-// rows) is computed once per pressure solve.
-//
-// Inverse diagonal, colour-split (and, under the mixed policy, the FP32 mirror of rAU).
-template <typename T>
-__global__ void k_fine_invdiag(Params P, FineOp O, T* invD, float* rAU32) {
-  int i, j, k;
-  tile_ijk(P, i, j, k);
-  if (i >= P.nx || j >= P.ny) return;
-  long long c = cidx(P, i, j, k);
-  Nbr N = make_nbr(P, i, j, k, c);
-  double cf[6];
-  fine_row(P, O, N, c, cf);
-  double dg = 0.0;
-#pragma unroll
-  for (int q = 0; q < 6; ++q) dg += cf[q];
-  invD[rb_split(P, i, j, k)] = (T)(dg == 0.0 ? 1.0 : 1.0 / dg);  // colour-split
-  if (rAU32) rAU32[c] = (float)O.rAU[c];
-}
+// rows) is formed once per pressure solve, by the initial residual pass.
 
 // Pre-smoothing sweep in one pass: the red value of a cell is r D^-1 (its
 // neighbours are 0 before the sweep), so each thread takes one red/black pair
@@ -1255,13 +1248,10 @@ PcgSet<float> pcg_set<float>(hfdib_ctx* c, const double* rAU) {
                        c->pr32};
 }
 
-// inverse diagonal of the fine smoother (and, mixed, the FP32 copy of rAU) and
-// the coarse operators from the FP64 fine operator
+// the coarse operators from the FP64 fine operator (the fine smoother's
+// inverse diagonal comes with the initial residual)
 template <typename T>
 static void pcg_operators(hfdib_ctx* c, const PcgSet<T>& A) {
-  const Params& P = c->P;
-  hipLaunchKernelGGL(k_fine_invdiag<T>, grid3(P), block3(P), 0, c->stream, P, A.O, const_cast<T*>(A.invD),
-                     sizeof(T) == sizeof(float) ? c->rAU32 : (float*)nullptr);
   build_levels<T>(c, A.O);
 }
 
@@ -1270,8 +1260,10 @@ template <typename T>
 static void pcg_start(hfdib_ctx* c, const PcgSet<T>& A, const double* rhs, double* x, const double* xmean_dev) {
   const Params& P = c->P;
   dim3 g = grid3(P), b = block3(P);
+  const bool f32 = sizeof(T) == sizeof(float);
   hipLaunchKernelGGL(k_fine_residual, g, b, 0, c->stream, P, A.O, rhs, x, c->pr, A.r32, xmean_dev, c->partials,
-                     c->pstride);
+                     c->pstride, f32 ? (double*)nullptr : (double*)A.invD, f32 ? (float*)A.invD : (float*)nullptr,
+                     f32 ? c->rAU32 : (float*)nullptr);
   // [20] = rr0, [21] = bb, [22..24] = residual sums
   launch_finalize(c, (int)((long long)g.x * g.y * g.z), 5, S_BB + 16, 0);
   launch_finalize(c, vcycle<T>(c, A.OM, A.invD, A.r_m, A.z_m, c->pr, c->pd), 1, S_RZ, 3);  // d = z
