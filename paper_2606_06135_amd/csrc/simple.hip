@@ -324,7 +324,8 @@ k_mom_explicit(Params P, Mom M, double* ex0, double* ex1, double* ex2, double* p
 // plane re-reads at the column ends) and the stencil reads are LDS reads at
 // fixed offsets; the values two planes away (d/dz of the z-neighbours'
 // gradients) are loaded per cell.  The host chooses exz so that the workgroups
-// fill the chip in few rounds.
+// fill the chip in few rounds.  Each workgroup also sums u, v, w, p and k over
+// its cells (the iteration means).
 // Domain faces cost no branches or selects in the gradients: a position one
 // cell beyond a domain face (and inside the domain along the other axes) is
 // staged as the ghost value 2 u_f - u_X of the face value u_f that the Gauss
@@ -337,10 +338,11 @@ constexpr int EXTX = 32, EXTY = 8, EXW = EXTX + 4, EXH = EXTY + 4;
 inline long long blocks_explicit_z(const Params& P, int exz) {
   return (long long)((P.nx + EXTX - 1) / EXTX) * ((P.ny + EXTY - 1) / EXTY) * ((P.nz + exz - 1) / exz);
 }
-// u_q at global position (gi, gj, gk) as staged: the value itself inside the
-// domain; one cell beyond exactly one domain face the ghost 2 u_f - u of its
+// u, v, w and nu_t at a position as staged: the values themselves inside the
+// domain; one cell beyond exactly one domain face the ghost 2 u_f - u of the
 // inner neighbour (face value u_bface, the inner cell's in-solid bit); any
-// other outside position the nearest cell's value
+// other outside position, and nu_t at every outside position, the nearest
+// cell's values
 struct Staged {
   double u[3], nu;
 };
