@@ -274,7 +274,7 @@ static size_t layout(hfdib_ctx* c, char* base) {
     // FP32 defects and relaxed diagonals, colour-split like their FP64 counterparts
     const long long n32 = 2 * P.nrb > N ? 2 * P.nrb : N;
     for (int q = 0; q < 3; ++q) c->r32[q] = B.take<float>(n32);
-    for (int q = 0; q < 3; ++q) c->d32[q] = B.take<float>(N);
+    for (int q = 0; q < 3; ++q) c->d32[q] = B.take<float>(n32);  // (colour-split)
     c->a32 = B.take<float>(n32);
     c->gam32 = B.take<float>(N);
     c->phi32[0] = B.take<float>((long long)(P.nx + 1) * P.ny * P.nz);

@@ -127,7 +127,7 @@ struct hfdib_ctx {
   // corrections of the stencil solves, mirrors of the sweep coefficients
   // (relaxed diagonal, face fluxes, nu_t, SST blending), pressure smoother
   // inputs (rAU) and the preconditioner residual / output
-  float *r32[3], *d32[3], *a32, *phi32[3], *nut32;
+  float *r32[3], *d32[3], *a32, *phi32[3], *nut32;  // (r32, d32, a32 colour-split)
   float *rAU32, *pr32, *pz32, *invD32;
   float *pzs32, *prs32;  // colour-split z and r of the V-cycle's fine level (mixed policy)
   float* gam32;  // FP32 diffusivity of the scalar being solved (mixed policy)

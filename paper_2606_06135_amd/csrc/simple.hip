@@ -778,15 +778,17 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
     // the partner cell of the other colour in this pair starts from d = 0
     int io = i ^ 1;
     if (io < P.nx) {
-      long long co = cidx(P, io, j, k);
-      d0[co] = 0.0f;
-      d1[co] = 0.0f;
-      if (three) d2[co] = 0.0f;
+      const long long so = rb_split(P, io, j, k);
+      d0[so] = 0.0f;
+      d1[so] = 0.0f;
+      if (three) d2[so] = 0.0f;
     }
   }
   if (i >= P.nx) return;
   long long c = cidx(P, i, j, k);
-  const long long sidx = rb_split(P, i, j, k);  // defects and diagonal are colour-split
+  // defects, diagonal and the corrections d are colour-split (a one-colour pass
+  // reads only the other colour's half of d)
+  const long long sidx = rb_split(P, i, j, k);
   // loads first (clamped neighbours, selects), stores last
   const float a = a32[sidx], b0 = r0[sidx], b1 = r1[sidx], b2 = r2[sidx];
   float n0 = 0.0f, n1 = 0.0f, n2 = 0.0f;
@@ -800,11 +802,12 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
       const int d = q >> 1, s = (q & 1) ? 1 : -1;
       const long long n = N.n[q];
       const long long f = fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0);
+      const long long ns = nb_split(P, N, i, j, k, q);
       nun[q] = M.nut[n];
       fo[q] = M.phi[d][f];
-      z0[q] = d0[n];
-      z1[q] = d1[n];
-      z2[q] = d2[n];
+      z0[q] = d0[ns];
+      z1[q] = d1[ns];
+      z2[q] = d2[ns];
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -824,14 +827,14 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
     uo[1] = u1[c];
     if (three) uo[2] = u2[c];
   }
-  d0[c] = e0;
-  d1[c] = e1;
+  d0[sidx] = e0;
+  d1[sidx] = e1;
   if (fin) {
     u0[c] = uo[0] + (double)e0;
     u1[c] = uo[1] + (double)e1;
   }
   if (three) {
-    d2[c] = e2;
+    d2[sidx] = e2;
     if (fin) u2[c] = uo[2] + (double)e2;
   }
 }

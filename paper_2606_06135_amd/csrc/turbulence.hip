@@ -477,11 +477,11 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, const
   if (init) {
     // the partner cell of the other colour in this pair starts from d = 0
     int io = i ^ 1;
-    if (io < P.nx) dv[cidx(P, io, j, k)] = 0.0f;
+    if (io < P.nx) dv[rb_split(P, io, j, k)] = 0.0f;
   }
   if (i >= P.nx) return;
   long long c = cidx(P, i, j, k);
-  const long long sidx = rb_split(P, i, j, k);
+  const long long sidx = rb_split(P, i, j, k);  // (d colour-split, like r and a)
   // loads first (clamped neighbours, selects), stores last
   const bool fixed = flags[c] & fixmask;
   const float rs = r[sidx], as = a32[sidx];
@@ -496,7 +496,7 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, const
       const long long n = N.n[q];
       gn[q] = gamc[n];
       fo[q] = S.phi[d][fidx(P, d, i, j, k) + (s > 0 ? stride(P, d) : 0)];
-      zn[q] = dv[n];
+      zn[q] = dv[nb_split(P, N, i, j, k, q)];
     }
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
@@ -507,12 +507,12 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, const
     }
   }
   if (fixed) {
-    if (init) dv[c] = 0.0f;
+    if (init) dv[sidx] = 0.0f;
     return;
   }
   const float e = (rs + nb) / as;
   const double xo = fin ? x[c] : 0.0;
-  dv[c] = e;
+  dv[sidx] = e;
   if (fin) x[c] = xo + (double)e;
 }
 
