@@ -160,14 +160,45 @@ k_turb_inputs(Params P, const uint8_t* flags, Vel U, const double* kv, const dou
 // walls) over the wall distance y: (|u_t,P - u_s,t| / y)^2 (the wall-face normal
 // gradient of the wall-function form of eq. omegaws; under the log law it makes
 // P_ib the equilibrium production u_tau^3 / (kappa y)).
+// k_ib of boundary cell c (list entry b): quadratic along n_P with the
+// wall-function surface value k_S = k_vis(y+) u_tau^2 and free-stream values of
+// k_old; 0 on cells off the viscous branch
+struct KibIn {
+  const uint8_t* flags;
+  const double* L;
+  const int* st1;
+  const double* w1;
+  const int* st2;
+  const double* w2;
+  double* kib;
+};
+__device__ __forceinline__ void k_ib_value(const Params& P, const KibIn& K, int b, int c, double yp, double ut,
+                                           const double* kold) {
+  if (!(K.flags[c] & F_ALPHA_U)) {
+    K.kib[c] = 0.0;
+    return;
+  }
+  double cc = P.C_wf;
+  double t = yp + cc;
+  double cf = 1.0 / (t * t) + 2.0 * yp / (cc * cc * cc) - 1.0 / (cc * cc);
+  double kvis = 2400.0 * cf / (P.Ceps2_wf * P.Ceps2_wf);
+  double kS = kvis * (ut * ut);
+  double v1 = 0.0, v2 = 0.0;
+  for (int q = 0; q < 8; ++q) v1 += K.w1[8 * b + q] * kold[K.st1[8 * b + q]];
+  for (int q = 0; q < 8; ++q) v2 += K.w2[8 * b + q] * kold[K.st2[8 * b + q]];
+  K.kib[c] = K.L[3 * b] * kS + K.L[3 * b + 1] * v1 + K.L[3 * b + 2] * v2;
+}
+
 struct Vel3 {
   const double* u[3];
   const double* us[3];
 };
 
+// (and k_ib of the boundary cells: it needs k_old and the boundary cells' y+
+// and u_tau, all in place here)
 __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, const int* ic_cells, const double* wmax,
                                Vel3 V, const double* S2, const double* kold, const double* nut, double* Pk,
-                               double* wib, double* w) {
+                               double* wib, double* w, KibIn K) {
   int b = blockIdx.x * NTHREADS + threadIdx.x;
   if (b >= L0.n + L1.n + nic) return;
   if (b >= L0.n + L1.n) {
@@ -183,6 +214,7 @@ __global__ void k_turb_imposed(Params P, WallList L0, WallList L1, int nic, cons
   if (!first) b -= L0.n;
   int c = L.cells[b];
   double yp = L.ypl[b], ut = L.utl[b], y = L.y[b];
+  if (first) k_ib_value(P, K, b, c, yp, ut, kold);
   double om = omega_ib(P, yp, y, ut);
   double kk = kold[c];
   double val = (P.model == HFDIB_KEPS || P.model == HFDIB_RKEPS) ? P.Cmu * kk * om : om;
@@ -516,30 +548,6 @@ __global__ void k_scalar_sweep32(Params P, Scal32 S, const uint8_t* flags, const
   if (fin) x[c] = xo + (double)e;
 }
 
-// k_ib on boundary cells: quadratic along n_P with the wall-function surface
-// value k_S = k_vis(y+) u_tau^2 and free-stream values of k_old; 0 elsewhere
-__global__ void k_kib(Params P, int nbc, const int* bc_cells, const uint8_t* flags, const double* bc_L,
-                      const int* st1, const double* w1, const int* st2, const double* w2, const double* ypl,
-                      const double* utl, const double* kold, double* kib) {
-  int b = blockIdx.x * NTHREADS + threadIdx.x;
-  if (b >= nbc) return;
-  int c = bc_cells[b];
-  if (!(flags[c] & F_ALPHA_U)) {
-    kib[c] = 0.0;
-    return;
-  }
-  double yp = ypl[b], ut = utl[b];
-  double cc = P.C_wf;
-  double t = yp + cc;
-  double cf = 1.0 / (t * t) + 2.0 * yp / (cc * cc * cc) - 1.0 / (cc * cc);
-  double kvis = 2400.0 * cf / (P.Ceps2_wf * P.Ceps2_wf);
-  double kS = kvis * (ut * ut);
-  double v1 = 0.0, v2 = 0.0;
-  for (int q = 0; q < 8; ++q) v1 += w1[8 * b + q] * kold[st1[8 * b + q]];
-  for (int q = 0; q < 8; ++q) v2 += w2[8 * b + q] * kold[st2[8 * b + q]];
-  kib[c] = bc_L[3 * b] * kS + bc_L[3 * b + 1] * v1 + bc_L[3 * b + 2] * v2;
-}
-
 // k <- k + alpha_k (k_ib - k), bounding, turbulent viscosity of the model
 // (in-solid cells 0); eps/omega is already bounded
 __global__ void k_turb_final(Params P, const uint8_t* flags, const double* S2, Vel U, const double* kib, double* k,
@@ -646,7 +654,8 @@ int turbulence_stage(hfdib_ctx* c) {
     if (ntot > 0)
       hipLaunchKernelGGL(k_turb_imposed, dim3(nblocks1(ntot)), dim3(NTHREADS), 0, c->stream, P, L0, L1, c->n_ic,
                          c->ic_cells, wmax, Vel3{{c->u[0], c->u[1], c->u[2]}, {c->us[0], c->us[1], c->us[2]}},
-                         c->S2, c->k, c->nut, c->Pk, c->wib, c->w);
+                         c->S2, c->k, c->nut, c->Pk, c->wib, c->w,
+                         KibIn{c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->kib});
   }
   const int nbs = nblocks_sum(P.N);
   hipLaunchKernelGGL(k_sum1, dim3(nbs), dim3(NTHREADS), 0, c->stream, P.N, c->w, c->partials, c->pstride);
@@ -695,11 +704,8 @@ int turbulence_stage(hfdib_ctx* c) {
             mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride, c->xsp);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
   sweeps(0, c->w, (uint8_t)F_ALPHA_W);
-  // k_ib, then the k equation with S_ib (bounds omega/eps on the way)
-  if (c->n_bc > 0)
-    hipLaunchKernelGGL(k_kib, dim3(nblocks1(c->n_bc)), dim3(NTHREADS), 0, c->stream, P, c->n_bc, c->bc_cells,
-                       c->flags, c->bc_L, c->bc_s1, c->bc_w1, c->bc_s2, c->bc_w2, c->bc_yplus, c->bc_utau, c->k,
-                       c->kib);
+  // the k equation with S_ib (k_ib came with the imposed values; bounds
+  // omega/eps on the way)
   ev = timer_launch(c, T_SCALASM, true, true);
   launch_ev(assemble, g, b, c->stream, ev, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
             mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride, c->xsp);
