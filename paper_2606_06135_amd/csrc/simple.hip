@@ -1261,7 +1261,7 @@ int refresh_mirrors(hfdib_ctx* c) {
 int simple_step(hfdib_ctx* c, int it, double* res_host) {
   (void)it;
   const Params& P = c->P;
-  dim3 g = grid3(P), b = block3(P);
+  const dim3 b = block3(P);
   double* S = c->scal + SCAL_PCG;
   int st;
   // the explicit momentum terms of the previous iterate, and its means (the
@@ -1313,7 +1313,12 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
     hipLaunchKernelGGL(k_hbya, grid3(PH), block3(PH), 0, c->stream, PH, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
                        c->hbya[0], c->hbya[1], c->hbya[2], c->rAU);
   }
-  hipLaunchKernelGGL(k_flux_rhs, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->lam, c->flags,
+  // the flux predictor, the flux correction and the velocity update on the
+  // z-first tiles too (planes of at most 32768 cells, as HbyA): 48 -> 43 us
+  // for the correction at 2.36 M cells
+  const Params PF = deep_tile_params(P, true);
+  const dim3 gf = grid3(PF), bf = block3(PF);
+  hipLaunchKernelGGL(k_flux_rhs, gf, bf, 0, c->stream, PF, c->hbya[0], c->hbya[1], c->hbya[2], c->lam, c->flags,
                      c->p, c->phi[0], c->phi[1], c->phi[2], c->rhs_p, c->px);
   HFDIB_CHECK_LAUNCH(c, "momentum stage");
   int iters = 0;
@@ -1326,9 +1331,9 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
   // 5. flux and velocity update
   Phi32Out m32{{nullptr, nullptr, nullptr}};
   if (mixed) m32 = Phi32Out{{c->phi32[0], c->phi32[1], c->phi32[2]}};
-  hipLaunchKernelGGL(k_flux_correct, g, b, 0, c->stream, P, c->rAU, c->px, c->p, c->flags, c->phi[0], c->phi[1],
+  hipLaunchKernelGGL(k_flux_correct, gf, bf, 0, c->stream, PF, c->rAU, c->px, c->p, c->flags, c->phi[0], c->phi[1],
                      c->phi[2], c->pnew, m32);
-  hipLaunchKernelGGL(k_vel_update, g, b, 0, c->stream, P, c->hbya[0], c->hbya[1], c->hbya[2], c->aPr, c->pnew,
+  hipLaunchKernelGGL(k_vel_update, gf, bf, 0, c->stream, PF, c->hbya[0], c->hbya[1], c->hbya[2], c->aPr, c->pnew,
                      c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1], c->u[2], c->p);
   double* tmp = c->p;
   c->p = c->pnew;

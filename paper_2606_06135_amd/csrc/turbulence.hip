@@ -87,14 +87,26 @@ struct WallList {
   const double* utl;
 };
 
+// diffusion coefficient of the transported scalar (0: omega/eps, 1: k) from
+// nu_t and, under SST, the blending F1 of the cell
+__device__ __forceinline__ double gam_of(const Params& P, int eq, double nut, double f) {
+  if (P.model == HFDIB_KEPS) return P.nu + nut * (eq == 0 ? P.isig_eps : P.isig_k);
+  if (P.model == HFDIB_KOMEGA) return P.nu + nut * (eq == 0 ? P.isig_w_kw : P.isig_k_kw);
+  if (P.model == HFDIB_RKEPS) return P.nu + nut * (eq == 0 ? P.isig_eps_rke : P.isig_k_rke);
+  const double sg = eq == 0 ? f * P.sigma_w1 + (1.0 - f) * P.sigma_w2 : f * P.sigma_k1 + (1.0 - f) * P.sigma_k2;
+  return P.nu + sg * nut;
+}
+
 // Turbulence inputs of the previous iterate, taken before this stage changes
 // any k or omega/eps value: 2 S:S of the current velocity (Gauss gradient, the
 // production term), the SST blending F1 and grad k . grad omega (the
-// cross-diffusion term), and per block the maximum of omega/eps over the cells
-// outside the in-solid group (the value imposed on in-solid cells)
+// cross-diffusion term), the diffusivities of the omega/eps and k equations
+// (nu_t and F1 do not change before both are assembled), and per block the
+// maximum of omega/eps over the cells outside the in-solid group (the value
+// imposed on in-solid cells)
 __global__ void __launch_bounds__(256)
-k_turb_inputs(Params P, const uint8_t* flags, Vel U, const double* kv, const double* wv, const double* dw, double* S2,
-              double* F1, double* kwo, double* part) {
+k_turb_inputs(Params P, const uint8_t* flags, Vel U, const double* kv, const double* wv, const double* dw,
+              const double* nut, double* S2, double* F1, double* kwo, double* gam_w, double* gam_k, double* part) {
   double wmx = 0.0;
   int i, j, k;
   tile_ijk(P, i, j, k);
@@ -104,7 +116,8 @@ k_turb_inputs(Params P, const uint8_t* flags, Vel U, const double* kv, const dou
     // loads first (clamped neighbours along all three axes; the terms beyond dim
     // are dropped by selects)
     const uint8_t fl = flags[c];
-    const double kk = kv[c], ww = wv[c];
+    const double kk = kv[c], ww = wv[c], nt = nut[c];
+    double f1 = 0.0;
     double s2;
     {
       double G[3][3];
@@ -138,10 +151,13 @@ k_turb_inputs(Params P, const uint8_t* flags, Vel U, const double* kv, const dou
       const double m2 = 4.0 * P.sigma_w2 * kk / (cd * dwc * dwc);
       const double arg1 = m1 < m2 ? m1 : m2;
       const double a2 = arg1 * arg1;
-      F1[c] = tanh(a2 * a2);
+      f1 = tanh(a2 * a2);
+      F1[c] = f1;
       kwo[c] = kw;
     }
     S2[c] = s2;
+    gam_w[c] = gam_of(P, 0, nt, f1);
+    gam_k[c] = gam_of(P, 1, nt, f1);
     wmx = (fl & F_IC) ? 0.0 : ww;
   }
   __shared__ double lmax[4];
@@ -253,15 +269,6 @@ __global__ void k_sum1(long long n, const double* a, double* part, long long pst
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
-// diffusion coefficient of the transported scalar (0: omega/eps, 1: k)
-__device__ __forceinline__ double gam(const Params& P, int eq, long long c, const double* nut, const double* F1) {
-  if (P.model == HFDIB_KEPS) return P.nu + nut[c] * (eq == 0 ? P.isig_eps : P.isig_k);
-  if (P.model == HFDIB_KOMEGA) return P.nu + nut[c] * (eq == 0 ? P.isig_w_kw : P.isig_k_kw);
-  if (P.model == HFDIB_RKEPS) return P.nu + nut[c] * (eq == 0 ? P.isig_eps_rke : P.isig_k_rke);
-  double f = F1[c];
-  double sg = eq == 0 ? f * P.sigma_w1 + (1.0 - f) * P.sigma_w2 : f * P.sigma_k1 + (1.0 - f) * P.sigma_k2;
-  return P.nu + sg * nut[c];
-}
 
 struct Scal {
   const double* phi[3];
@@ -279,9 +286,10 @@ struct Scal {
 };
 
 // neighbour coefficients of a scalar row (faces W, E, S, N, B, T; 0 on domain
-// faces and beyond dim), loads from clamped indices
-__device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq, double gP, const Nbr& N, int i, int j,
-                                         int k, double (&anb)[6]) {
+// faces and beyond dim) from the stored diffusivities gam, loads from clamped
+// indices
+__device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, double gP, const double* gam, const Nbr& N,
+                                         int i, int j, int k, double (&anb)[6]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -289,7 +297,7 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
       const int s = sh ? 1 : -1, q = 2 * d + sh;
       // loads from clamped indices for every face, chosen with selects
       const double mf = -outward_flux(P, S.phi, d, s, i, j, k);
-      const double a = 0.5 * (gP + gam(P, eq, N.n[q], S.nut, S.F1)) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
+      const double a = 0.5 * (gP + gam[N.n[q]]) * P.AoD[d] + (mf > 0.0 ? mf : 0.0);
       anb[q] = sel(d < P.dim && !is_bnd(N, q), a, 0.0);
     }
 }
@@ -298,9 +306,11 @@ __device__ __forceinline__ void scal_anb(const Params& P, const Scal& S, int eq,
 // relaxed diagonal -> aPr_out; residual sums of the solved rows
 // (RKE: the realizable k-epsilon eps sources, instantiated separately so the
 // other closures keep their register budget)
+// gam: the equation's diffusivity per cell, stored by the stage's first pass
+// (mixed policy: copied to gam_out32 for the FP32 sweeps)
 template <bool RKE>
 __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, double* aPr_out, float* r32, float* a32,
-                                  double* gam_out, float* gam_out32, const double* xmean, double* part,
+                                  const double* gam, float* gam_out32, const double* xmean, double* part,
                                   long long pstride, double* xs_out) {
   int i, j, k;
   tile_ijk(P, i, j, k);
@@ -309,12 +319,11 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
     long long c = cidx(P, i, j, k);
     uint8_t fl = S.flags[c];
     bool solid = fl & F_SOLID;
-    double gP = gam(P, eq, c, S.nut, S.F1);
-    if (gam_out) gam_out[c] = gP;
+    const double gP = gam[c];
     if (gam_out32) gam_out32[c] = (float)gP;
     Nbr N = make_nbr(P, i, j, k, c);
     double anb[6];
-    scal_anb(P, S, eq, gP, N, i, j, k, anb);
+    scal_anb(P, S, gP, gam, N, i, j, k, anb);
     double aP = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; ++q) aP += anb[q];
@@ -439,7 +448,7 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 // red-black Gauss-Seidel half sweep of a scalar equation; rows flagged `fixmask`
 // are not updated
 // (FP64) the diffusivity of each cell comes from the array the assembly wrote
-// (the same value gam() gives), rhs and a'_P from the colour-split arrays, so a
+// (the stage's first pass stored it), rhs and a'_P from the colour-split arrays, so a
 // one-colour launch streams only its own half of them
 // The sweeps work on the colour-split copy xs of x that the assembly wrote (a
 // one-colour pass reads only the other colour's half and writes only its
@@ -643,8 +652,14 @@ int turbulence_stage(hfdib_ctx* c) {
   const Vel U{{c->u[0], c->u[1], c->u[2]}};
   // SST blending and cross diffusion of the previous iterate, maximum of
   // omega/eps over cells outside the in-solid group
+  // per-cell diffusivities of the omega/eps and the k equations, stored by the
+  // first pass for both assemblies and the FP64 sweeps (the momentum
+  // right-hand sides are dead during this stage)
+  double* gam_w = c->rhs[0];
+  double* gam_k = c->rhs[1];
   hipLaunchKernelGGL(k_turb_inputs, g, b, 0, c->stream, P, (const uint8_t*)c->flags, U, (const double*)c->k,
-                     (const double*)c->w, (const double*)c->dw, c->S2, c->F1, c->t2, c->partials);
+                     (const double*)c->w, (const double*)c->dw, (const double*)c->nut, c->S2, c->F1, c->t2, gam_w,
+                     gam_k, c->partials);
   launch_finalize(c, (int)nblk3, 1, SC_WMAX, 4);
   // imposed omega/eps and production on boundary, wall and in-solid cells
   {
@@ -679,12 +694,9 @@ int turbulence_stage(hfdib_ctx* c) {
   float* r32 = mixed ? c->r32[0] : nullptr;
   float* a32 = mixed ? c->a32 : nullptr;
   Scal32 S32{{c->phi32[0], c->phi32[1], c->phi32[2]}};
-  // per-cell diffusivity of the equation being solved (FP64 sweeps; the
-  // momentum right-hand sides are dead during this stage)
-  double* gam_c = c->rhs[0];
   // n_s red-black sweeps of equation eq (FP64, or the FP32 correction)
   // (one timing span over the 2 n_s consecutive launches)
-  auto sweeps = [&](int eq, double* x, uint8_t fixmask) {
+  auto sweeps = [&](const double* gam_c, double* x, uint8_t fixmask) {
     for (int s = 0; s < P.n_sweeps; ++s)
       for (int color = 0; color < 2; ++color) {
         const bool first = s == 0 && color == 0, last = s == P.n_sweeps - 1 && color == 1;
@@ -700,17 +712,17 @@ int turbulence_stage(hfdib_ctx* c) {
   // omega / eps equation, alpha_omega rows fixed
   auto assemble = P.model == HFDIB_RKEPS ? k_scalar_assemble<true> : k_scalar_assemble<false>;
   LaunchEv ev = timer_launch(c, T_SCALASM, true, true);
-  launch_ev(assemble, g, b, c->stream, ev, P, Sc, 0, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
+  launch_ev(assemble, g, b, c->stream, ev, P, Sc, 0, c->t0, c->t1, r32, a32, (const double*)gam_w,
             mixed ? c->gam32 : nullptr, S + SC_MEANS + 5, c->partials, c->pstride, c->xsp);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 9, 0);
-  sweeps(0, c->w, (uint8_t)F_ALPHA_W);
+  sweeps(gam_w, c->w, (uint8_t)F_ALPHA_W);
   // the k equation with S_ib (k_ib came with the imposed values; bounds
   // omega/eps on the way)
   ev = timer_launch(c, T_SCALASM, true, true);
-  launch_ev(assemble, g, b, c->stream, ev, P, Sc, 1, c->t0, c->t1, r32, a32, mixed ? nullptr : gam_c,
+  launch_ev(assemble, g, b, c->stream, ev, P, Sc, 1, c->t0, c->t1, r32, a32, (const double*)gam_k,
             mixed ? c->gam32 : nullptr, S + SC_MEANS + 4, c->partials, c->pstride, c->xsp);
   launch_finalize(c, (int)nblk3, 3, SC_RESSUM + 12, 0);
-  sweeps(1, c->k, (uint8_t)0);
+  sweeps(gam_k, c->k, (uint8_t)0);
   hipLaunchKernelGGL(k_turb_final, g, b, 0, c->stream, P, c->flags, c->S2, U, c->kib, c->k, c->w,
                      c->dw, c->nut, mixed ? c->nut32 : nullptr);
   if (c->n_bc > 0) {
