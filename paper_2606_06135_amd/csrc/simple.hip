@@ -698,12 +698,19 @@ k_mom_assemble(Params P, Mom M, MixOut X, double* rhs0, double* rhs1, double* rh
   block_sums_store<9>(red, part, pstride, block_linear());
 }
 
+// u <- u + alpha_u (u_ib - u) (alpha_u = 1) on a forced cell, the value v
+// unchanged on the others; u_ib is read on forced cells only
+__device__ __forceinline__ double ib_correct(bool forced, double v, const double* uib, long long c) {
+  return forced ? v + 1.0 * (uib[c] - v) : v;
+}
+
 // one colour of a red-black Gauss-Seidel sweep over the three components, on
 // the colour-split copy s of u that the assembly wrote (a one-colour pass reads
 // only the other colour's half and writes only its own).  fin: the last half
 // sweep (black), which writes u in the natural order instead, for both cells of
 // its pair (the red partner is a face neighbour, its final value already
-// loaded); the split copy is dead after it.
+// loaded), with u <- u + alpha_u (u_ib - u) on the forced cells; the split copy
+// is dead after it.
 __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* rhs1, const double* rhs2,
                             const double* aPr, double* s0, double* s1, double* s2, double* u0, double* u1, double* u2,
                             int color, int fin) {
@@ -717,9 +724,10 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
     if (fin && io < P.nx) {
       const long long co = cidx(P, io, j, k), so = rb_split(P, io, j, k);
       const double* sv[3] = {s0, s1, s2};
+      const bool forced = M.flags[co] & F_ALPHA_U;
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc)
-        if (cc < P.dim) uo[cc][co] = sv[cc][so];
+        if (cc < P.dim) uo[cc][co] = ib_correct(forced, sv[cc][so], M.uib[cc], co);
     }
     return;
   }
@@ -752,11 +760,12 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
     const int io = i ^ 1;
     const bool partner = io < P.nx, west = i & 1;
     const long long co = cidx(P, io < P.nx ? io : i, j, k);
+    const bool fc = M.flags[c] & F_ALPHA_U, fp = M.flags[co] & F_ALPHA_U;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
       if (cc >= P.dim) continue;
-      uo[cc][c] = v[cc];
-      if (partner) uo[cc][co] = sel(west, un[cc][0], un[cc][1]);
+      uo[cc][c] = ib_correct(fc, v[cc], M.uib[cc], c);
+      if (partner) uo[cc][co] = ib_correct(fp, sel(west, un[cc][0], un[cc][1]), M.uib[cc], co);
     }
   }
 }
@@ -765,11 +774,11 @@ __global__ void k_mom_sweep(Params P, Mom M, const double* rhs0, const double* r
 // correction d (A d = r, r the FP64 defect of the assembled rows, d = 0 before
 // the first sweep), coefficients from the FP32 mirrors.  init: first sweep
 // (cells of the other colour set to 0); fin: last sweep of this colour, which
-// also writes u <- u_old + d in FP64.  Equal to the FP64 sweeps from u_old in
-// exact arithmetic.
+// also writes u <- u_old + d in FP64, then u <- u + alpha_u (u_ib - u) on the
+// forced cells.  Equal to the FP64 sweeps from u_old in exact arithmetic.
 __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r1, const float* r2, const float* a32,
                               float* d0, float* d1, float* d2, double* u0, double* u1, double* u2, int color, int init,
-                              int fin) {
+                              int fin, const uint8_t* flags, const double* ub0, const double* ub1, const double* ub2) {
   int i, j, k;
   tile_ijk_rb(P, color, i, j, k);
   if (j >= P.ny) return;
@@ -822,37 +831,23 @@ __global__ void k_mom_sweep32(Params P, Mir32 M, const float* r0, const float* r
   }
   const float e0 = (b0 + n0) / a, e1 = (b1 + n1) / a, e2 = (b2 + n2) / a;
   double uo[3] = {0.0, 0.0, 0.0};
+  bool forced = false;
   if (fin) {
     uo[0] = u0[c];
     uo[1] = u1[c];
     if (three) uo[2] = u2[c];
+    forced = flags[c] & F_ALPHA_U;
   }
   d0[sidx] = e0;
   d1[sidx] = e1;
   if (fin) {
-    u0[c] = uo[0] + (double)e0;
-    u1[c] = uo[1] + (double)e1;
+    u0[c] = ib_correct(forced, uo[0] + (double)e0, ub0, c);
+    u1[c] = ib_correct(forced, uo[1] + (double)e1, ub1, c);
   }
   if (three) {
     d2[sidx] = e2;
-    if (fin) u2[c] = uo[2] + (double)e2;
+    if (fin) u2[c] = ib_correct(forced, uo[2] + (double)e2, ub2, c);
   }
-}
-
-// u <- u + alpha_u (u_ib - u) on forced cells (list kernels: boundary cells with
-// alpha_u, and every in-solid cell)
-// u <- u + alpha_u (u_ib - u) on the forced cells of two lists (boundary cells,
-// then in-solid cells) in one launch
-__global__ void k_correct_list(Params P, int n1, const int* cells1, int n2, const int* cells2, const uint8_t* flags,
-                               const double* ub0, const double* ub1, const double* ub2, double* u0, double* u1,
-                               double* u2) {
-  int b = blockIdx.x * NTHREADS + threadIdx.x;
-  if (b >= n1 + n2) return;
-  int c = b < n1 ? cells1[b] : cells2[b - n1];
-  if (!(flags[c] & F_ALPHA_U)) return;
-  u0[c] = u0[c] + 1.0 * (ub0[c] - u0[c]);
-  u1[c] = u1[c] + 1.0 * (ub1[c] - u1[c]);
-  if (P.dim == 3) u2[c] = u2[c] + 1.0 * (ub2[c] - u2[c]);
 }
 
 // HbyA = (sum a_nb u_nb + rhs + V grad p_old) / a'_P and rAU = V / a'_P
@@ -1297,16 +1292,13 @@ int simple_step(hfdib_ctx* c, int it, double* res_host) {
       if (mixed)
         launch_ev(k_mom_sweep32, grid3_rb(P), b, c->stream, ev, P, M32, c->r32[0], c->r32[1], c->r32[2], c->a32,
                   c->d32[0], c->d32[1], c->d32[2], c->u[0], c->u[1], c->u[2], color, first ? 1 : 0,
-                  s == P.n_sweeps - 1 ? 1 : 0);
+                  s == P.n_sweeps - 1 ? 1 : 0, (const uint8_t*)c->flags, (const double*)c->uib[0],
+                  (const double*)c->uib[1], (const double*)c->uib[2]);
       else
         launch_ev(k_mom_sweep, grid3_rb(P), b, c->stream, ev, P, M, c->rhs[0], c->rhs[1], c->rhs[2], c->aPr,
                   c->usp[0], c->usp[1], c->usp[2], c->u[0], c->u[1], c->u[2], color, last ? 1 : 0);
     }
-  // 3. u <- u + alpha_u (u_ib - u)
-  if (c->n_bc + c->n_ic > 0)
-    hipLaunchKernelGGL(k_correct_list, dim3(nblocks1(c->n_bc + c->n_ic)), dim3(NTHREADS), 0, c->stream, P, c->n_bc,
-                       c->bc_cells, c->n_ic, c->ic_cells, c->flags, c->uib[0], c->uib[1], c->uib[2], c->u[0], c->u[1],
-                       c->u[2]);
+  // 3. u <- u + alpha_u (u_ib - u): done by the last half sweep
   // 4. pressure corrector
   {
     const Params PH = deep_tile_params(P, true);

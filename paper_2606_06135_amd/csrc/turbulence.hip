@@ -447,9 +447,9 @@ __global__ void k_scalar_assemble(Params P, Scal S, int eq, double* rhs_out, dou
 
 // red-black Gauss-Seidel half sweep of a scalar equation; rows flagged `fixmask`
 // are not updated
-// (FP64) the diffusivity of each cell comes from the array the assembly wrote
-// (the stage's first pass stored it), rhs and a'_P from the colour-split arrays, so a
-// one-colour launch streams only its own half of them
+// (FP64) the diffusivity of each cell comes from the array the stage's first
+// pass stored, rhs and a'_P from the colour-split arrays, so a one-colour
+// launch streams only its own half of them
 // The sweeps work on the colour-split copy xs of x that the assembly wrote (a
 // one-colour pass reads only the other colour's half and writes only its
 // own); fin: the last half sweep (black), which writes x in the natural order
