@@ -104,6 +104,10 @@ CONVERGING = {
     "block2d_laminar": lambda: synth.case_cavity_block(),
     "box3d_sst": lambda: synth.case_small_body3d(model="sst", shape="box", nu=1e-5),
     "ahmed_small_sst": lambda: synth.case_ahmed_small(),
+    # the other closures (their diffusivities, sources and nu_t) at a fixed point
+    "box3d_keps": lambda: synth.case_small_body3d(model="keps", shape="box", nu=1e-5),
+    "box3d_rkeps": lambda: synth.case_small_body3d(model="rkeps", shape="box", nu=1e-5),
+    "box3d_komega": lambda: synth.case_small_body3d(model="komega", shape="box", nu=1e-5),
 }
 FIELDS = ("ux", "uy", "uz", "p", "k", "w", "nut")
 
