@@ -48,3 +48,26 @@ def compare(sim, solver, fields=FIELDS, dim=3, model="keps"):
         else:
             out[k] = rel_l2(gf[k], of[k])
     return out
+
+
+CELL_FIELDS = ("ux", "uy", "uz", "p", "k", "w", "nut")
+
+
+def compare_at(sim, solver, cells, dim=3, model="keps"):
+    """Largest error over the given cells (e.g. the immersed-boundary cells, a
+    small fraction of the grid that whole-field norms dilute), relative to the
+    largest magnitude of the field over the whole grid (the velocity scale for
+    the velocity components)."""
+    cells = np.asarray(cells, dtype=np.int64).ravel()
+    of = oracle_fields(sim)
+    gf = {k: solver.get_field(k).cpu().numpy() for k in CELL_FIELDS}
+    vscale = max(np.abs(of["ux"]).max(), np.abs(of["uy"]).max(), np.abs(of["uz"]).max(), 1e-300)
+    out = {}
+    for k in CELL_FIELDS:
+        if dim == 2 and k == "uz":
+            continue
+        if model == "laminar" and k in ("k", "w", "nut"):
+            continue
+        scale = vscale if k in ("ux", "uy", "uz") else max(np.abs(of[k]).max(), 1e-300)
+        out[k] = float(np.abs(gf[k][cells] - of[k][cells]).max()) / scale if cells.size else 0.0
+    return out

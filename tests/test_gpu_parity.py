@@ -15,7 +15,7 @@ import pytest
 import synth
 from oracle.geometry import precompute
 from oracle.solver import Simple
-from parity_util import compare, rel_l2
+from parity_util import compare, compare_at, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -162,6 +162,11 @@ def test_simple_iteration_parity(gpu, name):
     _say("  rel L2", {k: f"{v:.2e}" for k, v in c.items()})
     for k, v in c.items():
         assert v <= 1e-9, (name, k, v)
+    # the boundary cells alone (where the forcing acts), in the max norm
+    cb = compare_at(sim, s, sim.bc_cells, dim=spec.dim, model=spec.model)
+    _say("  boundary cells, max error / field max", {k: f"{v:.2e}" for k, v in cb.items()})
+    for k, v in cb.items():
+        assert v <= 1e-9, (name, "boundary cells", k, v)
     # normalised residuals of the last iteration (diagnostic, both computed in FP64;
     # below 1e-8 they are ratios of rounding noise and are not compared)
     names = ["Ux", "Uy", "Uz", "p", "k", "eps" if spec.model in ("keps", "rkeps") else "omega"]
