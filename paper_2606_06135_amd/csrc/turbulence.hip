@@ -269,7 +269,6 @@ __global__ void k_sum1(long long n, const double* a, double* part, long long pst
   block_sums_store<1>(v, part, pstride, blockIdx.x);
 }
 
-
 struct Scal {
   const double* phi[3];
   const double* S2;  // 2 S:S of the current velocity
@@ -650,13 +649,13 @@ int turbulence_stage(hfdib_ctx* c) {
   double* S = c->scal + SCAL_PCG;
   double* wmax = S + SC_WMAX;
   const Vel U{{c->u[0], c->u[1], c->u[2]}};
-  // SST blending and cross diffusion of the previous iterate, maximum of
-  // omega/eps over cells outside the in-solid group
   // per-cell diffusivities of the omega/eps and the k equations, stored by the
   // first pass for both assemblies and the FP64 sweeps (the momentum
   // right-hand sides are dead during this stage)
   double* gam_w = c->rhs[0];
   double* gam_k = c->rhs[1];
+  // SST blending and cross diffusion of the previous iterate, the
+  // diffusivities, maximum of omega/eps over cells outside the in-solid group
   hipLaunchKernelGGL(k_turb_inputs, g, b, 0, c->stream, P, (const uint8_t*)c->flags, U, (const double*)c->k,
                      (const double*)c->w, (const double*)c->dw, (const double*)c->nut, c->S2, c->F1, c->t2, gam_w,
                      gam_k, c->partials);
