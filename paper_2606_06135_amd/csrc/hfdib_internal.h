@@ -153,6 +153,7 @@ struct hfdib_ctx {
   double* hmir;
   double* hmir_dev;    // its device address
   long long mir_seq;   // sequence number of the last CG step enqueued
+  int pcg_prev_iters;  // CG steps of the previous adaptive solve (0: none yet)
   // --- multigrid
   int nlev;
   hfdib::Level lev[hfdib::MAX_LEVELS];

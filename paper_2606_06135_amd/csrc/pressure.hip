@@ -1309,7 +1309,10 @@ static void pcg_direction(hfdib_ctx* c, const PcgSet<T>& A, bool presmoothed = f
 // While the host waits for a step's scalars the first pass of the next
 // V-cycle is already queued (it only writes the preconditioner output z, so it
 // is harmless when the solve has converged): the device does not idle for the
-// host's round trip.
+// host's round trip.  It is left out at the step where the previous solve
+// converged (consecutive solves mostly take the same number of steps, and a
+// pass queued after a converged step is thrown away); values are the same
+// either way.
 template <typename T>
 static void pcg_begin_t(hfdib_ctx* c, const double* rAU, const double* rhs, double* x, const double* xmean_dev) {
   PcgSet<T> A = pcg_set<T>(c, rAU);
@@ -1425,7 +1428,8 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
   pcg_begin(c, rAU, rhs, x, xmean_dev);
   HFDIB_CHECK_LAUNCH(c, "pcg set-up");
   for (it = 1; it <= maxit; ++it) {
-    if (it < maxit) pcg_ahead(c, rAU);
+    const bool ahead = it < maxit && it != c->pcg_prev_iters;
+    if (ahead) pcg_ahead(c, rAU);
     HFDIB_CHECK_LAUNCH(c, "pcg look-ahead");
     int st = wait_mirror(c);
     if (st != HFDIB_OK) return st;
@@ -1444,10 +1448,11 @@ int pressure_solve(hfdib_ctx* c, const double* rAU, const double* rhs, double* x
       return HFDIB_EDIVERGED;
     }
     if (sqrt(rr) <= target || it == maxit) break;
-    pcg_continue(c, rAU, x, true);
+    pcg_continue(c, rAU, x, ahead);
     HFDIB_CHECK_LAUNCH(c, "pcg iteration");
   }
   if (it > maxit) it = maxit;
+  c->pcg_prev_iters = it;
   timer_end(c, T_PSOLVE);
   if (iters) *iters = it;
   if (relres) *relres = sqrt(rr) / bnorm;
